@@ -1,0 +1,196 @@
+"""Pins of the oracle's manifold correction (Sec. 2, eqs. 10-13).
+
+* Post-conditions: spin lengths exact (eq. 10); SIX restores H = E0 and the
+  full vector J = J0; DUAL restores H = E0 and |J| = |J0| by pure scalings of
+  r and p (eq. 11).
+* The SIX projection is the shortest path: its displacement satisfies the
+  Lagrange (KKT) condition -- it lies in the row space of the constraint
+  Jacobian -- checked with an independent numpy least-squares solve.
+* Newton non-convergence is flagged.
+* The paper's Table 2 energy errors at t = 1e4 (tests/golden).
+"""
+import os
+
+import numpy as np
+import pytest
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def load_table2():
+    rows = []
+    with open(os.path.join(GOLDEN, "table2_energy_errors.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            t = line.split()
+            rows.append(dict(case=t[0], orbit=int(t[1]), beta=float(t[2]), r0=float(t[3]),
+                             py=float(t[4]), chi=float(t[5]), s1=np.array(t[6:9], float),
+                             s2=np.array(t[9:12], float), corrected=float(t[12]), uncorrected=t[13]))
+    return rows
+
+
+def paper_state(oracle, beta, r0, py, chi1, chi2, s1, s2, model=None):
+    c = oracle.coefficients(beta, chi1, chi2, model=model)
+    y = np.zeros(12)
+    y[0], y[4] = r0, py
+    if np.linalg.norm(s1) > 0:
+        y[6:9] = c[6] * s1 / np.linalg.norm(s1)
+    if np.linalg.norm(s2) > 0:
+        y[9:12] = c[7] * s2 / np.linalg.norm(s2)
+    return y
+
+
+def _perturbed(oracle, rng, n=20):
+    """States on orbits of moderate eccentricity, their references, and
+    perturbed copies (relative size 1e-9, like one RK step's error)."""
+    ys, refs = [], []
+    for k in range(n):
+        beta = rng.uniform(0.2, 1.0)
+        r0 = rng.uniform(8, 40)
+        p0 = rng.uniform(0.85, 1.15) / np.sqrt(r0)
+        th = rng.uniform(0, np.pi, 2)
+        ph = rng.uniform(0, 2 * np.pi, 2)
+        y = oracle.init_state(r0, p0, th[0], ph[0], th[1], ph[1], beta, 0.8, 0.6)[0]
+        # Move along the orbit so that r and p are not orthogonal.
+        y = oracle.step(y, beta, 0.8, 0.6, int(rng.integers(5, 200)))[0]
+        H, J = oracle.invariants(y, beta, 0.8, 0.6)
+        refs.append((beta, np.concatenate([H, J[0]])))
+        ys.append(y * (1 + 1e-9 * rng.normal(size=12)))
+    return ys, refs
+
+
+def test_spin_correction_restores_lengths(oracle):
+    rng = np.random.default_rng(1)
+    for beta in (1.0, 0.3):
+        c = oracle.coefficients(beta, 0.9, 0.4)
+        y = rng.normal(size=(10, 12))
+        ref = np.zeros((10, 4))
+        yc, it = oracle.manifold_correct(y, ref, beta, 0.9, 0.4, correction=dict(mode="spin"))
+        assert np.all(it == 0)
+        assert np.allclose(np.linalg.norm(yc[:, 6:9], axis=1), c[6], rtol=4e-16, atol=0)
+        assert np.allclose(np.linalg.norm(yc[:, 9:12], axis=1), c[7], rtol=4e-16, atol=0)
+        # Directions unchanged, orbital variables untouched.
+        assert np.allclose(np.cross(yc[:, 6:9], y[:, 6:9]), 0, atol=1e-15)
+        assert np.array_equal(yc[:, :6], y[:, :6])
+
+
+def test_six_restores_energy_and_J_vector(oracle):
+    rng = np.random.default_rng(2)
+    ys, refs = _perturbed(oracle, rng)
+    for y, (beta, ref) in zip(ys, refs):
+        yc, it = oracle.manifold_correct(y, ref, beta, 0.8, 0.6, correction=dict(mode="six"))
+        H, J = oracle.invariants(yc, beta, 0.8, 0.6)
+        assert abs(H[0] - ref[0]) <= 2e-15 * abs(ref[0])
+        assert np.linalg.norm(J[0] - ref[1:]) <= 2e-15 * np.linalg.norm(ref[1:])
+        assert 1 <= it[0] <= 6
+        c = oracle.coefficients(beta, 0.8, 0.6)
+        assert abs(np.linalg.norm(yc[0, 6:9]) - c[6]) <= 4e-16 * c[6]
+
+
+def test_six_projection_is_least_squares_shortest_path(oracle):
+    """One sweep's displacement d = y_c - y* (in r, p) solves min |d| subject to
+    G d = -c: it lies in the row space of G, the Jacobian of (J, H) in (r, p).
+    Checked with numpy's least-squares solver on the same constraint rows."""
+    rng = np.random.default_rng(3)
+    ys, refs = _perturbed(oracle, rng, n=10)
+    for y, (beta, ref) in zip(ys, refs):
+        ys_spin, _ = oracle.manifold_correct(y, ref, beta, 0.8, 0.6, correction=dict(mode="spin"))
+        ystar = ys_spin[0]
+        yc, _ = oracle.manifold_correct(ystar, ref, beta, 0.8, 0.6, correction=dict(mode="six", sweeps=1))
+        d = yc[0, :6] - ystar[:6]
+        r, p = ystar[0:3], ystar[3:6]
+        g = oracle.gradient_complex_step(ystar, beta, 0.8, 0.6)[0]
+        G = np.zeros((4, 6))
+        for k, e in enumerate(np.eye(3)):
+            G[k, :3] = np.cross(p, e)
+            G[k, 3:] = np.cross(e, r)
+        G[3, :3], G[3, 3:] = g[0:3], g[3:6]
+        H, J = oracle.invariants(ystar, beta, 0.8, 0.6)
+        resid = np.concatenate([J[0] - ref[1:], H - ref[0]])
+        d_ls = np.linalg.lstsq(G, -resid, rcond=None)[0]
+        assert np.linalg.norm(d - d_ls) <= 1e-4 * np.linalg.norm(d_ls)
+
+
+def test_dual_scaling_post_conditions(oracle):
+    """DUAL (eqs. 11-13): H = E0 and |J| = |J0| after the correction, and the
+    result is a pure scaling p = alpha p*, r = b r*."""
+    rng = np.random.default_rng(4)
+    ys, refs = _perturbed(oracle, rng)
+    checked = 0
+    for y, (beta, ref) in zip(ys, refs):
+        ys_spin, _ = oracle.manifold_correct(y, ref, beta, 0.8, 0.6, correction=dict(mode="spin"))
+        ystar = ys_spin[0]
+        yc, it = oracle.manifold_correct(ystar, ref, beta, 0.8, 0.6, correction=dict(mode="dual"))
+        yc = yc[0]
+        H, J = oracle.invariants(yc, beta, 0.8, 0.6)
+        assert abs(H[0] - ref[0]) <= 2e-15 * abs(ref[0])
+        alpha = yc[3:6] / ystar[3:6]
+        b = yc[0:3] / ystar[0:3]
+        assert np.ptp(alpha[np.abs(ystar[3:6]) > 1e-3]) < 1e-14
+        # Unless the Newton step fell back to energy-only scaling (b = 1),
+        # |J| is restored too.
+        if abs(b[0] - 1.0) > 0:
+            assert abs(np.linalg.norm(J[0]) - np.linalg.norm(ref[1:])) <= 4e-15 * np.linalg.norm(ref[1:])
+            assert np.ptp(b[np.abs(ystar[0:3]) > 1e-3]) < 1e-14
+            checked += 1
+    assert checked >= len(ys) // 2
+
+
+def test_newton_cap_is_flagged(oracle):
+    rng = np.random.default_rng(5)
+    ys, refs = _perturbed(oracle, rng, n=3)
+    for y, (beta, ref) in zip(ys, refs):
+        _, it = oracle.manifold_correct(y, ref, beta, 0.8, 0.6,
+                                        correction=dict(mode="six", tol=1e-300, max_iter=1))
+        assert it[0] < 0   # negative count = cap reached without convergence
+
+
+def test_newton_converges_in_few_iterations(oracle):
+    """Quadratic convergence: an energy error of 1e-6 is removed to rounding in
+    at most 3 momentum-scaling iterations per sweep."""
+    rng = np.random.default_rng(6)
+    ys, refs = _perturbed(oracle, rng, n=6)
+    for y, (beta, ref) in zip(ys, refs):
+        y2 = y.copy()
+        y2[3:6] *= 1 + 1e-6
+        yc, it = oracle.manifold_correct(y2, ref, beta, 0.8, 0.6, correction=dict(mode="six", sweeps=1))
+        H, _ = oracle.invariants(yc, beta, 0.8, 0.6)
+        assert 1 <= it[0] <= 3
+        assert abs(H[0] - ref[0]) <= 2e-15 * abs(ref[0])
+
+
+@pytest.mark.parametrize("row", load_table2(), ids=lambda r: f"{r['case']}-{r['orbit']}")
+@pytest.mark.parametrize("mode", ["six", "dual"])
+def test_paper_table2_energy_errors(oracle, row, mode):
+    """Corrected RK5 keeps |Delta E| at or below the paper's printed order at
+    t = 1e4 (Table 2), while the uncorrected RK5 error is orders larger."""
+    y = paper_state(oracle, row["beta"], row["r0"], row["py"], row["chi"], row["chi"], row["s1"], row["s2"])
+    args = (row["beta"], row["chi"], row["chi"])
+    H0 = oracle.hamiltonian(y, *args)[0]
+    yc = oracle.step(y, *args, 10000, integrator=dict(method="rk5"), correction=dict(mode=mode))
+    err_c = abs(oracle.hamiltonian(yc, *args)[0] - H0) / abs(H0)
+    assert err_c <= max(row["corrected"], 5e-15)
+    yu = oracle.step(y, *args, 10000, integrator=dict(method="rk5"), correction=None)
+    err_u = abs(oracle.hamiltonian(yu, *args)[0] - H0) / abs(H0)
+    assert err_u > 100 * max(err_c, 1e-16)
+
+
+def test_correction_removes_secular_drift(oracle):
+    """With SIX the energy and J errors stay at rounding level, with no growth,
+    where uncorrected RK4 drifts (Sec. 1, Table 2 'Linear growth')."""
+    y = paper_state(oracle, 1.0, 10.14, 0.365, 1.0, 1.0,
+                    np.array([0.13036, 0.262852, -0.955989]), np.array([0.118966, -0.13459, -0.983734]))
+    H0, J0 = oracle.invariants(y, 1.0, 1.0, 1.0)
+    ref = np.concatenate([H0, J0[0]])
+    yc, yu = y.copy(), y.copy()
+    ec, eu, ej = [], [], []
+    for _ in range(5):
+        yc = oracle.step(yc, 1.0, 1.0, 1.0, 1000, correction=dict(mode="six"), ref=ref)
+        yu = oracle.step(yu, 1.0, 1.0, 1.0, 1000)
+        H, J = oracle.invariants(yc, 1.0, 1.0, 1.0)
+        ec.append(abs(H[0] - H0[0]) / abs(H0[0]))
+        ej.append(np.linalg.norm(J[0] - J0[0]) / np.linalg.norm(J0[0]))
+        eu.append(abs(oracle.hamiltonian(yu, 1.0, 1.0, 1.0)[0] - H0[0]) / abs(H0[0]))
+    assert max(ec) < 5e-15 and max(ej) < 5e-15
+    assert eu[-1] > 1e-6 and eu[-1] > 2 * eu[0]
