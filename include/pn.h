@@ -1,0 +1,234 @@
+/*
+ * pn.h -- C ABI of the MI355X (gfx950) library for batched, manifold-corrected
+ * integration of spinning compact binaries in the conservative post-Newtonian
+ * (PN) Hamiltonian formulation, with the two-nearby-trajectory fast Lyapunov
+ * indicator (FLI) used in phase-space scans.
+ *
+ * Source: Ran, Liu & Zhong, "GPU accelerated manifold correction method for
+ * spinning compact binaries", arXiv:1802.00147.
+ *   Sec. 2, eq. (1)       Hamiltonian H = H_N + H_1PN + H_2PN + H_SO + H_SS
+ *                         (the 2.5PN radiation and 3PN terms are not modelled)
+ *   Sec. 2, eqs. (2)-(5)  spin-spin (S1S2) and quadrupole-monopole terms
+ *   Sec. 2, eqs. (6)-(9)  Hamilton's equations and spin precession
+ *   Sec. 2, eqs. (10)-(13) manifold correction (spin lengths; dual scaling)
+ *   Sec. 3B               Newton iteration limit eps <= 1e-10
+ *   Sec. 3C               FLI phase-space scans, chaos threshold 5.8 at t = 1e5
+ *
+ * Units (Sec. 2): G = c = M = 1 with M = m1 + m2; r in M, p = P/mu, t in M,
+ * H is the Hamiltonian per unit reduced mass mu.  beta = m1/m2 in (0, 1],
+ * eta = mu/M.  Spin units: see pn_spin_units.
+ *
+ * State layout (all entry points): structure of arrays.  Component c of
+ * orbit i is y[c * ld + i], c = 0..11 = (rx, ry, rz, px, py, pz, S1x, S1y,
+ * S1z, S2x, S2y, S2z), ld >= n.  "[k][ld]" below means k rows of length ld.
+ *
+ * Memory: every array pointer is a DEVICE pointer (hipMalloc or a torch
+ * CUDA tensor), 8-byte aligned; 256-byte alignment is recommended.  The
+ * caller allocates and frees everything; the library keeps no per-call
+ * allocation.  All work is enqueued on the given stream and is complete when
+ * the stream is synchronised.  Inputs are not modified unless documented as
+ * in/out.  Results depend only on each orbit's inputs and the settings, never
+ * on the launch shape.
+ *
+ * Errors: every call returns a pn_status.  All argument validation happens on
+ * the host before anything is launched; a call that returns PN_EINVAL has
+ * touched no memory.  PN_EDEVICE reports a HIP launch error (the HIP error
+ * text is available from pn_last_error()).  Physical failures of individual
+ * orbits are not call errors: they are reported per orbit in the status
+ * output (PN_ORBIT_*).
+ */
+#ifndef PN_H
+#define PN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PN_OK = 0,
+    PN_EINVAL = 1,   /* null pointer, n < 0, ld < n, parameter out of range, unknown enum */
+    PN_ENOWS = 2,    /* workspace smaller than the documented size */
+    PN_EDEVICE = 3   /* HIP error while launching */
+} pn_status;
+
+/* Per-orbit status codes (low byte) and flags. */
+enum {
+    PN_ORBIT_OK = 0,
+    PN_ORBIT_MERGED = 1,        /* r fell below r_merge */
+    PN_ORBIT_ESCAPED = 2,       /* r rose above r_esc */
+    PN_ORBIT_NONFINITE = 3,     /* a state component became NaN or infinite */
+    PN_ORBIT_UNBOUND_INIT = 4,  /* H(y0) >= 0: not a bound orbit (Sec. 3C removes these) */
+    PN_ORBIT_BADPARAM = 5,      /* per-orbit beta / chi outside (0,1] / [0,1] */
+    PN_ORBIT_NEWTON_NOCONV = 0x100 /* flag: some Newton solve hit max_iter */
+};
+
+/* Spin units.  The two choices describe the same Hamiltonian; they differ in
+ * the unit of the spin variables and hence in the spin flow.
+ *   PN_SPIN_PHYS:      spins in units of mu*M, |S_i| = chi_1 beta and chi_2 / beta;
+ *                      dS_i/dt = (dH/dS_i) x S_i is the physical precession and
+ *                      J = r x p + S1 + S2 is the conserved total angular momentum.
+ *   PN_SPIN_PAPER_EQ8: spins in units of M^2, |S_i| = chi_i m_i^2; dH/dS_i is
+ *                      exactly eqs. (8)-(9) and the flow is eq. (7) taken
+ *                      literally (faster than the physical rate by 1/eta). */
+typedef enum { PN_SPIN_PHYS = 0, PN_SPIN_PAPER_EQ8 = 1 } pn_spin_units;
+
+typedef enum { PN_RK4 = 0, PN_RK5 = 1 } pn_method;
+
+typedef enum {
+    PN_CORR_NONE = 0,
+    PN_CORR_SPIN = 1,  /* eq. (10) only */
+    PN_CORR_SIX = 2,   /* eq. (10), then least-squares projection onto H = E0 and the
+                          vector J = J0 followed by energy restoration by momentum scaling */
+    PN_CORR_DUAL = 3   /* eq. (10), then the dual scaling of eqs. (11)-(13) */
+} pn_corr_mode;
+
+typedef enum { PN_THR_LITERAL = 0, PN_THR_LOG_T = 1 } pn_thr_scaling;
+
+/* Terms of eq. (1).  pn_order: 0 Newtonian, 1 +1PN, 2 +1PN+2PN. */
+typedef struct {
+    int32_t pn_order;
+    int32_t spin_orbit;  /* 1.5PN spin-orbit */
+    int32_t spin_spin;   /* eq. (3) */
+    int32_t quad_mono;   /* eqs. (4)-(5) */
+    int32_t spin_units;  /* pn_spin_units */
+} pn_model;
+
+/* Mass ratio and dimensionless spins.  Either per-orbit DEVICE arrays of
+ * length n (all three non-NULL), or all three NULL and the host scalars
+ * beta0, chi1_0, chi2_0 apply to every orbit.  Host scalars are validated
+ * (beta in (0,1], chi in [0,1]); per-orbit values outside these ranges give
+ * the orbit status PN_ORBIT_BADPARAM. */
+typedef struct {
+    const double* beta;
+    const double* chi1;
+    const double* chi2;
+    double beta0, chi1_0, chi2_0;
+} pn_params;
+
+/* Fixed-step integrator.  PN_RK4: classical RK4.  PN_RK5: the paper's fifth-order
+ * Runge-Kutta (Sec. 2, 3A), with the fifth-order weights of Dormand-Prince.
+ * h > 0.  An integration to t_end takes ceil(t_end / h) steps. */
+typedef struct {
+    int32_t method;
+    double h;
+} pn_integrator;
+
+/* Correction applied after every step (Sec. 2, eqs. 10-13).  tol is the
+ * Newton iteration limit on the scale factors (the paper uses 1e-10, Sec. 3B);
+ * max_iter caps each Newton solve (>= 1); sweeps (>= 1) is the number of
+ * projection + momentum-scaling passes of PN_CORR_SIX; w1, w2 > 0 are the
+ * weights of eq. (12) (the Newton root does not depend on them). */
+typedef struct {
+    int32_t mode;
+    double tol;
+    int32_t max_iter;
+    int32_t sweeps;
+    double w1, w2;
+} pn_correction;
+
+/* Fast Lyapunov indicator of two nearby trajectories (Sec. 3B-3C).  The shadow
+ * starts at y0 + d0 e_{shadow_axis}; when the 12-component Euclidean separation
+ * reaches d_renorm, log10(d/d0) is accumulated and the shadow is pulled back to
+ * distance d0 along the same direction (its spin lengths and its own reference
+ * integrals are then reset).  FLI(t_end) = sum + log10(d/d0).  An orbit is
+ * labelled chaotic when FLI > threshold: thr_at_1e5 (5.8 in the paper) for
+ * PN_THR_LITERAL, thr_at_1e5 + log10(t_end / 1e5) for PN_THR_LOG_T.  r_merge and
+ * r_esc bound r (merged / escaped orbits are removed, Sec. 3C). */
+typedef struct {
+    double d0;
+    double d_renorm;
+    int32_t shadow_axis;
+    double thr_at_1e5;
+    int32_t thr_scaling;
+    double r_merge;
+    double r_esc;
+} pn_fli_cfg;
+
+/* Outputs of a scan.  fli, label, status are required; the rest may be NULL.
+ *   fli[n]          FLI(t_end) (NaN for an orbit whose status is not OK)
+ *   label[n]        1 chaotic, 0 regular, -1 invalid orbit
+ *   status[n]       PN_ORBIT_* code, possibly with PN_ORBIT_NEWTON_NOCONV set
+ *   y_final[12][ld] state of the orbit at t_end (or where it stopped)
+ *   dH[n]           |H(y_final) - E0| / |E0|
+ *   dJ[n]           |J(y_final) - J0| / |J0|
+ *   newton_max[n]   largest Newton iteration count of any correction
+ *   renorms[n]      number of shadow renormalisations
+ *   trace[ntrace][ld] FLI after every trace_every steps (trace_every > 0;
+ *                   entries past an orbit's last step are left untouched) */
+typedef struct {
+    double* fli;
+    int8_t* label;
+    int32_t* status;
+    double* y_final;
+    double* dH;
+    double* dJ;
+    int32_t* newton_max;
+    int64_t* renorms;
+    double* trace;
+    int64_t trace_every;
+    int64_t ntrace;
+} pn_scan_out;
+
+/* Defaults used by the tests and benchmark (filled into caller structs). */
+void pn_default_model(pn_model* m);
+void pn_default_integrator(pn_integrator* in);
+void pn_default_correction(pn_correction* c);
+void pn_default_fli_cfg(pn_fli_cfg* f);
+
+/* Initial conditions of a scan (Sec. 3B-3C, Sec. 4): r = (r0, 0, 0),
+ * p = (0, p0, 0), S_i = |S_i| (sin th_i cos ph_i, sin th_i sin ph_i, cos th_i).
+ * Inputs r0, p0, th1, ph1, th2, ph2 are [n] device arrays; output y0 [12][ld]. */
+pn_status pn_init_state(const pn_model* model, pn_params params, int64_t n,
+                        const double* r0, const double* p0, const double* th1,
+                        const double* ph1, const double* th2, const double* ph2,
+                        double* y0, int64_t ld, hipStream_t stream);
+
+/* Right-hand side of Hamilton's equations and the spin precession (eqs. 6-9):
+ * dydt = (dH/dp, -dH/dr, (dH/dS1) x S1, (dH/dS2) x S2).  y, dydt: [12][ld]. */
+pn_status pn_rhs(const pn_model* model, pn_params params, int64_t n, const double* y,
+                 int64_t ld, double* dydt, hipStream_t stream);
+
+/* H and J = r x p + S1 + S2 per orbit.  H: [n]; J: [3][ld]. */
+pn_status pn_invariants(const pn_model* model, pn_params params, int64_t n, const double* y,
+                        int64_t ld, double* H, double* J, hipStream_t stream);
+
+/* One manifold correction of each state against its reference integrals.
+ * y: [12][ld] in/out.  ref: [4][ld] = (E0, J0x, J0y, J0z).  iters [n] (nullable):
+ * total Newton iterations, negated when some solve hit max_iter. */
+pn_status pn_manifold_correct(const pn_model* model, pn_params params,
+                              const pn_correction* corr, int64_t n, double* y, int64_t ld,
+                              const double* ref, int32_t* iters, hipStream_t stream);
+
+/* nsteps integration steps of each state, each followed by the correction
+ * (corr NULL or mode PN_CORR_NONE: no correction).  y: [12][ld] in/out.
+ * ref: [4][ld] reference integrals, or NULL to capture them from y after its
+ * spin lengths are set (only when a correction is requested). */
+pn_status pn_step(const pn_model* model, pn_params params, const pn_integrator* integ,
+                  const pn_correction* corr, int64_t n, double* y, int64_t ld,
+                  const double* ref, int64_t nsteps, hipStream_t stream);
+
+/* Fused FLI scan: for every orbit, integrate the orbit and its shadow from y0
+ * to t_end with a correction after every step, and report the FLI, the
+ * chaos label and the status (Sec. 3C).  y0: [12][ld] (not modified).
+ * t_end: [n] device array, or NULL to use t_end_all for every orbit.
+ * All of one orbit's work happens in one GPU lane. */
+pn_status pn_fli_scan(const pn_model* model, pn_params params, const pn_integrator* integ,
+                      const pn_correction* corr, const pn_fli_cfg* fli, int64_t n,
+                      const double* y0, int64_t ld, const double* t_end, double t_end_all,
+                      const pn_scan_out* out, hipStream_t stream);
+
+/* Library version and last error text (thread-local; "" when none). */
+int32_t pn_version(void);
+const char* pn_status_string(pn_status s);
+const char* pn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PN_H */

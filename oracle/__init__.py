@@ -28,7 +28,7 @@ FLI = dict(d0=1e-8, d_renorm=0.1, shadow_axis=0, thr_at_1e5=5.8, thr_scaling=1,
 
 METHODS = {"rk4": 0, "rk5": 1}
 MODES = {"none": 0, "spin": 1, "six": 2, "dual": 3}
-STATUS_OK, STATUS_MERGED, STATUS_ESCAPED, STATUS_NONFINITE, STATUS_UNBOUND_INIT = 0, 1, 2, 3, 4
+STATUS_OK, STATUS_MERGED, STATUS_ESCAPED, STATUS_NONFINITE, STATUS_UNBOUND_INIT, STATUS_BADPARAM = range(6)
 STATUS_NEWTON_NOCONV = 0x100
 
 

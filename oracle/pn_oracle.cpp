@@ -128,7 +128,12 @@ typedef struct {
 }  // extern "C"
 
 enum { ST_OK = 0, ST_MERGED = 1, ST_ESCAPED = 2, ST_NONFINITE = 3, ST_UNBOUND_INIT = 4,
-       ST_NEWTON_NOCONV = 0x100 };
+       ST_BADPARAM = 5, ST_NEWTON_NOCONV = 0x100 };
+
+// Parameter ranges of Sec. 2: beta = m1/m2 in (0, 1]; Kerr spins chi in [0, 1].
+static bool params_valid(double beta, double chi1, double chi2) {
+    return beta > 0.0 && beta <= 1.0 && chi1 >= 0.0 && chi1 <= 1.0 && chi2 >= 0.0 && chi2 <= 1.0;
+}
 
 // ---------------------------------------------------------------------------
 // Mass and spin coefficients (Sec. 2 mass definitions; eqs. (3)-(5), (8)-(9)).
@@ -873,6 +878,17 @@ void or_fli_scan(const or_model* m, const double* beta, const double* chi1, cons
         for (;;) {
             const int64_t i = next.fetch_add(1);
             if (i >= n) break;
+            if (!params_valid(pick(beta, pstride, i), pick(chi1, pstride, i), pick(chi2, pstride, i))) {
+                fli[i] = NAN;
+                label[i] = -1;
+                status[i] = ST_BADPARAM;
+                if (y_final) for (int k = 0; k < 12; ++k) y_final[12 * i + k] = y0[12 * i + k];
+                if (dH) dH[i] = NAN;
+                if (dJ) dJ[i] = NAN;
+                if (newton_max) newton_max[i] = 0;
+                if (renorms) renorms[i] = 0;
+                continue;
+            }
             const Coef c = make_coef(*m, pick(beta, pstride, i), pick(chi1, pstride, i), pick(chi2, pstride, i));
             const FliResult r = fli_run<double>(*m, c, *in, *cc, *fc, y0 + 12 * i, t_end[tstride * i],
                                                 trace ? trace + ntrace * i : nullptr, trace_every);

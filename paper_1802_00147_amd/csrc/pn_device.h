@@ -1,0 +1,493 @@
+// pn_device.h -- register-resident FP64 physics of one trajectory per lane.
+//
+// Hamiltonian (arXiv:1802.00147, Sec. 2, eq. 1) per unit reduced mass in ADM
+// variables, as a table-driven polynomial in P2 = p.p, NP = n.p and u = 1/r:
+//   H_orb = P2/2 - u + a1 P2^2 + (a2 P2 + a3 NP^2) u + a4 u^2
+//         + b1 P2^3 + (b2 P2^2 + b3 P2 NP^2 + b4 NP^4) u + (b5 P2 + b6 NP^2) u^2 + b7 u^3
+//   H_SO  = u^3 L.(cso1 S1 + cso2 S2)                              (1.5PN spin-orbit)
+//   H_SS  = u^3 { c12 [3 (S1.n)(S2.n) - S1.S2]                      (eq. 3)
+//               + c11 [3 (S1.n)^2 - S1.S1] + c22 [3 (S2.n)^2 - S2.S2] }  (eqs. 4-5)
+// Terms that a model switches off have zero coefficients, so every kernel
+// evaluates one branch-free expression.  The gradient is written out by hand
+// (combined terms, one reciprocal square root per evaluation); equations of
+// motion follow eqs. (6)-(7).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pn.h"
+
+#define PN_HD __host__ __device__ __forceinline__
+
+struct PnCoef {
+    double a1, a2, a3, a4;                 // 1PN
+    double b1, b2, b3, b4, b5, b6, b7;     // 2PN
+    double cso1, cso2, c12, c11, c22;      // spin couplings
+    double s1, s2;                         // spin lengths
+};
+
+// Coefficient table of one parameter set (Sec. 2: M = 1, eta = m1 m2).
+// Returns false when beta or chi is out of range (or not finite).
+PN_HD bool pn_make_coef(const pn_model& m, double beta, double chi1, double chi2, PnCoef& k) {
+    const bool ok = (beta > 0.0) && (beta <= 1.0) && (chi1 >= 0.0) && (chi1 <= 1.0) &&
+                    (chi2 >= 0.0) && (chi2 <= 1.0);
+    if (!ok) beta = 1.0;  // keep the table finite; the caller flags the orbit
+    const double m1 = beta / (1.0 + beta), m2 = 1.0 / (1.0 + beta);
+    const double eta = m1 * m2;
+    const double o1 = m.pn_order >= 1 ? 1.0 : 0.0;
+    const double o2 = m.pn_order >= 2 ? 1.0 : 0.0;
+    k.a1 = o1 * (3.0 * eta - 1.0) / 8.0;
+    k.a2 = o1 * -(3.0 + eta) / 2.0;
+    k.a3 = o1 * -eta / 2.0;
+    k.a4 = o1 * 0.5;
+    k.b1 = o2 * (1.0 - 5.0 * eta + 5.0 * eta * eta) / 16.0;
+    k.b2 = o2 * (5.0 - 20.0 * eta - 3.0 * eta * eta) / 8.0;
+    k.b3 = o2 * -(eta * eta) / 4.0;
+    k.b4 = o2 * -3.0 * eta * eta / 8.0;
+    k.b5 = o2 * (5.0 + 8.0 * eta) / 2.0;
+    k.b6 = o2 * 3.0 * eta / 2.0;
+    k.b7 = o2 * -(1.0 + 3.0 * eta) / 4.0;
+    // Spin units: PHYS (mu M) multiplies every spin coupling by eta relative
+    // to M^2 units, where dH/dS_i reproduces eqs. (8)-(9) exactly.
+    const double f = (m.spin_units == PN_SPIN_PHYS) ? eta : 1.0;
+    const double so = m.spin_orbit ? 1.0 : 0.0;
+    const double ss = m.spin_spin ? 1.0 : 0.0;
+    const double qm = m.quad_mono ? 1.0 : 0.0;
+    k.cso1 = so * f * (2.0 + 1.5 / beta);
+    k.cso2 = so * f * (2.0 + 1.5 * beta);
+    k.c12 = ss * f / eta;
+    k.c11 = qm * f / (2.0 * beta * eta);
+    k.c22 = qm * f * beta / (2.0 * eta);
+    if (m.spin_units == PN_SPIN_PHYS) {
+        k.s1 = chi1 * beta;         // chi1 m1^2 / (mu M)
+        k.s2 = chi2 / beta;         // chi2 m2^2 / (mu M)
+    } else {
+        k.s1 = chi1 * m1 * m1;
+        k.s2 = chi2 * m2 * m2;
+    }
+    return ok;
+}
+
+// 1/sqrt(x) to ~1 ulp: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double pn_rsqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
+// 1/x to ~1 ulp: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double pn_rcp(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    return y;
+}
+
+__device__ __forceinline__ double dot3(double ax, double ay, double az, double bx, double by, double bz) {
+    return fma(ax, bx, fma(ay, by, az * bz));
+}
+
+// Right-hand side: f = (dH/dp, -dH/dr, Omega1 x S1, Omega2 x S2).
+__device__ __forceinline__ void pn_rhs_eval(const PnCoef& k, const double* y, double* f) {
+    const double rx = y[0], ry = y[1], rz = y[2];
+    const double px = y[3], py = y[4], pz = y[5];
+    const double s1x = y[6], s1y = y[7], s1z = y[8];
+    const double s2x = y[9], s2y = y[10], s2z = y[11];
+    const double r2 = dot3(rx, ry, rz, rx, ry, rz);
+    const double u = pn_rsqrt(r2);
+    const double u2 = u * u, u3 = u2 * u, u4 = u2 * u2;
+    const double nx = rx * u, ny = ry * u, nz = rz * u;
+    const double P2 = dot3(px, py, pz, px, py, pz);
+    const double NP = dot3(nx, ny, nz, px, py, pz);
+    const double NP2 = NP * NP;
+
+    // Partial derivatives of H_orb(P2, NP, u).
+    const double HP2 = 0.5 + 2.0 * k.a1 * P2 + k.a2 * u + 3.0 * k.b1 * P2 * P2
+                     + fma(2.0 * k.b2, P2, k.b3 * NP2) * u + k.b5 * u2;
+    const double HNP = 2.0 * NP * (k.a3 * u + fma(k.b3, P2, 2.0 * k.b4 * NP2) * u + k.b6 * u2);
+    const double Hu = -1.0 + fma(k.a2, P2, k.a3 * NP2) + 2.0 * k.a4 * u
+                    + (k.b2 * P2 * P2 + k.b3 * P2 * NP2 + k.b4 * NP2 * NP2)
+                    + 2.0 * fma(k.b5, P2, k.b6 * NP2) * u + 3.0 * k.b7 * u2;
+
+    // Spin geometry.
+    const double Lx = ry * pz - rz * py, Ly = rz * px - rx * pz, Lz = rx * py - ry * px;
+    const double ex = k.cso1 * s1x + k.cso2 * s2x;   // S_eff
+    const double ey = k.cso1 * s1y + k.cso2 * s2y;
+    const double ez = k.cso1 * s1z + k.cso2 * s2z;
+    const double LS = dot3(Lx, Ly, Lz, ex, ey, ez);
+    const double sn1 = dot3(s1x, s1y, s1z, nx, ny, nz);
+    const double sn2 = dot3(s2x, s2y, s2z, nx, ny, nz);
+    const double S12 = dot3(s1x, s1y, s1z, s2x, s2y, s2z);
+    const double S11 = dot3(s1x, s1y, s1z, s1x, s1y, s1z);
+    const double S22 = dot3(s2x, s2y, s2z, s2x, s2y, s2z);
+    const double w1 = 3.0 * k.c12 * sn2 + 6.0 * k.c11 * sn1;   // Omega1 = u^3 (cso1 L + w1 n - c12 S2) + (...) S1
+    const double w2 = 3.0 * k.c12 * sn1 + 6.0 * k.c22 * sn2;
+
+    // dH/dp = 2 HP2 p + HNP n + u^3 (S_eff x r).
+    const double cp = 2.0 * HP2;
+    f[0] = cp * px + HNP * nx + u3 * (ey * rz - ez * ry);
+    f[1] = cp * py + HNP * ny + u3 * (ez * rx - ex * rz);
+    f[2] = cp * pz + HNP * nz + u3 * (ex * ry - ey * rx);
+
+    // dH/dr = An n + Ap p + u^4 (w1 S1 + w2 S2) + u^3 (p x S_eff).
+    const double Ap = HNP * u;
+    const double An = -Ap * NP - Hu * u2 - 3.0 * u4 * LS
+                    - 3.0 * u4 * (k.c12 * (5.0 * sn1 * sn2 - S12) + k.c11 * (5.0 * sn1 * sn1 - S11)
+                                  + k.c22 * (5.0 * sn2 * sn2 - S22));
+    const double B1 = u4 * w1, B2 = u4 * w2;
+    f[3] = -(An * nx + Ap * px + B1 * s1x + B2 * s2x + u3 * (py * ez - pz * ey));
+    f[4] = -(An * ny + Ap * py + B1 * s1y + B2 * s2y + u3 * (pz * ex - px * ez));
+    f[5] = -(An * nz + Ap * pz + B1 * s1z + B2 * s2z + u3 * (px * ey - py * ex));
+
+    // Spin precession, eq. (7).
+    const double o1x = u3 * (k.cso1 * Lx + w1 * nx - k.c12 * s2x);
+    const double o1y = u3 * (k.cso1 * Ly + w1 * ny - k.c12 * s2y);
+    const double o1z = u3 * (k.cso1 * Lz + w1 * nz - k.c12 * s2z);
+    const double o2x = u3 * (k.cso2 * Lx + w2 * nx - k.c12 * s1x);
+    const double o2y = u3 * (k.cso2 * Ly + w2 * ny - k.c12 * s1y);
+    const double o2z = u3 * (k.cso2 * Lz + w2 * nz - k.c12 * s1z);
+    f[6] = o1y * s1z - o1z * s1y;
+    f[7] = o1z * s1x - o1x * s1z;
+    f[8] = o1x * s1y - o1y * s1x;
+    f[9] = o2y * s2z - o2z * s2y;
+    f[10] = o2z * s2x - o2x * s2z;
+    f[11] = o2x * s2y - o2y * s2x;
+}
+
+// Energy as a polynomial in a momentum scale factor a (r and spins fixed):
+// H(r, a p, S) = K0 + K1 a + K2 a^2 + K4 a^4 + K6 a^6.
+struct PnEnergyPoly { double K0, K1, K2, K4, K6; };
+
+__device__ __forceinline__ PnEnergyPoly pn_energy_poly(const PnCoef& k, const double* y) {
+    const double rx = y[0], ry = y[1], rz = y[2];
+    const double px = y[3], py = y[4], pz = y[5];
+    const double s1x = y[6], s1y = y[7], s1z = y[8];
+    const double s2x = y[9], s2y = y[10], s2z = y[11];
+    const double r2 = dot3(rx, ry, rz, rx, ry, rz);
+    const double u = pn_rsqrt(r2);
+    const double u2 = u * u, u3 = u2 * u;
+    const double P2 = dot3(px, py, pz, px, py, pz);
+    const double NP = dot3(rx, ry, rz, px, py, pz) * u;
+    const double NP2 = NP * NP;
+    const double Lx = ry * pz - rz * py, Ly = rz * px - rx * pz, Lz = rx * py - ry * px;
+    const double LS = k.cso1 * dot3(Lx, Ly, Lz, s1x, s1y, s1z) + k.cso2 * dot3(Lx, Ly, Lz, s2x, s2y, s2z);
+    const double sn1 = dot3(s1x, s1y, s1z, rx, ry, rz) * u;
+    const double sn2 = dot3(s2x, s2y, s2z, rx, ry, rz) * u;
+    const double S12 = dot3(s1x, s1y, s1z, s2x, s2y, s2z);
+    const double S11 = dot3(s1x, s1y, s1z, s1x, s1y, s1z);
+    const double S22 = dot3(s2x, s2y, s2z, s2x, s2y, s2z);
+    PnEnergyPoly e;
+    e.K0 = -u + k.a4 * u2 + k.b7 * u3
+         + u3 * (k.c12 * (3.0 * sn1 * sn2 - S12) + k.c11 * (3.0 * sn1 * sn1 - S11)
+                 + k.c22 * (3.0 * sn2 * sn2 - S22));
+    e.K1 = u3 * LS;
+    e.K2 = 0.5 * P2 + fma(k.a2, P2, k.a3 * NP2) * u + fma(k.b5, P2, k.b6 * NP2) * u2;
+    e.K4 = k.a1 * P2 * P2 + (k.b2 * P2 * P2 + k.b3 * P2 * NP2 + k.b4 * NP2 * NP2) * u;
+    e.K6 = k.b1 * P2 * P2 * P2;
+    return e;
+}
+
+__device__ __forceinline__ double pn_energy(const PnCoef& k, const double* y) {
+    const PnEnergyPoly e = pn_energy_poly(k, y);
+    return e.K0 + e.K1 + e.K2 + e.K4 + e.K6;
+}
+
+// H and its gradient with respect to r and p (spins held fixed).
+__device__ __forceinline__ void pn_energy_grad_rp(const PnCoef& k, const double* y, double& H,
+                                                  double* gr, double* gp) {
+    const double rx = y[0], ry = y[1], rz = y[2];
+    const double px = y[3], py = y[4], pz = y[5];
+    const double s1x = y[6], s1y = y[7], s1z = y[8];
+    const double s2x = y[9], s2y = y[10], s2z = y[11];
+    const double r2 = dot3(rx, ry, rz, rx, ry, rz);
+    const double u = pn_rsqrt(r2);
+    const double u2 = u * u, u3 = u2 * u, u4 = u2 * u2;
+    const double nx = rx * u, ny = ry * u, nz = rz * u;
+    const double P2 = dot3(px, py, pz, px, py, pz);
+    const double NP = dot3(nx, ny, nz, px, py, pz);
+    const double NP2 = NP * NP;
+    const double HP2 = 0.5 + 2.0 * k.a1 * P2 + k.a2 * u + 3.0 * k.b1 * P2 * P2
+                     + fma(2.0 * k.b2, P2, k.b3 * NP2) * u + k.b5 * u2;
+    const double HNP = 2.0 * NP * (k.a3 * u + fma(k.b3, P2, 2.0 * k.b4 * NP2) * u + k.b6 * u2);
+    const double Hu = -1.0 + fma(k.a2, P2, k.a3 * NP2) + 2.0 * k.a4 * u
+                    + (k.b2 * P2 * P2 + k.b3 * P2 * NP2 + k.b4 * NP2 * NP2)
+                    + 2.0 * fma(k.b5, P2, k.b6 * NP2) * u + 3.0 * k.b7 * u2;
+    const double Lx = ry * pz - rz * py, Ly = rz * px - rx * pz, Lz = rx * py - ry * px;
+    const double ex = k.cso1 * s1x + k.cso2 * s2x;
+    const double ey = k.cso1 * s1y + k.cso2 * s2y;
+    const double ez = k.cso1 * s1z + k.cso2 * s2z;
+    const double LS = dot3(Lx, Ly, Lz, ex, ey, ez);
+    const double sn1 = dot3(s1x, s1y, s1z, nx, ny, nz);
+    const double sn2 = dot3(s2x, s2y, s2z, nx, ny, nz);
+    const double S12 = dot3(s1x, s1y, s1z, s2x, s2y, s2z);
+    const double S11 = dot3(s1x, s1y, s1z, s1x, s1y, s1z);
+    const double S22 = dot3(s2x, s2y, s2z, s2x, s2y, s2z);
+    const double w1 = 3.0 * k.c12 * sn2 + 6.0 * k.c11 * sn1;
+    const double w2 = 3.0 * k.c12 * sn1 + 6.0 * k.c22 * sn2;
+    const double Hss = k.c12 * (3.0 * sn1 * sn2 - S12) + k.c11 * (3.0 * sn1 * sn1 - S11)
+                     + k.c22 * (3.0 * sn2 * sn2 - S22);
+    H = 0.5 * P2 - u + k.a1 * P2 * P2 + fma(k.a2, P2, k.a3 * NP2) * u + k.a4 * u2
+      + k.b1 * P2 * P2 * P2 + (k.b2 * P2 * P2 + k.b3 * P2 * NP2 + k.b4 * NP2 * NP2) * u
+      + fma(k.b5, P2, k.b6 * NP2) * u2 + k.b7 * u3 + u3 * LS + u3 * Hss;
+    const double cp = 2.0 * HP2;
+    gp[0] = cp * px + HNP * nx + u3 * (ey * rz - ez * ry);
+    gp[1] = cp * py + HNP * ny + u3 * (ez * rx - ex * rz);
+    gp[2] = cp * pz + HNP * nz + u3 * (ex * ry - ey * rx);
+    const double Ap = HNP * u;
+    const double An = -Ap * NP - Hu * u2 - 3.0 * u4 * LS
+                    - 3.0 * u4 * (k.c12 * (5.0 * sn1 * sn2 - S12) + k.c11 * (5.0 * sn1 * sn1 - S11)
+                                  + k.c22 * (5.0 * sn2 * sn2 - S22));
+    const double B1 = u4 * w1, B2 = u4 * w2;
+    gr[0] = An * nx + Ap * px + B1 * s1x + B2 * s2x + u3 * (py * ez - pz * ey);
+    gr[1] = An * ny + Ap * py + B1 * s1y + B2 * s2y + u3 * (pz * ex - px * ez);
+    gr[2] = An * nz + Ap * pz + B1 * s1z + B2 * s2z + u3 * (px * ey - py * ex);
+}
+
+// Total angular momentum J = r x p + S1 + S2.
+__device__ __forceinline__ void pn_total_J(const double* y, double* J) {
+    J[0] = y[1] * y[5] - y[2] * y[4] + y[6] + y[9];
+    J[1] = y[2] * y[3] - y[0] * y[5] + y[7] + y[10];
+    J[2] = y[0] * y[4] - y[1] * y[3] + y[8] + y[11];
+}
+
+// eq. (10): S_i <- s_i S_i / |S_i| (a zero spin stays zero).
+__device__ __forceinline__ void pn_correct_spins(const PnCoef& k, double* y) {
+    const double l1 = dot3(y[6], y[7], y[8], y[6], y[7], y[8]);
+    const double l2 = dot3(y[9], y[10], y[11], y[9], y[10], y[11]);
+    const double f1 = l1 > 0.0 ? k.s1 * pn_rsqrt(l1) : 0.0;
+    const double f2 = l2 > 0.0 ? k.s2 * pn_rsqrt(l2) : 0.0;
+    y[6] *= f1; y[7] *= f1; y[8] *= f1;
+    y[9] *= f2; y[10] *= f2; y[11] *= f2;
+}
+
+// Energy restoration by momentum scaling: Newton on a for
+// g(a) = H(r, a p, S) - E0 using the polynomial form of H in a.
+// Returns the iteration count; *conv is false if max_iter was reached.
+__device__ __forceinline__ int pn_energy_scale(const PnCoef& k, double* y, double E0, double tol,
+                                               int max_iter, bool& conv) {
+    const PnEnergyPoly e = pn_energy_poly(k, y);
+    double a = 1.0;
+    int it = 0;
+    conv = false;
+    while (it < max_iter) {
+        const double a2 = a * a, a3 = a2 * a;
+        const double g = fma(fma(fma(e.K6, a2, e.K4), a2, e.K2), a2, fma(e.K1, a, e.K0)) - E0;
+        const double dg = fma(fma(6.0 * e.K6, a2, 4.0 * e.K4), a3, fma(2.0 * e.K2, a, e.K1));
+        const double da = -g / dg;
+        a += da;
+        ++it;
+        if (fabs(da) <= tol) { conv = true; break; }
+    }
+    y[3] *= a; y[4] *= a; y[5] *= a;
+    return it;
+}
+
+// Least-squares projection of (r, p) onto H = E0, J = J0 (spins fixed): the
+// smallest displacement d with G d = -c, d = -G^T lam, (G G^T) lam = c, where
+// the rows of G are grad J_x, grad J_y, grad J_z, grad H.  Solved by LDL^T; the
+// energy row is dropped when its pivot is below 1e-12 of its diagonal (near
+// circular orbits, where the energy row depends on the J rows).
+__device__ __forceinline__ void pn_project_EJ(const PnCoef& k, double* y, const double* ref) {
+    double H, gr[3], gp[3], J[3];
+    pn_energy_grad_rp(k, y, H, gr, gp);
+    pn_total_J(y, J);
+    const double rx = y[0], ry = y[1], rz = y[2];
+    const double px = y[3], py = y[4], pz = y[5];
+    const double s = dot3(rx, ry, rz, rx, ry, rz) + dot3(px, py, pz, px, py, pz);
+    const double A00 = s - rx * rx - px * px, A11 = s - ry * ry - py * py, A22 = s - rz * rz - pz * pz;
+    const double A10 = -(ry * rx + py * px), A20 = -(rz * rx + pz * px), A21 = -(rz * ry + pz * py);
+    // Cross terms e_k . (dH/dr x p + r x dH/dp).
+    const double A30 = (gr[1] * pz - gr[2] * py) + (ry * gp[2] - rz * gp[1]);
+    const double A31 = (gr[2] * px - gr[0] * pz) + (rz * gp[0] - rx * gp[2]);
+    const double A32 = (gr[0] * py - gr[1] * px) + (rx * gp[1] - ry * gp[0]);
+    const double A33 = dot3(gr[0], gr[1], gr[2], gr[0], gr[1], gr[2]) + dot3(gp[0], gp[1], gp[2], gp[0], gp[1], gp[2]);
+    const double c0 = J[0] - ref[1], c1 = J[1] - ref[2], c2 = J[2] - ref[3], c3 = H - ref[0];
+    // LDL^T.
+    const double d0 = A00, i0 = pn_rcp(d0);
+    const double l10 = A10 * i0, l20 = A20 * i0, l30 = A30 * i0;
+    const double d1 = A11 - l10 * l10 * d0, i1 = pn_rcp(d1);
+    const double l21 = (A21 - l20 * l10 * d0) * i1;
+    const double l31 = (A31 - l30 * l10 * d0) * i1;
+    const double d2 = A22 - l20 * l20 * d0 - l21 * l21 * d1, i2 = pn_rcp(d2);
+    const double l32 = (A32 - l30 * l20 * d0 - l31 * l21 * d1) * i2;
+    const double d3 = A33 - l30 * l30 * d0 - l31 * l31 * d1 - l32 * l32 * d2;
+    const bool use_e = d3 > 1e-12 * A33;
+    const double z0 = c0, z1 = c1 - l10 * z0, z2 = c2 - l20 * z0 - l21 * z1;
+    const double z3 = c3 - l30 * z0 - l31 * z1 - l32 * z2;
+    const double lam3 = use_e ? z3 / d3 : 0.0;
+    const double lam2 = z2 * i2 - l32 * lam3;
+    const double lam1 = z1 * i1 - l21 * lam2 - l31 * lam3;
+    const double lam0 = z0 * i0 - l10 * lam1 - l20 * lam2 - l30 * lam3;
+    // d = -G^T lam: dr = -(p x lamJ) - lam3 dH/dr, dp = -(lamJ x r) - lam3 dH/dp.
+    y[0] = rx - (py * lam2 - pz * lam1) - lam3 * gr[0];
+    y[1] = ry - (pz * lam0 - px * lam2) - lam3 * gr[1];
+    y[2] = rz - (px * lam1 - py * lam0) - lam3 * gr[2];
+    y[3] = px - (lam1 * rz - lam2 * ry) - lam3 * gp[0];
+    y[4] = py - (lam2 * rx - lam0 * rz) - lam3 * gp[1];
+    y[5] = pz - (lam0 * ry - lam1 * rx) - lam3 * gp[2];
+}
+
+// Dual scaling of eqs. (11)-(13): p = alpha p*, r = b r*, Newton on
+// f1 = H(b r*, alpha p*, S) - E0 and f2 = |alpha b L* + S1 + S2| - |J0|
+// (Gauss-Newton on eq. 12, same root for any weights).  A Jacobian whose
+// determinant is below 1e-3 of |j11 j22| falls back to energy-only momentum
+// scaling for this step.
+__device__ __forceinline__ int pn_dual_scale(const PnCoef& k, double* y, const double* ref, double tol,
+                                             int max_iter, bool& conv) {
+    const double r0x = y[0], r0y = y[1], r0z = y[2];
+    const double p0x = y[3], p0y = y[4], p0z = y[5];
+    const double Lx = r0y * p0z - r0z * p0y, Ly = r0z * p0x - r0x * p0z, Lz = r0x * p0y - r0y * p0x;
+    const double Sx = y[6] + y[9], Sy = y[7] + y[10], Sz = y[8] + y[11];
+    const double J0n = sqrt(ref[1] * ref[1] + ref[2] * ref[2] + ref[3] * ref[3]);
+    double al = 1.0, b = 1.0;
+    int it = 0;
+    conv = false;
+    bool singular = false;
+    double ys[12];
+#pragma unroll
+    for (int c = 6; c < 12; ++c) ys[c] = y[c];
+    while (it < max_iter) {
+        ys[0] = b * r0x; ys[1] = b * r0y; ys[2] = b * r0z;
+        ys[3] = al * p0x; ys[4] = al * p0y; ys[5] = al * p0z;
+        double H, gr[3], gp[3];
+        pn_energy_grad_rp(k, ys, H, gr, gp);
+        const double f1 = H - ref[0];
+        const double ab = al * b;
+        const double Jx = ab * Lx + Sx, Jy = ab * Ly + Sy, Jz = ab * Lz + Sz;
+        const double Jn = sqrt(dot3(Jx, Jy, Jz, Jx, Jy, Jz));
+        const double f2 = Jn - J0n;
+        const double JhL = dot3(Jx, Jy, Jz, Lx, Ly, Lz) / Jn;
+        const double j11 = dot3(gp[0], gp[1], gp[2], p0x, p0y, p0z);
+        const double j12 = dot3(gr[0], gr[1], gr[2], r0x, r0y, r0z);
+        const double j21 = b * JhL;
+        const double j22 = al * JhL;
+        const double det = j11 * j22 - j12 * j21;
+        if (fabs(det) < 1e-3 * fabs(j22) * fabs(j11)) { singular = true; break; }
+        const double dal = -(j22 * f1 - j12 * f2) / det;
+        const double db = -(-j21 * f1 + j11 * f2) / det;
+        al += dal;
+        b += db;
+        ++it;
+        if (fabs(dal) <= tol && fabs(db) <= tol) { conv = true; break; }
+    }
+    if (singular) return it + pn_energy_scale(k, y, ref[0], tol, max_iter, conv);
+    y[0] = b * r0x; y[1] = b * r0y; y[2] = b * r0z;
+    y[3] = al * p0x; y[4] = al * p0y; y[5] = al * p0z;
+    return it;
+}
+
+// One correction against ref = (E0, J0x, J0y, J0z); returns Newton iterations.
+template <int MODE>
+__device__ __forceinline__ int pn_correct(const PnCoef& k, double* y, const double* ref, double tol,
+                                          int max_iter, int sweeps, bool& noconv) {
+    noconv = false;
+    if (MODE == PN_CORR_NONE) return 0;
+    pn_correct_spins(k, y);
+    if (MODE == PN_CORR_SPIN) return 0;
+    int iters = 0;
+    bool conv = true;
+    if (MODE == PN_CORR_SIX) {
+        for (int s = 0; s < sweeps; ++s) {
+            pn_project_EJ(k, y, ref);
+            iters += pn_energy_scale(k, y, ref[0], tol, max_iter, conv);
+            noconv = noconv || !conv;
+        }
+        return iters;
+    }
+    iters = pn_dual_scale(k, y, ref, tol, max_iter, conv);
+    noconv = !conv;
+    return iters;
+}
+
+// One fixed step of RK4 or of the Dormand-Prince fifth-order weights.
+template <int METHOD>
+__device__ __forceinline__ void pn_rk_step(const PnCoef& k, double* y, double h) {
+    double kk[12], acc[12], t[12];
+    if (METHOD == PN_RK4) {
+        pn_rhs_eval(k, y, kk);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) { acc[c] = kk[c]; t[c] = fma(0.5 * h, kk[c], y[c]); }
+        pn_rhs_eval(k, t, kk);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) { acc[c] = fma(2.0, kk[c], acc[c]); t[c] = fma(0.5 * h, kk[c], y[c]); }
+        pn_rhs_eval(k, t, kk);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) { acc[c] = fma(2.0, kk[c], acc[c]); t[c] = fma(h, kk[c], y[c]); }
+        pn_rhs_eval(k, t, kk);
+        const double h6 = h / 6.0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) y[c] = fma(h6, acc[c] + kk[c], y[c]);
+        return;
+    }
+    // Dormand-Prince: the stage derivatives are folded into running stage
+    // inputs so that only the current derivative is live.
+    constexpr double a21 = 1.0 / 5.0;
+    constexpr double a31 = 3.0 / 40.0, a32 = 9.0 / 40.0;
+    constexpr double a41 = 44.0 / 45.0, a42 = -56.0 / 15.0, a43 = 32.0 / 9.0;
+    constexpr double a51 = 19372.0 / 6561.0, a52 = -25360.0 / 2187.0, a53 = 64448.0 / 6561.0,
+                     a54 = -212.0 / 729.0;
+    constexpr double a61 = 9017.0 / 3168.0, a62 = -355.0 / 33.0, a63 = 46732.0 / 5247.0,
+                     a64 = 49.0 / 176.0, a65 = -5103.0 / 18656.0;
+    constexpr double b1 = 35.0 / 384.0, b3 = 500.0 / 1113.0, b4 = 125.0 / 192.0,
+                     b5 = -2187.0 / 6784.0, b6 = 11.0 / 84.0;
+    double s3[12], s4[12], s5[12], s6[12];
+    pn_rhs_eval(k, y, kk);  // k1
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        t[c] = fma(h * a21, kk[c], y[c]);
+        s3[c] = fma(h * a31, kk[c], y[c]);
+        s4[c] = fma(h * a41, kk[c], y[c]);
+        s5[c] = fma(h * a51, kk[c], y[c]);
+        s6[c] = fma(h * a61, kk[c], y[c]);
+        acc[c] = fma(h * b1, kk[c], y[c]);
+    }
+    pn_rhs_eval(k, t, kk);  // k2
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        s3[c] = fma(h * a32, kk[c], s3[c]);
+        s4[c] = fma(h * a42, kk[c], s4[c]);
+        s5[c] = fma(h * a52, kk[c], s5[c]);
+        s6[c] = fma(h * a62, kk[c], s6[c]);
+    }
+    pn_rhs_eval(k, s3, kk);  // k3
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        s4[c] = fma(h * a43, kk[c], s4[c]);
+        s5[c] = fma(h * a53, kk[c], s5[c]);
+        s6[c] = fma(h * a63, kk[c], s6[c]);
+        acc[c] = fma(h * b3, kk[c], acc[c]);
+    }
+    pn_rhs_eval(k, s4, kk);  // k4
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        s5[c] = fma(h * a54, kk[c], s5[c]);
+        s6[c] = fma(h * a64, kk[c], s6[c]);
+        acc[c] = fma(h * b4, kk[c], acc[c]);
+    }
+    pn_rhs_eval(k, s5, kk);  // k5
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        s6[c] = fma(h * a65, kk[c], s6[c]);
+        acc[c] = fma(h * b5, kk[c], acc[c]);
+    }
+    pn_rhs_eval(k, s6, kk);  // k6
+#pragma unroll
+    for (int c = 0; c < 12; ++c) y[c] = fma(h * b6, kk[c], acc[c]);
+}
+
+// Orbit validity in the order: non-finite, merged, escaped.
+__device__ __forceinline__ int pn_validity(const double* y, double rmerge2, double resc2) {
+    bool fin = true;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) fin = fin && isfinite(y[c]);
+    if (!fin) return PN_ORBIT_NONFINITE;
+    const double r2 = dot3(y[0], y[1], y[2], y[0], y[1], y[2]);
+    if (r2 < rmerge2) return PN_ORBIT_MERGED;
+    if (r2 > resc2) return PN_ORBIT_ESCAPED;
+    return PN_ORBIT_OK;
+}

@@ -1,0 +1,550 @@
+// pn_kernels.hip -- gfx950 kernels and the C ABI of include/pn.h.
+//
+// One lane integrates one orbit (and, in the scan, its shadow): the whole
+// 12-component state, the Runge-Kutta stages and the correction live in
+// registers; global memory is touched only to read the initial state and to
+// write results, in structure-of-arrays rows (coalesced across a wavefront).
+// The physics path is scalar FP64 end to end.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "pn.h"
+#include "pn_device.h"
+
+namespace {
+
+constexpr int kBlock = 64;  // one wavefront per workgroup
+
+thread_local char g_last_error[256] = "";
+
+void set_error(const char* what, hipError_t e) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
+}
+
+// Parameters of a kernel: either per-orbit device arrays, or one shared
+// coefficient table computed on the host (held in scalar registers).
+struct ParamArgs {
+    const double* beta;
+    const double* chi1;
+    const double* chi2;
+    PnCoef coef;
+    pn_model model;
+};
+
+__device__ __forceinline__ bool load_coef(const ParamArgs& pa, int64_t i, PnCoef& k) {
+    if (pa.beta == nullptr) {
+        k = pa.coef;
+        return true;
+    }
+    return pn_make_coef(pa.model, pa.beta[i], pa.chi1[i], pa.chi2[i], k);
+}
+
+__device__ __forceinline__ void load_state(const double* y, int64_t ld, int64_t i, double* s) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) s[c] = y[c * ld + i];
+}
+
+__device__ __forceinline__ void store_state(double* y, int64_t ld, int64_t i, const double* s) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) y[c * ld + i] = s[c];
+}
+
+__device__ __forceinline__ void capture_ref(const PnCoef& k, const double* y, double* ref) {
+    ref[0] = pn_energy(k, y);
+    pn_total_J(y, ref + 1);
+}
+
+// ---------------------------------------------------------------------------
+// Kernels.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_init_state(ParamArgs pa, int64_t n, const double* r0,
+                                                      const double* p0, const double* th1,
+                                                      const double* ph1, const double* th2,
+                                                      const double* ph2, double* y, int64_t ld) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    PnCoef k;
+    load_coef(pa, i, k);
+    double s[12];
+    s[0] = r0[i]; s[1] = 0.0; s[2] = 0.0;
+    s[3] = 0.0; s[4] = p0[i]; s[5] = 0.0;
+    double sa, ca, sb, cb;
+    sincos(th1[i], &sa, &ca);
+    sincos(ph1[i], &sb, &cb);
+    s[6] = k.s1 * sa * cb; s[7] = k.s1 * sa * sb; s[8] = k.s1 * ca;
+    sincos(th2[i], &sa, &ca);
+    sincos(ph2[i], &sb, &cb);
+    s[9] = k.s2 * sa * cb; s[10] = k.s2 * sa * sb; s[11] = k.s2 * ca;
+    store_state(y, ld, i, s);
+}
+
+__global__ __launch_bounds__(kBlock) void k_rhs(ParamArgs pa, int64_t n, const double* y, int64_t ld,
+                                               double* f) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    PnCoef k;
+    load_coef(pa, i, k);
+    double s[12], d[12];
+    load_state(y, ld, i, s);
+    pn_rhs_eval(k, s, d);
+    store_state(f, ld, i, d);
+}
+
+__global__ __launch_bounds__(kBlock) void k_invariants(ParamArgs pa, int64_t n, const double* y,
+                                                      int64_t ld, double* H, double* J) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    PnCoef k;
+    load_coef(pa, i, k);
+    double s[12], j[3];
+    load_state(y, ld, i, s);
+    H[i] = pn_energy(k, s);
+    pn_total_J(s, j);
+    J[i] = j[0];
+    J[ld + i] = j[1];
+    J[2 * ld + i] = j[2];
+}
+
+struct CorrArgs {
+    double tol;
+    int32_t max_iter;
+    int32_t sweeps;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_correct(ParamArgs pa, CorrArgs ca, int64_t n, double* y,
+                                                   int64_t ld, const double* ref, int32_t* iters) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    PnCoef k;
+    load_coef(pa, i, k);
+    double s[12], r[4];
+    load_state(y, ld, i, s);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) r[c] = ref[c * ld + i];
+    bool nc = false;
+    const int it = pn_correct<MODE>(k, s, r, ca.tol, ca.max_iter, ca.sweeps, nc);
+    store_state(y, ld, i, s);
+    if (iters) iters[i] = nc ? -it : it;
+}
+
+template <int METHOD, int MODE>
+__global__ __launch_bounds__(kBlock) void k_step(ParamArgs pa, CorrArgs ca, double h, int64_t n,
+                                                double* y, int64_t ld, const double* ref,
+                                                int64_t nsteps) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    PnCoef k;
+    load_coef(pa, i, k);
+    double s[12], r[4];
+    load_state(y, ld, i, s);
+    if (ref) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) r[c] = ref[c * ld + i];
+    } else {
+        if (MODE != PN_CORR_NONE) pn_correct_spins(k, s);
+        capture_ref(k, s, r);
+    }
+    for (int64_t t = 0; t < nsteps; ++t) {
+        pn_rk_step<METHOD>(k, s, h);
+        bool nc;
+        pn_correct<MODE>(k, s, r, ca.tol, ca.max_iter, ca.sweeps, nc);
+    }
+    store_state(y, ld, i, s);
+}
+
+struct FliArgs {
+    double h;
+    CorrArgs corr;
+    double d0, d_renorm2, rmerge2, resc2;
+    double thr_at_1e5;
+    int32_t thr_scaling;
+    int32_t shadow_axis;
+    const double* t_end;
+    double t_end_all;
+    pn_scan_out out;
+    int64_t n, ld;
+    const double* y0;
+};
+
+__device__ __forceinline__ double sq_dist(const double* a, const double* b) {
+    double d2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const double e = b[c] - a[c];
+        d2 = fma(e, e, d2);
+    }
+    return d2;
+}
+
+// Fused scan: orbit and shadow of one lane, every step RK + correction of
+// both, validity, separation and (rarely) renormalisation.
+template <int METHOD, int MODE>
+__global__ __launch_bounds__(kBlock) void k_fli_scan(ParamArgs pa, FliArgs fa) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= fa.n) return;
+    const int64_t ld = fa.ld;
+    PnCoef k;
+    const bool param_ok = load_coef(pa, i, k);
+    double y[12], ys[12], ref[4], refs[4];
+    load_state(fa.y0, ld, i, y);
+    pn_correct_spins(k, y);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) ys[c] = y[c];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) ys[c] += (c == fa.shadow_axis) ? fa.d0 : 0.0;
+    capture_ref(k, y, ref);
+    capture_ref(k, ys, refs);
+    const double t_end = fa.t_end ? fa.t_end[i] : fa.t_end_all;
+    const int64_t nsteps = t_end > 0.0 ? (int64_t)ceil(t_end / fa.h) : 0;
+
+    int st = param_ok ? pn_validity(y, fa.rmerge2, fa.resc2) : PN_ORBIT_BADPARAM;
+    if (st == PN_ORBIT_OK && !(ref[0] < 0.0)) st = PN_ORBIT_UNBOUND_INIT;
+
+    double acc = 0.0;
+    int nmax = 0;
+    bool any_nc = false;
+    int64_t renorms = 0;
+    const double d0 = fa.d0;
+    const int64_t tev = fa.out.trace_every;
+    for (int64_t t = 0; t < nsteps && st == PN_ORBIT_OK; ++t) {
+        bool nc;
+        pn_rk_step<METHOD>(k, y, fa.h);
+        int it = pn_correct<MODE>(k, y, ref, fa.corr.tol, fa.corr.max_iter, fa.corr.sweeps, nc);
+        any_nc = any_nc || nc;
+        nmax = max(nmax, it);
+        pn_rk_step<METHOD>(k, ys, fa.h);
+        it = pn_correct<MODE>(k, ys, refs, fa.corr.tol, fa.corr.max_iter, fa.corr.sweeps, nc);
+        any_nc = any_nc || nc;
+        nmax = max(nmax, it);
+        st = pn_validity(y, fa.rmerge2, fa.resc2);
+        if (st == PN_ORBIT_OK) st = pn_validity(ys, fa.rmerge2, fa.resc2);
+        if (st != PN_ORBIT_OK) break;
+        const double d2 = sq_dist(y, ys);
+        if (d2 >= fa.d_renorm2) {
+            const double d = sqrt(d2);
+            acc += log10(d / d0);
+            const double f = d0 / d;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) ys[c] = fma(f, ys[c] - y[c], y[c]);
+            pn_correct_spins(k, ys);
+            capture_ref(k, ys, refs);
+            ++renorms;
+        }
+        if (tev > 0 && ((t + 1) % tev) == 0) {
+            const int64_t row = (t + 1) / tev - 1;
+            if (row < fa.out.ntrace) fa.out.trace[row * ld + i] = acc + log10(sqrt(sq_dist(y, ys)) / d0);
+        }
+    }
+    const pn_scan_out& o = fa.out;
+    if (o.y_final) store_state(o.y_final, ld, i, y);
+    if (o.dH || o.dJ) {
+        double J[3];
+        const double H = pn_energy(k, y);
+        pn_total_J(y, J);
+        if (o.dH) o.dH[i] = fabs(H - ref[0]) / fabs(ref[0]);
+        if (o.dJ) {
+            const double ex = J[0] - ref[1], ey = J[1] - ref[2], ez = J[2] - ref[3];
+            o.dJ[i] = sqrt(dot3(ex, ey, ez, ex, ey, ez)) /
+                      sqrt(dot3(ref[1], ref[2], ref[3], ref[1], ref[2], ref[3]));
+        }
+    }
+    if (st == PN_ORBIT_OK) {
+        const double fli = acc + log10(sqrt(sq_dist(y, ys)) / d0);
+        const double thr = (fa.thr_scaling == PN_THR_LOG_T && t_end > 0.0)
+                               ? fa.thr_at_1e5 + log10(t_end / 1e5) : fa.thr_at_1e5;
+        o.fli[i] = fli;
+        o.label[i] = fli > thr ? 1 : 0;
+    } else {
+        o.fli[i] = __builtin_nan("");
+        o.label[i] = -1;
+    }
+    o.status[i] = st | (any_nc ? PN_ORBIT_NEWTON_NOCONV : 0);
+    if (o.newton_max) o.newton_max[i] = nmax;
+    if (o.renorms) o.renorms[i] = renorms;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side validation and dispatch.
+// ---------------------------------------------------------------------------
+bool is_fin(double x) { return std::isfinite(x); }
+
+pn_status check_model(const pn_model* m) {
+    if (!m) return PN_EINVAL;
+    if (m->pn_order < 0 || m->pn_order > 2) return PN_EINVAL;
+    if ((m->spin_orbit | m->spin_spin | m->quad_mono) & ~1) return PN_EINVAL;
+    if (m->spin_units != PN_SPIN_PHYS && m->spin_units != PN_SPIN_PAPER_EQ8) return PN_EINVAL;
+    return PN_OK;
+}
+
+pn_status make_params(const pn_model* m, const pn_params& p, ParamArgs& pa) {
+    const int nnull = (p.beta == nullptr) + (p.chi1 == nullptr) + (p.chi2 == nullptr);
+    if (nnull != 0 && nnull != 3) return PN_EINVAL;
+    pa.beta = p.beta;
+    pa.chi1 = p.chi1;
+    pa.chi2 = p.chi2;
+    pa.model = *m;
+    std::memset(&pa.coef, 0, sizeof(pa.coef));
+    if (nnull == 3) {
+        if (!is_fin(p.beta0) || !is_fin(p.chi1_0) || !is_fin(p.chi2_0)) return PN_EINVAL;
+        if (!pn_make_coef(*m, p.beta0, p.chi1_0, p.chi2_0, pa.coef)) return PN_EINVAL;
+    }
+    return PN_OK;
+}
+
+pn_status check_corr(const pn_correction* c) {
+    if (!c) return PN_OK;
+    if (c->mode < PN_CORR_NONE || c->mode > PN_CORR_DUAL) return PN_EINVAL;
+    if (c->mode >= PN_CORR_SIX) {
+        if (!(c->tol >= 0.0) || !is_fin(c->tol)) return PN_EINVAL;
+        if (c->max_iter < 1 || c->max_iter > 1000) return PN_EINVAL;
+        if (c->mode == PN_CORR_SIX && (c->sweeps < 1 || c->sweeps > 16)) return PN_EINVAL;
+        if (!(c->w1 > 0.0) || !(c->w2 > 0.0)) return PN_EINVAL;
+    }
+    return PN_OK;
+}
+
+pn_status check_integ(const pn_integrator* in) {
+    if (!in) return PN_EINVAL;
+    if (in->method != PN_RK4 && in->method != PN_RK5) return PN_EINVAL;
+    if (!(in->h > 0.0) || !is_fin(in->h)) return PN_EINVAL;
+    return PN_OK;
+}
+
+CorrArgs corr_args(const pn_correction* c) {
+    CorrArgs a;
+    a.tol = c ? c->tol : 0.0;
+    a.max_iter = c ? c->max_iter : 1;
+    a.sweeps = c ? c->sweeps : 1;
+    return a;
+}
+
+unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+pn_status launched(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(what, e);
+        return PN_EDEVICE;
+    }
+    return PN_OK;
+}
+
+#define PN_REQUIRE(cond) do { if (!(cond)) return PN_EINVAL; } while (0)
+
+template <int METHOD, int MODE>
+void launch_step(const ParamArgs& pa, const CorrArgs& ca, double h, int64_t n, double* y, int64_t ld,
+                 const double* ref, int64_t nsteps, hipStream_t s) {
+    hipLaunchKernelGGL((k_step<METHOD, MODE>), dim3(grid_for(n)), dim3(kBlock), 0, s, pa, ca, h, n, y,
+                       ld, ref, nsteps);
+}
+
+template <int METHOD>
+void launch_step_m(int mode, const ParamArgs& pa, const CorrArgs& ca, double h, int64_t n, double* y,
+                   int64_t ld, const double* ref, int64_t nsteps, hipStream_t s) {
+    switch (mode) {
+        case PN_CORR_NONE: launch_step<METHOD, PN_CORR_NONE>(pa, ca, h, n, y, ld, ref, nsteps, s); break;
+        case PN_CORR_SPIN: launch_step<METHOD, PN_CORR_SPIN>(pa, ca, h, n, y, ld, ref, nsteps, s); break;
+        case PN_CORR_SIX: launch_step<METHOD, PN_CORR_SIX>(pa, ca, h, n, y, ld, ref, nsteps, s); break;
+        default: launch_step<METHOD, PN_CORR_DUAL>(pa, ca, h, n, y, ld, ref, nsteps, s); break;
+    }
+}
+
+template <int METHOD, int MODE>
+void launch_scan(const ParamArgs& pa, const FliArgs& fa, hipStream_t s) {
+    hipLaunchKernelGGL((k_fli_scan<METHOD, MODE>), dim3(grid_for(fa.n)), dim3(kBlock), 0, s, pa, fa);
+}
+
+template <int METHOD>
+void launch_scan_m(int mode, const ParamArgs& pa, const FliArgs& fa, hipStream_t s) {
+    switch (mode) {
+        case PN_CORR_NONE: launch_scan<METHOD, PN_CORR_NONE>(pa, fa, s); break;
+        case PN_CORR_SPIN: launch_scan<METHOD, PN_CORR_SPIN>(pa, fa, s); break;
+        case PN_CORR_SIX: launch_scan<METHOD, PN_CORR_SIX>(pa, fa, s); break;
+        default: launch_scan<METHOD, PN_CORR_DUAL>(pa, fa, s); break;
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI.
+// ===========================================================================
+extern "C" {
+
+void pn_default_model(pn_model* m) {
+    if (!m) return;
+    m->pn_order = 2;
+    m->spin_orbit = 1;
+    m->spin_spin = 1;
+    m->quad_mono = 1;
+    m->spin_units = PN_SPIN_PHYS;
+}
+
+void pn_default_integrator(pn_integrator* in) {
+    if (!in) return;
+    in->method = PN_RK4;
+    in->h = 1.0;
+}
+
+void pn_default_correction(pn_correction* c) {
+    if (!c) return;
+    c->mode = PN_CORR_SIX;
+    c->tol = 1e-10;
+    c->max_iter = 20;
+    c->sweeps = 2;
+    c->w1 = 1.0;
+    c->w2 = 1.0;
+}
+
+void pn_default_fli_cfg(pn_fli_cfg* f) {
+    if (!f) return;
+    f->d0 = 1e-8;
+    f->d_renorm = 0.1;
+    f->shadow_axis = 0;
+    f->thr_at_1e5 = 5.8;
+    f->thr_scaling = PN_THR_LOG_T;
+    f->r_merge = 2.0;
+    f->r_esc = 1e3;
+}
+
+int32_t pn_version(void) { return 1; }
+
+const char* pn_status_string(pn_status s) {
+    switch (s) {
+        case PN_OK: return "ok";
+        case PN_EINVAL: return "invalid argument";
+        case PN_ENOWS: return "workspace too small";
+        case PN_EDEVICE: return "device error";
+    }
+    return "unknown status";
+}
+
+const char* pn_last_error(void) { return g_last_error; }
+
+pn_status pn_init_state(const pn_model* model, pn_params params, int64_t n, const double* r0,
+                        const double* p0, const double* th1, const double* ph1, const double* th2,
+                        const double* ph2, double* y0, int64_t ld, hipStream_t stream) {
+    PN_REQUIRE(check_model(model) == PN_OK);
+    PN_REQUIRE(n >= 0 && ld >= n);
+    ParamArgs pa;
+    PN_REQUIRE(make_params(model, params, pa) == PN_OK);
+    if (n == 0) return PN_OK;
+    PN_REQUIRE(r0 && p0 && th1 && ph1 && th2 && ph2 && y0);
+    hipLaunchKernelGGL(k_init_state, dim3(grid_for(n)), dim3(kBlock), 0, stream, pa, n, r0, p0, th1, ph1,
+                       th2, ph2, y0, ld);
+    return launched("pn_init_state");
+}
+
+pn_status pn_rhs(const pn_model* model, pn_params params, int64_t n, const double* y, int64_t ld,
+                 double* dydt, hipStream_t stream) {
+    PN_REQUIRE(check_model(model) == PN_OK);
+    PN_REQUIRE(n >= 0 && ld >= n);
+    ParamArgs pa;
+    PN_REQUIRE(make_params(model, params, pa) == PN_OK);
+    if (n == 0) return PN_OK;
+    PN_REQUIRE(y && dydt);
+    hipLaunchKernelGGL(k_rhs, dim3(grid_for(n)), dim3(kBlock), 0, stream, pa, n, y, ld, dydt);
+    return launched("pn_rhs");
+}
+
+pn_status pn_invariants(const pn_model* model, pn_params params, int64_t n, const double* y, int64_t ld,
+                        double* H, double* J, hipStream_t stream) {
+    PN_REQUIRE(check_model(model) == PN_OK);
+    PN_REQUIRE(n >= 0 && ld >= n);
+    ParamArgs pa;
+    PN_REQUIRE(make_params(model, params, pa) == PN_OK);
+    if (n == 0) return PN_OK;
+    PN_REQUIRE(y && H && J);
+    hipLaunchKernelGGL(k_invariants, dim3(grid_for(n)), dim3(kBlock), 0, stream, pa, n, y, ld, H, J);
+    return launched("pn_invariants");
+}
+
+pn_status pn_manifold_correct(const pn_model* model, pn_params params, const pn_correction* corr,
+                              int64_t n, double* y, int64_t ld, const double* ref, int32_t* iters,
+                              hipStream_t stream) {
+    PN_REQUIRE(check_model(model) == PN_OK);
+    PN_REQUIRE(corr != nullptr && check_corr(corr) == PN_OK);
+    PN_REQUIRE(n >= 0 && ld >= n);
+    ParamArgs pa;
+    PN_REQUIRE(make_params(model, params, pa) == PN_OK);
+    if (n == 0) return PN_OK;
+    PN_REQUIRE(y && ref);
+    const CorrArgs ca = corr_args(corr);
+    const dim3 g(grid_for(n)), b(kBlock);
+    switch (corr->mode) {
+        case PN_CORR_NONE: hipLaunchKernelGGL(k_correct<PN_CORR_NONE>, g, b, 0, stream, pa, ca, n, y, ld, ref, iters); break;
+        case PN_CORR_SPIN: hipLaunchKernelGGL(k_correct<PN_CORR_SPIN>, g, b, 0, stream, pa, ca, n, y, ld, ref, iters); break;
+        case PN_CORR_SIX: hipLaunchKernelGGL(k_correct<PN_CORR_SIX>, g, b, 0, stream, pa, ca, n, y, ld, ref, iters); break;
+        default: hipLaunchKernelGGL(k_correct<PN_CORR_DUAL>, g, b, 0, stream, pa, ca, n, y, ld, ref, iters); break;
+    }
+    return launched("pn_manifold_correct");
+}
+
+pn_status pn_step(const pn_model* model, pn_params params, const pn_integrator* integ,
+                  const pn_correction* corr, int64_t n, double* y, int64_t ld, const double* ref,
+                  int64_t nsteps, hipStream_t stream) {
+    PN_REQUIRE(check_model(model) == PN_OK);
+    PN_REQUIRE(check_integ(integ) == PN_OK);
+    PN_REQUIRE(check_corr(corr) == PN_OK);
+    PN_REQUIRE(n >= 0 && ld >= n && nsteps >= 0);
+    ParamArgs pa;
+    PN_REQUIRE(make_params(model, params, pa) == PN_OK);
+    if (n == 0 || nsteps == 0) return PN_OK;
+    PN_REQUIRE(y);
+    const int mode = corr ? corr->mode : PN_CORR_NONE;
+    const CorrArgs ca = corr_args(corr);
+    if (integ->method == PN_RK4)
+        launch_step_m<PN_RK4>(mode, pa, ca, integ->h, n, y, ld, ref, nsteps, stream);
+    else
+        launch_step_m<PN_RK5>(mode, pa, ca, integ->h, n, y, ld, ref, nsteps, stream);
+    return launched("pn_step");
+}
+
+pn_status pn_fli_scan(const pn_model* model, pn_params params, const pn_integrator* integ,
+                      const pn_correction* corr, const pn_fli_cfg* fli, int64_t n, const double* y0,
+                      int64_t ld, const double* t_end, double t_end_all, const pn_scan_out* out,
+                      hipStream_t stream) {
+    PN_REQUIRE(check_model(model) == PN_OK);
+    PN_REQUIRE(check_integ(integ) == PN_OK);
+    PN_REQUIRE(corr != nullptr && check_corr(corr) == PN_OK);
+    PN_REQUIRE(fli != nullptr && out != nullptr);
+    PN_REQUIRE(n >= 0 && ld >= n);
+    PN_REQUIRE(fli->d0 > 0.0 && is_fin(fli->d0) && fli->d_renorm > fli->d0 && is_fin(fli->d_renorm));
+    PN_REQUIRE(fli->shadow_axis >= 0 && fli->shadow_axis < 12);
+    PN_REQUIRE(is_fin(fli->thr_at_1e5));
+    PN_REQUIRE(fli->thr_scaling == PN_THR_LITERAL || fli->thr_scaling == PN_THR_LOG_T);
+    PN_REQUIRE(fli->r_merge >= 0.0 && fli->r_esc > fli->r_merge);
+    PN_REQUIRE(t_end != nullptr || (t_end_all >= 0.0 && is_fin(t_end_all)));
+    ParamArgs pa;
+    PN_REQUIRE(make_params(model, params, pa) == PN_OK);
+    if (n == 0) return PN_OK;
+    PN_REQUIRE(y0 && out->fli && out->label && out->status);
+    PN_REQUIRE(out->trace_every >= 0 && (out->trace_every == 0 || (out->trace && out->ntrace >= 0)));
+    FliArgs fa;
+    fa.h = integ->h;
+    fa.corr = corr_args(corr);
+    fa.d0 = fli->d0;
+    fa.d_renorm2 = fli->d_renorm * fli->d_renorm;
+    fa.rmerge2 = fli->r_merge * fli->r_merge;
+    fa.resc2 = fli->r_esc * fli->r_esc;
+    fa.thr_at_1e5 = fli->thr_at_1e5;
+    fa.thr_scaling = fli->thr_scaling;
+    fa.shadow_axis = fli->shadow_axis;
+    fa.t_end = t_end;
+    fa.t_end_all = t_end_all;
+    fa.out = *out;
+    fa.n = n;
+    fa.ld = ld;
+    fa.y0 = y0;
+    if (integ->method == PN_RK4)
+        launch_scan_m<PN_RK4>(corr->mode, pa, fa, stream);
+    else
+        launch_scan_m<PN_RK5>(corr->mode, pa, fa, stream);
+    return launched("pn_fli_scan");
+}
+
+}  // extern "C"

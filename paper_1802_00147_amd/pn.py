@@ -1,0 +1,268 @@
+"""Thin ctypes binding of the C ABI in include/pn.h (libpn_hip.so).
+
+Argument marshalling only: every computation runs in the HIP kernels of
+csrc/pn_kernels.hip.  Arrays are torch tensors on a ROCm device (torch is used
+for device memory and streams); states use the library's structure-of-arrays
+layout, a (12, ld) float64 tensor whose row c holds component c of every orbit.
+
+Settings are plain dicts whose keys are the fields of the C structs; missing
+keys take the library's own defaults (pn_default_*).  The library is loaded on
+first use; a missing library raises, there is no fallback path.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpn_hip.so")
+
+PN_OK, PN_EINVAL, PN_ENOWS, PN_EDEVICE = 0, 1, 2, 3
+ORBIT_OK, ORBIT_MERGED, ORBIT_ESCAPED, ORBIT_NONFINITE, ORBIT_UNBOUND_INIT, ORBIT_BADPARAM = range(6)
+ORBIT_NEWTON_NOCONV = 0x100
+METHODS = {"rk4": 0, "rk5": 1}
+MODES = {"none": 0, "spin": 1, "six": 2, "dual": 3}
+THR = {"literal": 0, "log_t": 1}
+
+
+class PnError(RuntimeError):
+    def __init__(self, fn, status, text):
+        super().__init__(f"{fn} returned {status} ({text})")
+        self.status = status
+
+
+class Model(ctypes.Structure):
+    _fields_ = [("pn_order", ctypes.c_int32), ("spin_orbit", ctypes.c_int32),
+                ("spin_spin", ctypes.c_int32), ("quad_mono", ctypes.c_int32),
+                ("spin_units", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_void_p), ("chi1", ctypes.c_void_p), ("chi2", ctypes.c_void_p),
+                ("beta0", ctypes.c_double), ("chi1_0", ctypes.c_double), ("chi2_0", ctypes.c_double)]
+
+
+class Integrator(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("h", ctypes.c_double)]
+
+
+class Correction(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("sweeps", ctypes.c_int32), ("w1", ctypes.c_double), ("w2", ctypes.c_double)]
+
+
+class FliCfg(ctypes.Structure):
+    _fields_ = [("d0", ctypes.c_double), ("d_renorm", ctypes.c_double), ("shadow_axis", ctypes.c_int32),
+                ("thr_at_1e5", ctypes.c_double), ("thr_scaling", ctypes.c_int32),
+                ("r_merge", ctypes.c_double), ("r_esc", ctypes.c_double)]
+
+
+class ScanOut(ctypes.Structure):
+    _fields_ = [("fli", ctypes.c_void_p), ("label", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("y_final", ctypes.c_void_p), ("dH", ctypes.c_void_p), ("dJ", ctypes.c_void_p),
+                ("newton_max", ctypes.c_void_p), ("renorms", ctypes.c_void_p),
+                ("trace", ctypes.c_void_p), ("trace_every", ctypes.c_int64), ("ntrace", ctypes.c_int64)]
+
+
+_lib = None
+
+# Every symbol include/pn.h declares.
+EXPORTS = ["pn_default_model", "pn_default_integrator", "pn_default_correction", "pn_default_fli_cfg",
+           "pn_init_state", "pn_rhs", "pn_invariants", "pn_manifold_correct", "pn_step", "pn_fli_scan",
+           "pn_version", "pn_status_string", "pn_last_error"]
+
+
+def lib():
+    """Load libpn_hip.so (raises OSError when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OSError(f"{LIB_PATH} is missing: build it with paper_1802_00147_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        L.pn_status_string.restype = ctypes.c_char_p
+        L.pn_last_error.restype = ctypes.c_char_p
+        L.pn_version.restype = ctypes.c_int32
+        for name in ("pn_init_state", "pn_rhs", "pn_invariants", "pn_manifold_correct", "pn_step",
+                     "pn_fli_scan"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _defaults(struct, fill):
+    s = struct()
+    getattr(lib(), fill)(ctypes.byref(s))
+    return s
+
+
+def model_struct(over=None):
+    s = _defaults(Model, "pn_default_model")
+    for k, v in (over or {}).items():
+        setattr(s, k, int(v))
+    return s
+
+
+def integrator_struct(over=None):
+    s = _defaults(Integrator, "pn_default_integrator")
+    for k, v in (over or {}).items():
+        setattr(s, k, METHODS[v] if k == "method" and isinstance(v, str) else v)
+    return s
+
+
+def correction_struct(over=None):
+    s = _defaults(Correction, "pn_default_correction")
+    for k, v in (over or {}).items():
+        setattr(s, k, MODES[v] if k == "mode" and isinstance(v, str) else v)
+    return s
+
+
+def fli_struct(over=None):
+    s = _defaults(FliCfg, "pn_default_fli_cfg")
+    for k, v in (over or {}).items():
+        setattr(s, k, THR[v] if k == "thr_scaling" and isinstance(v, str) else v)
+    return s
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check(fn, st):
+    if st != PN_OK:
+        L = lib()
+        raise PnError(fn, st, (L.pn_status_string(st) or b"").decode() + " " + (L.pn_last_error() or b"").decode())
+
+
+def _dev_f64(t, n=None):
+    assert t.dtype == torch.float64 and t.is_cuda, "expected a float64 device tensor"
+    if n is not None:
+        assert t.numel() >= n
+    return t.contiguous()
+
+
+def params_struct(beta, chi1, chi2):
+    """Scalars give one shared parameter set; tensors give per-orbit device arrays.
+    Returns (struct, keepalive)."""
+    if all(isinstance(v, torch.Tensor) for v in (beta, chi1, chi2)):
+        keep = [_dev_f64(v) for v in (beta, chi1, chi2)]
+        return Params(keep[0].data_ptr(), keep[1].data_ptr(), keep[2].data_ptr(), 0.0, 0.0, 0.0), keep
+    return Params(None, None, None, float(beta), float(chi1), float(chi2)), []
+
+
+def _state(y):
+    assert y.dim() == 2 and y.shape[0] == 12 and y.dtype == torch.float64 and y.is_cuda
+    assert y.is_contiguous()
+    return y.shape[1]
+
+
+def init_state(r0, p0, th1, ph1, th2, ph2, beta, chi1, chi2, model=None, ld=None):
+    n = r0.numel()
+    ld = ld or n
+    cols = [_dev_f64(t, n) for t in (r0, p0, th1, ph1, th2, ph2)]
+    y0 = torch.empty((12, ld), dtype=torch.float64, device=r0.device)
+    m = model_struct(model)
+    p, keep = params_struct(beta, chi1, chi2)
+    st = lib().pn_init_state(ctypes.byref(m), p, ctypes.c_int64(n), *[_ptr(c) for c in cols], _ptr(y0),
+                             ctypes.c_int64(ld), _stream(r0.device))
+    _check("pn_init_state", st)
+    return y0
+
+
+def rhs(y, beta, chi1, chi2, model=None, n=None):
+    ld = _state(y)
+    n = ld if n is None else n
+    f = torch.empty_like(y)
+    p, keep = params_struct(beta, chi1, chi2)
+    st = lib().pn_rhs(ctypes.byref(model_struct(model)), p, ctypes.c_int64(n), _ptr(y), ctypes.c_int64(ld),
+                      _ptr(f), _stream(y.device))
+    _check("pn_rhs", st)
+    return f
+
+
+def invariants(y, beta, chi1, chi2, model=None, n=None):
+    ld = _state(y)
+    n = ld if n is None else n
+    H = torch.empty(ld, dtype=torch.float64, device=y.device)
+    J = torch.empty((3, ld), dtype=torch.float64, device=y.device)
+    p, keep = params_struct(beta, chi1, chi2)
+    st = lib().pn_invariants(ctypes.byref(model_struct(model)), p, ctypes.c_int64(n), _ptr(y),
+                             ctypes.c_int64(ld), _ptr(H), _ptr(J), _stream(y.device))
+    _check("pn_invariants", st)
+    return H, J
+
+
+def manifold_correct(y, ref, beta, chi1, chi2, model=None, correction=None, n=None):
+    """Correct y (12, ld) in place against ref (4, ld); returns iteration counts."""
+    ld = _state(y)
+    n = ld if n is None else n
+    assert ref.shape == (4, ld) and ref.dtype == torch.float64 and ref.is_contiguous()
+    it = torch.empty(ld, dtype=torch.int32, device=y.device)
+    p, keep = params_struct(beta, chi1, chi2)
+    st = lib().pn_manifold_correct(ctypes.byref(model_struct(model)), p,
+                                   ctypes.byref(correction_struct(correction)), ctypes.c_int64(n), _ptr(y),
+                                   ctypes.c_int64(ld), _ptr(ref), _ptr(it), _stream(y.device))
+    _check("pn_manifold_correct", st)
+    return it
+
+
+def step(y, beta, chi1, chi2, nsteps, model=None, integrator=None, correction=None, ref=None, n=None):
+    """nsteps steps of y (12, ld) in place; correction None means uncorrected."""
+    ld = _state(y)
+    n = ld if n is None else n
+    if ref is not None:
+        assert ref.shape == (4, ld) and ref.dtype == torch.float64 and ref.is_contiguous()
+    p, keep = params_struct(beta, chi1, chi2)
+    cc = ctypes.byref(correction_struct(correction)) if correction is not None else None
+    st = lib().pn_step(ctypes.byref(model_struct(model)), p, ctypes.byref(integrator_struct(integrator)), cc,
+                       ctypes.c_int64(n), _ptr(y), ctypes.c_int64(ld), _ptr(ref), ctypes.c_int64(nsteps),
+                       _stream(y.device))
+    _check("pn_step", st)
+    return y
+
+
+def scan_outputs(n, ld, device, full=True, trace_every=0, nsteps_max=0):
+    o = dict(fli=torch.empty(ld, dtype=torch.float64, device=device),
+             label=torch.empty(ld, dtype=torch.int8, device=device),
+             status=torch.empty(ld, dtype=torch.int32, device=device))
+    if full:
+        o.update(y_final=torch.empty((12, ld), dtype=torch.float64, device=device),
+                 dH=torch.empty(ld, dtype=torch.float64, device=device),
+                 dJ=torch.empty(ld, dtype=torch.float64, device=device),
+                 newton_max=torch.empty(ld, dtype=torch.int32, device=device),
+                 renorms=torch.empty(ld, dtype=torch.int64, device=device))
+    if trace_every > 0:
+        ntrace = nsteps_max // trace_every
+        o["trace"] = torch.full((ntrace, ld), float("nan"), dtype=torch.float64, device=device)
+        o["trace_every"] = trace_every
+    return o
+
+
+def fli_scan(y0, t_end, beta, chi1, chi2, model=None, integrator=None, correction=None, fli=None,
+             out=None, n=None, full=True, trace_every=0):
+    """Fused FLI scan of the orbits in y0 (12, ld).  t_end: float or (ld,) tensor.
+    Returns the dict of output tensors (allocated unless out is given)."""
+    ld = _state(y0)
+    n = ld if n is None else n
+    integ = integrator_struct(integrator)
+    if out is None:
+        tmax = float(t_end.max()) if isinstance(t_end, torch.Tensor) else float(t_end)
+        nmax = int(-(-tmax // integ.h)) if tmax > 0 else 0
+        out = scan_outputs(n, ld, y0.device, full=full, trace_every=trace_every, nsteps_max=nmax)
+    so = ScanOut(*[out[k].data_ptr() if k in out else None
+                   for k in ("fli", "label", "status", "y_final", "dH", "dJ", "newton_max", "renorms", "trace")],
+                 int(out.get("trace_every", 0)), int(out["trace"].shape[0]) if "trace" in out else 0)
+    p, keep = params_struct(beta, chi1, chi2)
+    if isinstance(t_end, torch.Tensor):
+        tptr, tall = _ptr(_dev_f64(t_end, n)), 0.0
+    else:
+        tptr, tall = None, float(t_end)
+    st = lib().pn_fli_scan(ctypes.byref(model_struct(model)), p, ctypes.byref(integ),
+                           ctypes.byref(correction_struct(correction)), ctypes.byref(fli_struct(fli)),
+                           ctypes.c_int64(n), _ptr(y0), ctypes.c_int64(ld), tptr, ctypes.c_double(tall),
+                           ctypes.byref(so), _stream(y0.device))
+    _check("pn_fli_scan", st)
+    return out

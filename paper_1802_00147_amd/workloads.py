@@ -1,0 +1,125 @@
+"""Seeded synthetic scan inputs, shared by the GPU path, the tests and the
+benchmark.  This module only draws and lays out raw per-orbit parameters
+(initial radius and momentum, spin angles, mass ratio, spins, end times); it
+contains none of the method's arithmetic.
+
+The paper's own scans (Sec. 3C, Table 3) vary spin angles of one orbit; there
+is no public dataset, so these grids stand in for them with the same shapes
+and kinds of axes:
+
+* single   : one orbit at r0 = 20, beta = 1, chi = 1, isotropic spin
+             directions (seed 1), p0 = 20^-1/2 (1 + 0.05 xi), t = 1e4.
+* grid64   : 64 x 64 grid, r0 in [10, 40] x spin polar angle theta in [0, pi]
+             (theta1 = pi/2, theta2 = theta, azimuths 0, as in Fig. 6),
+             p0 = r0^-1/2, beta = 1, chi = 1, t = 1e5.
+* grid314  : 314 x 314 grid (Table 3 size), r0 in [10, 40] x p-scaling
+             s in [0.8, 1.2], p0 = s r0^-1/2, theta1 = 1.0, theta2 = 1.325
+             (orbit 4 of Sec. 4), chi = 1, t = 1e6; variants beta in {1, 0.5}
+             x quadrupole-monopole on/off.
+* batch1M  : 10^6 orbits (seed 4): beta ~ U[0.1, 1], chi_i ~ U[0, 1],
+             isotropic spin directions, r0 ~ U[8, 60], p0 = r0^-1/2,
+             t_end = 10^U[3, 6].
+* grid4096 : 4096 x 4096 grid over (r0, theta) as grid64.
+
+All orbits start at r = (r0, 0, 0), p = (0, p0, 0).
+"""
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+
+@dataclass
+class Workload:
+    name: str
+    r0: np.ndarray
+    p0: np.ndarray
+    th1: np.ndarray
+    ph1: np.ndarray
+    th2: np.ndarray
+    ph2: np.ndarray
+    beta: object            # float, or np.ndarray per orbit
+    chi1: object
+    chi2: object
+    t_end: object           # float, or np.ndarray per orbit
+    model: dict = field(default_factory=dict)
+    shape: Optional[tuple] = None
+
+    @property
+    def n(self):
+        return len(self.r0)
+
+    def subset(self, idx):
+        idx = np.asarray(idx)
+        pick = (lambda v: v[idx] if isinstance(v, np.ndarray) else v)
+        return Workload(self.name + "[subset]", *(pick(getattr(self, k)) for k in
+                        ("r0", "p0", "th1", "ph1", "th2", "ph2", "beta", "chi1", "chi2", "t_end")),
+                        model=dict(self.model), shape=None)
+
+    def steps(self, h=1.0):
+        """Orbit-steps of the whole workload (each orbit takes ceil(t_end/h) steps)."""
+        t = np.broadcast_to(np.asarray(self.t_end, dtype=np.float64), (self.n,))
+        return int(np.ceil(t / h).sum())
+
+
+def _isotropic(rng, n):
+    return np.arccos(rng.uniform(-1.0, 1.0, n)), rng.uniform(0.0, 2.0 * np.pi, n)
+
+
+def single(seed=1, t_end=1e4):
+    rng = np.random.default_rng(seed)
+    th1, ph1 = _isotropic(rng, 1)
+    th2, ph2 = _isotropic(rng, 1)
+    xi = rng.uniform(-1.0, 1.0, 1)
+    r0 = np.array([20.0])
+    p0 = r0 ** -0.5 * (1.0 + 0.05 * xi)
+    return Workload("single", r0, p0, th1, ph1, th2, ph2, 1.0, 1.0, 1.0, float(t_end))
+
+
+def grid_r_theta(nr, nth, t_end, name):
+    r = np.linspace(10.0, 40.0, nr)
+    th = np.linspace(0.0, np.pi, nth)
+    R, TH = np.meshgrid(r, th, indexing="ij")
+    r0 = R.ravel().copy()
+    n = r0.size
+    return Workload(name, r0, r0 ** -0.5, np.full(n, np.pi / 2), np.zeros(n), TH.ravel().copy(), np.zeros(n),
+                    1.0, 1.0, 1.0, float(t_end), shape=(nr, nth))
+
+
+def grid64(t_end=1e5):
+    return grid_r_theta(64, 64, t_end, "grid64")
+
+
+def grid4096(t_end=1e5):
+    return grid_r_theta(4096, 4096, t_end, "grid4096")
+
+
+def grid314(beta=1.0, quad_mono=1, t_end=1e6):
+    r = np.linspace(10.0, 40.0, 314)
+    s = np.linspace(0.8, 1.2, 314)
+    R, S = np.meshgrid(r, s, indexing="ij")
+    r0 = R.ravel().copy()
+    n = r0.size
+    return Workload(f"grid314_beta{beta:g}_qm{int(quad_mono)}", r0, S.ravel() * r0 ** -0.5,
+                    np.full(n, 1.0), np.zeros(n), np.full(n, 1.325), np.zeros(n), float(beta), 1.0, 1.0,
+                    float(t_end), model=dict(quad_mono=int(quad_mono)), shape=(314, 314))
+
+
+def batch(n=1_000_000, seed=4, tmin=1e3, tmax=1e6):
+    rng = np.random.default_rng(seed)
+    beta = rng.uniform(0.1, 1.0, n)
+    chi1 = rng.uniform(0.0, 1.0, n)
+    chi2 = rng.uniform(0.0, 1.0, n)
+    th1, ph1 = _isotropic(rng, n)
+    th2, ph2 = _isotropic(rng, n)
+    r0 = rng.uniform(8.0, 60.0, n)
+    t_end = 10.0 ** rng.uniform(np.log10(tmin), np.log10(tmax), n)
+    return Workload("batch1M" if n == 1_000_000 else f"batch{n}", r0, r0 ** -0.5, th1, ph1, th2, ph2,
+                    beta, chi1, chi2, t_end)
+
+
+def strided_sample(n, k, seed=0):
+    """k distinct indices in [0, n), seeded, spread over the whole range."""
+    rng = np.random.default_rng(seed)
+    k = min(k, n)
+    return np.sort(rng.choice(n, size=k, replace=False))

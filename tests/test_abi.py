@@ -1,0 +1,119 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol that
+include/pn.h declares, fills its defaults, and rejects invalid arguments on the
+host before anything is launched (PN_EINVAL), as the header documents."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pn.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(pn_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def pn():
+    from paper_1802_00147_amd import pn as P
+    if not os.path.exists(P.LIB_PATH):
+        from paper_1802_00147_amd import build
+        build.build()
+    P.lib()
+    return P
+
+
+def test_library_exports_every_declared_symbol(pn):
+    names = declared_functions()
+    assert len(names) >= 13
+    L = pn.lib()
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(names) == sorted(pn.EXPORTS)
+
+
+def test_defaults_match_paper_settings(pn):
+    m, i, c, f = pn.model_struct(), pn.integrator_struct(), pn.correction_struct(), pn.fli_struct()
+    assert (m.pn_order, m.spin_orbit, m.spin_spin, m.quad_mono, m.spin_units) == (2, 1, 1, 1, 0)
+    assert (i.method, i.h) == (0, 1.0)
+    assert (c.mode, c.tol, c.max_iter, c.sweeps) == (2, 1e-10, 20, 2)
+    assert (f.d0, f.d_renorm, f.thr_at_1e5, f.thr_scaling, f.r_merge, f.r_esc) == (1e-8, 0.1, 5.8, 1, 2.0, 1e3)
+    assert pn.lib().pn_version() == 1
+    assert pn.lib().pn_status_string(1) == b"invalid argument"
+
+
+def _call_rhs(pn, model=None, beta=1.0, chi=1.0, n=4, ld=4, y=1, f=1):
+    m = pn.model_struct(model)
+    p = pn.Params(None, None, None, beta, chi, chi)
+    return pn.lib().pn_rhs(ctypes.byref(m), p, ctypes.c_int64(n),
+                           ctypes.c_void_p(y) if y else None, ctypes.c_int64(ld),
+                           ctypes.c_void_p(f) if f else None, None)
+
+
+def test_invalid_arguments_rejected_before_launch(pn):
+    # Fake non-null "device" pointers are never dereferenced: validation fails first.
+    assert _call_rhs(pn, beta=0.0) == pn.PN_EINVAL
+    assert _call_rhs(pn, beta=1.5) == pn.PN_EINVAL
+    assert _call_rhs(pn, chi=-0.1) == pn.PN_EINVAL
+    assert _call_rhs(pn, chi=float("nan")) == pn.PN_EINVAL
+    assert _call_rhs(pn, model=dict(pn_order=3)) == pn.PN_EINVAL
+    assert _call_rhs(pn, model=dict(spin_units=7)) == pn.PN_EINVAL
+    assert _call_rhs(pn, n=-1) == pn.PN_EINVAL
+    assert _call_rhs(pn, n=8, ld=4) == pn.PN_EINVAL
+    assert _call_rhs(pn, y=0) == pn.PN_EINVAL
+    assert _call_rhs(pn, f=0) == pn.PN_EINVAL
+    # n = 0 is a valid no-op.
+    assert _call_rhs(pn, n=0, ld=0, y=0, f=0) == pn.PN_OK
+    # A null model pointer.
+    p = pn.Params(None, None, None, 1.0, 1.0, 1.0)
+    assert pn.lib().pn_rhs(None, p, ctypes.c_int64(1), ctypes.c_void_p(1), ctypes.c_int64(1),
+                           ctypes.c_void_p(1), None) == pn.PN_EINVAL
+    # Per-orbit arrays must be all present or all absent.
+    p = pn.Params(1, None, None, 0.0, 0.0, 0.0)
+    assert pn.lib().pn_rhs(ctypes.byref(pn.model_struct()), p, ctypes.c_int64(1), ctypes.c_void_p(1),
+                           ctypes.c_int64(1), ctypes.c_void_p(1), None) == pn.PN_EINVAL
+
+
+def test_invalid_scan_settings_rejected(pn):
+    L = pn.lib()
+    m = pn.model_struct()
+    p = pn.Params(None, None, None, 1.0, 1.0, 1.0)
+    one = ctypes.c_void_p(8)
+    so = pn.ScanOut(8, 8, 8, None, None, None, None, None, None, 0, 0)
+
+    def scan(integ=None, corr=None, fli=None, t_all=1.0, out=so):
+        return L.pn_fli_scan(ctypes.byref(m), p, ctypes.byref(pn.integrator_struct(integ)),
+                             ctypes.byref(pn.correction_struct(corr)), ctypes.byref(pn.fli_struct(fli)),
+                             ctypes.c_int64(4), one, ctypes.c_int64(4), None, ctypes.c_double(t_all),
+                             ctypes.byref(out), None)
+
+    assert scan(integ=dict(h=0.0)) == pn.PN_EINVAL
+    assert scan(integ=dict(h=-1.0)) == pn.PN_EINVAL
+    assert scan(integ=dict(method=9)) == pn.PN_EINVAL
+    assert scan(corr=dict(mode=7)) == pn.PN_EINVAL
+    assert scan(corr=dict(max_iter=0)) == pn.PN_EINVAL
+    assert scan(corr=dict(sweeps=0)) == pn.PN_EINVAL
+    assert scan(corr=dict(tol=float("nan"))) == pn.PN_EINVAL
+    assert scan(fli=dict(d0=0.0)) == pn.PN_EINVAL
+    assert scan(fli=dict(d_renorm=1e-9)) == pn.PN_EINVAL
+    assert scan(fli=dict(shadow_axis=12)) == pn.PN_EINVAL
+    assert scan(fli=dict(r_esc=1.0)) == pn.PN_EINVAL
+    assert scan(t_all=-1.0) == pn.PN_EINVAL
+    assert scan(t_all=float("inf")) == pn.PN_EINVAL
+    bad_out = pn.ScanOut(8, None, 8, None, None, None, None, None, None, 0, 0)
+    assert scan(out=bad_out) == pn.PN_EINVAL
+    bad_trace = pn.ScanOut(8, 8, 8, None, None, None, None, None, None, 10, 5)
+    assert scan(out=bad_trace) == pn.PN_EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    from paper_1802_00147_amd import pn as P
+    monkeypatch.setattr(P, "_lib", None)
+    monkeypatch.setattr(P, "LIB_PATH", "/nonexistent/libpn_hip.so")
+    with pytest.raises(OSError):
+        P.lib()
