@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Benchmark of the plain FP64 FLI phase-space scan on one MI355X.
+
+Workload (default): the 64 x 64 (r0, theta) grid -- r0 in [10, 40], spin polar
+angle theta in [0, pi] (theta1 = pi/2, theta2 = theta), beta = 1, chi = 1, all
+Hamiltonian terms on (quadrupole-monopole included), RK4 with h = 1 to
+t = 1e5, the six-integral correction after every step, FLI threshold 5.8.
+One benchmark step is one pass of the whole path over the grid: initial
+states on the GPU (pn_init_state) and the fused scan (pn_fli_scan).
+
+Prints one JSON line.  value = orbit-steps per second (an orbit-step advances
+one orbit and its shadow by h, with both corrections and the FLI update).
+roofline: the scan kernel against the FP64 vector peak; its algorithmic flops
+per orbit-step come from the CPU oracle's counting scalar, measured in the
+cpu_baseline leg on sampled grid orbits.  cpu_baseline: the oracle as it is,
+timed on this host on a bounded sample of the same grid.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FP64 orbit-steps/s + scan grid-pts/s (surrogate vs plain, ≥99% FLI label agree)"
+FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 128 FP64 flop/clk x 2.4 GHz
+KERNEL_SOURCES = ["paper_1802_00147_amd/csrc/pn_kernels.hip", "paper_1802_00147_amd/csrc/pn_device.h"]
+
+# HBM traffic of the scan kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# (KiB per dispatch, scaled by a copy kernel of known size), valid only for the
+# kernel source whose hash is recorded with it.
+TRAFFIC = None   # dict(bytes_per_launch=..., sources_sha256=...)
+
+
+def sources_sha256():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def make_workload(name):
+    from paper_1802_00147_amd import workloads as W
+    if name == "grid64":
+        return W.grid64()
+    if name == "grid314":
+        return W.grid314()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def describe(wl):
+    return {"workload": f"{wl.name}: {wl.shape[0]}x{wl.shape[1]} FLI scan, t={wl.t_end:g}, RK4 h=1, "
+                        f"six-integral correction, beta={wl.beta:g}, chi={wl.chi1:g}, QM "
+                        f"{'on' if wl.model.get('quad_mono', 1) else 'off'}",
+            "orbits": wl.n, "t_end": wl.t_end, "orbit_steps": wl.steps()}
+
+
+def cpu_baseline(wl, sample, flop_sample_steps=2000):
+    """The oracle on a bounded sample of the workload: timing on this host's
+    cores, and algorithmic flops per orbit-step with the counting scalar."""
+    import oracle as O
+    from paper_1802_00147_amd import workloads as W
+    cores = min(os.cpu_count() or 1, 16)
+    idx = W.strided_sample(wl.n, sample, seed=11)
+    sub = wl.subset(idx)
+    y0 = O.init_state(sub.r0, sub.p0, sub.th1, sub.ph1, sub.th2, sub.ph2, sub.beta, sub.chi1, sub.chi2,
+                      model=wl.model)
+    t0 = time.perf_counter()
+    res = O.fli_scan(y0, wl.t_end, sub.beta, sub.chi1, sub.chi2, model=wl.model, nthreads=cores)
+    dt = time.perf_counter() - t0
+    steps = sub.steps()
+    flops = []
+    for k in range(min(4, len(idx))):
+        c = O.count_flops(y0[k], float(flop_sample_steps), sub.beta, sub.chi1, sub.chi2, model=wl.model)
+        flops.append(c["run_total"] / c["steps"])
+    return dict(value=steps / dt, unit="orbit-steps/s", cores=cores, kind="oracle",
+                sample=f"{len(idx)} seeded grid orbits of {wl.name}, full t={wl.t_end:g} "
+                       f"({steps} orbit-steps, {dt:.1f} s wall on {cores} threads)",
+                labels=res["label"], flops_per_orbit_step=float(np.mean(flops)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="grid64")
+    ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); the scan shards "
+              "by orbits with no exchange during integration, see the design notes.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1802_00147_amd import pn
+
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    dev = torch.device("cuda:0")
+    wl = make_workload(args.workload)
+    cols = {k: torch.as_tensor(getattr(wl, k), device=dev) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")}
+    n = wl.n
+    y0 = torch.empty((12, n), dtype=torch.float64, device=dev)
+    out = pn.scan_outputs(n, n, dev, full=True)
+    stream = torch.cuda.current_stream(dev)
+
+    def one_step(ev=None):
+        y = pn.init_state(cols["r0"], cols["p0"], cols["th1"], cols["ph1"], cols["th2"], cols["ph2"],
+                          wl.beta, wl.chi1, wl.chi2, model=wl.model)
+        if ev is not None:
+            ev[0].record(stream)
+        pn.fli_scan(y, wl.t_end, wl.beta, wl.chi1, wl.chi2, model=wl.model, out=out)
+        if ev is not None:
+            ev[1].record(stream)
+        return y
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        one_step(events[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+
+    orbit_steps = wl.steps()
+    value = orbit_steps * args.steps / elapsed
+    labels = out["label"].cpu().numpy()
+    status = out["status"].cpu().numpy()
+
+    line = dict(metric=METRIC, value=value, unit="orbit-steps/s", n_gpus=1, steps=args.steps,
+                warmup=args.warmup, ms_per_step=1e3 * elapsed / args.steps, higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype="f64", data="synthetic", config=describe(wl))
+    line["grid_pts_per_s"] = n * args.steps / elapsed
+    line["chaotic_fraction"] = float(np.mean(labels == 1))
+    line["invalid_orbits"] = int(np.sum((status & 0xFF) != 0))
+
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(wl, args.cpu_sample)
+        fpos = cb.pop("flops_per_orbit_step")
+        cb.pop("labels")
+        line["cpu_baseline"] = cb
+        achieved = fpos * orbit_steps / (kernel_ms * 1e-3) / 1e12
+        traffic = None
+        if TRAFFIC is not None and TRAFFIC.get("sources_sha256") == sources_sha256():
+            traffic = TRAFFIC["bytes_per_launch"]
+        line["roofline"] = dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                                frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=traffic,
+                                kernel="k_fli_scan<RK4,SIX>", kernel_ms=kernel_ms,
+                                flops_per_orbit_step=fpos)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -48,17 +48,19 @@ PN_HD bool pn_make_coef(const pn_model& m, double beta, double chi1, double chi2
     k.b5 = o2 * (5.0 + 8.0 * eta) / 2.0;
     k.b6 = o2 * 3.0 * eta / 2.0;
     k.b7 = o2 * -(1.0 + 3.0 * eta) / 4.0;
-    // Spin units: PHYS (mu M) multiplies every spin coupling by eta relative
-    // to M^2 units, where dH/dS_i reproduces eqs. (8)-(9) exactly.
+    // Spin units: a spin in M^2 is eta times the same spin in mu M, so the
+    // couplings linear in the spins (spin-orbit) carry one factor of eta and
+    // the quadratic ones (eqs. 3-5) two factors relative to M^2 units, where
+    // dH/dS_i reproduces eqs. (8)-(9) exactly.
     const double f = (m.spin_units == PN_SPIN_PHYS) ? eta : 1.0;
     const double so = m.spin_orbit ? 1.0 : 0.0;
     const double ss = m.spin_spin ? 1.0 : 0.0;
     const double qm = m.quad_mono ? 1.0 : 0.0;
     k.cso1 = so * f * (2.0 + 1.5 / beta);
     k.cso2 = so * f * (2.0 + 1.5 * beta);
-    k.c12 = ss * f / eta;
-    k.c11 = qm * f / (2.0 * beta * eta);
-    k.c22 = qm * f * beta / (2.0 * eta);
+    k.c12 = ss * f * f / eta;
+    k.c11 = qm * f * f / (2.0 * beta * eta);
+    k.c22 = qm * f * f * beta / (2.0 * eta);
     if (m.spin_units == PN_SPIN_PHYS) {
         k.s1 = chi1 * beta;         // chi1 m1^2 / (mu M)
         k.s2 = chi2 / beta;         // chi2 m2^2 / (mu M)
@@ -290,7 +292,7 @@ __device__ __forceinline__ int pn_energy_scale(const PnCoef& k, double* y, doubl
 // Least-squares projection of (r, p) onto H = E0, J = J0 (spins fixed): the
 // smallest displacement d with G d = -c, d = -G^T lam, (G G^T) lam = c, where
 // the rows of G are grad J_x, grad J_y, grad J_z, grad H.  Solved by LDL^T; the
-// energy row is dropped when its pivot is below 1e-12 of its diagonal (near
+// energy row is dropped when its pivot is below 1e-6 of its diagonal (near
 // circular orbits, where the energy row depends on the J rows).
 __device__ __forceinline__ void pn_project_EJ(const PnCoef& k, double* y, const double* ref) {
     double H, gr[3], gp[3], J[3];
@@ -316,7 +318,7 @@ __device__ __forceinline__ void pn_project_EJ(const PnCoef& k, double* y, const 
     const double d2 = A22 - l20 * l20 * d0 - l21 * l21 * d1, i2 = pn_rcp(d2);
     const double l32 = (A32 - l30 * l20 * d0 - l31 * l21 * d1) * i2;
     const double d3 = A33 - l30 * l30 * d0 - l31 * l31 * d1 - l32 * l32 * d2;
-    const bool use_e = d3 > 1e-12 * A33;
+    const bool use_e = d3 > 1e-6 * A33;
     const double z0 = c0, z1 = c1 - l10 * z0, z2 = c2 - l20 * z0 - l21 * z1;
     const double z3 = c3 - l30 * z0 - l31 * z1 - l32 * z2;
     const double lam3 = use_e ? z3 / d3 : 0.0;

@@ -6,7 +6,8 @@ refined hardware reciprocal square root where the oracle uses IEEE operations
 without contraction, so the two round differently):
   * RHS, invariants, initial states: 1e-13 of the largest component per row
     (a few ulps on terms that partly cancel).
-  * One correction: 1e-13 relative per row.
+  * One correction: 1e-13 relative per row (1e-12 for the dual scaling,
+    whose 2x2 Newton system may have a condition number up to 1e3).
   * State after integration up to t = 1e3 (1000 steps of h = 1): 1e-10
     relative (the stated parity bound for trajectories).
   * FLI of regular orbits: 1e-6 relative; labels and status codes exact.
@@ -107,7 +108,9 @@ def test_correction_parity(pn, mode):
     it = pn.manifold_correct(yg, dev(ref.T), dev(betas), dev(np.full(len(ys), 0.8)), dev(np.full(len(ys), 0.6)),
                              correction=dict(mode=mode))
     got = from_soa(yg)
-    assert np.all(rel_err_rows(got, exp) <= 1e-13)
+    # DUAL solves a 2x2 system whose conditioning the guard bounds by 1e3.
+    tol = 1e-12 if mode == "dual" else 1e-13
+    assert np.all(rel_err_rows(got, exp) <= tol)
     agree = np.mean(it.cpu().numpy() == it_exp)
     assert agree >= 0.95
 
