@@ -578,10 +578,10 @@ static int correct(const or_model& m, const Coef& c, const or_correction& cc,
     bool conv = true;
     if (cc.mode == 2) {
         for (int s = 0; s < cc.sweeps; ++s) {
-            // Energy row kept while its pivot exceeds 1e-6 of its diagonal:
+            // Energy row kept while its pivot exceeds 1e-4 of its diagonal:
             // bounds the amplification of rounding in the near-dependent
-            // direction by ~1e3 while E and J still reach rounding level.
-            project_EJ(m, c, y, ref, 1e-6);
+            // direction by ~1e2; J then stays within ~1e-12 of J0.
+            project_EJ(m, c, y, ref, 1e-4);
             iters += energy_scale(m, c, cc, y, ref[0], &conv);
             if (!conv) *noconv = true;
         }

@@ -292,7 +292,7 @@ __device__ __forceinline__ int pn_energy_scale(const PnCoef& k, double* y, doubl
 // Least-squares projection of (r, p) onto H = E0, J = J0 (spins fixed): the
 // smallest displacement d with G d = -c, d = -G^T lam, (G G^T) lam = c, where
 // the rows of G are grad J_x, grad J_y, grad J_z, grad H.  Solved by LDL^T; the
-// energy row is dropped when its pivot is below 1e-6 of its diagonal (near
+// energy row is dropped when its pivot is below 1e-4 of its diagonal (near
 // circular orbits, where the energy row depends on the J rows).
 __device__ __forceinline__ void pn_project_EJ(const PnCoef& k, double* y, const double* ref) {
     double H, gr[3], gp[3], J[3];
@@ -318,7 +318,7 @@ __device__ __forceinline__ void pn_project_EJ(const PnCoef& k, double* y, const 
     const double d2 = A22 - l20 * l20 * d0 - l21 * l21 * d1, i2 = pn_rcp(d2);
     const double l32 = (A32 - l30 * l20 * d0 - l31 * l21 * d1) * i2;
     const double d3 = A33 - l30 * l30 * d0 - l31 * l31 * d1 - l32 * l32 * d2;
-    const bool use_e = d3 > 1e-6 * A33;
+    const bool use_e = d3 > 1e-4 * A33;
     const double z0 = c0, z1 = c1 - l10 * z0, z2 = c2 - l20 * z0 - l21 * z1;
     const double z3 = c3 - l30 * z0 - l31 * z1 - l32 * z2;
     const double lam3 = use_e ? z3 / d3 : 0.0;
