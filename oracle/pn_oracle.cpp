@@ -131,6 +131,10 @@ enum { ST_OK = 0, ST_MERGED = 1, ST_ESCAPED = 2, ST_NONFINITE = 3, ST_UNBOUND_IN
        ST_BADPARAM = 5, ST_NEWTON_NOCONV = 0x100 };
 
 // Parameter ranges of Sec. 2: beta = m1/m2 in (0, 1]; Kerr spins chi in [0, 1].
+#ifndef PN_SIX_MU
+#define PN_SIX_MU 1e-5
+#endif
+
 static bool params_valid(double beta, double chi1, double chi2) {
     return beta > 0.0 && beta <= 1.0 && chi1 >= 0.0 && chi1 <= 1.0 && chi2 >= 0.0 && chi2 <= 1.0;
 }
@@ -452,13 +456,17 @@ static int energy_scale(const or_model& m, const Coef& c, const or_correction& c
 // J = J0 (Nacozy's shortest path, cited in Sec. 1), spins held fixed: the
 // smallest (dr, dp) in the Euclidean norm that satisfies the linearised
 // constraints G d = -c, with G the 4x6 Jacobian of (J, H) in (r, p) and c the
-// residual.  d = -G^T lam, (G G^T) lam = c, solved by Cholesky.  Near
+// residual: d = -G^T lam with (G G^T) lam = c.  The system is solved by block
+// elimination of the J block M (3x3, Cholesky): with M u = c_J, M v = a (a the
+// J-energy coupling column), the energy multiplier is t/s where s = A33 - a.v
+// is the Schur complement and t = c_E - a.u the reduced residual.  Near
 // circular orbits the energy row becomes dependent on the J rows (a circular
-// orbit extremises H at fixed J); when its Cholesky pivot falls below
-// rel_floor times its diagonal entry, only the J rows are used and the energy
-// is left to the momentum scaling that follows.
+// orbit extremises H at fixed J) and s -> 0; the multiplier is then damped
+// smoothly, lam_E = t s / (s^2 + (mu A33)^2), so that it never amplifies the
+// rounding of the energy residual by more than 1/(2 mu A33).  Whatever energy
+// error remains goes to the momentum scaling that follows.
 template <class T>
-static void project_EJ(const or_model& m, const Coef& c, T* y, const double* ref, double rel_floor) {
+static void project_EJ(const or_model& m, const Coef& c, T* y, const double* ref, double mu) {
     const V3<T> r = get3(y, 0), p = get3(y, 3);
     const Grad<T> g = gradient(m, c, y);
     const T H = hamiltonian(m, c, y);
@@ -466,48 +474,52 @@ static void project_EJ(const or_model& m, const Coef& c, T* y, const double* ref
     // Rows 0..2: grad of J_k = (p x e_k, e_k x r); row 3: grad H = (dH/dr, dH/dp).
     const T rv[3] = {r.x, r.y, r.z}, pv[3] = {p.x, p.y, p.z};
     const T rr = dot(r, r), pp = dot(p, p);
-    T A[4][4];
+    T M[3][3];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
-            A[i][j] = (i == j ? rr + pp : T(0.0)) - rv[i] * rv[j] - pv[i] * pv[j];
+            M[i][j] = (i == j ? rr + pp : T(0.0)) - rv[i] * rv[j] - pv[i] * pv[j];
     // (p x e_k).dH/dr + (e_k x r).dH/dp = e_k . (dH/dr x p + r x dH/dp)
     const V3<T> cx = add(cross(g.dr, p), cross(r, g.dp));
-    A[0][3] = A[3][0] = cx.x;
-    A[1][3] = A[3][1] = cx.y;
-    A[2][3] = A[3][2] = cx.z;
-    A[3][3] = dot(g.dr, g.dr) + dot(g.dp, g.dp);
-    T rhs_[4] = {J.x - ref[1], J.y - ref[2], J.z - ref[3], H - ref[0]};
-    // Cholesky A = L L^T.
-    T Lc[4][4];
-    for (int i = 0; i < 4; ++i) for (int j = 0; j < 4; ++j) Lc[i][j] = T(0.0);
-    int nrow = 4;
-    for (int j = 0; j < 4; ++j) {
-        T s = A[j][j];
-        for (int k = 0; k < j; ++k) s = s - Lc[j][k] * Lc[j][k];
-        if (j == 3 && !(val(s) > rel_floor * val(A[3][3]))) { nrow = 3; break; }
-        Lc[j][j] = sqrt(s);
-        for (int i = j + 1; i < 4; ++i) {
-            T t = A[i][j];
-            for (int k = 0; k < j; ++k) t = t - Lc[i][k] * Lc[j][k];
-            Lc[i][j] = t / Lc[j][j];
+    const T a[3] = {cx.x, cx.y, cx.z};
+    const T A33 = dot(g.dr, g.dr) + dot(g.dp, g.dp);
+    const T cJ[3] = {J.x - ref[1], J.y - ref[2], J.z - ref[3]};
+    const T cE = H - ref[0];
+    // Cholesky of the J block, M = L L^T.
+    T L[3][3] = {{T(0.0), T(0.0), T(0.0)}, {T(0.0), T(0.0), T(0.0)}, {T(0.0), T(0.0), T(0.0)}};
+    for (int j = 0; j < 3; ++j) {
+        T s = M[j][j];
+        for (int k = 0; k < j; ++k) s = s - L[j][k] * L[j][k];
+        L[j][j] = sqrt(s);
+        for (int i = j + 1; i < 3; ++i) {
+            T t = M[i][j];
+            for (int k = 0; k < j; ++k) t = t - L[i][k] * L[j][k];
+            L[i][j] = t / L[j][j];
         }
     }
-    // Forward and back substitution on the leading nrow rows.
-    T z[4], lam[4] = {T(0.0), T(0.0), T(0.0), T(0.0)};
-    for (int i = 0; i < nrow; ++i) {
-        T t = rhs_[i];
-        for (int k = 0; k < i; ++k) t = t - Lc[i][k] * z[k];
-        z[i] = t / Lc[i][i];
-    }
-    for (int i = nrow - 1; i >= 0; --i) {
-        T t = z[i];
-        for (int k = i + 1; k < nrow; ++k) t = t - Lc[k][i] * lam[k];
-        lam[i] = t / Lc[i][i];
-    }
+    auto solve = [&](const T* b, T* x) {
+        T z[3];
+        for (int i = 0; i < 3; ++i) {
+            T t = b[i];
+            for (int k = 0; k < i; ++k) t = t - L[i][k] * z[k];
+            z[i] = t / L[i][i];
+        }
+        for (int i = 2; i >= 0; --i) {
+            T t = z[i];
+            for (int k = i + 1; k < 3; ++k) t = t - L[k][i] * x[k];
+            x[i] = t / L[i][i];
+        }
+    };
+    T u[3], v[3];
+    solve(cJ, u);
+    solve(a, v);
+    const T s = A33 - (a[0] * v[0] + a[1] * v[1] + a[2] * v[2]);
+    const T t = cE - (a[0] * u[0] + a[1] * u[1] + a[2] * u[2]);
+    const T damp = mu * A33;
+    const T lamE = t * s / (s * s + damp * damp);
+    const V3<T> lJ = v3<T>(u[0] - v[0] * lamE, u[1] - v[1] * lamE, u[2] - v[2] * lamE);
     // d = -G^T lam: dr = -(p x lamJ) - lamE dH/dr, dp = -(lamJ x r) - lamE dH/dp.
-    const V3<T> lJ = v3<T>(lam[0], lam[1], lam[2]);
-    const V3<T> dr = sub(scl(-1.0, cross(p, lJ)), scl(lam[3], g.dr));
-    const V3<T> dp = sub(scl(-1.0, cross(lJ, r)), scl(lam[3], g.dp));
+    const V3<T> dr = sub(scl(-1.0, cross(p, lJ)), scl(lamE, g.dr));
+    const V3<T> dp = sub(scl(-1.0, cross(lJ, r)), scl(lamE, g.dp));
     put3(y, 0, add(r, dr));
     put3(y, 3, add(p, dp));
 }
@@ -578,10 +590,7 @@ static int correct(const or_model& m, const Coef& c, const or_correction& cc,
     bool conv = true;
     if (cc.mode == 2) {
         for (int s = 0; s < cc.sweeps; ++s) {
-            // Energy row kept while its pivot exceeds 1e-4 of its diagonal:
-            // bounds the amplification of rounding in the near-dependent
-            // direction by ~1e2; J then stays within ~1e-12 of J0.
-            project_EJ(m, c, y, ref, 1e-4);
+            project_EJ(m, c, y, ref, PN_SIX_MU);
             iters += energy_scale(m, c, cc, y, ref[0], &conv);
             if (!conv) *noconv = true;
         }

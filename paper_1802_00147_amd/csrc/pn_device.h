@@ -20,6 +20,10 @@
 
 #define PN_HD __host__ __device__ __forceinline__
 
+#ifndef PN_SIX_MU
+#define PN_SIX_MU 1e-5
+#endif
+
 struct PnCoef {
     double a1, a2, a3, a4;                 // 1PN
     double b1, b2, b3, b4, b5, b6, b7;     // 2PN
@@ -318,10 +322,10 @@ __device__ __forceinline__ void pn_project_EJ(const PnCoef& k, double* y, const 
     const double d2 = A22 - l20 * l20 * d0 - l21 * l21 * d1, i2 = pn_rcp(d2);
     const double l32 = (A32 - l30 * l20 * d0 - l31 * l21 * d1) * i2;
     const double d3 = A33 - l30 * l30 * d0 - l31 * l31 * d1 - l32 * l32 * d2;
-    const bool use_e = d3 > 1e-4 * A33;
     const double z0 = c0, z1 = c1 - l10 * z0, z2 = c2 - l20 * z0 - l21 * z1;
     const double z3 = c3 - l30 * z0 - l31 * z1 - l32 * z2;
-    const double lam3 = use_e ? z3 / d3 : 0.0;
+    const double damp = PN_SIX_MU * A33;
+    const double lam3 = z3 * d3 / fma(d3, d3, damp * damp);
     const double lam2 = z2 * i2 - l32 * lam3;
     const double lam1 = z1 * i1 - l21 * lam2 - l31 * lam3;
     const double lam0 = z0 * i0 - l10 * lam1 - l20 * lam2 - l30 * lam3;
