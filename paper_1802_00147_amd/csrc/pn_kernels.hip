@@ -180,29 +180,52 @@ __device__ __forceinline__ double sq_dist(const double* a, const double* b) {
     return d2;
 }
 
-// Fused scan: orbit and shadow of one lane, every step RK + correction of
-// both, validity, separation and (rarely) renormalisation.
+// Exchange a value with the partner lane (lanes 2j and 2j+1 of a wavefront)
+// through DPP quad permutation [1,0,3,2]; no LDS traffic.
+__device__ __forceinline__ int swap_pair_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ double swap_pair(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)swap_pair_i32((int)(unsigned)b);
+    const unsigned hi = (unsigned)swap_pair_i32((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Fused scan.  Each orbit occupies two adjacent lanes: the even lane
+// integrates the orbit, the odd lane its shadow, so a wavefront carries 32
+// orbits and every lane holds a single trajectory.  Per step each lane takes
+// its RK step and correction, then the pair exchanges states through DPP to
+// form the separation (identical in both lanes), the validity verdict and,
+// rarely, the renormalisation of the shadow.  The even lane writes results.
 template <int METHOD, int MODE>
 __global__ __launch_bounds__(kBlock) void k_fli_scan(ParamArgs pa, FliArgs fa) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= fa.n) return;
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i = g >> 1;
+    if (i >= fa.n) return;                 // pairs are whole: both lanes leave together
+    const bool shadow = (g & 1) != 0;
     const int64_t ld = fa.ld;
     PnCoef k;
     const bool param_ok = load_coef(pa, i, k);
-    double y[12], ys[12], ref[4], refs[4];
+    double y[12], ref[4];
     load_state(fa.y0, ld, i, y);
     pn_correct_spins(k, y);
+    if (shadow) {
 #pragma unroll
-    for (int c = 0; c < 12; ++c) ys[c] = y[c];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) ys[c] += (c == fa.shadow_axis) ? fa.d0 : 0.0;
+        for (int c = 0; c < 12; ++c) y[c] += (c == fa.shadow_axis) ? fa.d0 : 0.0;
+    }
     capture_ref(k, y, ref);
-    capture_ref(k, ys, refs);
     const double t_end = fa.t_end ? fa.t_end[i] : fa.t_end_all;
     const int64_t nsteps = t_end > 0.0 ? (int64_t)ceil(t_end / fa.h) : 0;
 
+    // Status at t = 0 is decided by the orbit (even) lane.
     int st = param_ok ? pn_validity(y, fa.rmerge2, fa.resc2) : PN_ORBIT_BADPARAM;
     if (st == PN_ORBIT_OK && !(ref[0] < 0.0)) st = PN_ORBIT_UNBOUND_INIT;
+    {
+        const int other = swap_pair_i32(st);
+        st = shadow ? other : st;
+    }
 
     double acc = 0.0;
     int nmax = 0;
@@ -210,35 +233,65 @@ __global__ __launch_bounds__(kBlock) void k_fli_scan(ParamArgs pa, FliArgs fa) {
     int64_t renorms = 0;
     const double d0 = fa.d0;
     const int64_t tev = fa.out.trace_every;
+    double d2 = 0.0;
+    double yp[12];                          // the partner's state
     for (int64_t t = 0; t < nsteps && st == PN_ORBIT_OK; ++t) {
         bool nc;
         pn_rk_step<METHOD>(k, y, fa.h);
-        int it = pn_correct<MODE>(k, y, ref, fa.corr.tol, fa.corr.max_iter, fa.corr.sweeps, nc);
+        const int it = pn_correct<MODE>(k, y, ref, fa.corr.tol, fa.corr.max_iter, fa.corr.sweeps, nc);
         any_nc = any_nc || nc;
         nmax = max(nmax, it);
-        pn_rk_step<METHOD>(k, ys, fa.h);
-        it = pn_correct<MODE>(k, ys, refs, fa.corr.tol, fa.corr.max_iter, fa.corr.sweeps, nc);
-        any_nc = any_nc || nc;
-        nmax = max(nmax, it);
-        st = pn_validity(y, fa.rmerge2, fa.resc2);
-        if (st == PN_ORBIT_OK) st = pn_validity(ys, fa.rmerge2, fa.resc2);
+        // Orbit verdict first, then the shadow's (same order in both lanes).
+        const int mine = pn_validity(y, fa.rmerge2, fa.resc2);
+        const int other = swap_pair_i32(mine);
+        const int vo = shadow ? other : mine, vs = shadow ? mine : other;
+        st = vo != PN_ORBIT_OK ? vo : vs;
         if (st != PN_ORBIT_OK) break;
-        const double d2 = sq_dist(y, ys);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) yp[c] = swap_pair(y[c]);
+        d2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const double e = shadow ? y[c] - yp[c] : yp[c] - y[c];
+            d2 = fma(e, e, d2);
+        }
         if (d2 >= fa.d_renorm2) {
             const double d = sqrt(d2);
             acc += log10(d / d0);
-            const double f = d0 / d;
+            if (shadow) {
+                const double f = d0 / d;
 #pragma unroll
-            for (int c = 0; c < 12; ++c) ys[c] = fma(f, ys[c] - y[c], y[c]);
-            pn_correct_spins(k, ys);
-            capture_ref(k, ys, refs);
+                for (int c = 0; c < 12; ++c) y[c] = fma(f, y[c] - yp[c], yp[c]);
+                pn_correct_spins(k, y);
+                capture_ref(k, y, ref);
+            }
             ++renorms;
+            d2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) yp[c] = swap_pair(y[c]);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const double e = shadow ? y[c] - yp[c] : yp[c] - y[c];
+                d2 = fma(e, e, d2);
+            }
         }
-        if (tev > 0 && ((t + 1) % tev) == 0) {
+        if (tev > 0 && ((t + 1) % tev) == 0 && !shadow) {
             const int64_t row = (t + 1) / tev - 1;
-            if (row < fa.out.ntrace) fa.out.trace[row * ld + i] = acc + log10(sqrt(sq_dist(y, ys)) / d0);
+            if (row < fa.out.ntrace) fa.out.trace[row * ld + i] = acc + log10(sqrt(d2) / d0);
         }
     }
+    // Final separation (after the loop, or at t = 0 when no step was taken).
+#pragma unroll
+    for (int c = 0; c < 12; ++c) yp[c] = swap_pair(y[c]);
+    d2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const double e = shadow ? y[c] - yp[c] : yp[c] - y[c];
+        d2 = fma(e, e, d2);
+    }
+    const int nmax_other = swap_pair_i32(nmax);
+    const int nc_other = swap_pair_i32(any_nc ? 1 : 0);
+    if (shadow) return;
     const pn_scan_out& o = fa.out;
     if (o.y_final) store_state(o.y_final, ld, i, y);
     if (o.dH || o.dJ) {
@@ -253,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_fli_scan(ParamArgs pa, FliArgs fa) {
         }
     }
     if (st == PN_ORBIT_OK) {
-        const double fli = acc + log10(sqrt(sq_dist(y, ys)) / d0);
+        const double fli = acc + log10(sqrt(d2) / d0);
         const double thr = (fa.thr_scaling == PN_THR_LOG_T && t_end > 0.0)
                                ? fa.thr_at_1e5 + log10(t_end / 1e5) : fa.thr_at_1e5;
         o.fli[i] = fli;
@@ -262,8 +315,8 @@ __global__ __launch_bounds__(kBlock) void k_fli_scan(ParamArgs pa, FliArgs fa) {
         o.fli[i] = __builtin_nan("");
         o.label[i] = -1;
     }
-    o.status[i] = st | (any_nc ? PN_ORBIT_NEWTON_NOCONV : 0);
-    if (o.newton_max) o.newton_max[i] = nmax;
+    o.status[i] = st | ((any_nc || nc_other) ? PN_ORBIT_NEWTON_NOCONV : 0);
+    if (o.newton_max) o.newton_max[i] = max(nmax, nmax_other);
     if (o.renorms) o.renorms[i] = renorms;
 }
 
@@ -355,7 +408,7 @@ void launch_step_m(int mode, const ParamArgs& pa, const CorrArgs& ca, double h, 
 
 template <int METHOD, int MODE>
 void launch_scan(const ParamArgs& pa, const FliArgs& fa, hipStream_t s) {
-    hipLaunchKernelGGL((k_fli_scan<METHOD, MODE>), dim3(grid_for(fa.n)), dim3(kBlock), 0, s, pa, fa);
+    hipLaunchKernelGGL((k_fli_scan<METHOD, MODE>), dim3(grid_for(2 * fa.n)), dim3(kBlock), 0, s, pa, fa);
 }
 
 template <int METHOD>
