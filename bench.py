@@ -51,10 +51,17 @@ def make_workload(name):
         return W.grid64()
     if name == "grid314":
         return W.grid314()
+    if name == "batch1M":
+        return W.batch()
     raise SystemExit(f"unknown workload {name}")
 
 
 def describe(wl):
+    if wl.shape is None:
+        return {"workload": f"{wl.name}: {wl.n} orbits, per-orbit beta in [0.1,1], chi in [0,1], isotropic "
+                            "spins, r0 in [8,60], t_end log-uniform in [1e3,1e6]; persistent work-stealing "
+                            "scan, autotuned; RK4 h=1, six-integral correction, QM on",
+                "orbits": wl.n, "orbit_steps": wl.steps()}
     return {"workload": f"{wl.name}: {wl.shape[0]}x{wl.shape[1]} FLI scan, t={wl.t_end:g}, RK4 h=1, "
                         f"six-integral correction, beta={wl.beta:g}, chi={wl.chi1:g}, QM "
                         f"{'on' if wl.model.get('quad_mono', 1) else 'off'}",
@@ -72,15 +79,18 @@ def cpu_baseline(wl, sample, flop_sample_steps=2000):
     y0 = O.init_state(sub.r0, sub.p0, sub.th1, sub.ph1, sub.th2, sub.ph2, sub.beta, sub.chi1, sub.chi2,
                       model=wl.model)
     t0 = time.perf_counter()
-    res = O.fli_scan(y0, wl.t_end, sub.beta, sub.chi1, sub.chi2, model=wl.model, nthreads=cores)
+    res = O.fli_scan(y0, sub.t_end, sub.beta, sub.chi1, sub.chi2, model=wl.model, nthreads=cores)
     dt = time.perf_counter() - t0
     steps = sub.steps()
     flops = []
-    for k in range(min(4, len(idx))):
-        c = O.count_flops(y0[k], float(flop_sample_steps), sub.beta, sub.chi1, sub.chi2, model=wl.model)
+    pick = (lambda v, k: v[k] if isinstance(v, np.ndarray) else v)
+    for k in range(min(8, len(idx))):
+        c = O.count_flops(y0[k], float(flop_sample_steps), pick(sub.beta, k), pick(sub.chi1, k),
+                          pick(sub.chi2, k), model=wl.model)
         flops.append(c["run_total"] / c["steps"])
+    tdesc = f"full t={wl.t_end:g}" if wl.shape is not None else "full per-orbit t_end"
     return dict(value=steps / dt, unit="orbit-steps/s", cores=cores, kind="oracle",
-                sample=f"{len(idx)} seeded grid orbits of {wl.name}, full t={wl.t_end:g} "
+                sample=f"{len(idx)} seeded orbits of {wl.name}, {tdesc} "
                        f"({steps} orbit-steps, {dt:.1f} s wall on {cores} threads)",
                 labels=res["label"], flops_per_orbit_step=float(np.mean(flops)))
 
@@ -107,16 +117,29 @@ def main():
     wl = make_workload(args.workload)
     cols = {k: torch.as_tensor(getattr(wl, k), device=dev) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")}
     n = wl.n
-    y0 = torch.empty((12, n), dtype=torch.float64, device=dev)
     out = pn.scan_outputs(n, n, dev, full=True)
     stream = torch.cuda.current_stream(dev)
+    batched = wl.shape is None
+    as_dev = (lambda v: torch.as_tensor(v, device=dev) if isinstance(v, np.ndarray) else v)
+    beta, chi1, chi2, t_end = as_dev(wl.beta), as_dev(wl.chi1), as_dev(wl.chi2), as_dev(wl.t_end)
+    kernel = "k_fli_scan<RK4,SIX>"
+    if batched:
+        ws = pn.batch_workspace(n, dev)
+        y = pn.init_state(cols["r0"], cols["p0"], cols["th1"], cols["ph1"], cols["th2"], cols["ph2"],
+                          beta, chi1, chi2, model=wl.model)
+        tuning, _ = pn.autotune_batch(y, t_end, beta, chi1, chi2, model=wl.model, step_scale=0.01, ws=ws,
+                                      out=out)
+        kernel = f"k_batch_scan<RK4,SIX> {tuning}"
 
     def one_step(ev=None):
         y = pn.init_state(cols["r0"], cols["p0"], cols["th1"], cols["ph1"], cols["th2"], cols["ph2"],
-                          wl.beta, wl.chi1, wl.chi2, model=wl.model)
+                          beta, chi1, chi2, model=wl.model)
         if ev is not None:
             ev[0].record(stream)
-        pn.fli_scan(y, wl.t_end, wl.beta, wl.chi1, wl.chi2, model=wl.model, out=out)
+        if batched:
+            pn.batch_scan(y, t_end, beta, chi1, chi2, model=wl.model, out=out, ws=ws)
+        else:
+            pn.fli_scan(y, t_end, beta, chi1, chi2, model=wl.model, out=out)
         if ev is not None:
             ev[1].record(stream)
         return y
@@ -157,7 +180,7 @@ def main():
             traffic = TRAFFIC["bytes_per_launch"]
         line["roofline"] = dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
                                 frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=traffic,
-                                kernel="k_fli_scan<RK4,SIX>", kernel_ms=kernel_ms,
+                                kernel=kernel, kernel_ms=kernel_ms,
                                 flops_per_orbit_step=fpos)
     print(json.dumps(line), flush=True)
 

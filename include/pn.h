@@ -222,6 +222,64 @@ pn_status pn_fli_scan(const pn_model* model, pn_params params, const pn_integrat
                       const double* y0, int64_t ld, const double* t_end, double t_end_all,
                       const pn_scan_out* out, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Batches of orbits of uneven length (persistent, work-stealing).
+ * ------------------------------------------------------------------------- */
+
+/* Launch shape of the persistent batch kernel.  block: threads per workgroup
+ * (64, 128 or 256); waves_per_simd: resident wavefronts per SIMD (1 or 2);
+ * chunk_steps: steps a slot runs between refills (>= 1). */
+typedef struct {
+    int32_t block;
+    int32_t waves_per_simd;
+    int32_t chunk_steps;
+} pn_tuning;
+
+void pn_default_tuning(pn_tuning* t);
+
+/* Bytes of device workspace pn_batch_scan needs for n orbits. */
+size_t pn_batch_workspace_size(int64_t n);
+
+/* Same computation and outputs as pn_fli_scan (bitwise, for any tuning),
+ * for orbits whose parameters and end times differ.  The orbits are ordered by
+ * step count, longest first (binned, 8 bins per octave), into a queue in the
+ * workspace; a persistent grid keeps every lane pair busy, claiming the next
+ * orbit whenever its current one ends (one atomic per wavefront and refill).
+ * t_end: [n] device array (required).  tuning: NULL uses the device's last
+ * pn_autotune_batch result, else pn_default_tuning.  ws: device workspace of
+ * at least pn_batch_workspace_size(n) bytes, owned by the caller; its contents
+ * on entry are irrelevant; calls that share a workspace must not overlap.
+ * Every orbit is claimed exactly once. */
+pn_status pn_batch_scan(const pn_model* model, pn_params params, const pn_integrator* integ,
+                        const pn_correction* corr, const pn_fli_cfg* fli, int64_t n,
+                        const double* y0, int64_t ld, const double* t_end, const pn_scan_out* out,
+                        const pn_tuning* tuning, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Project-written autotuner: times the batch for block in {64, 256} x
+ * waves_per_simd in {1, 2} x chunk_steps in {64, 256, 1024} with every
+ * orbit's step count multiplied by step_scale (0 < step_scale <= 1), returns
+ * the fastest in *best (and its time in *best_ms, nullable) and remembers it
+ * for the current device.  Blocks the calling thread (synchronises the
+ * stream).  The outputs in *out are overwritten with trial results. */
+pn_status pn_autotune_batch(const pn_model* model, pn_params params, const pn_integrator* integ,
+                            const pn_correction* corr, const pn_fli_cfg* fli, int64_t n,
+                            const double* y0, int64_t ld, const double* t_end, const pn_scan_out* out,
+                            double step_scale, void* ws, size_t ws_bytes, pn_tuning* best,
+                            float* best_ms, hipStream_t stream);
+
+/* A batch captured once into a HIP graph (clear, bin, order, persistent scan)
+ * and replayed with pn_graph_launch.  The pointers and sizes are frozen at
+ * creation; the caller keeps every buffer alive until pn_graph_destroy.  The
+ * graph holds only kernel nodes. */
+typedef struct pn_graph pn_graph;
+pn_status pn_batch_graph_create(const pn_model* model, pn_params params, const pn_integrator* integ,
+                                const pn_correction* corr, const pn_fli_cfg* fli, int64_t n,
+                                const double* y0, int64_t ld, const double* t_end,
+                                const pn_scan_out* out, const pn_tuning* tuning, void* ws,
+                                size_t ws_bytes, pn_graph** graph);
+pn_status pn_graph_launch(pn_graph* graph, hipStream_t stream);
+void pn_graph_destroy(pn_graph* graph);
+
 /* Library version and last error text (thread-local; "" when none). */
 int32_t pn_version(void);
 const char* pn_status_string(pn_status s);

@@ -168,6 +168,7 @@ struct FliArgs {
     pn_scan_out out;
     int64_t n, ld;
     const double* y0;
+    double step_scale;      // 1 for real runs; < 1 shortens every orbit (autotune trials)
 };
 
 __device__ __forceinline__ double sq_dist(const double* a, const double* b) {
@@ -193,111 +194,115 @@ __device__ __forceinline__ double swap_pair(double v) {
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-// Fused scan.  Each orbit occupies two adjacent lanes: the even lane
-// integrates the orbit, the odd lane its shadow, so a wavefront carries 32
-// orbits and every lane holds a single trajectory.  Per step each lane takes
-// its RK step and correction, then the pair exchanges states through DPP to
-// form the separation (identical in both lanes), the validity verdict and,
-// rarely, the renormalisation of the shadow.  The even lane writes results.
-template <int METHOD, int MODE>
-__global__ __launch_bounds__(kBlock) void k_fli_scan(ParamArgs pa, FliArgs fa) {
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t i = g >> 1;
-    if (i >= fa.n) return;                 // pairs are whole: both lanes leave together
-    const bool shadow = (g & 1) != 0;
-    const int64_t ld = fa.ld;
-    PnCoef k;
-    const bool param_ok = load_coef(pa, i, k);
+// Per-lane state of one trajectory of an orbit/shadow pair.  Each orbit
+// occupies two adjacent lanes: the even lane integrates the orbit, the odd
+// lane its shadow, so every lane holds a single trajectory.
+struct PairState {
     double y[12], ref[4];
-    load_state(fa.y0, ld, i, y);
-    pn_correct_spins(k, y);
-    if (shadow) {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) y[c] += (c == fa.shadow_axis) ? fa.d0 : 0.0;
-    }
-    capture_ref(k, y, ref);
-    const double t_end = fa.t_end ? fa.t_end[i] : fa.t_end_all;
-    const int64_t nsteps = t_end > 0.0 ? (int64_t)ceil(t_end / fa.h) : 0;
+    double acc, d2, t_end;
+    int64_t t, nsteps, renorms;
+    int st, nmax;
+    bool any_nc;
+};
 
-    // Status at t = 0 is decided by the orbit (even) lane.
-    int st = param_ok ? pn_validity(y, fa.rmerge2, fa.resc2) : PN_ORBIT_BADPARAM;
-    if (st == PN_ORBIT_OK && !(ref[0] < 0.0)) st = PN_ORBIT_UNBOUND_INIT;
-    {
-        const int other = swap_pair_i32(st);
-        st = shadow ? other : st;
-    }
-
-    double acc = 0.0;
-    int nmax = 0;
-    bool any_nc = false;
-    int64_t renorms = 0;
-    const double d0 = fa.d0;
-    const int64_t tev = fa.out.trace_every;
+// Separation of the pair, computed identically in both lanes.
+__device__ __forceinline__ double pair_d2(const double* y, bool shadow) {
     double d2 = 0.0;
-    double yp[12];                          // the partner's state
-    for (int64_t t = 0; t < nsteps && st == PN_ORBIT_OK; ++t) {
-        bool nc;
-        pn_rk_step<METHOD>(k, y, fa.h);
-        const int it = pn_correct<MODE>(k, y, ref, fa.corr.tol, fa.corr.max_iter, fa.corr.sweeps, nc);
-        any_nc = any_nc || nc;
-        nmax = max(nmax, it);
-        // Orbit verdict first, then the shadow's (same order in both lanes).
-        const int mine = pn_validity(y, fa.rmerge2, fa.resc2);
-        const int other = swap_pair_i32(mine);
-        const int vo = shadow ? other : mine, vs = shadow ? mine : other;
-        st = vo != PN_ORBIT_OK ? vo : vs;
-        if (st != PN_ORBIT_OK) break;
-#pragma unroll
-        for (int c = 0; c < 12; ++c) yp[c] = swap_pair(y[c]);
-        d2 = 0.0;
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            const double e = shadow ? y[c] - yp[c] : yp[c] - y[c];
-            d2 = fma(e, e, d2);
-        }
-        if (d2 >= fa.d_renorm2) {
-            const double d = sqrt(d2);
-            acc += log10(d / d0);
-            if (shadow) {
-                const double f = d0 / d;
-#pragma unroll
-                for (int c = 0; c < 12; ++c) y[c] = fma(f, y[c] - yp[c], yp[c]);
-                pn_correct_spins(k, y);
-                capture_ref(k, y, ref);
-            }
-            ++renorms;
-            d2 = 0.0;
-#pragma unroll
-            for (int c = 0; c < 12; ++c) yp[c] = swap_pair(y[c]);
-#pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                const double e = shadow ? y[c] - yp[c] : yp[c] - y[c];
-                d2 = fma(e, e, d2);
-            }
-        }
-        if (tev > 0 && ((t + 1) % tev) == 0 && !shadow) {
-            const int64_t row = (t + 1) / tev - 1;
-            if (row < fa.out.ntrace) fa.out.trace[row * ld + i] = acc + log10(sqrt(d2) / d0);
-        }
-    }
-    // Final separation (after the loop, or at t = 0 when no step was taken).
-#pragma unroll
-    for (int c = 0; c < 12; ++c) yp[c] = swap_pair(y[c]);
-    d2 = 0.0;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-        const double e = shadow ? y[c] - yp[c] : yp[c] - y[c];
+        const double yp = swap_pair(y[c]);
+        const double e = shadow ? y[c] - yp : yp - y[c];
         d2 = fma(e, e, d2);
     }
-    const int nmax_other = swap_pair_i32(nmax);
-    const int nc_other = swap_pair_i32(any_nc ? 1 : 0);
+    return d2;
+}
+
+// Start orbit i in this pair: spin lengths (eq. 10), shadow offset,
+// reference integrals, status at t = 0 (decided by the orbit lane).
+__device__ __forceinline__ void pair_begin(PairState& ps, const PnCoef& k, bool param_ok, bool shadow,
+                                           const FliArgs& fa, int64_t i) {
+    load_state(fa.y0, fa.ld, i, ps.y);
+    pn_correct_spins(k, ps.y);
+    if (shadow) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) ps.y[c] += (c == fa.shadow_axis) ? fa.d0 : 0.0;
+    }
+    capture_ref(k, ps.y, ps.ref);
+    ps.t_end = fa.t_end ? fa.t_end[i] : fa.t_end_all;
+    ps.nsteps = ps.t_end > 0.0 ? (int64_t)ceil(ps.t_end / fa.h) : 0;
+    if (fa.step_scale != 1.0) ps.nsteps = (int64_t)ceil((double)ps.nsteps * fa.step_scale);
+    int st = param_ok ? pn_validity(ps.y, fa.rmerge2, fa.resc2) : PN_ORBIT_BADPARAM;
+    if (st == PN_ORBIT_OK && !(ps.ref[0] < 0.0)) st = PN_ORBIT_UNBOUND_INIT;
+    const int other = swap_pair_i32(st);
+    ps.st = shadow ? other : st;
+    ps.acc = 0.0;
+    ps.d2 = 0.0;
+    ps.t = 0;
+    ps.renorms = 0;
+    ps.nmax = 0;
+    ps.any_nc = false;
+}
+
+// One step of both trajectories (each lane its own), then the pair's
+// validity, separation and, rarely, the shadow's renormalisation.
+template <int METHOD, int MODE>
+__device__ __forceinline__ void pair_step(PairState& ps, const PnCoef& k, bool shadow, const FliArgs& fa,
+                                          int64_t i) {
+    bool nc;
+    pn_rk_step<METHOD>(k, ps.y, fa.h);
+    const int it = pn_correct<MODE>(k, ps.y, ps.ref, fa.corr.tol, fa.corr.max_iter, fa.corr.sweeps, nc);
+    ps.any_nc = ps.any_nc || nc;
+    ps.nmax = max(ps.nmax, it);
+    ps.t += 1;
+    // Orbit verdict first, then the shadow's (same order in both lanes).
+    const int mine = pn_validity(ps.y, fa.rmerge2, fa.resc2);
+    const int other = swap_pair_i32(mine);
+    const int vo = shadow ? other : mine, vs = shadow ? mine : other;
+    ps.st = vo != PN_ORBIT_OK ? vo : vs;
+    if (ps.st != PN_ORBIT_OK) return;
+    ps.d2 = pair_d2(ps.y, shadow);
+    if (ps.d2 >= fa.d_renorm2) {
+        const double d = sqrt(ps.d2);
+        ps.acc += log10(d / fa.d0);
+        double yp[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) yp[c] = swap_pair(ps.y[c]);
+        if (shadow) {
+            const double f = fa.d0 / d;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) ps.y[c] = fma(f, ps.y[c] - yp[c], yp[c]);
+            pn_correct_spins(k, ps.y);
+            capture_ref(k, ps.y, ps.ref);
+        }
+        ps.renorms += 1;
+        ps.d2 = pair_d2(ps.y, shadow);
+    }
+    const int64_t tev = fa.out.trace_every;
+    if (tev > 0 && (ps.t % tev) == 0 && !shadow) {
+        const int64_t row = ps.t / tev - 1;
+        if (row < fa.out.ntrace) fa.out.trace[row * fa.ld + i] = ps.acc + log10(sqrt(ps.d2) / fa.d0);
+    }
+}
+
+__device__ __forceinline__ bool pair_running(const PairState& ps) {
+    return ps.st == PN_ORBIT_OK && ps.t < ps.nsteps;
+}
+
+// Final separation and outputs of orbit i (written by the orbit lane).
+__device__ __forceinline__ void pair_finish(PairState& ps, const PnCoef& k, bool shadow, const FliArgs& fa,
+                                            int64_t i) {
+    const double d2 = pair_d2(ps.y, shadow);
+    const int nmax_other = swap_pair_i32(ps.nmax);
+    const int nc_other = swap_pair_i32(ps.any_nc ? 1 : 0);
     if (shadow) return;
+    const int64_t ld = fa.ld;
     const pn_scan_out& o = fa.out;
-    if (o.y_final) store_state(o.y_final, ld, i, y);
+    if (o.y_final) store_state(o.y_final, ld, i, ps.y);
     if (o.dH || o.dJ) {
         double J[3];
-        const double H = pn_energy(k, y);
-        pn_total_J(y, J);
+        const double H = pn_energy(k, ps.y);
+        pn_total_J(ps.y, J);
+        const double* ref = ps.ref;
         if (o.dH) o.dH[i] = fabs(H - ref[0]) / fabs(ref[0]);
         if (o.dJ) {
             const double ex = J[0] - ref[1], ey = J[1] - ref[2], ez = J[2] - ref[3];
@@ -305,19 +310,134 @@ __global__ __launch_bounds__(kBlock) void k_fli_scan(ParamArgs pa, FliArgs fa) {
                       sqrt(dot3(ref[1], ref[2], ref[3], ref[1], ref[2], ref[3]));
         }
     }
-    if (st == PN_ORBIT_OK) {
-        const double fli = acc + log10(sqrt(d2) / d0);
-        const double thr = (fa.thr_scaling == PN_THR_LOG_T && t_end > 0.0)
-                               ? fa.thr_at_1e5 + log10(t_end / 1e5) : fa.thr_at_1e5;
+    if (ps.st == PN_ORBIT_OK) {
+        const double fli = ps.acc + log10(sqrt(d2) / fa.d0);
+        const double thr = (fa.thr_scaling == PN_THR_LOG_T && ps.t_end > 0.0)
+                               ? fa.thr_at_1e5 + log10(ps.t_end / 1e5) : fa.thr_at_1e5;
         o.fli[i] = fli;
         o.label[i] = fli > thr ? 1 : 0;
     } else {
         o.fli[i] = __builtin_nan("");
         o.label[i] = -1;
     }
-    o.status[i] = st | ((any_nc || nc_other) ? PN_ORBIT_NEWTON_NOCONV : 0);
-    if (o.newton_max) o.newton_max[i] = max(nmax, nmax_other);
-    if (o.renorms) o.renorms[i] = renorms;
+    o.status[i] = ps.st | ((ps.any_nc || nc_other) ? PN_ORBIT_NEWTON_NOCONV : 0);
+    if (o.newton_max) o.newton_max[i] = max(ps.nmax, nmax_other);
+    if (o.renorms) o.renorms[i] = ps.renorms;
+}
+
+// Fused scan: orbit i on lanes (2i, 2i+1) from t = 0 to t_end.
+template <int METHOD, int MODE>
+__global__ __launch_bounds__(kBlock) void k_fli_scan(ParamArgs pa, FliArgs fa) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i = g >> 1;
+    if (i >= fa.n) return;                 // pairs are whole: both lanes leave together
+    const bool shadow = (g & 1) != 0;
+    PnCoef k;
+    const bool param_ok = load_coef(pa, i, k);
+    PairState ps;
+    pair_begin(ps, k, param_ok, shadow, fa, i);
+    while (pair_running(ps)) pair_step<METHOD, MODE>(ps, k, shadow, fa, i);
+    pair_finish(ps, k, shadow, fa, i);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent work-stealing batch (orbits of uneven length and parameters).
+// Workspace: queue head, bin counters, and the processing order.
+// ---------------------------------------------------------------------------
+constexpr int kBins = 256;           // 8 bins per octave of the step count
+
+struct BatchWs {
+    unsigned long long* head;        // next queue position to hand out
+    unsigned int* bins;              // kBins counters, then kBins offsets
+    int32_t* order;                  // queue position -> orbit index
+};
+
+__device__ __forceinline__ int step_bin(double t_end, double h) {
+    const double ns = t_end > 0.0 ? ceil(t_end / h) : 0.0;
+    int b = (int)floor(8.0 * log2(ns + 1.0));
+    b = b < 0 ? 0 : (b >= kBins ? kBins - 1 : b);
+    return kBins - 1 - b;            // longest first
+}
+
+__global__ __launch_bounds__(256) void k_batch_clear(BatchWs ws) {
+    const int t = threadIdx.x;
+    if (t == 0) *ws.head = 0ull;
+    for (int b = t; b < 2 * kBins; b += 256) ws.bins[b] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_batch_bin_count(BatchWs ws, const double* t_end, double h, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    atomicAdd(&ws.bins[step_bin(t_end[i], h)], 1u);
+}
+
+// Exclusive prefix sum of the bin counters into the offsets (one workgroup).
+__global__ __launch_bounds__(kBins) void k_batch_bin_scan(BatchWs ws) {
+    __shared__ unsigned int sh[kBins];
+    const int t = threadIdx.x;
+    sh[t] = ws.bins[t];
+    __syncthreads();
+    for (int off = 1; off < kBins; off <<= 1) {
+        const unsigned int v = t >= off ? sh[t - off] : 0u;
+        __syncthreads();
+        sh[t] += v;
+        __syncthreads();
+    }
+    ws.bins[kBins + t] = sh[t] - ws.bins[t];
+}
+
+__global__ __launch_bounds__(256) void k_batch_bin_scatter(BatchWs ws, const double* t_end, double h, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const unsigned int pos = atomicAdd(&ws.bins[kBins + step_bin(t_end[i], h)], 1u);
+    ws.order[pos] = (int32_t)i;
+}
+
+// Persistent kernel: every wavefront keeps 32 orbit slots busy.  Between
+// chunks of `chunk` steps, pairs whose orbit has ended write its results and
+// claim the next queue position (one atomic per wavefront), so long orbits,
+// started first, overlap with the short ones that fill the tail.  The
+// wavefront leaves when the queue is drained and all its slots are empty.
+template <int METHOD, int MODE>
+__global__ __launch_bounds__(256) void k_batch_scan(ParamArgs pa, FliArgs fa, BatchWs ws, int32_t chunk) {
+    const int lane = threadIdx.x & 63;
+    const bool shadow = (lane & 1) != 0;
+    const unsigned long long n = (unsigned long long)fa.n;
+    int64_t cur = -1;                    // orbit in this pair's slot, -1 none
+    bool drained = false;
+    PnCoef k;
+    PairState ps;
+    for (;;) {
+        // Refill empty slots: one atomic per wavefront for all claiming pairs.
+        const bool need = (cur < 0) && !drained;
+        const unsigned long long m = __ballot(need && !shadow);
+        if (m != 0ull) {
+            const int cnt = __popcll(m);
+            const int leader = __ffsll((long long)m) - 1;
+            unsigned long long base = 0ull;
+            if (lane == leader) base = atomicAdd(ws.head, (unsigned long long)cnt);
+            base = __shfl(base, leader);
+            if (need) {
+                const int even = lane & ~1;
+                const unsigned long long q = base + __popcll(m & ((1ull << even) - 1ull));
+                if (q < n) {
+                    cur = ws.order[q];
+                    const bool ok = load_coef(pa, cur, k);
+                    pair_begin(ps, k, ok, shadow, fa, cur);
+                } else {
+                    drained = true;
+                }
+            }
+        }
+        if (__ballot(cur >= 0) == 0ull) break;
+        if (cur >= 0) {
+            for (int c = 0; c < chunk && pair_running(ps); ++c) pair_step<METHOD, MODE>(ps, k, shadow, fa, cur);
+            if (!pair_running(ps)) {
+                pair_finish(ps, k, shadow, fa, cur);
+                cur = -1;
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -419,6 +539,113 @@ void launch_scan_m(int mode, const ParamArgs& pa, const FliArgs& fa, hipStream_t
         case PN_CORR_SIX: launch_scan<METHOD, PN_CORR_SIX>(pa, fa, s); break;
         default: launch_scan<METHOD, PN_CORR_DUAL>(pa, fa, s); break;
     }
+}
+
+template <int METHOD, int MODE>
+void launch_batch(const ParamArgs& pa, const FliArgs& fa, const BatchWs& ws, const pn_tuning& tu, int ncu,
+                  hipStream_t s) {
+    const unsigned blocks = (unsigned)((int64_t)ncu * 4 * tu.waves_per_simd * 64 / tu.block);
+    hipLaunchKernelGGL((k_batch_scan<METHOD, MODE>), dim3(blocks), dim3(tu.block), 0, s, pa, fa, ws,
+                       tu.chunk_steps);
+}
+
+template <int METHOD>
+void launch_batch_m(int mode, const ParamArgs& pa, const FliArgs& fa, const BatchWs& ws, const pn_tuning& tu,
+                    int ncu, hipStream_t s) {
+    switch (mode) {
+        case PN_CORR_NONE: launch_batch<METHOD, PN_CORR_NONE>(pa, fa, ws, tu, ncu, s); break;
+        case PN_CORR_SPIN: launch_batch<METHOD, PN_CORR_SPIN>(pa, fa, ws, tu, ncu, s); break;
+        case PN_CORR_SIX: launch_batch<METHOD, PN_CORR_SIX>(pa, fa, ws, tu, ncu, s); break;
+        default: launch_batch<METHOD, PN_CORR_DUAL>(pa, fa, ws, tu, ncu, s); break;
+    }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t batch_ws_bytes(int64_t n) {
+    return align256(sizeof(unsigned long long)) + align256(2 * kBins * sizeof(unsigned int)) +
+           align256((size_t)n * sizeof(int32_t));
+}
+
+BatchWs carve(void* ws, int64_t n) {
+    char* b = static_cast<char*>(ws);
+    BatchWs w;
+    w.head = reinterpret_cast<unsigned long long*>(b);
+    b += align256(sizeof(unsigned long long));
+    w.bins = reinterpret_cast<unsigned int*>(b);
+    b += align256(2 * kBins * sizeof(unsigned int));
+    w.order = reinterpret_cast<int32_t*>(b);
+    (void)n;
+    return w;
+}
+
+bool valid_tuning(const pn_tuning& t) {
+    return (t.block == 64 || t.block == 128 || t.block == 256) && t.waves_per_simd >= 1 &&
+           t.waves_per_simd <= 2 && t.chunk_steps >= 1 && t.chunk_steps <= (1 << 20);
+}
+
+// Last autotune result per device.
+pn_tuning g_tuned[64];
+bool g_has_tuned[64] = {false};
+
+int device_cus(int& dev) {
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
+    return ncu;
+}
+
+// Validation shared by the scan entry points; fills fa on success.
+pn_status prepare_scan(const pn_model* model, const pn_params& params, const pn_integrator* integ,
+                       const pn_correction* corr, const pn_fli_cfg* fli, int64_t n, const double* y0, int64_t ld,
+                       const double* t_end, double t_end_all, const pn_scan_out* out, ParamArgs& pa,
+                       FliArgs& fa) {
+    if (check_model(model) != PN_OK || check_integ(integ) != PN_OK) return PN_EINVAL;
+    if (corr == nullptr || check_corr(corr) != PN_OK) return PN_EINVAL;
+    if (fli == nullptr || out == nullptr) return PN_EINVAL;
+    if (!(n >= 0 && ld >= n)) return PN_EINVAL;
+    if (!(fli->d0 > 0.0 && is_fin(fli->d0) && fli->d_renorm > fli->d0 && is_fin(fli->d_renorm))) return PN_EINVAL;
+    if (fli->shadow_axis < 0 || fli->shadow_axis >= 12) return PN_EINVAL;
+    if (!is_fin(fli->thr_at_1e5)) return PN_EINVAL;
+    if (fli->thr_scaling != PN_THR_LITERAL && fli->thr_scaling != PN_THR_LOG_T) return PN_EINVAL;
+    if (!(fli->r_merge >= 0.0 && fli->r_esc > fli->r_merge)) return PN_EINVAL;
+    if (!(t_end != nullptr || (t_end_all >= 0.0 && is_fin(t_end_all)))) return PN_EINVAL;
+    if (make_params(model, params, pa) != PN_OK) return PN_EINVAL;
+    if (n > 0) {
+        if (!(y0 && out->fli && out->label && out->status)) return PN_EINVAL;
+        if (!(out->trace_every >= 0 && (out->trace_every == 0 || (out->trace && out->ntrace >= 0)))) return PN_EINVAL;
+    }
+    fa.h = integ->h;
+    fa.corr = corr_args(corr);
+    fa.d0 = fli->d0;
+    fa.d_renorm2 = fli->d_renorm * fli->d_renorm;
+    fa.rmerge2 = fli->r_merge * fli->r_merge;
+    fa.resc2 = fli->r_esc * fli->r_esc;
+    fa.thr_at_1e5 = fli->thr_at_1e5;
+    fa.thr_scaling = fli->thr_scaling;
+    fa.shadow_axis = fli->shadow_axis;
+    fa.t_end = t_end;
+    fa.t_end_all = t_end_all;
+    fa.out = *out;
+    fa.n = n;
+    fa.ld = ld;
+    fa.y0 = y0;
+    fa.step_scale = 1.0;
+    return PN_OK;
+}
+
+// Enqueue the whole batch: clear, bin by step count, order, persistent scan.
+void enqueue_batch(int method, int mode, const ParamArgs& pa, const FliArgs& fa, const BatchWs& w,
+                   const pn_tuning& tu, int ncu, hipStream_t stream) {
+    const unsigned g256 = (unsigned)((fa.n + 255) / 256);
+    hipLaunchKernelGGL(k_batch_clear, dim3(1), dim3(256), 0, stream, w);
+    hipLaunchKernelGGL(k_batch_bin_count, dim3(g256), dim3(256), 0, stream, w, fa.t_end, fa.h, fa.n);
+    hipLaunchKernelGGL(k_batch_bin_scan, dim3(1), dim3(kBins), 0, stream, w);
+    hipLaunchKernelGGL(k_batch_bin_scatter, dim3(g256), dim3(256), 0, stream, w, fa.t_end, fa.h, fa.n);
+    if (method == PN_RK4)
+        launch_batch_m<PN_RK4>(mode, pa, fa, w, tu, ncu, stream);
+    else
+        launch_batch_m<PN_RK5>(mode, pa, fa, w, tu, ncu, stream);
 }
 
 }  // namespace
@@ -561,43 +788,160 @@ pn_status pn_fli_scan(const pn_model* model, pn_params params, const pn_integrat
                       const pn_correction* corr, const pn_fli_cfg* fli, int64_t n, const double* y0,
                       int64_t ld, const double* t_end, double t_end_all, const pn_scan_out* out,
                       hipStream_t stream) {
-    PN_REQUIRE(check_model(model) == PN_OK);
-    PN_REQUIRE(check_integ(integ) == PN_OK);
-    PN_REQUIRE(corr != nullptr && check_corr(corr) == PN_OK);
-    PN_REQUIRE(fli != nullptr && out != nullptr);
-    PN_REQUIRE(n >= 0 && ld >= n);
-    PN_REQUIRE(fli->d0 > 0.0 && is_fin(fli->d0) && fli->d_renorm > fli->d0 && is_fin(fli->d_renorm));
-    PN_REQUIRE(fli->shadow_axis >= 0 && fli->shadow_axis < 12);
-    PN_REQUIRE(is_fin(fli->thr_at_1e5));
-    PN_REQUIRE(fli->thr_scaling == PN_THR_LITERAL || fli->thr_scaling == PN_THR_LOG_T);
-    PN_REQUIRE(fli->r_merge >= 0.0 && fli->r_esc > fli->r_merge);
-    PN_REQUIRE(t_end != nullptr || (t_end_all >= 0.0 && is_fin(t_end_all)));
     ParamArgs pa;
-    PN_REQUIRE(make_params(model, params, pa) == PN_OK);
-    if (n == 0) return PN_OK;
-    PN_REQUIRE(y0 && out->fli && out->label && out->status);
-    PN_REQUIRE(out->trace_every >= 0 && (out->trace_every == 0 || (out->trace && out->ntrace >= 0)));
     FliArgs fa;
-    fa.h = integ->h;
-    fa.corr = corr_args(corr);
-    fa.d0 = fli->d0;
-    fa.d_renorm2 = fli->d_renorm * fli->d_renorm;
-    fa.rmerge2 = fli->r_merge * fli->r_merge;
-    fa.resc2 = fli->r_esc * fli->r_esc;
-    fa.thr_at_1e5 = fli->thr_at_1e5;
-    fa.thr_scaling = fli->thr_scaling;
-    fa.shadow_axis = fli->shadow_axis;
-    fa.t_end = t_end;
-    fa.t_end_all = t_end_all;
-    fa.out = *out;
-    fa.n = n;
-    fa.ld = ld;
-    fa.y0 = y0;
+    PN_REQUIRE(prepare_scan(model, params, integ, corr, fli, n, y0, ld, t_end, t_end_all, out, pa, fa) == PN_OK);
+    if (n == 0) return PN_OK;
     if (integ->method == PN_RK4)
         launch_scan_m<PN_RK4>(corr->mode, pa, fa, stream);
     else
         launch_scan_m<PN_RK5>(corr->mode, pa, fa, stream);
     return launched("pn_fli_scan");
+}
+
+void pn_default_tuning(pn_tuning* t) {
+    if (!t) return;
+    t->block = 256;
+    t->waves_per_simd = 2;
+    t->chunk_steps = 256;
+}
+
+size_t pn_batch_workspace_size(int64_t n) { return n < 0 ? 0 : batch_ws_bytes(n); }
+
+pn_status pn_batch_scan(const pn_model* model, pn_params params, const pn_integrator* integ,
+                        const pn_correction* corr, const pn_fli_cfg* fli, int64_t n, const double* y0,
+                        int64_t ld, const double* t_end, const pn_scan_out* out, const pn_tuning* tuning,
+                        void* ws, size_t ws_bytes, hipStream_t stream) {
+    ParamArgs pa;
+    FliArgs fa;
+    PN_REQUIRE(t_end != nullptr);
+    PN_REQUIRE(n < 0x7fffffffLL);
+    PN_REQUIRE(prepare_scan(model, params, integ, corr, fli, n, y0, ld, t_end, 0.0, out, pa, fa) == PN_OK);
+    int dev = 0;
+    const int ncu = device_cus(dev);
+    if (ncu <= 0) { set_error("pn_batch_scan", hipErrorInvalidDevice); return PN_EDEVICE; }
+    pn_tuning tu;
+    if (tuning) tu = *tuning;
+    else if (dev < 64 && g_has_tuned[dev]) tu = g_tuned[dev];
+    else pn_default_tuning(&tu);
+    PN_REQUIRE(valid_tuning(tu));
+    if (n == 0) return PN_OK;
+    if (ws == nullptr || ws_bytes < batch_ws_bytes(n)) return PN_ENOWS;
+    enqueue_batch(integ->method, corr->mode, pa, fa, carve(ws, n), tu, ncu, stream);
+    return launched("pn_batch_scan");
+}
+
+pn_status pn_autotune_batch(const pn_model* model, pn_params params, const pn_integrator* integ,
+                            const pn_correction* corr, const pn_fli_cfg* fli, int64_t n, const double* y0,
+                            int64_t ld, const double* t_end, const pn_scan_out* out, double step_scale,
+                            void* ws, size_t ws_bytes, pn_tuning* best, float* best_ms, hipStream_t stream) {
+    ParamArgs pa;
+    FliArgs fa;
+    PN_REQUIRE(t_end != nullptr && best != nullptr);
+    PN_REQUIRE(step_scale > 0.0 && step_scale <= 1.0);
+    PN_REQUIRE(n < 0x7fffffffLL);
+    PN_REQUIRE(prepare_scan(model, params, integ, corr, fli, n, y0, ld, t_end, 0.0, out, pa, fa) == PN_OK);
+    int dev = 0;
+    const int ncu = device_cus(dev);
+    if (ncu <= 0) { set_error("pn_autotune_batch", hipErrorInvalidDevice); return PN_EDEVICE; }
+    pn_default_tuning(best);
+    if (n == 0) return PN_OK;
+    if (ws == nullptr || ws_bytes < batch_ws_bytes(n)) return PN_ENOWS;
+    fa.step_scale = step_scale;
+    const BatchWs w = carve(ws, n);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        set_error("pn_autotune_batch", hipErrorOutOfMemory);
+        return PN_EDEVICE;
+    }
+    const int blocks[] = {64, 256};
+    const int waves[] = {1, 2};
+    const int chunks[] = {64, 256, 1024};
+    float best_t = 1e30f;
+    pn_status st = PN_OK;
+    for (int b : blocks)
+        for (int wv : waves)
+            for (int c : chunks) {
+                pn_tuning tu;
+                tu.block = b;
+                tu.waves_per_simd = wv;
+                tu.chunk_steps = c;
+                (void)hipEventRecord(e0, stream);
+                enqueue_batch(integ->method, corr->mode, pa, fa, w, tu, ncu, stream);
+                (void)hipEventRecord(e1, stream);
+                if (launched("pn_autotune_batch") != PN_OK) { st = PN_EDEVICE; goto done; }
+                if (hipEventSynchronize(e1) != hipSuccess) { set_error("pn_autotune_batch", hipGetLastError()); st = PN_EDEVICE; goto done; }
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best_t) { best_t = ms; *best = tu; }
+            }
+    if (dev < 64) { g_tuned[dev] = *best; g_has_tuned[dev] = true; }
+    if (best_ms) *best_ms = best_t;
+done:
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+struct pn_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+pn_status pn_batch_graph_create(const pn_model* model, pn_params params, const pn_integrator* integ,
+                                const pn_correction* corr, const pn_fli_cfg* fli, int64_t n, const double* y0,
+                                int64_t ld, const double* t_end, const pn_scan_out* out,
+                                const pn_tuning* tuning, void* ws, size_t ws_bytes, pn_graph** graph) {
+    ParamArgs pa;
+    FliArgs fa;
+    PN_REQUIRE(graph != nullptr && t_end != nullptr && n > 0);
+    PN_REQUIRE(n < 0x7fffffffLL);
+    *graph = nullptr;
+    PN_REQUIRE(prepare_scan(model, params, integ, corr, fli, n, y0, ld, t_end, 0.0, out, pa, fa) == PN_OK);
+    int dev = 0;
+    const int ncu = device_cus(dev);
+    if (ncu <= 0) { set_error("pn_batch_graph_create", hipErrorInvalidDevice); return PN_EDEVICE; }
+    pn_tuning tu;
+    if (tuning) tu = *tuning;
+    else if (dev < 64 && g_has_tuned[dev]) tu = g_tuned[dev];
+    else pn_default_tuning(&tu);
+    PN_REQUIRE(valid_tuning(tu));
+    if (ws == nullptr || ws_bytes < batch_ws_bytes(n)) return PN_ENOWS;
+    hipStream_t cs;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) { set_error("pn_batch_graph_create", e); return PN_EDEVICE; }
+    pn_graph* g = new pn_graph;
+    g->graph = nullptr;
+    g->exec = nullptr;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        enqueue_batch(integ->method, corr->mode, pa, fa, carve(ws, n), tu, ncu, cs);
+        e = hipStreamEndCapture(cs, &g->graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        set_error("pn_batch_graph_create", e);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return PN_EDEVICE;
+    }
+    *graph = g;
+    return PN_OK;
+}
+
+pn_status pn_graph_launch(pn_graph* graph, hipStream_t stream) {
+    PN_REQUIRE(graph != nullptr && graph->exec != nullptr);
+    const hipError_t e = hipGraphLaunch(graph->exec, stream);
+    if (e != hipSuccess) { set_error("pn_graph_launch", e); return PN_EDEVICE; }
+    return PN_OK;
+}
+
+void pn_graph_destroy(pn_graph* graph) {
+    if (!graph) return;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
 }
 
 }  // extern "C"

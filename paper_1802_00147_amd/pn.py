@@ -64,11 +64,17 @@ class ScanOut(ctypes.Structure):
                 ("trace", ctypes.c_void_p), ("trace_every", ctypes.c_int64), ("ntrace", ctypes.c_int64)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32), ("chunk_steps", ctypes.c_int32)]
+
+
 _lib = None
 
 # Every symbol include/pn.h declares.
 EXPORTS = ["pn_default_model", "pn_default_integrator", "pn_default_correction", "pn_default_fli_cfg",
            "pn_init_state", "pn_rhs", "pn_invariants", "pn_manifold_correct", "pn_step", "pn_fli_scan",
+           "pn_default_tuning", "pn_batch_workspace_size", "pn_batch_scan", "pn_autotune_batch",
+           "pn_batch_graph_create", "pn_graph_launch", "pn_graph_destroy",
            "pn_version", "pn_status_string", "pn_last_error"]
 
 
@@ -83,8 +89,12 @@ def lib():
         L.pn_last_error.restype = ctypes.c_char_p
         L.pn_version.restype = ctypes.c_int32
         for name in ("pn_init_state", "pn_rhs", "pn_invariants", "pn_manifold_correct", "pn_step",
-                     "pn_fli_scan"):
+                     "pn_fli_scan", "pn_batch_scan", "pn_autotune_batch", "pn_batch_graph_create",
+                     "pn_graph_launch"):
             getattr(L, name).restype = ctypes.c_int
+        L.pn_batch_workspace_size.restype = ctypes.c_size_t
+        L.pn_batch_workspace_size.argtypes = [ctypes.c_int64]
+        L.pn_graph_destroy.argtypes = [ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -266,3 +276,112 @@ def fli_scan(y0, t_end, beta, chi1, chi2, model=None, integrator=None, correctio
                            ctypes.byref(so), _stream(y0.device))
     _check("pn_fli_scan", st)
     return out
+
+
+def tuning_struct(over=None):
+    t = _defaults(Tuning, "pn_default_tuning")
+    for k, v in (over or {}).items():
+        setattr(t, k, int(v))
+    return t
+
+
+def batch_workspace(n, device):
+    nbytes = int(lib().pn_batch_workspace_size(ctypes.c_int64(n)))
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+def _scan_out_struct(out):
+    return ScanOut(*[out[k].data_ptr() if k in out else None
+                     for k in ("fli", "label", "status", "y_final", "dH", "dJ", "newton_max", "renorms", "trace")],
+                   int(out.get("trace_every", 0)), int(out["trace"].shape[0]) if "trace" in out else 0)
+
+
+def _batch_common(y0, t_end, beta, chi1, chi2, model, integrator, correction, fli, out, n, full, trace_every, ws):
+    ld = _state(y0)
+    n = ld if n is None else n
+    integ = integrator_struct(integrator)
+    assert isinstance(t_end, torch.Tensor), "batch scans take per-orbit end times"
+    t_end = _dev_f64(t_end, n)
+    if out is None:
+        tmax = float(t_end[:n].max()) if n > 0 else 0.0
+        nmax = int(-(-tmax // integ.h)) if tmax > 0 else 0
+        out = scan_outputs(n, ld, y0.device, full=full, trace_every=trace_every, nsteps_max=nmax)
+    if ws is None:
+        ws = batch_workspace(n, y0.device)
+    p, keep = params_struct(beta, chi1, chi2)
+    return ld, n, integ, t_end, out, ws, p, keep
+
+
+def batch_scan(y0, t_end, beta, chi1, chi2, model=None, integrator=None, correction=None, fli=None, out=None,
+               n=None, full=True, trace_every=0, tuning=None, ws=None):
+    """Persistent work-stealing scan of orbits with per-orbit t_end (tensor).
+    tuning: dict or Tuning (None: the device's autotuned or default shape)."""
+    ld, n, integ, t_end, out, ws, p, keep = _batch_common(y0, t_end, beta, chi1, chi2, model, integrator,
+                                                          correction, fli, out, n, full, trace_every, ws)
+    tu = None
+    if tuning is not None:
+        tu = ctypes.byref(tuning if isinstance(tuning, Tuning) else tuning_struct(tuning))
+    so = _scan_out_struct(out)
+    st = lib().pn_batch_scan(ctypes.byref(model_struct(model)), p, ctypes.byref(integ),
+                             ctypes.byref(correction_struct(correction)), ctypes.byref(fli_struct(fli)),
+                             ctypes.c_int64(n), _ptr(y0), ctypes.c_int64(ld), _ptr(t_end), ctypes.byref(so), tu,
+                             _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(y0.device))
+    _check("pn_batch_scan", st)
+    return out
+
+
+def autotune_batch(y0, t_end, beta, chi1, chi2, model=None, integrator=None, correction=None, fli=None,
+                   step_scale=0.01, n=None, ws=None, out=None):
+    """Run the library's autotuner; returns (tuning dict, best trial ms)."""
+    ld, n, integ, t_end, out, ws, p, keep = _batch_common(y0, t_end, beta, chi1, chi2, model, integrator,
+                                                          correction, fli, out, n, True, 0, ws)
+    best = Tuning()
+    ms = ctypes.c_float(0.0)
+    so = _scan_out_struct(out)
+    st = lib().pn_autotune_batch(ctypes.byref(model_struct(model)), p, ctypes.byref(integ),
+                                 ctypes.byref(correction_struct(correction)), ctypes.byref(fli_struct(fli)),
+                                 ctypes.c_int64(n), _ptr(y0), ctypes.c_int64(ld), _ptr(t_end), ctypes.byref(so),
+                                 ctypes.c_double(step_scale), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                                 ctypes.byref(best), ctypes.byref(ms), _stream(y0.device))
+    _check("pn_autotune_batch", st)
+    return dict(block=best.block, waves_per_simd=best.waves_per_simd, chunk_steps=best.chunk_steps), ms.value
+
+
+class BatchGraph:
+    """A batch scan captured once into a HIP graph; replay() relaunches it on
+    the current stream with the buffers it was created with."""
+
+    def __init__(self, y0, t_end, beta, chi1, chi2, model=None, integrator=None, correction=None, fli=None,
+                 out=None, n=None, full=True, tuning=None, ws=None):
+        ld, n, integ, t_end, out, ws, p, keep = _batch_common(y0, t_end, beta, chi1, chi2, model, integrator,
+                                                              correction, fli, out, n, full, 0, ws)
+        self._keep = (y0, t_end, ws, keep)
+        self.out = out
+        tu = None
+        if tuning is not None:
+            tu = ctypes.byref(tuning if isinstance(tuning, Tuning) else tuning_struct(tuning))
+        so = _scan_out_struct(out)
+        g = ctypes.c_void_p()
+        st = lib().pn_batch_graph_create(ctypes.byref(model_struct(model)), p, ctypes.byref(integ),
+                                         ctypes.byref(correction_struct(correction)), ctypes.byref(fli_struct(fli)),
+                                         ctypes.c_int64(n), _ptr(y0), ctypes.c_int64(ld), _ptr(t_end),
+                                         ctypes.byref(so), tu, _ptr(ws), ctypes.c_size_t(ws.numel()),
+                                         ctypes.byref(g))
+        _check("pn_batch_graph_create", st)
+        self._g = g
+        self._device = y0.device
+
+    def replay(self):
+        _check("pn_graph_launch", lib().pn_graph_launch(self._g, _stream(self._device)))
+        return self.out
+
+    def close(self):
+        if self._g:
+            lib().pn_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
