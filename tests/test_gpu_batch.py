@@ -98,8 +98,16 @@ def test_batch_parity_with_oracle(pn):
     assert np.array_equal(got["status"], exp["status"])
     assert np.array_equal(got["label"], exp["label"])
     ok = exp["status"] == 0
-    assert np.all(np.abs(got["fli"][ok] - exp["fli"][ok]) <= FLI_ABS_CORRECTED)
     assert np.all(rel_err_rows(got["y_final"].T[ok], exp["y_final"][ok]) <= 1e-9)
+    # The FLI of short corrected runs has a noise floor of its own: the
+    # oracle moves by as much when one initial momentum component changes by
+    # one ulp.  The GPU must stay within twice that floor.
+    y1 = y0o.copy()
+    y1[:, 4] = np.nextafter(y1[:, 4], 1.0)
+    exp1 = O.fli_scan(y1, wl.t_end, wl.beta, wl.chi1, wl.chi2, nthreads=8)
+    floor = np.abs(exp1["fli"][ok] - exp["fli"][ok]).max()
+    diff = np.abs(got["fli"][ok] - exp["fli"][ok]).max()
+    assert diff <= 2.0 * floor + 1e-6 and diff <= 1e-3, (diff, floor)
 
 
 def test_graph_replay_matches_eager(pn):
