@@ -280,6 +280,99 @@ pn_status pn_batch_graph_create(const pn_model* model, pn_params params, const p
 pn_status pn_graph_launch(pn_graph* graph, hipStream_t stream);
 void pn_graph_destroy(pn_graph* graph);
 
+/* ---------------------------------------------------------------------------
+ * Learned surrogate: a multilayer perceptron 7 -> 256 -> 256 -> 256 -> 2
+ * (ReLU) that maps scan-point features to (chaos logit, FLI - log10 t_end),
+ * trained on FLIs the scan itself produced, with integration as fallback.
+ * Matrix products: bfloat16 operands, FP32 accumulation on MFMA.
+ * ------------------------------------------------------------------------- */
+
+/* Device buffers of the network, all owned by the caller.  Layer l (0..3) has
+ * in_l = 7, 256, 256, 256 inputs and out_l = 256, 256, 256, 2 outputs.
+ *   w[l]  FP32 master weights [out_l][in_l] row-major;  b[l]  FP32 biases [out_l]
+ *   wb[l] bfloat16 copies of w[l] (bit patterns, uint16) read by the products
+ *   mw, vw, mb, vb  Adam first/second moments of w and b (training only). */
+typedef struct {
+    float* w[4];
+    float* b[4];
+    uint16_t* wb[4];
+    float* mw[4];
+    float* vw[4];
+    float* mb[4];
+    float* vb[4];
+} pn_mlp;
+
+/* Elements of layer l's weights (which = 0) or biases (which = 1); 0 if l is
+ * out of range. */
+size_t pn_mlp_param_count(int32_t layer, int32_t which);
+
+/* Refresh wb[] from w[] (round to nearest even bfloat16). */
+pn_status pn_mlp_sync_bf16(pn_mlp* net, hipStream_t stream);
+
+/* Standardised features of scan points into feat [n][8] (FP32, column 7 = 0):
+ * (beta, chi1, chi2, r0, cos th1, cos th2, log10 t_end), each (x - mean[c]) /
+ * stdv[c] with host arrays mean[7], stdv[7] (stdv > 0).  Point j takes row idx[j]
+ * of the parameter arrays (idx NULL: row j).  t_end: [rows] array or NULL for
+ * t_end_all > 0. */
+pn_status pn_mlp_features(pn_params params, int64_t n, const double* r0, const double* th1,
+                          const double* th2, const double* t_end, double t_end_all,
+                          const int32_t* idx, const float* mean, const float* stdv, float* feat,
+                          hipStream_t stream);
+
+/* Training targets from a scan's outputs: lab[i] = 1 if label[i] == 1 else 0,
+ * target[i] = fli[i] - log10 t_end (0 where the FLI is not finite).  t_end:
+ * [n] array or NULL for t_end_all > 0. */
+pn_status pn_mlp_targets(const double* fli, const int8_t* label, const double* t_end, double t_end_all,
+                         int64_t n, float* lab, float* target, hipStream_t stream);
+
+/* Bytes of workspace for one training step of `batch` samples. */
+size_t pn_mlp_train_workspace_size(int32_t batch);
+
+/* One training step on rows idx[0..batch) of feat [rows][8], label [rows]
+ * (1 chaotic, 0 regular) and target [rows] (FLI - log10 t_end): forward,
+ * loss (binary cross-entropy of output 0 + Huber, delta 1, of output 1,
+ * mean over the batch), backward, and an Adam update (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias correction for step >= 1) of w and b, with wb refreshed.
+ * The batch's mean loss is ADDED to the device scalar *loss. */
+pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, const float* target,
+                            const int32_t* idx, int32_t batch, int32_t step, float lr, float* loss,
+                            void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Bytes of workspace for inference in chunks of `chunk` rows. */
+size_t pn_mlp_infer_workspace_size(int64_t chunk);
+
+/* Network outputs out [n][2] (FP32) for feat [n][8], `chunk` rows at a time. */
+pn_status pn_mlp_infer(const pn_mlp* net, const float* feat, int64_t n, float* out, int64_t chunk,
+                       void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Gate of the surrogate-assisted scan: label[i] = (out[i][0] > 0), fli_pred[i]
+ * = out[i][1] (nullable), and every point with |logit| < margin or drawn for
+ * the audit (SplitMix64(seed + i) / 2^64 < audit_frac) appended to list[]
+ * (order unspecified); *count (device) receives the number appended. */
+pn_status pn_surrogate_gate(const float* out, int64_t n, float margin, double audit_frac,
+                            uint64_t seed, int8_t* label, float* fli_pred, int32_t* list,
+                            unsigned long long* count, hipStream_t stream);
+
+/* label[list[j]] = integrated[j] for j < m (the integrated labels win). */
+pn_status pn_surrogate_merge(const int32_t* list, int64_t m, const int8_t* integrated, int8_t* label,
+                             hipStream_t stream);
+
+/* The matrix-core product used above, exposed for testing:
+ * C = A B (+ bias[n]) (ReLU if relu) (times [mask(m,n) > 0] if mask), M x N,
+ * A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn] (bfloat16 bit
+ * patterns), FP32 accumulation; Cf (FP32, ld ldcf) and/or Cb (bfloat16). */
+pn_status pn_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, int64_t sam, int64_t sak,
+                       const uint16_t* B, int64_t sbk, int64_t sbn, const float* bias, int32_t relu,
+                       const uint16_t* mask, int64_t ldm, float* Cf, int64_t ldcf, uint16_t* Cb,
+                       int64_t ldcb, hipStream_t stream);
+
+/* Initial states of selected points: like pn_init_state, but point j takes
+ * row idx[j] of r0, p0, th1, ph1, th2, ph2 (and of per-orbit parameters). */
+pn_status pn_init_state_gather(const pn_model* model, pn_params params, int64_t m, const int32_t* idx,
+                               const double* r0, const double* p0, const double* th1,
+                               const double* ph1, const double* th2, const double* ph2, double* y0,
+                               int64_t ld, hipStream_t stream);
+
 /* Library version and last error text (thread-local; "" when none). */
 int32_t pn_version(void);
 const char* pn_status_string(pn_status s);

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpn_hip.so")
-SOURCES = [os.path.join(CSRC, "pn_kernels.hip")]
+SOURCES = [os.path.join(CSRC, "pn_kernels.hip"), os.path.join(CSRC, "pn_mlp.hip")]
 HEADERS = [os.path.join(CSRC, "pn_device.h"), os.path.join(ROOT, "include", "pn.h")]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-shared", "-fPIC",
@@ -28,11 +28,13 @@ def build(verbose: bool = False, extra=None) -> str:
 
 def resource_usage() -> str:
     """Per-kernel VGPR/AGPR/SGPR/scratch/occupancy report from the compiler."""
-    cmd = ["hipcc"] + FLAGS[:-4] + ["-c", "-o", os.devnull, "-Rpass-analysis=kernel-resource-usage",
-                                    "--cuda-device-only", "-I", os.path.join(ROOT, "include"), "-I", CSRC] + SOURCES
-    cmd = [c for c in cmd if c not in ("-shared", "-fPIC")]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    return r.stderr
+    out = []
+    for src in SOURCES:
+        cmd = ["hipcc"] + FLAGS[:-4] + ["-c", "-o", os.devnull, "-Rpass-analysis=kernel-resource-usage",
+                                        "--cuda-device-only", "-I", os.path.join(ROOT, "include"), "-I", CSRC, src]
+        cmd = [c for c in cmd if c not in ("-shared", "-fPIC")]
+        out.append(subprocess.run(cmd, capture_output=True, text=True).stderr)
+    return "\n".join(out)
 
 
 if __name__ == "__main__":

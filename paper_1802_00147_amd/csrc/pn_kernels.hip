@@ -60,12 +60,13 @@ __device__ __forceinline__ void capture_ref(const PnCoef& k, const double* y, do
 // ---------------------------------------------------------------------------
 // Kernels.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_init_state(ParamArgs pa, int64_t n, const double* r0,
-                                                      const double* p0, const double* th1,
+__global__ __launch_bounds__(kBlock) void k_init_state(ParamArgs pa, int64_t n, const int32_t* idx,
+                                                      const double* r0, const double* p0, const double* th1,
                                                       const double* ph1, const double* th2,
                                                       const double* ph2, double* y, int64_t ld) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    const int64_t i = idx ? (int64_t)idx[j] : j;   // row of the inputs; output column j
     PnCoef k;
     load_coef(pa, i, k);
     double s[12];
@@ -78,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_init_state(ParamArgs pa, int64_t n, 
     sincos(th2[i], &sa, &ca);
     sincos(ph2[i], &sb, &cb);
     s[9] = k.s2 * sa * cb; s[10] = k.s2 * sa * sb; s[11] = k.s2 * ca;
-    store_state(y, ld, i, s);
+    store_state(y, ld, j, s);
 }
 
 __global__ __launch_bounds__(kBlock) void k_rhs(ParamArgs pa, int64_t n, const double* y, int64_t ld,
@@ -714,9 +715,24 @@ pn_status pn_init_state(const pn_model* model, pn_params params, int64_t n, cons
     PN_REQUIRE(make_params(model, params, pa) == PN_OK);
     if (n == 0) return PN_OK;
     PN_REQUIRE(r0 && p0 && th1 && ph1 && th2 && ph2 && y0);
-    hipLaunchKernelGGL(k_init_state, dim3(grid_for(n)), dim3(kBlock), 0, stream, pa, n, r0, p0, th1, ph1,
-                       th2, ph2, y0, ld);
+    hipLaunchKernelGGL(k_init_state, dim3(grid_for(n)), dim3(kBlock), 0, stream, pa, n,
+                       (const int32_t*)nullptr, r0, p0, th1, ph1, th2, ph2, y0, ld);
     return launched("pn_init_state");
+}
+
+pn_status pn_init_state_gather(const pn_model* model, pn_params params, int64_t m, const int32_t* idx,
+                               const double* r0, const double* p0, const double* th1, const double* ph1,
+                               const double* th2, const double* ph2, double* y0, int64_t ld,
+                               hipStream_t stream) {
+    PN_REQUIRE(check_model(model) == PN_OK);
+    PN_REQUIRE(m >= 0 && ld >= m);
+    ParamArgs pa;
+    PN_REQUIRE(make_params(model, params, pa) == PN_OK);
+    if (m == 0) return PN_OK;
+    PN_REQUIRE(idx && r0 && p0 && th1 && ph1 && th2 && ph2 && y0);
+    hipLaunchKernelGGL(k_init_state, dim3(grid_for(m)), dim3(kBlock), 0, stream, pa, m, idx, r0, p0, th1, ph1,
+                       th2, ph2, y0, ld);
+    return launched("pn_init_state_gather");
 }
 
 pn_status pn_rhs(const pn_model* model, pn_params params, int64_t n, const double* y, int64_t ld,

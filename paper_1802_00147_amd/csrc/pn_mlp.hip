@@ -1,0 +1,490 @@
+// pn_mlp.hip -- learned surrogate of the FLI scan: a 7-256-256-256-2 ReLU
+// multilayer perceptron trained and evaluated on gfx950 matrix cores.
+//
+// Every matrix product runs in one hand-written kernel, k_gemm_bf16: bfloat16
+// operands, FP32 accumulation on v_mfma_f32_16x16x32_bf16, 64x64 output tiles
+// per 256-thread workgroup (each wavefront a 32x32 quarter as 2x2 MFMA
+// tiles), operands staged through LDS with K contiguous so that a lane reads
+// its eight K values with one 16-byte LDS load, and fused epilogues (bias,
+// ReLU, ReLU-mask of the backward pass, FP32 and/or bfloat16 stores).
+// Arbitrary strides let the same kernel form X W^T, G W and G^T H.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+
+#include "pn.h"
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 32, LDSK = BK + 8;
+constexpr int kIn[4] = {7, 256, 256, 256};
+constexpr int kOut[4] = {256, 256, 256, 2};
+constexpr int kFeatLd = 8;     // feature rows are padded to 8 values
+
+thread_local char g_mlp_error[256] = "";
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;   // NaN stays NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                        // round to nearest, ties to even
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+struct GemmArgs {
+    int M, N, K;
+    const uint16_t* A;
+    int64_t sam, sak;          // A(m, k) = A[m * sam + k * sak]
+    const uint16_t* B;
+    int64_t sbk, sbn;          // B(k, n) = B[k * sbk + n * sbn]
+    const float* bias;         // [N] or null
+    const uint16_t* mask;      // ReLU mask source [M x N] (value > 0 keeps), or null
+    int64_t ldm;
+    float* Cf;                 // FP32 result or null
+    int64_t ldcf;
+    uint16_t* Cb;              // bfloat16 result or null
+    int64_t ldcb;
+    int relu;
+};
+
+// C = A B (+ bias) (ReLU) (* mask), M x N, FP32 accumulation.
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[BM][LDSK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bt[BN][LDSK];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int lr = lane & 15, lk = (lane >> 4) * 8;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+#pragma unroll
+        for (int e = tid; e < BM * BK; e += 256) {
+            const int r = e / BK, c = e % BK;
+            const int64_t m = m0 + r, k = k0 + c;
+            As[r][c] = (m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : (uint16_t)0;
+        }
+#pragma unroll
+        for (int e = tid; e < BN * BK; e += 256) {
+            const int r = e / BK, c = e % BK;
+            const int64_t n = n0 + r, k = k0 + c;
+            Bt[r][c] = (n < g.N && k < g.K) ? g.B[k * g.sbk + n * g.sbn] : (uint16_t)0;
+        }
+        __syncthreads();
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * i + lr][lk]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bt[wn + 16 * j + lr][lk]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // Accumulator layout: element v of lane l is row 4 (l / 16) + v, column l % 16.
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t m = m0 + wm + 16 * i + (lane >> 4) * 4 + v;
+                const int64_t n = n0 + wn + 16 * j + lr;
+                if (m >= g.M || n >= g.N) continue;
+                float x = acc[i][j][v];
+                if (g.bias) x += g.bias[n];
+                if (g.relu) x = fmaxf(x, 0.0f);
+                if (g.mask && !(bf2f(g.mask[m * g.ldm + n]) > 0.0f)) x = 0.0f;
+                if (g.Cf) g.Cf[m * g.ldcf + n] = x;
+                if (g.Cb) g.Cb[m * g.ldcb + n] = f2bf(x);
+            }
+}
+
+// Rows idx[b] (or b) of the FP32 features -> bfloat16 [rows x 8].
+__global__ __launch_bounds__(256) void k_gather_rows(const float* feat, const int32_t* idx, int64_t rows,
+                                                     int64_t row0, uint16_t* X) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= rows * kFeatLd) return;
+    const int64_t b = e / kFeatLd;
+    const int c = (int)(e % kFeatLd);
+    const int64_t r = idx ? (int64_t)idx[b] : row0 + b;
+    X[e] = c < 7 ? f2bf(feat[r * kFeatLd + c]) : (uint16_t)0;
+}
+
+// Loss of a batch and its gradient with respect to the two outputs:
+// binary cross-entropy of the logit + Huber (delta 1) of the FLI output.
+__global__ __launch_bounds__(256) void k_loss(const float* out, const float* label, const float* target,
+                                              const int32_t* idx, int B, uint16_t* gout, float* loss) {
+    __shared__ float part[256];
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    float l = 0.0f;
+    if (b < B) {
+        const int r = idx[b];
+        const float z = out[2 * b], f = out[2 * b + 1];
+        const float y = label[r], t = target[r];
+        l = fmaxf(z, 0.0f) - y * z + log1pf(expf(-fabsf(z)));
+        const float d = f - t;
+        l += fabsf(d) <= 1.0f ? 0.5f * d * d : fabsf(d) - 0.5f;
+        const float sig = 1.0f / (1.0f + expf(-z));
+        gout[2 * b] = f2bf((sig - y) / (float)B);
+        gout[2 * b + 1] = f2bf(fminf(fmaxf(d, -1.0f), 1.0f) / (float)B);
+    }
+    part[threadIdx.x] = l;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(loss, part[0] / (float)B);
+}
+
+// db[n] = sum over rows of the bfloat16 gradient G [rows x N] (one block per n).
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* G, int64_t rows, int N, int64_t ldg, float* db) {
+    __shared__ float part[256];
+    const int n = blockIdx.x;
+    float s = 0.0f;
+    for (int64_t m = threadIdx.x; m < rows; m += 256) s += bf2f(G[m * ldg + n]);
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) part[threadIdx.x] += part[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[n] = part[0];
+}
+
+struct AdamArgs {
+    float* w;
+    const float* g;
+    float* m;
+    float* v;
+    uint16_t* wb;   // bfloat16 copy (null for biases)
+    int64_t n;
+    float lr, c1, c2;   // c1 = 1 - b1^t, c2 = 1 - b2^t
+};
+
+__global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= a.n) return;
+    const float g = a.g[e];
+    const float m = 0.9f * a.m[e] + 0.1f * g;
+    const float v = 0.999f * a.v[e] + 0.001f * g * g;
+    a.m[e] = m;
+    a.v[e] = v;
+    const float w = a.w[e] - a.lr * (m / a.c1) / (sqrtf(v / a.c2) + 1e-8f);
+    a.w[e] = w;
+    if (a.wb) a.wb[e] = f2bf(w);
+}
+
+__global__ __launch_bounds__(256) void k_to_bf16(const float* x, int64_t n, uint16_t* y) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < n) y[e] = f2bf(x[e]);
+}
+
+// Standardised features of scan points: (beta, chi1, chi2, r0, cos th1,
+// cos th2, log10 t_end), each (x - mean) / std; column 7 is zero padding.
+struct FeatArgs {
+    const double *beta, *chi1, *chi2;
+    double beta0, chi1_0, chi2_0;
+    const double *r0, *th1, *th2, *t_end;
+    double t_end_all;
+    const int32_t* idx;     // rows to take (null: all)
+    int64_t n;
+    float mean[7], stdv[7];
+    float* feat;
+};
+
+__global__ __launch_bounds__(256) void k_features(FeatArgs f) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= f.n) return;
+    const int64_t i = f.idx ? (int64_t)f.idx[j] : j;
+    double x[7];
+    x[0] = f.beta ? f.beta[i] : f.beta0;
+    x[1] = f.chi1 ? f.chi1[i] : f.chi1_0;
+    x[2] = f.chi2 ? f.chi2[i] : f.chi2_0;
+    x[3] = f.r0[i];
+    x[4] = cos(f.th1[i]);
+    x[5] = cos(f.th2[i]);
+    x[6] = log10(f.t_end ? f.t_end[i] : f.t_end_all);
+#pragma unroll
+    for (int c = 0; c < 7; ++c) f.feat[j * kFeatLd + c] = (float)((x[c] - f.mean[c]) / f.stdv[c]);
+    f.feat[j * kFeatLd + 7] = 0.0f;
+}
+
+// Training targets from a scan: label 1.0 chaotic / 0.0 otherwise, and the
+// FLI relative to log10 t_end (0 for orbits whose FLI is not finite).
+__global__ __launch_bounds__(256) void k_targets(const double* fli, const int8_t* label, const double* t_end,
+                                                 double t_end_all, int64_t n, float* lab, float* target) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    lab[i] = label[i] == 1 ? 1.0f : 0.0f;
+    const double t = t_end ? t_end[i] : t_end_all;
+    const double f = fli[i];
+    target[i] = isfinite(f) ? (float)(f - log10(t)) : 0.0f;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): the audit draw of point i.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+
+__global__ void k_clear_count(unsigned long long* c) { *c = 0ull; }
+
+// Surrogate label sign(logit); points with |logit| < margin or drawn for the
+// audit (SplitMix64(seed + i) / 2^64 < audit) join the integration list.
+__global__ __launch_bounds__(256) void k_gate(const float* out, int64_t n, float margin, double audit,
+                                              unsigned long long seed, int8_t* label, float* fli_pred,
+                                              int32_t* list, unsigned long long* count) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float z = out[2 * i];
+    label[i] = z > 0.0f ? 1 : 0;
+    if (fli_pred) fli_pred[i] = out[2 * i + 1];
+    const double u = (double)(splitmix64(seed + (uint64_t)i) >> 11) * 0x1.0p-53;
+    if (fabsf(z) < margin || u < audit) {
+        const unsigned long long pos = atomicAdd(count, 1ull);
+        list[pos] = (int32_t)i;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_merge(const int32_t* list, int64_t m, const int8_t* integrated,
+                                               int8_t* label) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j < m) label[list[j]] = integrated[j];
+}
+
+unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+void gemm(hipStream_t s, int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B,
+          int64_t sbk, int64_t sbn, const float* bias, int relu, const uint16_t* mask, int64_t ldm, float* Cf,
+          int64_t ldcf, uint16_t* Cb, int64_t ldcb) {
+    GemmArgs g;
+    g.M = M; g.N = N; g.K = K;
+    g.A = A; g.sam = sam; g.sak = sak;
+    g.B = B; g.sbk = sbk; g.sbn = sbn;
+    g.bias = bias; g.relu = relu; g.mask = mask; g.ldm = ldm;
+    g.Cf = Cf; g.ldcf = ldcf; g.Cb = Cb; g.ldcb = ldcb;
+    hipLaunchKernelGGL(k_gemm_bf16, dim3(blocks_for(N, BN), blocks_for(M, BM)), dim3(256), 0, s, g);
+}
+
+pn_status launched(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        std::snprintf(g_mlp_error, sizeof(g_mlp_error), "%s: %s", what, hipGetErrorString(e));
+        return PN_EDEVICE;
+    }
+    return PN_OK;
+}
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool net_ok(const pn_mlp* net, bool training) {
+    if (!net) return false;
+    for (int l = 0; l < 4; ++l) {
+        if (!net->w[l] || !net->b[l] || !net->wb[l]) return false;
+        if (training && (!net->mw[l] || !net->vw[l] || !net->mb[l] || !net->vb[l])) return false;
+    }
+    return true;
+}
+
+// Forward pass of rows [0, rows) whose bfloat16 inputs are in X (ld 8).
+void forward(hipStream_t s, const pn_mlp* net, int64_t rows, const uint16_t* X, uint16_t* h1, uint16_t* h2,
+             uint16_t* h3, float* out) {
+    const int M = (int)rows;
+    gemm(s, M, 256, 7, X, kFeatLd, 1, net->wb[0], 1, 7, net->b[0], 1, nullptr, 0, nullptr, 0, h1, 256);
+    gemm(s, M, 256, 256, h1, 256, 1, net->wb[1], 1, 256, net->b[1], 1, nullptr, 0, nullptr, 0, h2, 256);
+    gemm(s, M, 256, 256, h2, 256, 1, net->wb[2], 1, 256, net->b[2], 1, nullptr, 0, nullptr, 0, h3, 256);
+    gemm(s, M, 2, 256, h3, 256, 1, net->wb[3], 1, 256, net->b[3], 0, nullptr, 0, out, 2, nullptr, 0);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pn_mlp_param_count(int32_t layer, int32_t which) {
+    if (layer < 0 || layer > 3) return 0;
+    return which == 0 ? (size_t)kIn[layer] * kOut[layer] : (size_t)kOut[layer];
+}
+
+size_t pn_mlp_train_workspace_size(int32_t batch) {
+    if (batch <= 0) return 0;
+    const size_t B = (size_t)batch;
+    return al(B * kFeatLd * 2) + 3 * al(B * 256 * 2) + al(B * 2 * 4) + al(B * 2 * 2) + 2 * al(B * 256 * 2) +
+           al(256 * 256 * 4) * 2 + al(256 * 7 * 4) + al(2 * 256 * 4) + 4 * al(256 * 4);
+}
+
+pn_status pn_mlp_sync_bf16(pn_mlp* net, hipStream_t stream) {
+    if (!net_ok(net, false)) return PN_EINVAL;
+    for (int l = 0; l < 4; ++l) {
+        const int64_t n = (int64_t)kIn[l] * kOut[l];
+        hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(n, 256)), dim3(256), 0, stream, net->w[l], n, net->wb[l]);
+    }
+    return launched("pn_mlp_sync_bf16");
+}
+
+pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, const float* target,
+                            const int32_t* idx, int32_t batch, int32_t step, float lr, float* loss,
+                            void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!net_ok(net, true) || !feat || !label || !target || !idx || !loss) return PN_EINVAL;
+    if (batch <= 0 || step < 1 || !(lr > 0.0f) || !std::isfinite(lr)) return PN_EINVAL;
+    if (!ws || ws_bytes < pn_mlp_train_workspace_size(batch)) return PN_ENOWS;
+    const int B = batch;
+    char* p = static_cast<char*>(ws);
+    auto take = [&](size_t bytes) { char* q = p; p += al(bytes); return q; };
+    uint16_t* X = (uint16_t*)take((size_t)B * kFeatLd * 2);
+    uint16_t* h[3];
+    for (int l = 0; l < 3; ++l) h[l] = (uint16_t*)take((size_t)B * 256 * 2);
+    float* out = (float*)take((size_t)B * 2 * 4);
+    uint16_t* g4 = (uint16_t*)take((size_t)B * 2 * 2);
+    uint16_t* gA = (uint16_t*)take((size_t)B * 256 * 2);
+    uint16_t* gB = (uint16_t*)take((size_t)B * 256 * 2);
+    float* dW[4];
+    dW[1] = (float*)take(256 * 256 * 4);
+    dW[2] = (float*)take(256 * 256 * 4);
+    dW[0] = (float*)take(256 * 7 * 4);
+    dW[3] = (float*)take(2 * 256 * 4);
+    float* db[4];
+    for (int l = 0; l < 4; ++l) db[l] = (float*)take(256 * 4);
+    hipStream_t s = stream;
+
+    hipLaunchKernelGGL(k_gather_rows, dim3(blocks_for((int64_t)B * kFeatLd, 256)), dim3(256), 0, s, feat, idx,
+                       (int64_t)B, (int64_t)0, X);
+    forward(s, net, B, X, h[0], h[1], h[2], out);
+    hipLaunchKernelGGL(k_loss, dim3(blocks_for(B, 256)), dim3(256), 0, s, out, label, target, idx, B, g4, loss);
+    // Layer 4: dW4 = g4^T h3, db4, g3 = (g4 W4) * (h3 > 0).
+    gemm(s, 2, 256, B, g4, 1, 2, h[2], 256, 1, nullptr, 0, nullptr, 0, dW[3], 256, nullptr, 0);
+    hipLaunchKernelGGL(k_bias_grad, dim3(2), dim3(256), 0, s, g4, (int64_t)B, 2, (int64_t)2, db[3]);
+    gemm(s, B, 256, 2, g4, 2, 1, net->wb[3], 256, 1, nullptr, 0, h[2], 256, nullptr, 0, gA, 256);
+    // Layer 3.
+    gemm(s, 256, 256, B, gA, 1, 256, h[1], 256, 1, nullptr, 0, nullptr, 0, dW[2], 256, nullptr, 0);
+    hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, s, gA, (int64_t)B, 256, (int64_t)256, db[2]);
+    gemm(s, B, 256, 256, gA, 256, 1, net->wb[2], 256, 1, nullptr, 0, h[1], 256, nullptr, 0, gB, 256);
+    // Layer 2.
+    gemm(s, 256, 256, B, gB, 1, 256, h[0], 256, 1, nullptr, 0, nullptr, 0, dW[1], 256, nullptr, 0);
+    hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, s, gB, (int64_t)B, 256, (int64_t)256, db[1]);
+    gemm(s, B, 256, 256, gB, 256, 1, net->wb[1], 256, 1, nullptr, 0, h[0], 256, nullptr, 0, gA, 256);
+    // Layer 1.
+    gemm(s, 256, 7, B, gA, 1, 256, X, kFeatLd, 1, nullptr, 0, nullptr, 0, dW[0], 7, nullptr, 0);
+    hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, s, gA, (int64_t)B, 256, (int64_t)256, db[0]);
+    // Adam on the FP32 master weights, refreshing the bfloat16 copies.
+    const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
+    for (int l = 0; l < 4; ++l) {
+        AdamArgs a;
+        a.w = net->w[l]; a.g = dW[l]; a.m = net->mw[l]; a.v = net->vw[l]; a.wb = net->wb[l];
+        a.n = (int64_t)kIn[l] * kOut[l]; a.lr = lr; a.c1 = c1; a.c2 = c2;
+        hipLaunchKernelGGL(k_adam, dim3(blocks_for(a.n, 256)), dim3(256), 0, s, a);
+        AdamArgs c;
+        c.w = net->b[l]; c.g = db[l]; c.m = net->mb[l]; c.v = net->vb[l]; c.wb = nullptr;
+        c.n = kOut[l]; c.lr = lr; c.c1 = c1; c.c2 = c2;
+        hipLaunchKernelGGL(k_adam, dim3(blocks_for(c.n, 256)), dim3(256), 0, s, c);
+    }
+    return launched("pn_mlp_train_step");
+}
+
+size_t pn_mlp_infer_workspace_size(int64_t chunk) {
+    if (chunk <= 0) return 0;
+    const size_t C = (size_t)chunk;
+    return al(C * kFeatLd * 2) + 3 * al(C * 256 * 2);
+}
+
+pn_status pn_mlp_infer(const pn_mlp* net, const float* feat, int64_t n, float* out, int64_t chunk, void* ws,
+                       size_t ws_bytes, hipStream_t stream) {
+    if (!net_ok(net, false) || n < 0 || chunk <= 0 || chunk > (1 << 26)) return PN_EINVAL;
+    if (n == 0) return PN_OK;
+    if (!feat || !out) return PN_EINVAL;
+    if (!ws || ws_bytes < pn_mlp_infer_workspace_size(chunk)) return PN_ENOWS;
+    char* p = static_cast<char*>(ws);
+    uint16_t* X = (uint16_t*)p;
+    p += al((size_t)chunk * kFeatLd * 2);
+    uint16_t* h[3];
+    for (int l = 0; l < 3; ++l) { h[l] = (uint16_t*)p; p += al((size_t)chunk * 256 * 2); }
+    for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+        const int64_t rows = (n - r0) < chunk ? (n - r0) : chunk;
+        hipLaunchKernelGGL(k_gather_rows, dim3(blocks_for(rows * kFeatLd, 256)), dim3(256), 0, stream, feat,
+                           (const int32_t*)nullptr, rows, r0, X);
+        forward(stream, net, rows, X, h[0], h[1], h[2], out + 2 * r0);
+    }
+    return launched("pn_mlp_infer");
+}
+
+pn_status pn_mlp_features(pn_params params, int64_t n, const double* r0, const double* th1, const double* th2,
+                          const double* t_end, double t_end_all, const int32_t* idx, const float* mean,
+                          const float* stdv, float* feat, hipStream_t stream) {
+    if (n < 0 || !mean || !stdv) return PN_EINVAL;
+    const int nnull = (params.beta == nullptr) + (params.chi1 == nullptr) + (params.chi2 == nullptr);
+    if (nnull != 0 && nnull != 3) return PN_EINVAL;
+    if (!t_end && !(t_end_all > 0.0 && std::isfinite(t_end_all))) return PN_EINVAL;
+    for (int c = 0; c < 7; ++c)
+        if (!(stdv[c] > 0.0f) || !std::isfinite(stdv[c]) || !std::isfinite(mean[c])) return PN_EINVAL;
+    if (n == 0) return PN_OK;
+    if (!r0 || !th1 || !th2 || !feat) return PN_EINVAL;
+    FeatArgs f;
+    f.beta = params.beta; f.chi1 = params.chi1; f.chi2 = params.chi2;
+    f.beta0 = params.beta0; f.chi1_0 = params.chi1_0; f.chi2_0 = params.chi2_0;
+    f.r0 = r0; f.th1 = th1; f.th2 = th2; f.t_end = t_end; f.t_end_all = t_end_all;
+    f.idx = idx; f.n = n; f.feat = feat;
+    for (int c = 0; c < 7; ++c) { f.mean[c] = mean[c]; f.stdv[c] = stdv[c]; }
+    hipLaunchKernelGGL(k_features, dim3(blocks_for(n, 256)), dim3(256), 0, stream, f);
+    return launched("pn_mlp_features");
+}
+
+pn_status pn_mlp_targets(const double* fli, const int8_t* label, const double* t_end, double t_end_all, int64_t n,
+                         float* lab, float* target, hipStream_t stream) {
+    if (n < 0) return PN_EINVAL;
+    if (n == 0) return PN_OK;
+    if (!fli || !label || !lab || !target) return PN_EINVAL;
+    if (!t_end && !(t_end_all > 0.0 && std::isfinite(t_end_all))) return PN_EINVAL;
+    hipLaunchKernelGGL(k_targets, dim3(blocks_for(n, 256)), dim3(256), 0, stream, fli, label, t_end, t_end_all, n,
+                       lab, target);
+    return launched("pn_mlp_targets");
+}
+
+pn_status pn_surrogate_gate(const float* out, int64_t n, float margin, double audit_frac, uint64_t seed,
+                            int8_t* label, float* fli_pred, int32_t* list, unsigned long long* count,
+                            hipStream_t stream) {
+    if (n < 0 || !(margin >= 0.0f) || !(audit_frac >= 0.0 && audit_frac <= 1.0)) return PN_EINVAL;
+    if (!count) return PN_EINVAL;
+    hipLaunchKernelGGL(k_clear_count, dim3(1), dim3(1), 0, stream, count);
+    if (n == 0) return launched("pn_surrogate_gate");
+    if (!out || !label || !list || n > 0x7fffffffLL) return PN_EINVAL;
+    hipLaunchKernelGGL(k_gate, dim3(blocks_for(n, 256)), dim3(256), 0, stream, out, n, margin, audit_frac,
+                       (unsigned long long)seed, label, fli_pred, list, count);
+    return launched("pn_surrogate_gate");
+}
+
+pn_status pn_surrogate_merge(const int32_t* list, int64_t m, const int8_t* integrated, int8_t* label,
+                             hipStream_t stream) {
+    if (m < 0) return PN_EINVAL;
+    if (m == 0) return PN_OK;
+    if (!list || !integrated || !label) return PN_EINVAL;
+    hipLaunchKernelGGL(k_merge, dim3(blocks_for(m, 256)), dim3(256), 0, stream, list, m, integrated, label);
+    return launched("pn_surrogate_merge");
+}
+
+pn_status pn_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, int64_t sam, int64_t sak,
+                       const uint16_t* B, int64_t sbk, int64_t sbn, const float* bias, int32_t relu,
+                       const uint16_t* mask, int64_t ldm, float* Cf, int64_t ldcf, uint16_t* Cb, int64_t ldcb,
+                       hipStream_t stream) {
+    if (M < 0 || N < 0 || K < 0) return PN_EINVAL;
+    if (M == 0 || N == 0) return PN_OK;
+    if (!A || !B || (!Cf && !Cb)) return PN_EINVAL;
+    if ((Cf && ldcf < N) || (Cb && ldcb < N) || (mask && ldm < N)) return PN_EINVAL;
+    gemm(stream, M, N, K, A, sam, sak, B, sbk, sbn, bias, relu, mask, ldm, Cf, ldcf, Cb, ldcb);
+    return launched("pn_gemm_bf16");
+}
+
+}  // extern "C"

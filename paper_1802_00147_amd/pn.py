@@ -75,6 +75,9 @@ EXPORTS = ["pn_default_model", "pn_default_integrator", "pn_default_correction",
            "pn_init_state", "pn_rhs", "pn_invariants", "pn_manifold_correct", "pn_step", "pn_fli_scan",
            "pn_default_tuning", "pn_batch_workspace_size", "pn_batch_scan", "pn_autotune_batch",
            "pn_batch_graph_create", "pn_graph_launch", "pn_graph_destroy",
+           "pn_mlp_param_count", "pn_mlp_sync_bf16", "pn_mlp_features", "pn_mlp_train_workspace_size",
+           "pn_mlp_train_step", "pn_mlp_infer_workspace_size", "pn_mlp_infer", "pn_surrogate_gate",
+           "pn_surrogate_merge", "pn_gemm_bf16", "pn_init_state_gather", "pn_mlp_targets",
            "pn_version", "pn_status_string", "pn_last_error"]
 
 
@@ -90,8 +93,15 @@ def lib():
         L.pn_version.restype = ctypes.c_int32
         for name in ("pn_init_state", "pn_rhs", "pn_invariants", "pn_manifold_correct", "pn_step",
                      "pn_fli_scan", "pn_batch_scan", "pn_autotune_batch", "pn_batch_graph_create",
-                     "pn_graph_launch"):
+                     "pn_graph_launch", "pn_mlp_sync_bf16", "pn_mlp_features", "pn_mlp_train_step",
+                     "pn_mlp_infer", "pn_surrogate_gate", "pn_surrogate_merge", "pn_gemm_bf16",
+                     "pn_init_state_gather", "pn_mlp_targets"):
             getattr(L, name).restype = ctypes.c_int
+        for name in ("pn_mlp_param_count", "pn_mlp_train_workspace_size", "pn_mlp_infer_workspace_size"):
+            getattr(L, name).restype = ctypes.c_size_t
+        L.pn_mlp_param_count.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.pn_mlp_train_workspace_size.argtypes = [ctypes.c_int32]
+        L.pn_mlp_infer_workspace_size.argtypes = [ctypes.c_int64]
         L.pn_batch_workspace_size.restype = ctypes.c_size_t
         L.pn_batch_workspace_size.argtypes = [ctypes.c_int64]
         L.pn_graph_destroy.argtypes = [ctypes.c_void_p]
@@ -385,3 +395,148 @@ class BatchGraph:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Learned surrogate.
+# ---------------------------------------------------------------------------
+P4 = ctypes.c_void_p * 4
+
+
+class Mlp(ctypes.Structure):
+    _fields_ = [("w", P4), ("b", P4), ("wb", P4), ("mw", P4), ("vw", P4), ("mb", P4), ("vb", P4)]
+
+
+LAYER_IN = (7, 256, 256, 256)
+LAYER_OUT = (256, 256, 256, 2)
+
+
+class Network:
+    """Device buffers of the 7-256-256-256-2 network (torch tensors) and the
+    C struct pointing at them.  Weights come from the caller (FP32 arrays of
+    shape [out, in]); the bfloat16 copies are made by the library."""
+
+    def __init__(self, weights, biases, device, training=True):
+        f32 = dict(dtype=torch.float32, device=device)
+        self.w = [torch.as_tensor(W, **f32).contiguous() for W in weights]
+        self.b = [torch.as_tensor(b, **f32).contiguous() for b in biases]
+        for l in range(4):
+            assert tuple(self.w[l].shape) == (LAYER_OUT[l], LAYER_IN[l])
+        self.wb = [torch.empty(W.shape, dtype=torch.int16, device=device) for W in self.w]
+        z = (lambda t: torch.zeros_like(t)) if training else (lambda t: None)
+        self.mw, self.vw = [z(W) for W in self.w], [z(W) for W in self.w]
+        self.mb, self.vb = [z(b) for b in self.b], [z(b) for b in self.b]
+        self.step = 0
+        self.struct = Mlp(*[P4(*[(t.data_ptr() if t is not None else None) for t in ts])
+                            for ts in (self.w, self.b, self.wb, self.mw, self.vw, self.mb, self.vb)])
+        _check("pn_mlp_sync_bf16", lib().pn_mlp_sync_bf16(ctypes.byref(self.struct), _stream(device)))
+
+    def params(self):
+        return [(W.detach().cpu().double().numpy(), b.detach().cpu().double().numpy())
+                for W, b in zip(self.w, self.b)]
+
+
+def mlp_features(n, r0, th1, th2, t_end, beta, chi1, chi2, mean, std, idx=None, out=None):
+    """Standardised features [n, 8] (FP32) of scan points."""
+    dev_ = r0.device
+    if out is None:
+        out = torch.empty((n, 8), dtype=torch.float32, device=dev_)
+    p, keep = params_struct(beta, chi1, chi2)
+    mean = (ctypes.c_float * 7)(*[float(x) for x in mean])
+    std = (ctypes.c_float * 7)(*[float(x) for x in std])
+    if isinstance(t_end, torch.Tensor):
+        tptr, tall = _ptr(_dev_f64(t_end)), 0.0
+    else:
+        tptr, tall = None, float(t_end)
+    st = lib().pn_mlp_features(p, ctypes.c_int64(n), _ptr(_dev_f64(r0)), _ptr(_dev_f64(th1)), _ptr(_dev_f64(th2)),
+                               tptr, ctypes.c_double(tall), _ptr(idx), mean, std, _ptr(out), _stream(dev_))
+    _check("pn_mlp_features", st)
+    return out
+
+
+def mlp_train_step(net, feat, label, target, idx, lr, loss, ws=None):
+    batch = idx.numel()
+    if ws is None:
+        ws = torch.empty(int(lib().pn_mlp_train_workspace_size(batch)), dtype=torch.uint8, device=feat.device)
+    net.step += 1
+    st = lib().pn_mlp_train_step(ctypes.byref(net.struct), _ptr(feat), _ptr(label), _ptr(target), _ptr(idx),
+                                 ctypes.c_int32(batch), ctypes.c_int32(net.step), ctypes.c_float(lr), _ptr(loss),
+                                 _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(feat.device))
+    _check("pn_mlp_train_step", st)
+    return ws
+
+
+def mlp_infer(net, feat, chunk=1 << 20, out=None, ws=None):
+    n = feat.shape[0]
+    if out is None:
+        out = torch.empty((n, 2), dtype=torch.float32, device=feat.device)
+    chunk = max(1, min(chunk, n))
+    if ws is None:
+        ws = torch.empty(int(lib().pn_mlp_infer_workspace_size(chunk)), dtype=torch.uint8, device=feat.device)
+    st = lib().pn_mlp_infer(ctypes.byref(net.struct), _ptr(feat), ctypes.c_int64(n), _ptr(out), ctypes.c_int64(chunk),
+                            _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(feat.device))
+    _check("pn_mlp_infer", st)
+    return out
+
+
+def surrogate_gate(out, margin, audit_frac, seed):
+    """Returns (labels int8 [n], predicted FLI - log10 t [n], list int32, count)."""
+    n = out.shape[0]
+    dev_ = out.device
+    label = torch.empty(n, dtype=torch.int8, device=dev_)
+    fli = torch.empty(n, dtype=torch.float32, device=dev_)
+    lst = torch.empty(max(n, 1), dtype=torch.int32, device=dev_)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev_)
+    st = lib().pn_surrogate_gate(_ptr(out), ctypes.c_int64(n), ctypes.c_float(margin), ctypes.c_double(audit_frac),
+                                 ctypes.c_uint64(seed), _ptr(label), _ptr(fli), _ptr(lst), _ptr(cnt), _stream(dev_))
+    _check("pn_surrogate_gate", st)
+    m = int(cnt.item())
+    return label, fli, lst[:m], m
+
+
+def surrogate_merge(lst, integrated, label):
+    st = lib().pn_surrogate_merge(_ptr(lst), ctypes.c_int64(lst.numel()), _ptr(integrated), _ptr(label),
+                                  _stream(label.device))
+    _check("pn_surrogate_merge", st)
+    return label
+
+
+def gemm_bf16(A, sam, sak, B, sbk, sbn, M, N, K, bias=None, relu=False, mask=None, ldm=0, out_f32=True,
+              out_bf16=False):
+    """Test access to the matrix-core product (A, B: int16 bit patterns of bfloat16)."""
+    dev_ = A.device
+    Cf = torch.empty((M, N), dtype=torch.float32, device=dev_) if out_f32 else None
+    Cb = torch.empty((M, N), dtype=torch.int16, device=dev_) if out_bf16 else None
+    st = lib().pn_gemm_bf16(ctypes.c_int32(M), ctypes.c_int32(N), ctypes.c_int32(K), _ptr(A), ctypes.c_int64(sam),
+                            ctypes.c_int64(sak), _ptr(B), ctypes.c_int64(sbk), ctypes.c_int64(sbn), _ptr(bias),
+                            ctypes.c_int32(int(relu)), _ptr(mask), ctypes.c_int64(ldm), _ptr(Cf),
+                            ctypes.c_int64(N), _ptr(Cb), ctypes.c_int64(N), _stream(dev_))
+    _check("pn_gemm_bf16", st)
+    return Cf, Cb
+
+
+def init_state_gather(idx, r0, p0, th1, ph1, th2, ph2, beta, chi1, chi2, model=None):
+    m = idx.numel()
+    y0 = torch.empty((12, max(m, 1)), dtype=torch.float64, device=idx.device)
+    p, keep = params_struct(beta, chi1, chi2)
+    cols = [_dev_f64(t) for t in (r0, p0, th1, ph1, th2, ph2)]
+    st = lib().pn_init_state_gather(ctypes.byref(model_struct(model)), p, ctypes.c_int64(m), _ptr(idx),
+                                    *[_ptr(c) for c in cols], _ptr(y0), ctypes.c_int64(max(m, 1)),
+                                    _stream(idx.device))
+    _check("pn_init_state_gather", st)
+    return y0
+
+
+def mlp_targets(fli, label, t_end):
+    """(label 1/0, FLI - log10 t_end) as FP32 device arrays from scan outputs."""
+    n = fli.numel()
+    lab = torch.empty(n, dtype=torch.float32, device=fli.device)
+    tgt = torch.empty(n, dtype=torch.float32, device=fli.device)
+    if isinstance(t_end, torch.Tensor):
+        tptr, tall = _ptr(_dev_f64(t_end)), 0.0
+    else:
+        tptr, tall = None, float(t_end)
+    st = lib().pn_mlp_targets(_ptr(fli), _ptr(label), tptr, ctypes.c_double(tall), ctypes.c_int64(n), _ptr(lab),
+                              _ptr(tgt), _stream(fli.device))
+    _check("pn_mlp_targets", st)
+    return lab, tgt

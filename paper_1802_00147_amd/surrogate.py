@@ -1,0 +1,123 @@
+"""Surrogate-assisted FLI scans: a small network trained on FLIs that the
+FP64 scan itself produced predicts the chaos label of scan points; points it
+is unsure of, and a random audit sample, are integrated, and the integrated
+labels win.
+
+Orchestration only: features, training steps, inference, gating, initial
+states, the fallback scan and the merge all run in the library's kernels
+(include/pn.h); this module moves tensors between those calls and holds the
+host-side bookkeeping of a data loader (feature statistics, the seeded order
+of training samples).
+"""
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import pn
+from . import workloads as W
+
+
+@dataclass
+class FeatureStats:
+    mean: np.ndarray
+    std: np.ndarray
+
+
+def feature_stats(wl):
+    """Mean and standard deviation of the seven raw inputs over a workload
+    (host preprocessing of the training set)."""
+    n = wl.n
+    col = (lambda v: np.broadcast_to(np.asarray(v, dtype=np.float64), (n,)))
+    raw = np.column_stack([col(wl.beta), col(wl.chi1), col(wl.chi2), wl.r0, np.cos(wl.th1), np.cos(wl.th2),
+                           np.log10(col(wl.t_end))])
+    std = raw.std(axis=0)
+    std[std == 0] = 1.0
+    return FeatureStats(raw.mean(axis=0), std)
+
+
+def _dev(a, device):
+    return torch.as_tensor(a, device=device) if isinstance(a, np.ndarray) else a
+
+
+def workload_features(wl, stats, device, idx=None):
+    cols = {k: torch.as_tensor(getattr(wl, k), device=device) for k in ("r0", "th1", "th2")}
+    n = wl.n if idx is None else idx.numel()
+    return pn.mlp_features(n, cols["r0"], cols["th1"], cols["th2"], _dev(wl.t_end, device),
+                           _dev(wl.beta, device), _dev(wl.chi1, device), _dev(wl.chi2, device),
+                           stats.mean, stats.std, idx=idx)
+
+
+@dataclass
+class TrainingSet:
+    feat: torch.Tensor         # [n, 8] standardised features (device)
+    label: torch.Tensor        # [n] 1.0 chaotic / 0.0 regular
+    target: torch.Tensor       # [n] FLI - log10 t_end
+    valid: np.ndarray          # indices of orbits with a valid status
+    stats: FeatureStats
+
+
+def training_set(wl, scan_out, device):
+    """Pairs (features, integrated label and FLI) from a scan of `wl`."""
+    stats = feature_stats(wl)
+    feat = workload_features(wl, stats, device)
+    status = scan_out["status"].cpu().numpy()
+    lab = scan_out["label"].cpu().numpy()
+    valid = np.nonzero(((status & 0xFF) == 0) & (lab >= 0))[0]
+    label, target = pn.mlp_targets(scan_out["fli"], scan_out["label"], _dev(wl.t_end, device))
+    return TrainingSet(feat, label, target, valid, stats)
+
+
+def train(ts, epochs=8, batch=4096, lr=1e-3, seed=50, init_seed=50, device="cuda:0", log=None):
+    """Train the network on the valid samples of `ts`; returns (network, mean
+    loss per epoch)."""
+    params = W.mlp_init_weights(init_seed)
+    net = pn.Network([W_ for W_, _ in params], [b for _, b in params], device)
+    rng = np.random.default_rng(seed)
+    loss = torch.zeros(1, dtype=torch.float32, device=device)
+    ws = None
+    history = []
+    nb = len(ts.valid) // batch
+    for ep in range(epochs):
+        order = torch.as_tensor(rng.permutation(ts.valid).astype(np.int32), device=device)
+        loss.zero_()
+        for b in range(nb):
+            ws = pn.mlp_train_step(net, ts.feat, ts.label, ts.target, order[b * batch:(b + 1) * batch], lr, loss, ws)
+        history.append(float(loss.item()) / max(nb, 1))
+        if log:
+            log(f"epoch {ep}: mean loss {history[-1]:.5f}")
+    return net, history
+
+
+@dataclass
+class SurrogateResult:
+    label: torch.Tensor          # final labels of the grid (int8)
+    integrated: int              # number of points integrated
+    points: torch.Tensor         # their indices (int32)
+    timings: dict = field(default_factory=dict)
+
+
+def surrogate_scan(net, wl, stats, margin=0.5, audit=0.01, seed=5, model=None, chunk=1 << 20):
+    """Labels of every point of the grid workload `wl`: network inference,
+    gate, integration of the uncertain and audited points, merge."""
+    device = net.w[0].device
+    t = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    feat = workload_features(wl, stats, device)
+    out = pn.mlp_infer(net, feat, chunk=chunk)
+    label, _, lst, m = pn.surrogate_gate(out, margin, audit, seed)
+    torch.cuda.synchronize()
+    t["infer_gate_s"] = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    if m > 0:
+        cols = {k: torch.as_tensor(getattr(wl, k), device=device) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")}
+        y0 = pn.init_state_gather(lst, cols["r0"], cols["p0"], cols["th1"], cols["ph1"], cols["th2"], cols["ph2"],
+                                  _dev(wl.beta, device), _dev(wl.chi1, device), _dev(wl.chi2, device), model=model)
+        sc = pn.fli_scan(y0, wl.t_end, wl.beta, wl.chi1, wl.chi2, model=model, full=False)
+        pn.surrogate_merge(lst, sc["label"][:m], label)
+    torch.cuda.synchronize()
+    t["fallback_s"] = time.perf_counter() - t1
+    t["total_s"] = time.perf_counter() - t0
+    return SurrogateResult(label, m, lst, t)

@@ -123,3 +123,18 @@ def strided_sample(n, k, seed=0):
     rng = np.random.default_rng(seed)
     k = min(k, n)
     return np.sort(rng.choice(n, size=k, replace=False))
+
+
+MLP_LAYERS = (7, 256, 256, 256, 2)
+
+
+def mlp_init_weights(seed=50):
+    """Seeded initial weights of the surrogate network: He-uniform W_l of shape
+    [n_out, n_in] (bound sqrt(6 / n_in)) and zero biases, float64."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for n_in, n_out in zip(MLP_LAYERS[:-1], MLP_LAYERS[1:]):
+        bound = np.sqrt(6.0 / n_in)
+        params.append((rng.uniform(-bound, bound, (n_out, n_in)), np.zeros(n_out)))
+    return params
+

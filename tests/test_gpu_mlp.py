@@ -1,0 +1,221 @@
+"""GPU tests of the learned surrogate against the CPU oracle (oracle/mlp.py):
+the MFMA matrix product, the forward pass, one training step (gradients and
+Adam update), features, targets, gate and merge, learning on a toy problem,
+and a small surrogate-assisted scan end to end.
+
+Tolerances: the GPU multiplies bfloat16 operands exactly and accumulates in
+FP32, so a product of length K differs from the FP64 sum of the same
+bfloat16 operands by at most ~K * 2^-24 of sum |a_k b_k|; 1e-5 of that sum is
+used.  Where a result is itself rounded to bfloat16 before the next layer,
+rare elements sit on a rounding boundary and differ by one bfloat16 ulp
+(2^-8 relative); comparisons after such roundings use norm-wise bounds.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle import mlp as M
+from gpu_helpers import DEV, dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pn():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_1802_00147_amd import pn as P
+    P.lib()
+    return P
+
+
+def bf16_bits(x):
+    """float64 array -> (device int16 bit patterns, the bfloat16 values as float64)."""
+    t = torch.as_tensor(np.asarray(x, dtype=np.float32)).to(torch.bfloat16)
+    return t.view(torch.int16).to(DEV), t.to(torch.float64).numpy()
+
+
+@pytest.mark.parametrize("M_,N_,K_,trans_a", [(37, 5, 7, False), (64, 64, 32, False), (130, 257, 300, False),
+                                               (256, 7, 1000, True), (3, 256, 2, False), (1, 1, 1, False)])
+def test_gemm_matches_fp64_of_bf16_operands(pn, M_, N_, K_, trans_a):
+    rng = np.random.default_rng(M_ * 1000 + N_)
+    A = rng.normal(size=(M_, K_))
+    B = rng.normal(size=(K_, N_))
+    if trans_a:    # A stored as [K, M]: A(m, k) = At[k, m]
+        At_bits, At = bf16_bits(A.T.copy())
+        a_bits, Aq, sam, sak = At_bits, At.T, 1, M_
+    else:
+        a_bits, Aq = bf16_bits(A)
+        sam, sak = K_, 1
+    # B stored as Wt [N, K]: B(k, n) = Wt[n, k]
+    w_bits, Wq = bf16_bits(B.T.copy())
+    Cf, _ = pn.gemm_bf16(a_bits, sam, sak, w_bits, 1, K_, M_, N_, K_)
+    ref = Aq @ Wq.T
+    bound = 1e-5 * (np.abs(Aq) @ np.abs(Wq.T)) + 1e-30
+    assert np.all(np.abs(Cf.cpu().numpy() - ref) <= bound)
+
+
+def test_gemm_epilogues(pn):
+    rng = np.random.default_rng(7)
+    M_, N_, K_ = 100, 70, 40
+    a_bits, Aq = bf16_bits(rng.normal(size=(M_, K_)))
+    w_bits, Wq = bf16_bits(rng.normal(size=(N_, K_)))
+    bias = rng.normal(size=N_).astype(np.float32)
+    mask_bits, maskq = bf16_bits(np.maximum(rng.normal(size=(M_, N_)), 0.0))
+    Cf, Cb = pn.gemm_bf16(a_bits, K_, 1, w_bits, 1, K_, M_, N_, K_, bias=dev(bias, torch.float32), relu=True,
+                          mask=mask_bits, ldm=N_, out_f32=True, out_bf16=True)
+    ref = np.maximum(Aq @ Wq.T + bias.astype(np.float64), 0.0) * (maskq > 0)
+    bound = 1e-5 * (np.abs(Aq) @ np.abs(Wq.T) + np.abs(bias)) + 1e-30
+    got = Cf.cpu().numpy()
+    assert np.all(np.abs(got - ref) <= bound)
+    # The bfloat16 output is the FP32 result rounded to nearest even.
+    gb = Cb.cpu().view(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(gb, M.round_bf16(got))
+
+
+def _network(pn, seed=50):
+    from paper_1802_00147_amd.workloads import mlp_init_weights
+    params = mlp_init_weights(seed)
+    # Non-zero biases so that the bias path is exercised.
+    params = [(W_, 0.05 * np.sin(np.arange(b.size) + l)) for l, (W_, b) in enumerate(params)]
+    net = pn.Network([W_ for W_, _ in params], [b for _, b in params], DEV)
+    return net, params
+
+
+def _as_f32(params):
+    return [(W_.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)) for W_, b in params]
+
+
+def test_forward_matches_oracle(pn):
+    rng = np.random.default_rng(8)
+    net, params = _network(pn)
+    X = rng.normal(size=(3000, 7))
+    feat = np.zeros((3000, 8), dtype=np.float32)
+    feat[:, :7] = X
+    out = pn.mlp_infer(net, dev(feat, torch.float32), chunk=1024).cpu().numpy()
+    ref, _ = M.forward(_as_f32(params), X.astype(np.float32).astype(np.float64), bf16=True)
+    err = np.abs(out - ref)
+    scale = np.abs(ref).max()
+    assert np.median(err) <= 1e-5 * scale
+    assert err.max() <= 5e-3 * scale     # rare one-ulp bfloat16 flips of hidden activations
+
+
+def test_train_step_matches_oracle(pn):
+    rng = np.random.default_rng(9)
+    net, params = _network(pn)
+    n, B = 5000, 1024
+    X = rng.normal(size=(n, 7))
+    feat = np.zeros((n, 8), dtype=np.float32)
+    feat[:, :7] = X
+    lab = (rng.uniform(size=n) < 0.3).astype(np.float32)
+    tgt = rng.normal(size=n).astype(np.float32)
+    idx = rng.choice(n, size=B, replace=False).astype(np.int32)
+    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+    pn.mlp_train_step(net, dev(feat, torch.float32), dev(lab, torch.float32), dev(tgt, torch.float32),
+                      dev(idx, torch.int32), 1e-3, loss)
+    torch.cuda.synchronize()
+    p32 = _as_f32(params)
+    Xb = X[idx].astype(np.float32).astype(np.float64)
+    out, acts = M.forward(p32, Xb, bf16=True)
+    ref_loss, g = M.loss_and_grad_out(out, lab[idx].astype(np.float64), tgt[idx].astype(np.float64))
+    grads = M.backward(p32, acts, g, bf16=True)
+    assert abs(loss.item() - ref_loss) <= 1e-4 * abs(ref_loss)
+    # First Adam step: m = 0.1 g, so the device moments give the device gradients.
+    for l in range(4):
+        gW = net.mw[l].cpu().double().numpy() / 0.1
+        gb = net.mb[l].cpu().double().numpy() / 0.1
+        rW, rb = grads[l]
+        assert np.linalg.norm(gW - rW) <= 2e-3 * np.linalg.norm(rW), l
+        assert np.linalg.norm(gb - rb) <= 2e-3 * np.linalg.norm(rb), l
+        # Updated weights and their bfloat16 copies.
+        new_W = net.w[l].cpu().double().numpy()
+        step = new_W - p32[l][0]
+        exp_step = -1e-3 * rW / (np.abs(rW) + 1e-8)
+        big = np.abs(rW) > 1e-3 * np.abs(rW).max()
+        assert np.allclose(step[big], exp_step[big], rtol=2e-2, atol=1e-6), l
+        wb = net.wb[l].cpu().view(torch.bfloat16).to(torch.float64).numpy()
+        assert np.array_equal(wb, M.round_bf16(new_W)), l
+
+
+def test_features_targets_gate_merge(pn):
+    from paper_1802_00147_amd import workloads as W
+    wl = W.batch(n=20000, seed=30, tmin=1e3, tmax=1e5)
+    mean = np.array([0.5, 0.5, 0.5, 30.0, 0.0, 0.0, 4.0])
+    std = np.array([0.3, 0.3, 0.3, 15.0, 0.6, 0.6, 0.6])
+    cols = {k: dev(getattr(wl, k)) for k in ("r0", "th1", "th2", "t_end", "beta", "chi1", "chi2")}
+    feat = pn.mlp_features(wl.n, cols["r0"], cols["th1"], cols["th2"], cols["t_end"], cols["beta"], cols["chi1"],
+                           cols["chi2"], mean, std).cpu().numpy()
+    ref = M.features(wl.beta, wl.chi1, wl.chi2, wl.r0, wl.th1, wl.th2, wl.t_end, mean, std)
+    assert np.allclose(feat[:, :7], ref, rtol=0, atol=1e-6 * (1 + np.abs(ref).max()))
+    assert np.all(feat[:, 7] == 0)
+    # Targets.
+    rng = np.random.default_rng(4)
+    fli = rng.uniform(0, 8, wl.n)
+    fli[::97] = np.nan
+    label = rng.integers(-1, 2, wl.n).astype(np.int8)
+    lab, tgt = pn.mlp_targets(dev(fli), dev(label, torch.int8), cols["t_end"])
+    assert np.array_equal(lab.cpu().numpy(), (label == 1).astype(np.float32))
+    exp_t = np.where(np.isfinite(fli), fli - np.log10(wl.t_end), 0.0)
+    assert np.allclose(tgt.cpu().numpy(), exp_t, rtol=1e-6, atol=1e-6)
+    # Gate: the same points as the oracle's SplitMix64 gate, bit for bit.
+    out = np.column_stack([rng.normal(size=wl.n), rng.normal(size=wl.n)]).astype(np.float32)
+    glab, gfli, lst, m = pn.surrogate_gate(dev(out, torch.float32), 0.5, 0.01, 12345)
+    elab, chosen = M.gate(out.astype(np.float64), 0.5, 0.01, 12345)
+    assert np.array_equal(glab.cpu().numpy(), elab)
+    assert np.array_equal(np.sort(lst.cpu().numpy()), chosen)
+    # Merge: integrated labels win on the listed points.
+    integ = torch.full((m,), 1, dtype=torch.int8, device=DEV)
+    pn.surrogate_merge(lst, integ, glab)
+    merged = glab.cpu().numpy()
+    assert np.all(merged[chosen] == 1)
+    rest = np.setdiff1d(np.arange(wl.n), chosen)
+    assert np.array_equal(merged[rest], elab[rest])
+
+
+def test_gpu_training_learns_toy_problem(pn):
+    rng = np.random.default_rng(11)
+    n = 40000
+    X = rng.normal(size=(n, 7))
+    feat = np.zeros((n, 8), dtype=np.float32)
+    feat[:, :7] = X
+    lab = (X[:, 0] + 0.5 * X[:, 3] - 0.3 * X[:, 6] > 0.2).astype(np.float32)
+    tgt = (0.5 * X[:, 1] - 0.2 * X[:, 2]).astype(np.float32)
+    net, _ = _network(pn, seed=12)
+    f_d, l_d, t_d = dev(feat, torch.float32), dev(lab, torch.float32), dev(tgt, torch.float32)
+    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+    ws = None
+    hist = []
+    for ep in range(6):
+        order = dev(rng.permutation(n).astype(np.int32), torch.int32)
+        loss.zero_()
+        for b in range(n // 2048):
+            ws = pn.mlp_train_step(net, f_d, l_d, t_d, order[b * 2048:(b + 1) * 2048], 2e-3, loss, ws)
+        hist.append(loss.item() / (n // 2048))
+    out = pn.mlp_infer(net, f_d).cpu().numpy()
+    acc = np.mean((out[:, 0] > 0) == (lab > 0.5))
+    assert hist[-1] < 0.3 * hist[0]
+    assert acc > 0.97
+
+
+def test_surrogate_scan_small_end_to_end(pn):
+    """Train on a 40k-orbit uneven batch, then scan a 96 x 96 (r0, theta) grid
+    at t = 2000: the merged labels equal the plain scan's labels wherever the
+    points were integrated, and agree overall on at least 97% of the grid."""
+    from paper_1802_00147_amd import surrogate as S, workloads as W
+    tr = W.batch(n=40000, seed=31, tmin=1e3, tmax=3e3)
+    cols = [dev(getattr(tr, k)) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")]
+    y0 = pn.init_state(*cols, dev(tr.beta), dev(tr.chi1), dev(tr.chi2))
+    sc = pn.batch_scan(y0, dev(tr.t_end), dev(tr.beta), dev(tr.chi1), dev(tr.chi2))
+    ts = S.training_set(tr, sc, DEV)
+    net, hist = S.train(ts, epochs=4, batch=2048, lr=1e-3)
+    assert hist[-1] < hist[0]
+    grid = W.grid_r_theta(96, 96, 2000.0, "grid96")
+    res = S.surrogate_scan(net, grid, ts.stats, margin=0.5, audit=0.05, seed=5)
+    gcols = [dev(getattr(grid, k)) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")]
+    plain = pn.fli_scan(pn.init_state(*gcols, 1.0, 1.0, 1.0), grid.t_end, 1.0, 1.0, 1.0, full=False)
+    torch.cuda.synchronize()
+    got, ref = res.label.cpu().numpy(), plain["label"].cpu().numpy()
+    pts = res.points.cpu().numpy()
+    assert res.integrated == len(pts) >= 0.03 * grid.n
+    assert np.array_equal(got[pts], ref[pts])
+    assert np.mean(got == ref) >= 0.97
