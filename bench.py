@@ -95,6 +95,90 @@ def cpu_baseline(wl, sample, flop_sample_steps=2000):
                 labels=res["label"], flops_per_orbit_step=float(np.mean(flops)))
 
 
+def surrogate_bench(args, dev):
+    """Surrogate-assisted scan of the 4096 x 4096 (r0, theta) grid at t = 1e5
+    against the plain FP64 scan.  The network is trained on the FP64 scan of
+    the 10^6-orbit uneven batch (untimed setup, reported); one benchmark step
+    is the whole assisted scan: features, inference, gate, integration of the
+    uncertain and audited points, merge.  The plain scan's rate and the label
+    agreement come from a seeded sample of grid points integrated by the plain
+    kernel."""
+    import torch
+    from paper_1802_00147_amd import pn, surrogate as S, workloads as W
+
+    t0 = time.perf_counter()
+    tr = W.batch()
+    tcols = [torch.as_tensor(getattr(tr, k), device=dev) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")]
+    tb, tc1, tc2, tt = (torch.as_tensor(getattr(tr, k), device=dev) for k in ("beta", "chi1", "chi2", "t_end"))
+    y0 = pn.init_state(*tcols, tb, tc1, tc2)
+    sc = pn.batch_scan(y0, tt, tb, tc1, tc2, full=False)
+    torch.cuda.synchronize()
+    data_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ts = S.training_set(tr, sc, dev)
+    net, hist = S.train(ts, epochs=args.epochs, batch=4096, lr=1e-3, device=dev)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del y0, sc
+
+    grid = W.grid4096()
+    for _ in range(args.warmup):
+        S.surrogate_scan(net, grid, ts.stats, margin=0.5, audit=0.01, seed=5)
+    res = None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = S.surrogate_scan(net, grid, ts.stats, margin=0.5, audit=0.01, seed=5)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    # Plain scan on a seeded sample of the grid: rate and label agreement.
+    idx = W.strided_sample(grid.n, args.plain_sample, seed=17)
+    sub = grid.subset(idx)
+    scols = [torch.as_tensor(getattr(sub, k), device=dev) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")]
+    ys = pn.init_state(*scols, 1.0, 1.0, 1.0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    plain = pn.fli_scan(ys, grid.t_end, 1.0, 1.0, 1.0, full=False)
+    e1.record()
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
+    plain_pts_s = len(idx) / (plain_ms * 1e-3)
+    got = res.label.cpu().numpy()[idx]
+    ref = plain["label"].cpu().numpy()
+    agree = float(np.mean(got == ref))
+    value = grid.n * args.steps / elapsed
+    line = dict(metric=METRIC, value=value, unit="grid-pts/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+                ms_per_step=1e3 * elapsed / args.steps, higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f64+bf16", data="synthetic",
+                config={"workload": "grid4096 surrogate-assisted FLI scan: 4096x4096 (r0, theta) grid, t=1e5, "
+                                    "beta=1, chi=1, QM on; MLP 7-256-256-256-2 (BF16 MFMA, FP32 accumulation) "
+                                    "trained on the FP64 scan of batch1M; integration fallback for |logit| < 0.5 "
+                                    "plus a 1% SplitMix64 audit", "grid_points": grid.n,
+                        "train_epochs": args.epochs})
+    line["plain_grid_pts_per_s"] = plain_pts_s
+    line["speedup_vs_plain"] = value / plain_pts_s
+    line["label_agreement"] = agree
+    line["label_agreement_sample"] = len(idx)
+    line["integrated_fraction"] = res.integrated / grid.n
+    line["timings_s"] = dict(res.timings, training_data=data_s, training=train_s)
+    line["train_loss"] = [round(h, 5) for h in hist]
+    if not args.no_cpu_baseline:
+        sub_cpu = W.grid_r_theta(64, 64, grid.t_end, "grid64")   # same recipe at 4,096 points
+        cb = cpu_baseline(sub_cpu, args.cpu_sample)
+        cb.pop("labels")
+        fpos = cb.pop("flops_per_orbit_step")
+        cb["value"] = cb["value"] / grid.t_end   # orbit-steps/s -> grid-pts/s (1e5 steps per point)
+        cb["unit"] = "grid-pts/s"
+        line["cpu_baseline"] = cb
+        achieved = fpos * len(idx) * grid.t_end / (plain_ms * 1e-3) / 1e12
+        line["roofline"] = dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                                frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=None,
+                                kernel="k_fli_scan<RK4,SIX> (plain sample; the fallback scan is the same kernel)",
+                                kernel_ms=plain_ms, flops_per_orbit_step=fpos)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +187,8 @@ def main():
     ap.add_argument("--workload", default="grid64")
     ap.add_argument("--cpu-sample", type=int, default=160)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--epochs", type=int, default=4, help="surrogate workload: training epochs")
+    ap.add_argument("--plain-sample", type=int, default=65536, help="surrogate workload: plain-scan sample")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); the scan shards "
@@ -114,6 +200,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
     dev = torch.device("cuda:0")
+    if args.workload == "surrogate4096":
+        surrogate_bench(args, dev)
+        return
     wl = make_workload(args.workload)
     cols = {k: torch.as_tensor(getattr(wl, k), device=dev) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")}
     n = wl.n
