@@ -188,8 +188,11 @@ def test_scan_single_orbit_c1(pn):
     assert got["dH"][0] < 1e-14 and got["dJ"][0] < 1e-14
 
 
-@pytest.mark.parametrize("method,mode", [("rk4", "six"), ("rk5", "six"), ("rk4", "dual"), ("rk4", "none")])
-def test_scan_parity_mixed_batch(pn, method, mode):
+@pytest.mark.parametrize("method,mode,model", [
+    ("rk4", "six", None), ("rk5", "six", None), ("rk4", "dual", None), ("rk4", "none", None),
+    ("rk4", "spin", None), ("rk4", "six", dict(spin_units=1)), ("rk4", "six", dict(quad_mono=0, spin_spin=0)),
+    ("rk5", "dual", dict(pn_order=1))])
+def test_scan_parity_mixed_batch(pn, method, mode, model):
     """Per-orbit beta, chi and t_end; ragged n; short runs (t <= 2000)."""
     rng = np.random.default_rng(107)
     n = 131
@@ -197,14 +200,14 @@ def test_scan_parity_mixed_batch(pn, method, mode):
     r0 = rng.uniform(8, 40, n)
     y0 = O.init_state(r0, r0 ** -0.5 * rng.uniform(0.9, 1.1, n), rng.uniform(0, np.pi, n),
                       rng.uniform(0, 2 * np.pi, n), rng.uniform(0, np.pi, n), rng.uniform(0, 2 * np.pi, n),
-                      beta, c1, c2)
+                      beta, c1, c2, model=model)
     t_end = rng.uniform(100, 2000, n)
-    exp, got = _scan_both(pn, y0, t_end, beta, c1, c2, n, integrator=dict(method=method),
+    exp, got = _scan_both(pn, y0, t_end, beta, c1, c2, n, model=model, integrator=dict(method=method),
                           correction=dict(mode=mode))
     assert np.array_equal(got["status"], exp["status"])
     assert np.array_equal(got["label"], exp["label"])
     ok = exp["status"] == 0
-    tol = FLI_ABS if mode == "none" else FLI_ABS_CORRECTED
+    tol = FLI_ABS if mode in ("none", "spin") else FLI_ABS_CORRECTED
     assert np.all(np.abs(got["fli"][ok] - exp["fli"][ok]) <= tol)
     assert np.all(rel_err_rows(got["y_final"][ok], exp["y_final"][ok]) <= 1e-9)
     assert np.array_equal(got["renorms"], exp["renorms"])
