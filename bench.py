@@ -122,14 +122,27 @@ def surrogate_bench(args, dev):
     del y0, sc
 
     grid = W.grid4096()
+    base = [t_.clone() for t_ in net.w + net.b + net.wb + net.mw + net.vw + net.mb + net.vb]
+    base_step = net.step
+
+    def restore():   # each assisted scan refines the network trained on batch1M afresh
+        for dst, src in zip(net.w + net.b + net.wb + net.mw + net.vw + net.mb + net.vb, base):
+            dst.copy_(src)
+        net.step = base_step
+
     for _ in range(args.warmup):
-        S.surrogate_scan(net, grid, ts.stats, margin=0.5, audit=0.01, seed=5)
+        restore()
+        S.surrogate_scan(net, grid, ts.stats, margin=args.margin, audit=0.01, seed=5, refine_epochs=args.refine)
     res = None
-    t0 = time.perf_counter()
+    elapsed = 0.0
     for _ in range(args.steps):
-        res = S.surrogate_scan(net, grid, ts.stats, margin=0.5, audit=0.01, seed=5)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+        restore()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = S.surrogate_scan(net, grid, ts.stats, margin=args.margin, audit=0.01, seed=5,
+                               refine_epochs=args.refine)
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
 
     # Plain scan on a seeded sample of the grid: rate and label agreement.
     idx = W.strided_sample(grid.n, args.plain_sample, seed=17)
@@ -153,9 +166,10 @@ def surrogate_bench(args, dev):
                 dtype="f64+bf16", data="synthetic",
                 config={"workload": "grid4096 surrogate-assisted FLI scan: 4096x4096 (r0, theta) grid, t=1e5, "
                                     "beta=1, chi=1, QM on; MLP 7-256-256-256-2 (BF16 MFMA, FP32 accumulation) "
-                                    "trained on the FP64 scan of batch1M; integration fallback for |logit| < 0.5 "
-                                    "plus a 1% SplitMix64 audit", "grid_points": grid.n,
-                        "train_epochs": args.epochs})
+                                    "trained on the FP64 scan of batch1M, refined on the integrated 1% "
+                                    "SplitMix64 audit of the grid; integration fallback for |logit| < margin",
+                        "grid_points": grid.n, "train_epochs": args.epochs, "refine_epochs": args.refine,
+                        "margin": args.margin})
     line["plain_grid_pts_per_s"] = plain_pts_s
     line["speedup_vs_plain"] = value / plain_pts_s
     line["label_agreement"] = agree
@@ -189,6 +203,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--epochs", type=int, default=4, help="surrogate workload: training epochs")
     ap.add_argument("--plain-sample", type=int, default=65536, help="surrogate workload: plain-scan sample")
+    ap.add_argument("--refine", type=int, default=3, help="surrogate workload: refinement epochs on the audit")
+    ap.add_argument("--margin", type=float, default=0.5, help="surrogate workload: logit margin of the gate")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of this many MiB (a kernel of known traffic "
                          "for scaling hardware byte counters)")

@@ -98,26 +98,65 @@ class SurrogateResult:
     timings: dict = field(default_factory=dict)
 
 
-def surrogate_scan(net, wl, stats, margin=0.5, audit=0.01, seed=5, model=None, chunk=1 << 20):
-    """Labels of every point of the grid workload `wl`: network inference,
-    gate, integration of the uncertain and audited points, merge."""
+def _integrate(wl, lst, device, model=None):
+    """FP64 scan of the listed grid points; returns its output tensors."""
+    cols = {k: torch.as_tensor(getattr(wl, k), device=device) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")}
+    y0 = pn.init_state_gather(lst, cols["r0"], cols["p0"], cols["th1"], cols["ph1"], cols["th2"], cols["ph2"],
+                              _dev(wl.beta, device), _dev(wl.chi1, device), _dev(wl.chi2, device), model=model)
+    return pn.fli_scan(y0, wl.t_end, wl.beta, wl.chi1, wl.chi2, model=model, full=False)
+
+
+def surrogate_scan(net, wl, stats, margin=0.5, audit=0.01, seed=5, model=None, chunk=1 << 20,
+                   refine_epochs=0, refine_batch=2048, refine_lr=5e-4, refine_seed=51):
+    """Labels of every point of the grid workload `wl`.
+
+    1. The audit sample (SplitMix64(seed + i) / 2^64 < audit) is integrated.
+    2. With refine_epochs > 0 the network is first trained further on those
+       integrated points (FLIs the method produced on this very scan).
+    3. Inference on every point; points with |logit| < margin are integrated.
+    4. Integrated labels replace the network's wherever they exist.
+    """
     device = net.w[0].device
     t = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     feat = workload_features(wl, stats, device)
-    out = pn.mlp_infer(net, feat, chunk=chunk)
-    label, _, lst, m = pn.surrogate_gate(out, margin, audit, seed)
+    zeros = torch.zeros((wl.n, 2), dtype=torch.float32, device=device)
+    _, _, audit_lst, ma = pn.surrogate_gate(zeros, 0.0, audit, seed)   # margin 0: the audit draw only
+    del zeros
+    audit_lst = audit_lst.clone()
+    sa = _integrate(wl, audit_lst, device, model) if ma > 0 else None
     torch.cuda.synchronize()
-    t["infer_gate_s"] = time.perf_counter() - t0
+    t["audit_s"] = time.perf_counter() - t0
     t1 = time.perf_counter()
-    if m > 0:
-        cols = {k: torch.as_tensor(getattr(wl, k), device=device) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")}
-        y0 = pn.init_state_gather(lst, cols["r0"], cols["p0"], cols["th1"], cols["ph1"], cols["th2"], cols["ph2"],
-                                  _dev(wl.beta, device), _dev(wl.chi1, device), _dev(wl.chi2, device), model=model)
-        sc = pn.fli_scan(y0, wl.t_end, wl.beta, wl.chi1, wl.chi2, model=model, full=False)
-        pn.surrogate_merge(lst, sc["label"][:m], label)
+    if refine_epochs > 0 and ma >= refine_batch:
+        fa = workload_features(wl, stats, device, idx=audit_lst)
+        la, ta = pn.mlp_targets(sa["fli"][:ma], sa["label"][:ma], _dev(wl.t_end, device))
+        st = sa["status"][:ma].cpu().numpy()
+        valid = np.nonzero((st & 0xFF) == 0)[0]
+        rng = np.random.default_rng(refine_seed)
+        loss = torch.zeros(1, dtype=torch.float32, device=device)
+        ws = None
+        for _ in range(refine_epochs):
+            order = torch.as_tensor(rng.permutation(valid).astype(np.int32), device=device)
+            for b in range(len(valid) // refine_batch):
+                ws = pn.mlp_train_step(net, fa, la, ta, order[b * refine_batch:(b + 1) * refine_batch], refine_lr,
+                                       loss, ws)
     torch.cuda.synchronize()
-    t["fallback_s"] = time.perf_counter() - t1
+    t["refine_s"] = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    out = pn.mlp_infer(net, feat, chunk=chunk)
+    label, _, lst, m = pn.surrogate_gate(out, margin, 0.0, seed)
+    torch.cuda.synchronize()
+    t["infer_gate_s"] = time.perf_counter() - t2
+    t3 = time.perf_counter()
+    if m > 0:
+        su = _integrate(wl, lst, device, model)
+        pn.surrogate_merge(lst, su["label"][:m], label)
+    if ma > 0:
+        pn.surrogate_merge(audit_lst, sa["label"][:ma], label)
+    torch.cuda.synchronize()
+    t["fallback_s"] = time.perf_counter() - t3
     t["total_s"] = time.perf_counter() - t0
-    return SurrogateResult(label, m, lst, t)
+    points = torch.cat([audit_lst, lst]) if m > 0 else audit_lst
+    return SurrogateResult(label, ma + m, points, t)
