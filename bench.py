@@ -34,7 +34,10 @@ KERNEL_SOURCES = ["paper_1802_00147_amd/csrc/pn_kernels.hip", "paper_1802_00147_
 # HBM traffic of the scan kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
 # (KiB per dispatch, scaled by a copy kernel of known size), valid only for the
 # kernel source whose hash is recorded with it.
-TRAFFIC = None   # dict(bytes_per_launch=..., sources_sha256=...)
+# grid64 launch: FETCH_SIZE 376.5 KiB x 1.99993 (a 1 GiB copy reads 524,307.8
+# KiB) + WRITE_SIZE 548.0 KiB x 1.0 (the copy writes 1,048,576 KiB).
+TRAFFIC = dict(workload="grid64", bytes_per_launch=771044 + 561152,
+               sources_sha256="b981525d4532d3cc130b950989ccc7039b054ff1695feecd52bcbe9a033bdfe8")
 
 
 def sources_sha256():
@@ -290,7 +293,8 @@ def main():
         line["cpu_baseline"] = cb
         achieved = fpos * orbit_steps / (kernel_ms * 1e-3) / 1e12
         traffic = None
-        if TRAFFIC is not None and TRAFFIC.get("sources_sha256") == sources_sha256():
+        if (TRAFFIC is not None and TRAFFIC.get("workload") == wl.name
+                and TRAFFIC.get("sources_sha256") == sources_sha256()):
             traffic = TRAFFIC["bytes_per_launch"]
         line["roofline"] = dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
                                 frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=traffic,

@@ -295,9 +295,11 @@ __device__ __forceinline__ int pn_energy_scale(const PnCoef& k, double* y, doubl
 
 // Least-squares projection of (r, p) onto H = E0, J = J0 (spins fixed): the
 // smallest displacement d with G d = -c, d = -G^T lam, (G G^T) lam = c, where
-// the rows of G are grad J_x, grad J_y, grad J_z, grad H.  Solved by LDL^T; the
-// energy row is dropped when its pivot is below 1e-4 of its diagonal (near
-// circular orbits, where the energy row depends on the J rows).
+// the rows of G are grad J_x, grad J_y, grad J_z, grad H.  Solved by LDL^T.
+// Near circular orbits the energy row is nearly a combination of the J rows
+// and its pivot d3 vanishes; its multiplier is damped (Tikhonov),
+// lam3 = z3 d3 / (d3^2 + (mu A33)^2) with mu = PN_SIX_MU, which bounds how far
+// rounding in z3 can move the state.
 __device__ __forceinline__ void pn_project_EJ(const PnCoef& k, double* y, const double* ref) {
     double H, gr[3], gp[3], J[3];
     pn_energy_grad_rp(k, y, H, gr, gp);
