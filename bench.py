@@ -56,6 +56,8 @@ def make_workload(name):
         return W.grid314()
     if name == "batch1M":
         return W.batch()
+    if name == "fig7":
+        return W.fig7()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -65,6 +67,11 @@ def describe(wl):
                             "spins, r0 in [8,60], t_end log-uniform in [1e3,1e6]; persistent work-stealing "
                             "scan, autotuned; RK4 h=1, six-integral correction, QM on",
                 "orbits": wl.n, "orbit_steps": wl.steps()}
+    if wl.name == "fig7":
+        return {"workload": "fig7: the paper's 314x314 (theta1, theta2) spin-angle plane, theta_i = 0.01k, "
+                            f"r0=10.14, p_y=0.365, beta=1, chi=1, QM on, t={wl.t_end:g}, RK4 h=1, "
+                            "six-integral correction, threshold 5.8",
+                "orbits": wl.n, "t_end": wl.t_end, "orbit_steps": wl.steps()}
     return {"workload": f"{wl.name}: {wl.shape[0]}x{wl.shape[1]} FLI scan, t={wl.t_end:g}, RK4 h=1, "
                         f"six-integral correction, beta={wl.beta:g}, chi={wl.chi1:g}, QM "
                         f"{'on' if wl.model.get('quad_mono', 1) else 'off'}",

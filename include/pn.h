@@ -227,8 +227,10 @@ pn_status pn_fli_scan(const pn_model* model, pn_params params, const pn_integrat
  * ------------------------------------------------------------------------- */
 
 /* Launch shape of the persistent batch kernel.  block: threads per workgroup
- * (64, 128 or 256); waves_per_simd: resident wavefronts per SIMD (1 or 2);
- * chunk_steps: steps a slot runs between refills (>= 1). */
+ * (64, 128 or 256); waves_per_simd: wavefronts per SIMD in the grid (1 or 2;
+ * with PN_RK4, 2 also selects the kernel build limited to 256 registers per
+ * lane so that two stay resident); chunk_steps: steps a slot runs between
+ * refills (>= 1). */
 typedef struct {
     int32_t block;
     int32_t waves_per_simd;
@@ -255,8 +257,8 @@ pn_status pn_batch_scan(const pn_model* model, pn_params params, const pn_integr
                         const double* y0, int64_t ld, const double* t_end, const pn_scan_out* out,
                         const pn_tuning* tuning, void* ws, size_t ws_bytes, hipStream_t stream);
 
-/* Project-written autotuner: times the batch for block in {64, 256} x
- * waves_per_simd in {1, 2} x chunk_steps in {64, 256, 1024} with every
+/* Project-written autotuner: times the batch for block in {64, 128, 256} x
+ * waves_per_simd in {1, 2} x chunk_steps in {32, 64, 256, 1024} with every
  * orbit's step count multiplied by step_scale (0 < step_scale <= 1), returns
  * the fastest in *best (and its time in *best_ms, nullable) and remembers it
  * for the current device.  Blocks the calling thread (synchronises the

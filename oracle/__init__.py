@@ -155,6 +155,20 @@ def invariants(y, beta, chi1, chi2, model=None):
     return out[:, 0].copy(), out[:, 1:].copy()
 
 
+def gw_polarizations(y, beta, chi1, chi2, N, p, dist=1.0, model=None):
+    """(h_plus[n], h_cross[n]) of eq. (14) for n states, observer direction N
+    and line of nodes p (unit, orthogonal), distance dist in units of M."""
+    y = _states(y)
+    b, c1, c2, s = _params(len(y), beta, chi1, chi2)
+    N = np.ascontiguousarray(N, dtype=np.float64)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    out = np.zeros((len(y), 2))
+    lib().or_gw_polarizations(ctypes.byref(_fill(_Model, MODEL, model)), _p(b), _p(c1), _p(c2),
+                              ctypes.c_int64(s), ctypes.c_int64(len(y)), _p(y), _p(N), _p(p),
+                              ctypes.c_double(dist), _p(out))
+    return out[:, 0].copy(), out[:, 1].copy()
+
+
 def init_state(r0, p0, th1, ph1, th2, ph2, beta, chi1, chi2, model=None):
     r0 = np.ascontiguousarray(np.atleast_1d(r0), dtype=np.float64)
     n = len(r0)

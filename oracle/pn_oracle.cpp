@@ -25,6 +25,7 @@
 //   Sec. 3B              iteration limit eps <= 1e-10
 //   Sec. 3C              two-nearby-trajectory FLI, threshold 5.8 at t = 1e5,
 //                        removal of unbounded / merged orbits
+//   Sec. 4, eq. (14)     gravitational-wave polarisations h_plus, h_cross
 // The orbital N/1PN/2PN and spin-orbit terms are not printed in the paper
 // (Sec. 2 cites them); the standard ADM-gauge expressions are used.  Every
 // reading of a silent or garbled passage is listed in the design notes.
@@ -955,6 +956,56 @@ void or_count_flops(const or_model* m, double beta, double chi1, double chi2,
     out[4] = (double)r.steps_done;
     out[5] = (double)r.newton_total;
     out[6] = (double)r.renorms;
+}
+
+// Gravitational-wave polarisations, Sec. 4, eq. (14), from the leading
+// (mass-quadrupole) radiation field written out as its definition:
+//   h_ij    = (4 eta / D) (v_i v_j - n_i n_j / r)      (G = c = M = 1, D in M)
+//   h^TT    = P h P - (1/2) P tr(P h),   P = I - N N^T   (transverse-traceless part)
+//   h_plus  = (1/2) (p_i p_j - q_i q_j) h^TT_ij
+//   h_cross = (1/2) (p_i q_j + q_i p_j) h^TT_ij,        q = N x p
+// with v = dr/dt = dH/dp (eq. 6) and eta = mu / M.  N points from the source to
+// the observer and p lies along the line of nodes (Sec. 4).  States y are n
+// rows of 12; out[2*i] = h_plus, out[2*i+1] = h_cross.
+void or_gw_polarizations(const or_model* m, const double* beta, const double* chi1, const double* chi2,
+                         int64_t pstride, int64_t n, const double* y, const double* N, const double* pn,
+                         double dist, double* out) {
+    double q[3] = {N[1] * pn[2] - N[2] * pn[1], N[2] * pn[0] - N[0] * pn[2], N[0] * pn[1] - N[1] * pn[0]};
+    double P[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) P[a][b] = (a == b ? 1.0 : 0.0) - N[a] * N[b];
+    for (int64_t i = 0; i < n; ++i) {
+        const Coef c = make_coef(*m, pick(beta, pstride, i), pick(chi1, pstride, i), pick(chi2, pstride, i));
+        const double* yi = y + 12 * i;
+        const Grad<double> g = gradient<double>(*m, c, yi);
+        const double v[3] = {g.dp.x, g.dp.y, g.dp.z};
+        const double r = std::sqrt(yi[0] * yi[0] + yi[1] * yi[1] + yi[2] * yi[2]);
+        const double nn[3] = {yi[0] / r, yi[1] / r, yi[2] / r};
+        double h[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) h[a][b] = 4.0 * c.eta / dist * (v[a] * v[b] - nn[a] * nn[b] / r);
+        double Ph[3][3], PhP[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                Ph[a][b] = 0.0;
+                for (int k = 0; k < 3; ++k) Ph[a][b] += P[a][k] * h[k][b];
+            }
+        double tr = Ph[0][0] + Ph[1][1] + Ph[2][2];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                PhP[a][b] = 0.0;
+                for (int k = 0; k < 3; ++k) PhP[a][b] += Ph[a][k] * P[k][b];
+            }
+        double hp = 0.0, hx = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                const double tt = PhP[a][b] - 0.5 * P[a][b] * tr;
+                hp += 0.5 * (pn[a] * pn[b] - q[a] * q[b]) * tt;
+                hx += 0.5 * (pn[a] * q[b] + q[a] * pn[b]) * tt;
+            }
+        out[2 * i] = hp;
+        out[2 * i + 1] = hx;
+    }
 }
 
 int32_t or_abi_version(void) { return 1; }

@@ -399,8 +399,8 @@ __global__ __launch_bounds__(256) void k_batch_bin_scatter(BatchWs ws, const dou
 // claim the next queue position (one atomic per wavefront), so long orbits,
 // started first, overlap with the short ones that fill the tail.  The
 // wavefront leaves when the queue is drained and all its slots are empty.
-template <int METHOD, int MODE>
-__global__ __launch_bounds__(256) void k_batch_scan(ParamArgs pa, FliArgs fa, BatchWs ws, int32_t chunk) {
+template <int METHOD, int MODE, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_batch_scan(ParamArgs pa, FliArgs fa, BatchWs ws, int32_t chunk) {
     const int lane = threadIdx.x & 63;
     const bool shadow = (lane & 1) != 0;
     const unsigned long long n = (unsigned long long)fa.n;
@@ -546,7 +546,17 @@ template <int METHOD, int MODE>
 void launch_batch(const ParamArgs& pa, const FliArgs& fa, const BatchWs& ws, const pn_tuning& tu, int ncu,
                   hipStream_t s) {
     const unsigned blocks = (unsigned)((int64_t)ncu * 4 * tu.waves_per_simd * 64 / tu.block);
-    hipLaunchKernelGGL((k_batch_scan<METHOD, MODE>), dim3(blocks), dim3(tu.block), 0, s, pa, fa, ws,
+    // Two resident waves per SIMD need <= 256 registers per lane: RK4 fits
+    // (a few bytes of spill at most); the six-stage RK5 would spill hundreds
+    // of bytes, so it keeps the one-wave build and only the grid grows.
+    if constexpr (METHOD == PN_RK4) {
+        if (tu.waves_per_simd == 2) {
+            hipLaunchKernelGGL((k_batch_scan<METHOD, MODE, 2>), dim3(blocks), dim3(tu.block), 0, s, pa, fa, ws,
+                               tu.chunk_steps);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_batch_scan<METHOD, MODE, 1>), dim3(blocks), dim3(tu.block), 0, s, pa, fa, ws,
                        tu.chunk_steps);
 }
 
@@ -870,9 +880,9 @@ pn_status pn_autotune_batch(const pn_model* model, pn_params params, const pn_in
         set_error("pn_autotune_batch", hipErrorOutOfMemory);
         return PN_EDEVICE;
     }
-    const int blocks[] = {64, 256};
+    const int blocks[] = {64, 128, 256};
     const int waves[] = {1, 2};
-    const int chunks[] = {64, 256, 1024};
+    const int chunks[] = {32, 64, 256, 1024};
     float best_t = 1e30f;
     pn_status st = PN_OK;
     for (int b : blocks)

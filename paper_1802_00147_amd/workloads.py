@@ -20,6 +20,15 @@ and kinds of axes:
              isotropic spin directions, r0 ~ U[8, 60], p0 = r0^-1/2,
              t_end = 10^U[3, 6].
 * grid4096 : 4096 x 4096 grid over (r0, theta) as grid64.
+* fig6     : the paper's spin-angle line (Sec. 3C, Fig. 6): theta2 = 0.01 k,
+             k = 0..313, theta1 = pi/2 (panel a) or 0 (panel b), phi = 0,
+             (beta, r, p_y) = (1/3, 5.65, 0.765), chi = 1, t = 1e5.  The
+             orbital energy of that state is positive; the spin terms make it
+             bound only at large theta2 (>= 2.21 in panel a, >= 2.51 in b),
+             and the scan removes the rest as UNBOUND_INIT.
+* fig7     : the paper's (theta1, theta2) plane (Sec. 3C, Fig. 7, Table 3):
+             314 x 314 points theta_i = 0.01 k, r = 10.14, p_y = 0.365,
+             beta = 1 (orbit 2 of Sec. 3A), chi = 1, t = 1e5.
 
 All orbits start at r = (r0, 0, 0), p = (0, p0, 0).
 """
@@ -103,6 +112,27 @@ def grid314(beta=1.0, quad_mono=1, t_end=1e6):
     return Workload(f"grid314_beta{beta:g}_qm{int(quad_mono)}", r0, S.ravel() * r0 ** -0.5,
                     np.full(n, 1.0), np.zeros(n), np.full(n, 1.325), np.zeros(n), float(beta), 1.0, 1.0,
                     float(t_end), model=dict(quad_mono=int(quad_mono)), shape=(314, 314))
+
+
+# Initial (beta, r0, p_y) of the paper's spin-angle scans (Sec. 3C).
+FIG6_STATE = (1.0 / 3.0, 5.65, 0.765)
+FIG7_STATE = (1.0, 10.14, 0.365)
+FIG_ANGLES = 0.01 * np.arange(314)      # 0 .. 3.13 rad in steps of 0.01
+
+
+def fig6(theta1=np.pi / 2, t_end=1e5):
+    beta, r, p = FIG6_STATE
+    n = FIG_ANGLES.size
+    return Workload(f"fig6_th1_{theta1:.4g}", np.full(n, r), np.full(n, p), np.full(n, float(theta1)),
+                    np.zeros(n), FIG_ANGLES.copy(), np.zeros(n), beta, 1.0, 1.0, float(t_end), shape=(1, n))
+
+
+def fig7(t_end=1e5):
+    beta, r, p = FIG7_STATE
+    T1, T2 = np.meshgrid(FIG_ANGLES, FIG_ANGLES, indexing="ij")
+    n = T1.size
+    return Workload("fig7", np.full(n, r), np.full(n, p), T1.ravel().copy(), np.zeros(n), T2.ravel().copy(),
+                    np.zeros(n), beta, 1.0, 1.0, float(t_end), shape=T1.shape)
 
 
 def batch(n=1_000_000, seed=4, tmin=1e3, tmax=1e6):

@@ -1,0 +1,118 @@
+"""The paper's accuracy studies (Sec. 3B: Table 2, Figs. 2 and 4) run on the
+GPU through the C ABI and set against the same studies on the oracle.
+
+* Table 2: RK5 (h = 1) to t = 1e4 on the four test orbits, corrected (SIX and
+  DUAL) and uncorrected.  Corrected energy errors stay at or below the
+  paper's printed order; the uncorrected error is truncation, the same on both
+  sides (1e-3 relative on the regular orbits, a factor of 2 on the chaotic
+  Case II orbit 2, whose trajectory itself is not reproducible to more).
+* Fig. 4: the dual scaling's iteration limit eps in {1e-6, 1e-8, 1e-10}:
+  energy errors at t = 1e3 .. 1e4 on the Case II orbits, bounded (no secular
+  growth) at every eps, on both sides.
+* Fig. 2: position error against a high-accuracy reference, here RK5 with
+  h = 1/16 (the paper's RKF8(9) tableau is not reproduced): both sides must
+  give the same error curve (10 % of the error, or the stated state parity
+  of 1e-10 of |r| per 1e3 of time if larger), and on both the corrected error
+  at t = 5e3 must be at least 5x below the uncorrected one.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_helpers import DEV
+from test_oracle_correction import load_table2, paper_state
+
+pytestmark = pytest.mark.gpu
+
+ROWS = load_table2()
+IDS = [f"{r['case']}-{r['orbit']}" for r in ROWS]
+
+
+@pytest.fixture(scope="module")
+def pn():
+    assert torch.cuda.is_available(), "GPU parity tests need a ROCm device"
+    from paper_1802_00147_amd import pn as P
+    P.lib()
+    return P
+
+
+def _setup(row):
+    y = paper_state(O, row["beta"], row["r0"], row["py"], row["chi"], row["chi"], row["s1"], row["s2"])
+    args = (row["beta"], row["chi"], row["chi"])
+    H0, J0 = O.invariants(y, *args)
+    ref = np.concatenate([H0, J0[0]])
+    return y, args, ref
+
+
+def _gpu_run(pn, y, args, ref, nsteps, chunks, integrator, correction):
+    """States (chunks, 12) after every `nsteps` steps on the GPU."""
+    yd = torch.tensor(y.reshape(12, 1), dtype=torch.float64, device=DEV).contiguous()
+    rd = torch.tensor(ref.reshape(4, 1), dtype=torch.float64, device=DEV).contiguous()
+    out = []
+    for _ in range(chunks):
+        pn.step(yd, *args, nsteps, integrator=integrator, correction=correction, ref=rd)
+        torch.cuda.synchronize()
+        out.append(yd[:, 0].cpu().numpy().copy())
+    return np.array(out)
+
+
+def _oracle_run(y, args, ref, nsteps, chunks, integrator, correction):
+    out, yc = [], y.copy()
+    for _ in range(chunks):
+        yc = O.step(yc, *args, nsteps, integrator=integrator, correction=correction, ref=ref)
+        out.append(yc[0].copy())
+    return np.array(out)
+
+
+def _energy_err(ys, args, E0):
+    return np.abs(O.hamiltonian(ys, *args) - E0) / abs(E0)
+
+
+@pytest.mark.parametrize("row", ROWS, ids=IDS)
+def test_table2_on_gpu(pn, row):
+    y, args, ref = _setup(row)
+    rk5 = dict(method="rk5")
+    for mode in ("six", "dual"):
+        g = _gpu_run(pn, y, args, ref, 10000, 1, rk5, dict(mode=mode))
+        assert _energy_err(g, args, ref[0])[-1] <= max(row["corrected"], 5e-15), mode
+    g = _gpu_run(pn, y, args, ref, 10000, 1, rk5, None)
+    o = _oracle_run(y, args, ref, 10000, 1, rk5, None)
+    eg, eo = _energy_err(g, args, ref[0])[-1], _energy_err(o, args, ref[0])[-1]
+    if row["case"] == "II" and row["orbit"] == 2:
+        assert 0.5 <= eg / eo <= 2.0, (eg, eo)
+    else:
+        assert abs(eg - eo) <= 1e-3 * eo, (eg, eo)
+
+
+@pytest.mark.parametrize("row", [r for r in ROWS if r["case"] == "II"], ids=["II-1", "II-2"])
+@pytest.mark.parametrize("eps", [1e-6, 1e-8, 1e-10])
+def test_fig4_dual_iteration_limit(pn, row, eps):
+    y, args, ref = _setup(row)
+    corr = dict(mode="dual", tol=eps)
+    rk5 = dict(method="rk5")
+    g = _energy_err(_gpu_run(pn, y, args, ref, 1000, 10, rk5, corr), args, ref[0])
+    o = _energy_err(_oracle_run(y, args, ref, 1000, 10, rk5, corr), args, ref[0])
+    for e in (g, o):
+        assert e.max() <= 1e-13, e
+        assert e[5:].max() <= 1e-13 and e[5:].mean() <= 10 * max(e[:5].mean(), 1e-15)
+
+
+@pytest.mark.parametrize("row", ROWS, ids=IDS)
+def test_fig2_position_error_vs_fine_reference(pn, row):
+    y, args, ref = _setup(row)
+    rk5, fine = dict(method="rk5"), dict(method="rk5", h=1.0 / 16)
+    rg = _gpu_run(pn, y, args, ref, 16000, 5, fine, None)
+    ro = _oracle_run(y, args, ref, 16000, 5, fine, None)
+    errs = {}
+    for mode in ("none", "six", "dual"):
+        corr = None if mode == "none" else dict(mode=mode)
+        dg = np.linalg.norm(_gpu_run(pn, y, args, ref, 1000, 5, rk5, corr)[:, :3] - rg[:, :3], axis=1)
+        do = np.linalg.norm(_oracle_run(y, args, ref, 1000, 5, rk5, corr)[:, :3] - ro[:, :3], axis=1)
+        r = np.linalg.norm(ro[:, :3], axis=1)
+        allow = 0.1 * do + 1e-10 * r * np.arange(1, 6)
+        assert np.all(np.abs(dg - do) <= allow), (mode, dg, do)
+        errs[mode] = (dg[-1], do[-1])
+    for side in (0, 1):
+        assert errs["none"][side] >= 5 * errs["six"][side], errs
+        assert errs["none"][side] >= 5 * errs["dual"][side], errs
