@@ -105,6 +105,49 @@ def cpu_baseline(wl, sample, flop_sample_steps=2000):
                 labels=res["label"], flops_per_orbit_step=float(np.mean(flops)))
 
 
+def gw_bench(args, dev):
+    """Gravitational-wave polarisations (eq. 14) of recorded trajectories: the
+    4,096 grid64 orbits integrated 2,000 steps (RK4, six-integral correction)
+    with every state recorded (untimed setup), then one benchmark step = one
+    pn_gw_polarizations launch over all 8.19e6 samples (face-on observer).
+    Algorithmic bytes per sample: 96 read + 16 written."""
+    import torch
+    from paper_1802_00147_amd import pn, workloads as W
+
+    wl = W.grid64()
+    cols = {k: torch.as_tensor(getattr(wl, k), device=dev) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")}
+    y = pn.init_state(cols["r0"], cols["p0"], cols["th1"], cols["ph1"], cols["th2"], cols["ph2"], 1.0, 1.0, 1.0)
+    rows = 2000
+    traj = pn.trajectory(y, 1.0, 1.0, 1.0, rows, 1, correction=dict(mode="six"))
+    torch.cuda.synchronize()
+    samples = rows * wl.n
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(max(args.warmup, 1)):
+        pn.gw_polarizations(traj, 1.0, 1.0, 1.0, [0, 0, 1], [1, 0, 0], dist=1.0)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        hp, hx = pn.gw_polarizations(traj, 1.0, 1.0, 1.0, [0, 0, 1], [1, 0, 0], dist=1.0)
+        b.record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    nbytes = samples * (96 + 16)
+    achieved = nbytes / (kernel_ms * 1e-3) / 1e9
+    line = dict(metric="GW polarisation samples/s (eq. 14, quadrupole field of recorded trajectories)",
+                value=samples * args.steps / elapsed, unit="samples/s", n_gpus=1, steps=args.steps,
+                warmup=args.warmup, ms_per_step=1e3 * elapsed / args.steps, higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+                config={"workload": f"gw: grid64 orbits (4096), {rows} recorded steps each, RK4 h=1, six-integral "
+                                    "correction; h_plus/h_cross for N=z, p=x", "samples": samples},
+                finite_fraction=float(torch.isfinite(hp).float().mean().item()),
+                roofline=dict(bound="hbm", achieved=achieved, peak=8000.0, unit="GB/s", frac=achieved / 8000.0,
+                              traffic=None, kernel="k_gw", kernel_ms=kernel_ms, bytes_per_sample=112))
+    print(json.dumps(line), flush=True)
+
+
 def surrogate_bench(args, dev):
     """Surrogate-assisted scan of the 4096 x 4096 (r0, theta) grid at t = 1e5
     against the plain FP64 scan.  The network is trained on the FP64 scan of
@@ -154,6 +197,26 @@ def surrogate_bench(args, dev):
         torch.cuda.synchronize()
         elapsed += time.perf_counter() - t0
 
+    # The network's own kernel: fused inference over every grid point against
+    # its matrix-core roofline (2 x 133,376 multiply-adds per point), and the
+    # layer-by-layer path it replaces.
+    feat = S.workload_features(grid, ts.stats, dev)
+    stream = torch.cuda.current_stream(dev)
+    inf = {}
+    for name, fn in (("fused", lambda: pn.mlp_infer_fused(net, feat)),
+                     ("layered", lambda: pn.mlp_infer(net, feat, chunk=1 << 20))):
+        fn()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+        for a, b in evs:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        inf[name + "_ms"] = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    del feat
+    inf_flops = 2.0 * (7 * 256 + 256 * 256 + 256 * 256 + 256 * 2) * grid.n
+    inf_achieved = inf_flops / (inf["fused_ms"] * 1e-3) / 1e12
+
     # Plain scan on a seeded sample of the grid: rate and label agreement.
     idx = W.strided_sample(grid.n, args.plain_sample, seed=17)
     sub = grid.subset(idx)
@@ -187,6 +250,10 @@ def surrogate_bench(args, dev):
     line["integrated_fraction"] = res.integrated / grid.n
     line["timings_s"] = dict(res.timings, training_data=data_s, training=train_s)
     line["train_loss"] = [round(h, 5) for h in hist]
+    line["inference_roofline"] = dict(bound="mfma", achieved=inf_achieved, peak=2500.0, unit="TFLOP/s",
+                                      frac=inf_achieved / 2500.0, traffic=None, kernel="k_mlp_fused",
+                                      kernel_ms=inf["fused_ms"], layered_ms=inf["layered_ms"],
+                                      flops_per_point=inf_flops / grid.n)
     if not args.no_cpu_baseline:
         sub_cpu = W.grid_r_theta(64, 64, grid.t_end, "grid64")   # same recipe at 4,096 points
         cb = cpu_baseline(sub_cpu, args.cpu_sample)
@@ -237,6 +304,9 @@ def main():
         del src, dst
     if args.workload == "surrogate4096":
         surrogate_bench(args, dev)
+        return
+    if args.workload == "gw":
+        gw_bench(args, dev)
         return
     wl = make_workload(args.workload)
     cols = {k: torch.as_tensor(getattr(wl, k), device=dev) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")}

@@ -216,11 +216,40 @@ pn_status pn_step(const pn_model* model, pn_params params, const pn_integrator* 
  * to t_end with a correction after every step, and report the FLI, the
  * chaos label and the status (Sec. 3C).  y0: [12][ld] (not modified).
  * t_end: [n] device array, or NULL to use t_end_all for every orbit.
- * All of one orbit's work happens in one GPU lane. */
+ * An orbit and its shadow run in two adjacent lanes of one wavefront. */
 pn_status pn_fli_scan(const pn_model* model, pn_params params, const pn_integrator* integ,
                       const pn_correction* corr, const pn_fli_cfg* fli, int64_t n,
                       const double* y0, int64_t ld, const double* t_end, double t_end_all,
                       const pn_scan_out* out, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Trajectories and gravitational waves (Sec. 4, eq. 14).
+ * ------------------------------------------------------------------------- */
+
+/* pn_step that also records the trajectory: after every `every` steps the
+ * state is written to row k of traj ([rows][12][ld], row k = state after
+ * (k + 1) * every steps, rows = nsteps / every).  traj: caller-owned device
+ * array of rows * 12 * ld doubles (may be NULL when rows == 0); every >= 1.
+ * y, ref, nsteps and errors as in pn_step. */
+pn_status pn_trajectory(const pn_model* model, pn_params params, const pn_integrator* integ,
+                        const pn_correction* corr, int64_t n, double* y, int64_t ld,
+                        const double* ref, int64_t nsteps, int64_t every, double* traj,
+                        hipStream_t stream);
+
+/* Gravitational-wave polarisations of eq. (14) from the leading
+ * (mass-quadrupole) radiation field h_ij = (4 eta / D)(v_i v_j - n_i n_j / r)
+ * (G = c = M = 1), with v = dr/dt = dH/dp of eq. (6) and eta = beta/(1+beta)^2:
+ *   h_plus = 1/2 (p_i p_j - q_i q_j) h^TT_ij,  h_cross = 1/2 (p_i q_j + q_i p_j) h^TT_ij,
+ * where N (nhat) points from the source to the observer, p (phat) lies along
+ * the line of nodes and q = N x p.  nhat, phat: host 3-vectors, unit length
+ * and orthogonal to 1e-12 (else PN_EINVAL).  dist: D in units of M (> 0).
+ * y: [ns][12][ld] device array, ns sample rows of n states (e.g. the traj of
+ * pn_trajectory); params per orbit (arrays of length >= n, indexed by the
+ * column) or shared.  hp, hx: [ns][ld] device outputs, caller-owned; a column
+ * whose per-orbit parameters are out of range gets NaN. */
+pn_status pn_gw_polarizations(const pn_model* model, pn_params params, int64_t n, int64_t ns,
+                              const double* y, int64_t ld, const double* nhat, const double* phat,
+                              double dist, double* hp, double* hx, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Batches of orbits of uneven length (persistent, work-stealing).
@@ -346,6 +375,13 @@ size_t pn_mlp_infer_workspace_size(int64_t chunk);
 /* Network outputs out [n][2] (FP32) for feat [n][8], `chunk` rows at a time. */
 pn_status pn_mlp_infer(const pn_mlp* net, const float* feat, int64_t n, float* out, int64_t chunk,
                        void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* The same outputs as pn_mlp_infer, bit for bit, from one persistent kernel
+ * that runs all four layers on 64-row tiles with the activations in LDS and
+ * the layer-2/3 weights in registers (a12: fused inference).  No workspace;
+ * feat [n][8], out [n][2] device arrays owned by the caller. */
+pn_status pn_mlp_infer_fused(const pn_mlp* net, const float* feat, int64_t n, float* out,
+                             hipStream_t stream);
 
 /* Gate of the surrogate-assisted scan: label[i] = (out[i][0] > 0), fli_pred[i]
  * = out[i][1] (nullable), and every point with |logit| < margin or drawn for

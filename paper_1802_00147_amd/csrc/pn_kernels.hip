@@ -14,15 +14,20 @@
 #include "pn.h"
 #include "pn_device.h"
 
+// Text of the last device error of the calling thread, shared by every
+// translation unit of the library and returned by pn_last_error().
+namespace pn_detail {
+thread_local char g_last_error[256] = "";
+void set_last_error(const char* what, const char* msg) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, msg);
+}
+}  // namespace pn_detail
+
 namespace {
 
 constexpr int kBlock = 64;  // one wavefront per workgroup
 
-thread_local char g_last_error[256] = "";
-
-void set_error(const char* what, hipError_t e) {
-    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
-}
+void set_error(const char* what, hipError_t e) { pn_detail::set_last_error(what, hipGetErrorString(e)); }
 
 // Parameters of a kernel: either per-orbit device arrays, or one shared
 // coefficient table computed on the host (held in scalar registers).
@@ -132,10 +137,12 @@ __global__ __launch_bounds__(kBlock) void k_correct(ParamArgs pa, CorrArgs ca, i
     if (iters) iters[i] = nc ? -it : it;
 }
 
+// nsteps corrected steps per orbit; with traj set, the state after every
+// `every` steps also goes to row (t / every - 1) of traj ([rows][12][ld]).
 template <int METHOD, int MODE>
 __global__ __launch_bounds__(kBlock) void k_step(ParamArgs pa, CorrArgs ca, double h, int64_t n,
                                                 double* y, int64_t ld, const double* ref,
-                                                int64_t nsteps) {
+                                                int64_t nsteps, double* traj, int64_t every) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     PnCoef k;
@@ -149,12 +156,59 @@ __global__ __launch_bounds__(kBlock) void k_step(ParamArgs pa, CorrArgs ca, doub
         if (MODE != PN_CORR_NONE) pn_correct_spins(k, s);
         capture_ref(k, s, r);
     }
+    int64_t left = every;
+    double* row = traj;
     for (int64_t t = 0; t < nsteps; ++t) {
         pn_rk_step<METHOD>(k, s, h);
         bool nc;
         pn_correct<MODE>(k, s, r, ca.tol, ca.max_iter, ca.sweeps, nc);
+        if (row != nullptr && --left == 0) {
+            store_state(row, ld, i, s);
+            row += 12 * ld;
+            left = every;
+        }
     }
     store_state(y, ld, i, s);
+}
+
+// Gravitational-wave polarisations (Sec. 4, eq. 14) of the mass-quadrupole
+// field h_ij = (4 eta / D)(v_i v_j - n_i n_j / r), v = dH/dp (eq. 6).  With p
+// and q transverse to the line of sight the contractions of eq. (14) see only
+// the transverse-traceless part, so they are taken on h_ij directly:
+//   h_plus  = (2 eta / D) [(p.v)^2 - (q.v)^2 - ((p.n)^2 - (q.n)^2) / r]
+//   h_cross = (4 eta / D) [(p.v)(q.v) - (p.n)(q.n) / r].
+// One thread per (sample row, orbit) of y[ns][12][ld].
+struct GwArgs {
+    double px, py, pz, qx, qy, qz;   // line of nodes p and q = N x p
+    double inv_dist;                 // 1 / D
+    double eta0;                     // eta of a shared parameter set
+};
+
+__global__ __launch_bounds__(256) void k_gw(ParamArgs pa, GwArgs ga, int64_t n, int64_t ns, const double* y,
+                                            int64_t ld, double* hp, double* hx) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n * ns) return;
+    const int64_t row = j / n, i = j - row * n;
+    PnCoef k;
+    const bool ok = load_coef(pa, i, k);
+    double eta = ga.eta0;
+    if (pa.beta != nullptr) {
+        const double b = pa.beta[i];
+        eta = b / ((1.0 + b) * (1.0 + b));
+    }
+    double s[12], f[12];
+    load_state(y + row * 12 * ld, ld, i, s);
+    pn_rhs_eval(k, s, f);
+    const double u = pn_rsqrt(dot3(s[0], s[1], s[2], s[0], s[1], s[2]));
+    const double pv = dot3(ga.px, ga.py, ga.pz, f[0], f[1], f[2]);
+    const double qv = dot3(ga.qx, ga.qy, ga.qz, f[0], f[1], f[2]);
+    const double pr = dot3(ga.px, ga.py, ga.pz, s[0], s[1], s[2]) * u;
+    const double qr = dot3(ga.qx, ga.qy, ga.qz, s[0], s[1], s[2]) * u;
+    const double a = eta * ga.inv_dist;
+    const double hplus = 2.0 * a * ((pv * pv - qv * qv) - (pr * pr - qr * qr) * u);
+    const double hcross = 4.0 * a * (pv * qv - pr * qr * u);
+    hp[row * ld + i] = ok ? hplus : __builtin_nan("");
+    hx[row * ld + i] = ok ? hcross : __builtin_nan("");
 }
 
 struct FliArgs {
@@ -511,19 +565,19 @@ pn_status launched(const char* what) {
 
 template <int METHOD, int MODE>
 void launch_step(const ParamArgs& pa, const CorrArgs& ca, double h, int64_t n, double* y, int64_t ld,
-                 const double* ref, int64_t nsteps, hipStream_t s) {
+                 const double* ref, int64_t nsteps, double* traj, int64_t every, hipStream_t s) {
     hipLaunchKernelGGL((k_step<METHOD, MODE>), dim3(grid_for(n)), dim3(kBlock), 0, s, pa, ca, h, n, y,
-                       ld, ref, nsteps);
+                       ld, ref, nsteps, traj, every);
 }
 
 template <int METHOD>
 void launch_step_m(int mode, const ParamArgs& pa, const CorrArgs& ca, double h, int64_t n, double* y,
-                   int64_t ld, const double* ref, int64_t nsteps, hipStream_t s) {
+                   int64_t ld, const double* ref, int64_t nsteps, double* traj, int64_t every, hipStream_t s) {
     switch (mode) {
-        case PN_CORR_NONE: launch_step<METHOD, PN_CORR_NONE>(pa, ca, h, n, y, ld, ref, nsteps, s); break;
-        case PN_CORR_SPIN: launch_step<METHOD, PN_CORR_SPIN>(pa, ca, h, n, y, ld, ref, nsteps, s); break;
-        case PN_CORR_SIX: launch_step<METHOD, PN_CORR_SIX>(pa, ca, h, n, y, ld, ref, nsteps, s); break;
-        default: launch_step<METHOD, PN_CORR_DUAL>(pa, ca, h, n, y, ld, ref, nsteps, s); break;
+        case PN_CORR_NONE: launch_step<METHOD, PN_CORR_NONE>(pa, ca, h, n, y, ld, ref, nsteps, traj, every, s); break;
+        case PN_CORR_SPIN: launch_step<METHOD, PN_CORR_SPIN>(pa, ca, h, n, y, ld, ref, nsteps, traj, every, s); break;
+        case PN_CORR_SIX: launch_step<METHOD, PN_CORR_SIX>(pa, ca, h, n, y, ld, ref, nsteps, traj, every, s); break;
+        default: launch_step<METHOD, PN_CORR_DUAL>(pa, ca, h, n, y, ld, ref, nsteps, traj, every, s); break;
     }
 }
 
@@ -714,7 +768,7 @@ const char* pn_status_string(pn_status s) {
     return "unknown status";
 }
 
-const char* pn_last_error(void) { return g_last_error; }
+const char* pn_last_error(void) { return pn_detail::g_last_error; }
 
 pn_status pn_init_state(const pn_model* model, pn_params params, int64_t n, const double* r0,
                         const double* p0, const double* th1, const double* ph1, const double* th2,
@@ -790,9 +844,9 @@ pn_status pn_manifold_correct(const pn_model* model, pn_params params, const pn_
     return launched("pn_manifold_correct");
 }
 
-pn_status pn_step(const pn_model* model, pn_params params, const pn_integrator* integ,
-                  const pn_correction* corr, int64_t n, double* y, int64_t ld, const double* ref,
-                  int64_t nsteps, hipStream_t stream) {
+static pn_status step_impl(const char* what, const pn_model* model, pn_params params, const pn_integrator* integ,
+                           const pn_correction* corr, int64_t n, double* y, int64_t ld, const double* ref,
+                           int64_t nsteps, double* traj, int64_t every, hipStream_t stream) {
     PN_REQUIRE(check_model(model) == PN_OK);
     PN_REQUIRE(check_integ(integ) == PN_OK);
     PN_REQUIRE(check_corr(corr) == PN_OK);
@@ -804,10 +858,55 @@ pn_status pn_step(const pn_model* model, pn_params params, const pn_integrator* 
     const int mode = corr ? corr->mode : PN_CORR_NONE;
     const CorrArgs ca = corr_args(corr);
     if (integ->method == PN_RK4)
-        launch_step_m<PN_RK4>(mode, pa, ca, integ->h, n, y, ld, ref, nsteps, stream);
+        launch_step_m<PN_RK4>(mode, pa, ca, integ->h, n, y, ld, ref, nsteps, traj, every, stream);
     else
-        launch_step_m<PN_RK5>(mode, pa, ca, integ->h, n, y, ld, ref, nsteps, stream);
-    return launched("pn_step");
+        launch_step_m<PN_RK5>(mode, pa, ca, integ->h, n, y, ld, ref, nsteps, traj, every, stream);
+    return launched(what);
+}
+
+pn_status pn_step(const pn_model* model, pn_params params, const pn_integrator* integ,
+                  const pn_correction* corr, int64_t n, double* y, int64_t ld, const double* ref,
+                  int64_t nsteps, hipStream_t stream) {
+    return step_impl("pn_step", model, params, integ, corr, n, y, ld, ref, nsteps, nullptr, 1, stream);
+}
+
+pn_status pn_trajectory(const pn_model* model, pn_params params, const pn_integrator* integ,
+                        const pn_correction* corr, int64_t n, double* y, int64_t ld, const double* ref,
+                        int64_t nsteps, int64_t every, double* traj, hipStream_t stream) {
+    PN_REQUIRE(every >= 1);
+    PN_REQUIRE(traj != nullptr || nsteps / every == 0 || n == 0);
+    return step_impl("pn_trajectory", model, params, integ, corr, n, y, ld, ref, nsteps,
+                     nsteps / every > 0 ? traj : nullptr, every, stream);
+}
+
+pn_status pn_gw_polarizations(const pn_model* model, pn_params params, int64_t n, int64_t ns, const double* y,
+                              int64_t ld, const double* nhat, const double* phat, double dist, double* hp,
+                              double* hx, hipStream_t stream) {
+    PN_REQUIRE(check_model(model) == PN_OK);
+    PN_REQUIRE(n >= 0 && ns >= 0 && ld >= n);
+    PN_REQUIRE(nhat != nullptr && phat != nullptr);
+    PN_REQUIRE(dist > 0.0 && is_fin(dist));
+    const double nn = nhat[0] * nhat[0] + nhat[1] * nhat[1] + nhat[2] * nhat[2];
+    const double pp = phat[0] * phat[0] + phat[1] * phat[1] + phat[2] * phat[2];
+    const double np = nhat[0] * phat[0] + nhat[1] * phat[1] + nhat[2] * phat[2];
+    PN_REQUIRE(std::fabs(nn - 1.0) <= 1e-12 && std::fabs(pp - 1.0) <= 1e-12 && std::fabs(np) <= 1e-12);
+    ParamArgs pa;
+    PN_REQUIRE(make_params(model, params, pa) == PN_OK);
+    if (n == 0 || ns == 0) return PN_OK;
+    PN_REQUIRE(y && hp && hx);
+    PN_REQUIRE(n <= (int64_t)1 << 40 && ns <= ((int64_t)1 << 62) / n);
+    GwArgs ga;
+    ga.px = phat[0]; ga.py = phat[1]; ga.pz = phat[2];
+    ga.qx = nhat[1] * phat[2] - nhat[2] * phat[1];       // q = N x p
+    ga.qy = nhat[2] * phat[0] - nhat[0] * phat[2];
+    ga.qz = nhat[0] * phat[1] - nhat[1] * phat[0];
+    ga.inv_dist = 1.0 / dist;
+    ga.eta0 = params.beta0 / ((1.0 + params.beta0) * (1.0 + params.beta0));
+    const int64_t total = n * ns;
+    const int64_t blocks = (total + 255) / 256;
+    PN_REQUIRE(blocks <= 0x7fffffffLL);
+    hipLaunchKernelGGL(k_gw, dim3((unsigned)blocks), dim3(256), 0, stream, pa, ga, n, ns, y, ld, hp, hx);
+    return launched("pn_gw_polarizations");
 }
 
 pn_status pn_fli_scan(const pn_model* model, pn_params params, const pn_integrator* integ,

@@ -20,6 +20,10 @@
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
+namespace pn_detail {
+void set_last_error(const char* what, const char* msg);   // pn_kernels.hip
+}
+
 namespace {
 
 constexpr int BM = 64, BN = 64, BK = 32, LDSK = BK + 8;
@@ -27,7 +31,6 @@ constexpr int kIn[4] = {7, 256, 256, 256};
 constexpr int kOut[4] = {256, 256, 256, 2};
 constexpr int kFeatLd = 8;     // feature rows are padded to 8 values
 
-thread_local char g_mlp_error[256] = "";
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
     uint32_t u = __float_as_uint(f);
@@ -120,6 +123,144 @@ __global__ __launch_bounds__(256) void k_gather_rows(const float* feat, const in
     const int c = (int)(e % kFeatLd);
     const int64_t r = idx ? (int64_t)idx[b] : row0 + b;
     X[e] = c < 7 ? f2bf(feat[r * kFeatLd + c]) : (uint16_t)0;
+}
+
+// Fused inference: all four layers of 64-row tiles in one persistent kernel.
+// A 512-thread workgroup (8 wavefronts, two per SIMD) keeps the bfloat16
+// fragments of W2 and W3 in registers for its whole life -- wavefront w owns
+// output columns 32w .. 32w+31 of both layers, 2 column blocks x 8 K-slices
+// of 16x16x32 MFMA B operands -- and walks row tiles; activations stay in LDS
+// (two 64 x 256 buffers, rows padded by 16 bytes), never in HBM.  Per tile:
+// layer 1 (K = 7 padded to one 32-deep slice, A straight from the features),
+// layers 2-3 from LDS, layer 4 (2 outputs padded to a 16-column block) on
+// wavefronts 0-3, one row block each.  The products, their order of
+// accumulation over K-slices, the bias/ReLU epilogues and the bfloat16
+// rounding between layers are those of k_gemm_bf16, so the result equals the
+// layer-by-layer path bit for bit.
+constexpr int FT = 64;              // rows per tile
+constexpr int FLD = 256 + 8;        // LDS row stride of an activation buffer (elements)
+
+__device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t* p) {
+    return *reinterpret_cast<const bf16x8*>(p);
+}
+
+__global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ w0, const uint16_t* __restrict__ w1,
+                                                   const uint16_t* __restrict__ w2, const uint16_t* __restrict__ w3,
+                                                   const float* __restrict__ b0, const float* __restrict__ b1,
+                                                   const float* __restrict__ b2, const float* __restrict__ b3,
+                                                   const float* __restrict__ feat, int64_t n, float* __restrict__ out) {
+    __shared__ __attribute__((aligned(16))) uint16_t hA[FT][FLD];
+    __shared__ __attribute__((aligned(16))) uint16_t hB[FT][FLD];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lq = lane >> 4, lk = lq * 8;
+    const int c0 = 32 * wave;                         // first output column of this wavefront
+
+    // Register-resident B fragments of layers 2 and 3: column c0 + 16 j + lr,
+    // K values 32 s + lk .. + 8 (weights are [out][in], K contiguous).
+    bf16x8 wf[2][2][8];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int sl = 0; sl < 8; ++sl) {
+            const int col = c0 + 16 * j + lr;
+            wf[0][j][sl] = load_bf16x8(w1 + (int64_t)col * 256 + 32 * sl + lk);
+            wf[1][j][sl] = load_bf16x8(w2 + (int64_t)col * 256 + 32 * sl + lk);
+        }
+    // Layer 1 fragments (K = 7; only the lanes of K-group 0 carry values).
+    bf16x8 wf0[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int col = c0 + 16 * j + lr;
+        uint16_t v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = (lq == 0 && t < 7) ? w0[col * 7 + t] : (uint16_t)0;
+        wf0[j] = *reinterpret_cast<const bf16x8*>(v);
+    }
+    float bias[3][2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        bias[0][j] = b0[c0 + 16 * j + lr];
+        bias[1][j] = b1[c0 + 16 * j + lr];
+        bias[2][j] = b2[c0 + 16 * j + lr];
+    }
+    const float bias3 = lr < 2 ? b3[lr] : 0.0f;
+
+    const int64_t ntiles = (n + FT - 1) / FT;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = tile * FT;
+        f32x4 acc[4][2];
+        // Layer 1: A fragment of row block i straight from the FP32 features.
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t row = r0 + 16 * i + lr;
+            uint16_t v[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                v[t] = (lq == 0 && t < 7 && row < n) ? f2bf(feat[row * kFeatLd + t]) : (uint16_t)0;
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(v);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wf0[j], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        }
+        // Epilogue: bias, ReLU, bfloat16 into an LDS buffer.
+        auto store = [&](uint16_t (*h)[FLD], int layer) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        h[16 * i + 4 * lq + v][c0 + 16 * j + lr] = f2bf(fmaxf(acc[i][j][v] + bias[layer][j], 0.0f));
+        };
+        store(hA, 0);
+        __syncthreads();
+        // Layers 2 and 3: A fragments from LDS, B fragments from registers.
+#pragma unroll
+        for (int layer = 1; layer < 3; ++layer) {
+            uint16_t (*hin)[FLD] = layer == 1 ? hA : hB;
+            uint16_t (*hout)[FLD] = layer == 1 ? hB : hA;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int sl = 0; sl < 8; ++sl) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const bf16x8 a = load_bf16x8(&hin[16 * i + lr][32 * sl + lk]);
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wf[layer - 1][j][sl], acc[i][j], 0, 0, 0);
+                }
+            }
+            store(hout, layer);
+            __syncthreads();
+        }
+        // Layer 4 on wavefronts 0-3 (row block = wavefront), outputs 0 and 1.
+        if (wave < 4) {
+            f32x4 o = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int sl = 0; sl < 8; ++sl) {
+                const bf16x8 a = load_bf16x8(&hA[16 * wave + lr][32 * sl + lk]);
+                bf16x8 b;
+                if (lr < 2) {
+                    b = load_bf16x8(w3 + (int64_t)lr * 256 + 32 * sl + lk);
+                } else {
+                    uint16_t z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                    b = *reinterpret_cast<const bf16x8*>(z);
+                }
+                o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, o, 0, 0, 0);
+            }
+            if (lr < 2) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t row = r0 + 16 * wave + 4 * lq + v;
+                    if (row < n) out[row * 2 + lr] = o[v] + bias3;
+                }
+            }
+        }
+        __syncthreads();   // hA is rewritten by the next tile's layer 1
+    }
 }
 
 // Loss of a batch and its gradient with respect to the two outputs:
@@ -284,7 +425,7 @@ void gemm(hipStream_t s, int M, int N, int K, const uint16_t* A, int64_t sam, in
 pn_status launched(const char* what) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
-        std::snprintf(g_mlp_error, sizeof(g_mlp_error), "%s: %s", what, hipGetErrorString(e));
+        pn_detail::set_last_error(what, hipGetErrorString(e));
         return PN_EDEVICE;
     }
     return PN_OK;
@@ -419,6 +560,23 @@ pn_status pn_mlp_infer(const pn_mlp* net, const float* feat, int64_t n, float* o
         forward(stream, net, rows, X, h[0], h[1], h[2], out + 2 * r0);
     }
     return launched("pn_mlp_infer");
+}
+
+pn_status pn_mlp_infer_fused(const pn_mlp* net, const float* feat, int64_t n, float* out, hipStream_t stream) {
+    if (!net_ok(net, false) || n < 0) return PN_EINVAL;
+    if (n == 0) return PN_OK;
+    if (!feat || !out) return PN_EINVAL;
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0) {
+        pn_detail::set_last_error("pn_mlp_infer_fused", "no device");
+        return PN_EDEVICE;
+    }
+    const int64_t ntiles = (n + FT - 1) / FT;
+    const unsigned grid = (unsigned)(ntiles < ncu ? ntiles : ncu);
+    hipLaunchKernelGGL(k_mlp_fused, dim3(grid), dim3(512), 0, stream, net->wb[0], net->wb[1], net->wb[2],
+                       net->wb[3], net->b[0], net->b[1], net->b[2], net->b[3], feat, n, out);
+    return launched("pn_mlp_infer_fused");
 }
 
 pn_status pn_mlp_features(pn_params params, int64_t n, const double* r0, const double* th1, const double* th2,

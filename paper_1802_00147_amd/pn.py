@@ -78,6 +78,7 @@ EXPORTS = ["pn_default_model", "pn_default_integrator", "pn_default_correction",
            "pn_mlp_param_count", "pn_mlp_sync_bf16", "pn_mlp_features", "pn_mlp_train_workspace_size",
            "pn_mlp_train_step", "pn_mlp_infer_workspace_size", "pn_mlp_infer", "pn_surrogate_gate",
            "pn_surrogate_merge", "pn_gemm_bf16", "pn_init_state_gather", "pn_mlp_targets",
+           "pn_trajectory", "pn_gw_polarizations", "pn_mlp_infer_fused",
            "pn_version", "pn_status_string", "pn_last_error"]
 
 
@@ -95,7 +96,8 @@ def lib():
                      "pn_fli_scan", "pn_batch_scan", "pn_autotune_batch", "pn_batch_graph_create",
                      "pn_graph_launch", "pn_mlp_sync_bf16", "pn_mlp_features", "pn_mlp_train_step",
                      "pn_mlp_infer", "pn_surrogate_gate", "pn_surrogate_merge", "pn_gemm_bf16",
-                     "pn_init_state_gather", "pn_mlp_targets"):
+                     "pn_init_state_gather", "pn_mlp_targets", "pn_trajectory", "pn_gw_polarizations",
+                     "pn_mlp_infer_fused"):
             getattr(L, name).restype = ctypes.c_int
         for name in ("pn_mlp_param_count", "pn_mlp_train_workspace_size", "pn_mlp_infer_workspace_size"):
             getattr(L, name).restype = ctypes.c_size_t
@@ -259,6 +261,45 @@ def scan_outputs(n, ld, device, full=True, trace_every=0, nsteps_max=0):
         o["trace"] = torch.full((ntrace, ld), float("nan"), dtype=torch.float64, device=device)
         o["trace_every"] = trace_every
     return o
+
+
+def trajectory(y, beta, chi1, chi2, nsteps, every, model=None, integrator=None, correction=None, ref=None,
+               n=None):
+    """pn_step that also returns the states after every `every` steps as a
+    (nsteps // every, 12, ld) tensor; y advances in place."""
+    ld = _state(y)
+    n = ld if n is None else n
+    rows = nsteps // every
+    traj = torch.empty((rows, 12, ld), dtype=torch.float64, device=y.device)
+    if ref is not None:
+        assert ref.shape == (4, ld) and ref.dtype == torch.float64 and ref.is_contiguous()
+    p, keep = params_struct(beta, chi1, chi2)
+    cc = ctypes.byref(correction_struct(correction)) if correction is not None else None
+    st = lib().pn_trajectory(ctypes.byref(model_struct(model)), p, ctypes.byref(integrator_struct(integrator)), cc,
+                             ctypes.c_int64(n), _ptr(y), ctypes.c_int64(ld), _ptr(ref), ctypes.c_int64(nsteps),
+                             ctypes.c_int64(every), _ptr(traj) if rows > 0 else None, _stream(y.device))
+    _check("pn_trajectory", st)
+    return traj
+
+
+def gw_polarizations(traj, beta, chi1, chi2, nhat, phat, dist=1.0, model=None, n=None):
+    """(h_plus, h_cross), each (ns, ld), of eq. (14) for states traj (ns, 12, ld)
+    or (12, ld)."""
+    if traj.dim() == 2:
+        traj = traj.unsqueeze(0)
+    assert traj.dim() == 3 and traj.shape[1] == 12 and traj.dtype == torch.float64 and traj.is_contiguous()
+    ns, _, ld = traj.shape
+    n = ld if n is None else n
+    hp = torch.empty((ns, ld), dtype=torch.float64, device=traj.device)
+    hx = torch.empty_like(hp)
+    p, keep = params_struct(beta, chi1, chi2)
+    N3 = (ctypes.c_double * 3)(*[float(v) for v in nhat])
+    P3 = (ctypes.c_double * 3)(*[float(v) for v in phat])
+    st = lib().pn_gw_polarizations(ctypes.byref(model_struct(model)), p, ctypes.c_int64(n), ctypes.c_int64(ns),
+                                   _ptr(traj), ctypes.c_int64(ld), N3, P3, ctypes.c_double(dist), _ptr(hp), _ptr(hx),
+                                   _stream(traj.device))
+    _check("pn_gw_polarizations", st)
+    return hp, hx
 
 
 def fli_scan(y0, t_end, beta, chi1, chi2, model=None, integrator=None, correction=None, fli=None,
@@ -476,6 +517,17 @@ def mlp_infer(net, feat, chunk=1 << 20, out=None, ws=None):
     st = lib().pn_mlp_infer(ctypes.byref(net.struct), _ptr(feat), ctypes.c_int64(n), _ptr(out), ctypes.c_int64(chunk),
                             _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(feat.device))
     _check("pn_mlp_infer", st)
+    return out
+
+
+def mlp_infer_fused(net, feat, out=None):
+    """pn_mlp_infer_fused: all four layers in one kernel; same bits as mlp_infer."""
+    n = feat.shape[0]
+    if out is None:
+        out = torch.empty((n, 2), dtype=torch.float32, device=feat.device)
+    st = lib().pn_mlp_infer_fused(ctypes.byref(net.struct), _ptr(feat), ctypes.c_int64(n), _ptr(out),
+                                  _stream(feat.device))
+    _check("pn_mlp_infer_fused", st)
     return out
 
 

@@ -106,7 +106,7 @@ def _integrate(wl, lst, device, model=None):
     return pn.fli_scan(y0, wl.t_end, wl.beta, wl.chi1, wl.chi2, model=model, full=False)
 
 
-def surrogate_scan(net, wl, stats, margin=0.5, audit=0.01, seed=5, model=None, chunk=1 << 20,
+def surrogate_scan(net, wl, stats, margin=0.5, audit=0.01, seed=5, model=None,
                    refine_epochs=0, refine_batch=2048, refine_lr=5e-4, refine_seed=51):
     """Labels of every point of the grid workload `wl`.
 
@@ -145,7 +145,7 @@ def surrogate_scan(net, wl, stats, margin=0.5, audit=0.01, seed=5, model=None, c
     torch.cuda.synchronize()
     t["refine_s"] = time.perf_counter() - t1
     t2 = time.perf_counter()
-    out = pn.mlp_infer(net, feat, chunk=chunk)
+    out = pn.mlp_infer_fused(net, feat)
     label, _, lst, m = pn.surrogate_gate(out, margin, 0.0, seed)
     torch.cuda.synchronize()
     t["infer_gate_s"] = time.perf_counter() - t2

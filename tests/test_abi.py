@@ -111,6 +111,38 @@ def test_invalid_scan_settings_rejected(pn):
     assert scan(out=bad_trace) == pn.PN_EINVAL
 
 
+def test_invalid_trajectory_and_gw_arguments_rejected(pn):
+    L = pn.lib()
+    m = ctypes.byref(pn.model_struct())
+    p = pn.Params(None, None, None, 1.0, 1.0, 1.0)
+    one = ctypes.c_void_p(8)
+
+    def traj(every=1, traj_ptr=one, nsteps=4):
+        return L.pn_trajectory(m, p, ctypes.byref(pn.integrator_struct()), None, ctypes.c_int64(4), one,
+                               ctypes.c_int64(4), None, ctypes.c_int64(nsteps), ctypes.c_int64(every),
+                               traj_ptr, None)
+
+    assert traj(every=0) == pn.PN_EINVAL
+    assert traj(every=-3) == pn.PN_EINVAL
+    assert traj(traj_ptr=None) == pn.PN_EINVAL          # rows = 4 need a buffer
+
+    def gw(nhat=(0, 0, 1), phat=(1, 0, 0), dist=10.0, n=4, ns=2, ld=4):
+        N3 = (ctypes.c_double * 3)(*nhat)
+        P3 = (ctypes.c_double * 3)(*phat)
+        return L.pn_gw_polarizations(m, p, ctypes.c_int64(n), ctypes.c_int64(ns), one, ctypes.c_int64(ld),
+                                     N3, P3, ctypes.c_double(dist), one, one, None)
+
+    assert gw(nhat=(0, 0, 2)) == pn.PN_EINVAL             # not unit
+    assert gw(phat=(1, 0, 0.01)) == pn.PN_EINVAL          # not unit, not transverse
+    assert gw(phat=(0, 0, 1)) == pn.PN_EINVAL             # along the line of sight
+    assert gw(dist=0.0) == pn.PN_EINVAL
+    assert gw(dist=float("inf")) == pn.PN_EINVAL
+    assert gw(n=8, ld=4) == pn.PN_EINVAL
+    assert gw(ns=-1) == pn.PN_EINVAL
+    assert gw(n=0, ld=0) == pn.PN_OK                      # nothing to do
+    assert gw(ns=0) == pn.PN_OK
+
+
 def test_missing_library_fails_loudly(monkeypatch):
     from paper_1802_00147_amd import pn as P
     monkeypatch.setattr(P, "_lib", None)

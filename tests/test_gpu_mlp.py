@@ -100,6 +100,27 @@ def test_forward_matches_oracle(pn):
     assert err.max() <= 5e-3 * scale     # rare one-ulp bfloat16 flips of hidden activations
 
 
+@pytest.mark.parametrize("n", [1, 63, 64, 3000, 70001])
+def test_fused_inference_equals_layer_by_layer(pn, n):
+    """The fused kernel runs the same products in the same order with the same
+    epilogues as the per-layer path: bitwise equal outputs, ragged tails
+    included (70,001 rows also spread tiles over every workgroup several
+    times), and the oracle bound of the forward test."""
+    rng = np.random.default_rng(80 + n)
+    net, params = _network(pn)
+    X = rng.normal(size=(n, 7))
+    feat = np.zeros((n, 8), dtype=np.float32)
+    feat[:, :7] = X
+    f = dev(feat, torch.float32)
+    a = pn.mlp_infer(net, f, chunk=4096)
+    b = pn.mlp_infer_fused(net, f)
+    torch.cuda.synchronize()
+    assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+    ref, _ = M.forward(_as_f32(params), X.astype(np.float32).astype(np.float64), bf16=True)
+    err = np.abs(b.cpu().numpy() - ref)
+    assert np.median(err) <= 1e-5 * np.abs(ref).max()
+
+
 def test_train_step_matches_oracle(pn):
     rng = np.random.default_rng(9)
     net, params = _network(pn)
