@@ -183,9 +183,11 @@ def surrogate_bench(args, dev):
             dst.copy_(src)
         net.step = base_step
 
+    ws = None
     for _ in range(args.warmup):
         restore()
-        S.surrogate_scan(net, grid, ts.stats, margin=args.margin, audit=0.01, seed=5, refine_epochs=args.refine)
+        ws = S.surrogate_scan(net, grid, ts.stats, margin=args.margin, audit=0.01, seed=5,
+                              refine_epochs=args.refine, ws=ws).ws
     res = None
     elapsed = 0.0
     for _ in range(args.steps):
@@ -193,7 +195,8 @@ def surrogate_bench(args, dev):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = S.surrogate_scan(net, grid, ts.stats, margin=args.margin, audit=0.01, seed=5,
-                               refine_epochs=args.refine)
+                               refine_epochs=args.refine, ws=ws)
+        ws = res.ws
         torch.cuda.synchronize()
         elapsed += time.perf_counter() - t0
 

@@ -404,6 +404,58 @@ pn_status pn_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, int64
                        const uint16_t* mask, int64_t ldm, float* Cf, int64_t ldcf, uint16_t* Cb,
                        int64_t ldcb, hipStream_t stream);
 
+/* Settings of pn_surrogate_scan (defaults from pn_default_surrogate_cfg). */
+typedef struct {
+    float margin;            /* points with |logit| < margin are integrated (0.5) */
+    double audit_frac;       /* audit: SplitMix64(seed + i) / 2^64 < audit_frac (0.01) */
+    uint64_t seed;           /* audit seed (5) */
+    int32_t refine_epochs;   /* passes of training on the integrated audit (3; 0: none) */
+    int32_t refine_batch;    /* samples per refinement step (2048) */
+    float refine_lr;         /* Adam learning rate of the refinement (5e-4) */
+    uint64_t refine_seed;    /* SplitMix64 seed of the sample order (51) */
+} pn_surrogate_cfg;
+
+void pn_default_surrogate_cfg(pn_surrogate_cfg* cfg);
+
+/* Bytes of workspace for pn_surrogate_scan over n points (0 if n is out of
+ * range or refine_batch <= 0). */
+size_t pn_surrogate_scan_workspace_size(int64_t n, int32_t refine_batch);
+
+/* The surrogate-assisted scan (a12) of n points, end to end on the stream:
+ *  1. features of every point (pn_mlp_features with mean/stdv);
+ *  2. the audit sample (SplitMix64(seed + i) / 2^64 < audit_frac), sorted by
+ *     point index, integrated by the persistent batch scan (pn_batch_scan,
+ *     cached tuning);
+ *  3. refine_epochs passes of training (pn_mlp_train_step, Adam steps counted
+ *     in *adam_step) on the valid audited orbits, in an order drawn from
+ *     SplitMix64(refine_seed) (Fisher-Yates per epoch), when at least
+ *     refine_batch of them were drawn;
+ *  4. fused inference (pn_mlp_infer_fused); label[i] = (logit > 0);
+ *  5. points with |logit| < margin not in the audit are integrated;
+ *     integrated labels (-1 for removed orbits) replace the network's.
+ * Point i has initial data r0[i], p0[i], th1[i], ph1[i], th2[i], ph2[i] (as
+ * pn_init_state), parameters `params` (shared or per point), end time
+ * t_end[i] or t_end_all.  label: [n] int8 device output; *integrated: host
+ * output, the number of points integrated; points (nullable): [n] int32
+ * device output whose first *integrated entries are the integrated points
+ * (the sorted audit, then the uncertain ones); phase_ms (nullable): host
+ * float[4], milliseconds of the audit (features, draw, integration), the
+ * refinement, inference with the gate, and the fallback integration.  net is
+ * updated by the
+ * refinement.  ws: caller-owned device workspace of at least
+ * pn_surrogate_scan_workspace_size(n, cfg->refine_batch) bytes.  Blocks the
+ * calling thread (it reads the audit and gate counts back); calls sharing a
+ * workspace or a network must not overlap.  Errors: PN_EINVAL for invalid
+ * arguments (checked before anything is launched), PN_ENOWS, PN_EDEVICE. */
+pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* model, pn_params params,
+                            const pn_integrator* integ, const pn_correction* corr,
+                            const pn_fli_cfg* fli, int64_t n, const double* r0, const double* p0,
+                            const double* th1, const double* ph1, const double* th2,
+                            const double* ph2, const double* t_end, double t_end_all,
+                            const float* mean, const float* stdv, const pn_surrogate_cfg* cfg,
+                            int8_t* label, int32_t* points, int64_t* integrated, float* phase_ms,
+                            void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Initial states of selected points: like pn_init_state, but point j takes
  * row idx[j] of r0, p0, th1, ph1, th2, ph2 (and of per-orbit parameters). */
 pn_status pn_init_state_gather(const pn_model* model, pn_params params, int64_t m, const int32_t* idx,

@@ -14,6 +14,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
+#include <vector>
 
 #include "pn.h"
 
@@ -402,6 +404,37 @@ __global__ __launch_bounds__(256) void k_gate(const float* out, int64_t n, float
     }
 }
 
+__device__ __forceinline__ bool audit_draw(uint64_t seed, int64_t i, double audit) {
+    return (double)(splitmix64(seed + (uint64_t)i) >> 11) * 0x1.0p-53 < audit;
+}
+
+// The audit sample alone: points with SplitMix64(seed + i) / 2^64 < audit.
+__global__ __launch_bounds__(256) void k_audit(int64_t n, double audit, unsigned long long seed, int32_t* list,
+                                               unsigned long long* count) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    if (audit_draw(seed, i, audit)) list[atomicAdd(count, 1ull)] = (int32_t)i;
+}
+
+// Network labels, and the uncertain points (|logit| < margin) that the audit
+// has not already drawn.
+__global__ __launch_bounds__(256) void k_gate_uncertain(const float* out, int64_t n, float margin, double audit,
+                                                        unsigned long long seed, int8_t* label, int32_t* list,
+                                                        unsigned long long* count) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float z = out[2 * i];
+    label[i] = z > 0.0f ? 1 : 0;
+    if (fabsf(z) < margin && !audit_draw(seed, i, audit)) list[atomicAdd(count, 1ull)] = (int32_t)i;
+}
+
+// dst[j] = src[idx[j]] (src NULL: fill).
+__global__ __launch_bounds__(256) void k_gather_f64(const double* src, double fill, const int32_t* idx, int64_t m,
+                                                    double* dst) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j < m) dst[j] = src ? src[idx[j]] : fill;
+}
+
 __global__ __launch_bounds__(256) void k_merge(const int32_t* list, int64_t m, const int8_t* integrated,
                                                int8_t* label) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -643,6 +676,229 @@ pn_status pn_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, int64
     if ((Cf && ldcf < N) || (Cb && ldcb < N) || (mask && ldm < N)) return PN_EINVAL;
     gemm(stream, M, N, K, A, sam, sak, B, sbk, sbn, bias, relu, mask, ldm, Cf, ldcf, Cb, ldcb);
     return launched("pn_gemm_bf16");
+}
+
+void pn_default_surrogate_cfg(pn_surrogate_cfg* c) {
+    if (!c) return;
+    c->margin = 0.5f;
+    c->audit_frac = 0.01;
+    c->seed = 5;
+    c->refine_epochs = 3;
+    c->refine_batch = 2048;
+    c->refine_lr = 5e-4f;
+    c->refine_seed = 51;
+}
+
+size_t pn_surrogate_scan_workspace_size(int64_t n, int32_t refine_batch) {
+    if (n <= 0 || n > 0x7fffffffLL || refine_batch <= 0) return 0;
+    const size_t N = (size_t)n;
+    return 2 * al(N * kFeatLd * 4) + al(N * 2 * 4) + 3 * al(N * 4) + al(2 * 8) + al(12 * N * 8) + 4 * al(N * 8) +
+           al(N * 8) + al(N) + al(N * 4) + 2 * al(N * 4) + al(4) + pn_batch_workspace_size(n) +
+           pn_mlp_train_workspace_size(refine_batch);
+}
+
+}  // extern "C"
+
+namespace {
+
+// SplitMix64 stream for the host-side order of the refinement samples.
+struct SplitMix {
+    uint64_t s;
+    uint64_t next() {
+        uint64_t x = (s += 0x9e3779b97f4a7c15ull);
+        x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+        x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+        return x ^ (x >> 31);
+    }
+};
+
+#define PN_TRY(call)                                  \
+    do {                                              \
+        const pn_status st_ = (call);                 \
+        if (st_ != PN_OK) return st_;                 \
+    } while (0)
+
+#define PN_HIP(call, what)                                                        \
+    do {                                                                          \
+        const hipError_t e_ = (call);                                             \
+        if (e_ != hipSuccess) {                                                   \
+            pn_detail::set_last_error(what, hipGetErrorString(e_));               \
+            return PN_EDEVICE;                                                    \
+        }                                                                         \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* model, pn_params params,
+                            const pn_integrator* integ, const pn_correction* corr, const pn_fli_cfg* fli,
+                            int64_t n, const double* r0, const double* p0, const double* th1, const double* ph1,
+                            const double* th2, const double* ph2, const double* t_end, double t_end_all,
+                            const float* mean, const float* stdv, const pn_surrogate_cfg* cfg, int8_t* label,
+                            int32_t* points, int64_t* integrated, float* phase_ms, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
+    const char* what = "pn_surrogate_scan";
+    if (!cfg || !label || !integrated || n < 0 || n > 0x7fffffffLL) return PN_EINVAL;
+    if (!(cfg->margin >= 0.0f) || !(cfg->audit_frac >= 0.0 && cfg->audit_frac <= 1.0)) return PN_EINVAL;
+    if (cfg->refine_epochs < 0 || cfg->refine_batch <= 0) return PN_EINVAL;
+    if (cfg->refine_epochs > 0 && (!adam_step || *adam_step < 0 || !(cfg->refine_lr > 0.0f))) return PN_EINVAL;
+    if (!net_ok(net, cfg->refine_epochs > 0)) return PN_EINVAL;
+    if (!r0 || !p0 || !th1 || !ph1 || !th2 || !ph2 || !mean || !stdv) return PN_EINVAL;
+    if (!t_end && !(t_end_all > 0.0 && std::isfinite(t_end_all))) return PN_EINVAL;
+    for (int c = 0; c < 7; ++c)
+        if (!(stdv[c] > 0.0f) || !std::isfinite(stdv[c]) || !std::isfinite(mean[c])) return PN_EINVAL;
+    {   // model, parameters, integrator, correction and FLI settings: the scan's own checks, nothing launched
+        pn_scan_out so0;
+        std::memset(&so0, 0, sizeof(so0));
+        if (pn_fli_scan(model, params, integ, corr, fli, 0, nullptr, 0, nullptr, 1.0, &so0, stream) != PN_OK)
+            return PN_EINVAL;
+    }
+    *integrated = 0;
+    if (n == 0) return PN_OK;
+    if (!ws || ws_bytes < pn_surrogate_scan_workspace_size(n, cfg->refine_batch)) return PN_ENOWS;
+    const size_t N = (size_t)n;
+    char* p = static_cast<char*>(ws);
+    auto take = [&](size_t bytes) { char* q = p; p += al(bytes); return q; };
+    float* feat = (float*)take(N * kFeatLd * 4);
+    float* featA = (float*)take(N * kFeatLd * 4);
+    float* out = (float*)take(N * 2 * 4);
+    int32_t* listA = (int32_t*)take(N * 4);
+    int32_t* listU = (int32_t*)take(N * 4);
+    int32_t* order = (int32_t*)take(N * 4);
+    unsigned long long* counts = (unsigned long long*)take(2 * 8);
+    double* y0 = (double*)take(12 * N * 8);
+    double* gp[4];
+    for (int c = 0; c < 4; ++c) gp[c] = (double*)take(N * 8);
+    double* sfli = (double*)take(N * 8);
+    int8_t* slab = (int8_t*)take(N);
+    int32_t* sstat = (int32_t*)take(N * 4);
+    float* labA = (float*)take(N * 4);
+    float* tgtA = (float*)take(N * 4);
+    float* loss = (float*)take(4);
+    void* bws = take(pn_batch_workspace_size(n));
+    void* tws = take(pn_mlp_train_workspace_size(cfg->refine_batch));
+    const bool per_orbit = params.beta != nullptr;
+
+    // Integrate the m listed points with the persistent batch kernel (a10),
+    // labels into slab[0..m).
+    auto integrate = [&](const int32_t* list, int64_t m) -> pn_status {
+        PN_TRY(pn_init_state_gather(model, params, m, list, r0, p0, th1, ph1, th2, ph2, y0, m, stream));
+        const unsigned g = blocks_for(m, 256);
+        hipLaunchKernelGGL(k_gather_f64, dim3(g), dim3(256), 0, stream, t_end, t_end_all, list, m, gp[3]);
+        pn_params q = params;
+        if (per_orbit) {
+            hipLaunchKernelGGL(k_gather_f64, dim3(g), dim3(256), 0, stream, params.beta, 0.0, list, m, gp[0]);
+            hipLaunchKernelGGL(k_gather_f64, dim3(g), dim3(256), 0, stream, params.chi1, 0.0, list, m, gp[1]);
+            hipLaunchKernelGGL(k_gather_f64, dim3(g), dim3(256), 0, stream, params.chi2, 0.0, list, m, gp[2]);
+            q.beta = gp[0]; q.chi1 = gp[1]; q.chi2 = gp[2];
+        }
+        PN_TRY(launched(what));
+        pn_scan_out so;
+        std::memset(&so, 0, sizeof(so));
+        so.fli = sfli; so.label = slab; so.status = sstat;
+        return pn_batch_scan(model, q, integ, corr, fli, m, y0, m, gp[3], &so, nullptr, bws,
+                             pn_batch_workspace_size(m), stream);
+    };
+
+    // Phase timing (host array phase_ms[4]: audit, refinement, inference and
+    // gate, fallback integration), from events on the stream.
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    struct EventGuard {
+        hipEvent_t* e;
+        ~EventGuard() { for (int k = 0; k < 5; ++k) if (e[k]) (void)hipEventDestroy(e[k]); }
+    } guard{ev};
+    if (phase_ms)
+        for (int k = 0; k < 5; ++k) PN_HIP(hipEventCreate(&ev[k]), what);
+    auto mark = [&](int k) -> pn_status {
+        if (phase_ms) PN_HIP(hipEventRecord(ev[k], stream), what);
+        return PN_OK;
+    };
+    PN_TRY(mark(0));
+    // 1. Features of every point; the audit list, sorted so that everything
+    //    derived from it is independent of the order of the atomic appends.
+    PN_TRY(pn_mlp_features(params, n, r0, th1, th2, t_end, t_end_all, nullptr, mean, stdv, feat, stream));
+    hipLaunchKernelGGL(k_clear_count, dim3(1), dim3(1), 0, stream, counts);
+    hipLaunchKernelGGL(k_clear_count, dim3(1), dim3(1), 0, stream, counts + 1);
+    hipLaunchKernelGGL(k_audit, dim3(blocks_for(n, 256)), dim3(256), 0, stream, n, cfg->audit_frac,
+                       (unsigned long long)cfg->seed, listA, counts);
+    PN_TRY(launched(what));
+    unsigned long long cnt = 0;
+    PN_HIP(hipMemcpyAsync(&cnt, counts, 8, hipMemcpyDeviceToHost, stream), what);
+    PN_HIP(hipStreamSynchronize(stream), what);
+    const int64_t ma = (int64_t)cnt;
+    std::vector<int32_t> host(ma > 0 ? (size_t)ma : 1);
+    if (ma > 0) {
+        PN_HIP(hipMemcpyAsync(host.data(), listA, (size_t)ma * 4, hipMemcpyDeviceToHost, stream), what);
+        PN_HIP(hipStreamSynchronize(stream), what);
+        std::sort(host.begin(), host.begin() + ma);
+        PN_HIP(hipMemcpyAsync(listA, host.data(), (size_t)ma * 4, hipMemcpyHostToDevice, stream), what);
+        // 2. Integrate the audit.
+        PN_TRY(integrate(listA, ma));
+    }
+    PN_TRY(mark(1));
+    // 3. Refine the network on the integrated audit (valid orbits only), in a
+    //    SplitMix64-seeded order per epoch.
+    if (cfg->refine_epochs > 0 && ma >= cfg->refine_batch) {
+        PN_TRY(pn_mlp_features(params, ma, r0, th1, th2, t_end, t_end_all, listA, mean, stdv, featA, stream));
+        if (t_end) {
+            PN_TRY(pn_mlp_targets(sfli, slab, gp[3], 0.0, ma, labA, tgtA, stream));
+        } else {
+            PN_TRY(pn_mlp_targets(sfli, slab, nullptr, t_end_all, ma, labA, tgtA, stream));
+        }
+        std::vector<int32_t> st((size_t)ma);
+        PN_HIP(hipMemcpyAsync(st.data(), sstat, (size_t)ma * 4, hipMemcpyDeviceToHost, stream), what);
+        PN_HIP(hipStreamSynchronize(stream), what);
+        std::vector<int32_t> valid;
+        valid.reserve((size_t)ma);
+        for (int64_t j = 0; j < ma; ++j)
+            if ((st[(size_t)j] & 0xFF) == 0) valid.push_back((int32_t)j);
+        const int64_t nb = (int64_t)valid.size() / cfg->refine_batch;
+        SplitMix rng{cfg->refine_seed};
+        std::vector<int32_t> ord(valid);
+        for (int32_t e = 0; e < cfg->refine_epochs && nb > 0; ++e) {
+            for (size_t k = ord.size(); k > 1; --k) {          // Fisher-Yates
+                const size_t r = (size_t)(rng.next() % k);
+                std::swap(ord[k - 1], ord[r]);
+            }
+            PN_HIP(hipMemcpyAsync(order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, stream), what);
+            for (int64_t b = 0; b < nb; ++b) {
+                *adam_step += 1;
+                PN_TRY(pn_mlp_train_step(net, featA, labA, tgtA, order + b * cfg->refine_batch, cfg->refine_batch,
+                                         *adam_step, cfg->refine_lr, loss, tws,
+                                         pn_mlp_train_workspace_size(cfg->refine_batch), stream));
+            }
+            PN_HIP(hipStreamSynchronize(stream), what);        // ord is reshuffled next epoch
+        }
+    }
+    PN_TRY(mark(2));
+    // 4. Inference and the gate of the uncertain, not audited points.
+    PN_TRY(pn_mlp_infer_fused(net, feat, n, out, stream));
+    hipLaunchKernelGGL(k_gate_uncertain, dim3(blocks_for(n, 256)), dim3(256), 0, stream, out, n, cfg->margin,
+                       cfg->audit_frac, (unsigned long long)cfg->seed, label, listU, counts + 1);
+    PN_TRY(launched(what));
+    // The audit's labels (in slab) are merged before the next scan reuses it.
+    if (ma > 0) PN_TRY(pn_surrogate_merge(listA, ma, slab, label, stream));
+    PN_HIP(hipMemcpyAsync(&cnt, counts + 1, 8, hipMemcpyDeviceToHost, stream), what);
+    PN_HIP(hipStreamSynchronize(stream), what);
+    const int64_t mu = (int64_t)cnt;
+    PN_TRY(mark(3));
+    // 5. Integrate the uncertain points; their labels replace the network's.
+    if (mu > 0) {
+        PN_TRY(integrate(listU, mu));
+        PN_TRY(pn_surrogate_merge(listU, mu, slab, label, stream));
+    }
+    if (points) {
+        if (ma > 0) PN_HIP(hipMemcpyAsync(points, listA, (size_t)ma * 4, hipMemcpyDeviceToDevice, stream), what);
+        if (mu > 0) PN_HIP(hipMemcpyAsync(points + ma, listU, (size_t)mu * 4, hipMemcpyDeviceToDevice, stream), what);
+    }
+    PN_TRY(mark(4));
+    if (phase_ms) {
+        PN_HIP(hipEventSynchronize(ev[4]), what);
+        for (int k = 0; k < 4; ++k) PN_HIP(hipEventElapsedTime(&phase_ms[k], ev[k], ev[k + 1]), what);
+    }
+    *integrated = ma + mu;
+    return PN_OK;
 }
 
 }  // extern "C"

@@ -64,6 +64,12 @@ class ScanOut(ctypes.Structure):
                 ("trace", ctypes.c_void_p), ("trace_every", ctypes.c_int64), ("ntrace", ctypes.c_int64)]
 
 
+class SurrogateCfg(ctypes.Structure):
+    _fields_ = [("margin", ctypes.c_float), ("audit_frac", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("refine_epochs", ctypes.c_int32), ("refine_batch", ctypes.c_int32), ("refine_lr", ctypes.c_float),
+                ("refine_seed", ctypes.c_uint64)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32), ("chunk_steps", ctypes.c_int32)]
 
@@ -79,6 +85,7 @@ EXPORTS = ["pn_default_model", "pn_default_integrator", "pn_default_correction",
            "pn_mlp_train_step", "pn_mlp_infer_workspace_size", "pn_mlp_infer", "pn_surrogate_gate",
            "pn_surrogate_merge", "pn_gemm_bf16", "pn_init_state_gather", "pn_mlp_targets",
            "pn_trajectory", "pn_gw_polarizations", "pn_mlp_infer_fused",
+           "pn_default_surrogate_cfg", "pn_surrogate_scan_workspace_size", "pn_surrogate_scan",
            "pn_version", "pn_status_string", "pn_last_error"]
 
 
@@ -97,8 +104,10 @@ def lib():
                      "pn_graph_launch", "pn_mlp_sync_bf16", "pn_mlp_features", "pn_mlp_train_step",
                      "pn_mlp_infer", "pn_surrogate_gate", "pn_surrogate_merge", "pn_gemm_bf16",
                      "pn_init_state_gather", "pn_mlp_targets", "pn_trajectory", "pn_gw_polarizations",
-                     "pn_mlp_infer_fused"):
+                     "pn_mlp_infer_fused", "pn_surrogate_scan"):
             getattr(L, name).restype = ctypes.c_int
+        L.pn_surrogate_scan_workspace_size.restype = ctypes.c_size_t
+        L.pn_surrogate_scan_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int32]
         for name in ("pn_mlp_param_count", "pn_mlp_train_workspace_size", "pn_mlp_infer_workspace_size"):
             getattr(L, name).restype = ctypes.c_size_t
         L.pn_mlp_param_count.argtypes = [ctypes.c_int32, ctypes.c_int32]
@@ -529,6 +538,49 @@ def mlp_infer_fused(net, feat, out=None):
                                   _stream(feat.device))
     _check("pn_mlp_infer_fused", st)
     return out
+
+
+def surrogate_cfg(over=None):
+    s = SurrogateCfg()
+    lib().pn_default_surrogate_cfg(ctypes.byref(s))
+    for k, v in (over or {}).items():
+        setattr(s, k, v)
+    return s
+
+
+def surrogate_scan(net, n, r0, p0, th1, ph1, th2, ph2, t_end, beta, chi1, chi2, mean, std, cfg=None, model=None,
+                   integrator=None, correction=None, fli=None, ws=None):
+    """pn_surrogate_scan: dict(label int8 [n], integrated, points int32 [integrated],
+    phase_ms [audit, refine, infer+gate, fallback], ws).  The network is refined
+    in place (net.step counts its Adam steps)."""
+    dev_ = r0.device
+    c = surrogate_cfg(cfg)
+    need = int(lib().pn_surrogate_scan_workspace_size(n, c.refine_batch))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev_)
+    label = torch.empty(max(n, 1), dtype=torch.int8, device=dev_)
+    points = torch.empty(max(n, 1), dtype=torch.int32, device=dev_)
+    phase = (ctypes.c_float * 4)()
+    p, keep = params_struct(beta, chi1, chi2)
+    mean = (ctypes.c_float * 7)(*[float(x) for x in mean])
+    std = (ctypes.c_float * 7)(*[float(x) for x in std])
+    if isinstance(t_end, torch.Tensor):
+        tptr, tall = _ptr(_dev_f64(t_end)), 0.0
+    else:
+        tptr, tall = None, float(t_end)
+    cols = [_dev_f64(t) for t in (r0, p0, th1, ph1, th2, ph2)]
+    step = ctypes.c_int32(net.step)
+    integrated = ctypes.c_int64(0)
+    st = lib().pn_surrogate_scan(ctypes.byref(net.struct), ctypes.byref(step), ctypes.byref(model_struct(model)), p,
+                                 ctypes.byref(integrator_struct(integrator)),
+                                 ctypes.byref(correction_struct(correction)), ctypes.byref(fli_struct(fli)),
+                                 ctypes.c_int64(n), *[_ptr(t) for t in cols], tptr, ctypes.c_double(tall), mean, std,
+                                 ctypes.byref(c), _ptr(label), _ptr(points), ctypes.byref(integrated), phase,
+                                 _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(dev_))
+    _check("pn_surrogate_scan", st)
+    net.step = step.value
+    m = integrated.value
+    return dict(label=label[:n], integrated=m, points=points[:m], phase_ms=list(phase), ws=ws)
 
 
 def surrogate_gate(out, margin, audit_frac, seed):

@@ -3,11 +3,10 @@ FP64 scan itself produced predicts the chaos label of scan points; points it
 is unsure of, and a random audit sample, are integrated, and the integrated
 labels win.
 
-Orchestration only: features, training steps, inference, gating, initial
-states, the fallback scan and the merge all run in the library's kernels
-(include/pn.h); this module moves tensors between those calls and holds the
-host-side bookkeeping of a data loader (feature statistics, the seeded order
-of training samples).
+The assisted scan itself is one library call (pn_surrogate_scan); training
+on a finished scan is a loop of pn_mlp_train_step calls.  This module holds
+the host-side bookkeeping of a data loader: feature statistics and the seeded
+order of training samples.
 """
 import time
 from dataclasses import dataclass, field
@@ -96,67 +95,31 @@ class SurrogateResult:
     integrated: int              # number of points integrated
     points: torch.Tensor         # their indices (int32)
     timings: dict = field(default_factory=dict)
-
-
-def _integrate(wl, lst, device, model=None):
-    """FP64 scan of the listed grid points; returns its output tensors."""
-    cols = {k: torch.as_tensor(getattr(wl, k), device=device) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")}
-    y0 = pn.init_state_gather(lst, cols["r0"], cols["p0"], cols["th1"], cols["ph1"], cols["th2"], cols["ph2"],
-                              _dev(wl.beta, device), _dev(wl.chi1, device), _dev(wl.chi2, device), model=model)
-    return pn.fli_scan(y0, wl.t_end, wl.beta, wl.chi1, wl.chi2, model=model, full=False)
+    ws: object = None            # the device workspace, reusable by the next call
 
 
 def surrogate_scan(net, wl, stats, margin=0.5, audit=0.01, seed=5, model=None,
-                   refine_epochs=0, refine_batch=2048, refine_lr=5e-4, refine_seed=51):
-    """Labels of every point of the grid workload `wl`.
+                   refine_epochs=0, refine_batch=2048, refine_lr=5e-4, refine_seed=51, ws=None):
+    """Labels of every point of the workload `wl` through pn_surrogate_scan:
 
-    1. The audit sample (SplitMix64(seed + i) / 2^64 < audit) is integrated.
-    2. With refine_epochs > 0 the network is first trained further on those
-       integrated points (FLIs the method produced on this very scan).
-    3. Inference on every point; points with |logit| < margin are integrated.
-    4. Integrated labels replace the network's wherever they exist.
+    1. the audit sample (SplitMix64(seed + i) / 2^64 < audit) is integrated;
+    2. with refine_epochs > 0 the network is first trained further on those
+       integrated points (FLIs the method produced on this very scan);
+    3. fused inference on every point; points with |logit| < margin are
+       integrated;
+    4. integrated labels replace the network's wherever they exist.
     """
     device = net.w[0].device
-    t = {}
+    cols = {k: torch.as_tensor(getattr(wl, k), device=device) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")}
+    cfg = dict(margin=margin, audit_frac=audit, seed=seed, refine_epochs=refine_epochs, refine_batch=refine_batch,
+               refine_lr=refine_lr, refine_seed=refine_seed)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    feat = workload_features(wl, stats, device)
-    zeros = torch.zeros((wl.n, 2), dtype=torch.float32, device=device)
-    _, _, audit_lst, ma = pn.surrogate_gate(zeros, 0.0, audit, seed)   # margin 0: the audit draw only
-    del zeros
-    audit_lst = audit_lst.clone()
-    sa = _integrate(wl, audit_lst, device, model) if ma > 0 else None
+    r = pn.surrogate_scan(net, wl.n, cols["r0"], cols["p0"], cols["th1"], cols["ph1"], cols["th2"], cols["ph2"],
+                          _dev(wl.t_end, device), _dev(wl.beta, device), _dev(wl.chi1, device),
+                          _dev(wl.chi2, device), stats.mean, stats.std, cfg=cfg, model=model, ws=ws)
     torch.cuda.synchronize()
-    t["audit_s"] = time.perf_counter() - t0
-    t1 = time.perf_counter()
-    if refine_epochs > 0 and ma >= refine_batch:
-        fa = workload_features(wl, stats, device, idx=audit_lst)
-        la, ta = pn.mlp_targets(sa["fli"][:ma], sa["label"][:ma], _dev(wl.t_end, device))
-        st = sa["status"][:ma].cpu().numpy()
-        valid = np.nonzero((st & 0xFF) == 0)[0]
-        rng = np.random.default_rng(refine_seed)
-        loss = torch.zeros(1, dtype=torch.float32, device=device)
-        ws = None
-        for _ in range(refine_epochs):
-            order = torch.as_tensor(rng.permutation(valid).astype(np.int32), device=device)
-            for b in range(len(valid) // refine_batch):
-                ws = pn.mlp_train_step(net, fa, la, ta, order[b * refine_batch:(b + 1) * refine_batch], refine_lr,
-                                       loss, ws)
-    torch.cuda.synchronize()
-    t["refine_s"] = time.perf_counter() - t1
-    t2 = time.perf_counter()
-    out = pn.mlp_infer_fused(net, feat)
-    label, _, lst, m = pn.surrogate_gate(out, margin, 0.0, seed)
-    torch.cuda.synchronize()
-    t["infer_gate_s"] = time.perf_counter() - t2
-    t3 = time.perf_counter()
-    if m > 0:
-        su = _integrate(wl, lst, device, model)
-        pn.surrogate_merge(lst, su["label"][:m], label)
-    if ma > 0:
-        pn.surrogate_merge(audit_lst, sa["label"][:ma], label)
-    torch.cuda.synchronize()
-    t["fallback_s"] = time.perf_counter() - t3
-    t["total_s"] = time.perf_counter() - t0
-    points = torch.cat([audit_lst, lst]) if m > 0 else audit_lst
-    return SurrogateResult(label, ma + m, points, t)
+    ph = r["phase_ms"]
+    t = dict(audit_s=ph[0] * 1e-3, refine_s=ph[1] * 1e-3, infer_gate_s=ph[2] * 1e-3, fallback_s=ph[3] * 1e-3,
+             total_s=time.perf_counter() - t0)
+    return SurrogateResult(r["label"], r["integrated"], r["points"], t, r["ws"])

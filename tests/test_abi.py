@@ -143,6 +143,42 @@ def test_invalid_trajectory_and_gw_arguments_rejected(pn):
     assert gw(ns=0) == pn.PN_OK
 
 
+def test_invalid_surrogate_scan_arguments_rejected(pn):
+    L = pn.lib()
+    one = ctypes.c_void_p(8)
+    mean = (ctypes.c_float * 7)(*([0.0] * 7))
+    std = (ctypes.c_float * 7)(*([1.0] * 7))
+    bad_std = (ctypes.c_float * 7)(*([1.0] * 6 + [0.0]))
+    net = pn.Mlp(*[pn.P4(*([8] * 4)) for _ in range(7)])
+    step = ctypes.c_int32(0)
+    integrated = ctypes.c_int64(-1)
+
+    def scan(cfg=None, n=4, t_all=1.0, std_=std, model=None, corr=None, ws=one, ws_bytes=1 << 40):
+        c = pn.surrogate_cfg(cfg)
+        return L.pn_surrogate_scan(ctypes.byref(net), ctypes.byref(step), ctypes.byref(pn.model_struct(model)),
+                                   pn.Params(None, None, None, 1.0, 1.0, 1.0), ctypes.byref(pn.integrator_struct()),
+                                   ctypes.byref(pn.correction_struct(corr)), ctypes.byref(pn.fli_struct()),
+                                   ctypes.c_int64(n), one, one, one, one, one, one, None, ctypes.c_double(t_all),
+                                   mean, std_, ctypes.byref(c), one, None, ctypes.byref(integrated), None, ws,
+                                   ctypes.c_size_t(ws_bytes), None)
+
+    assert scan(cfg=dict(margin=-1.0)) == pn.PN_EINVAL
+    assert scan(cfg=dict(audit_frac=1.5)) == pn.PN_EINVAL
+    assert scan(cfg=dict(refine_batch=0)) == pn.PN_EINVAL
+    assert scan(cfg=dict(refine_lr=0.0)) == pn.PN_EINVAL
+    assert scan(t_all=0.0) == pn.PN_EINVAL
+    assert scan(std_=bad_std) == pn.PN_EINVAL
+    assert scan(model=dict(pn_order=5)) == pn.PN_EINVAL
+    assert scan(corr=dict(mode=9)) == pn.PN_EINVAL
+    assert scan(n=-1) == pn.PN_EINVAL
+    assert scan(ws=None) == pn.PN_ENOWS
+    assert scan(ws_bytes=16) == pn.PN_ENOWS
+    assert scan(n=0) == pn.PN_OK and integrated.value == 0
+    assert L.pn_surrogate_scan_workspace_size(0, 2048) == 0
+    assert L.pn_surrogate_scan_workspace_size(1000, 0) == 0
+    assert L.pn_surrogate_scan_workspace_size(1000, 2048) > 1000 * (8 * 4 * 2 + 12 * 8)
+
+
 def test_missing_library_fails_loudly(monkeypatch):
     from paper_1802_00147_amd import pn as P
     monkeypatch.setattr(P, "_lib", None)

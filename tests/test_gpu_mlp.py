@@ -240,3 +240,32 @@ def test_surrogate_scan_small_end_to_end(pn):
     assert res.integrated == len(pts) >= 0.03 * grid.n
     assert np.array_equal(got[pts], ref[pts])
     assert np.mean(got == ref) >= 0.97
+
+
+@pytest.mark.parametrize("margin,audit", [(1e30, 0.0), (0.0, 0.2), (0.3, 0.05)])
+def test_native_surrogate_scan_per_point_parameters(pn, margin, audit):
+    """pn_surrogate_scan on points with their own mass ratio, spins and end
+    times (gathered for the fallback batch scan): every integrated point
+    carries exactly the plain batch scan's label; margin 1e30 integrates all
+    points, margin 0 only the audit; the audit draw is the oracle's."""
+    from paper_1802_00147_amd import surrogate as S, workloads as W
+    wl = W.batch(n=3000, seed=33, tmin=200.0, tmax=1500.0)
+    cols = [dev(getattr(wl, k)) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")]
+    b, c1, c2, t = (dev(getattr(wl, k)) for k in ("beta", "chi1", "chi2", "t_end"))
+    plain = pn.batch_scan(pn.init_state(*cols, b, c1, c2), t, b, c1, c2, full=False)
+    net, _ = _network(pn)
+    stats = S.feature_stats(wl)
+    r = pn.surrogate_scan(net, wl.n, *cols, t, b, c1, c2, stats.mean, stats.std,
+                          cfg=dict(margin=margin, audit_frac=audit, seed=9, refine_epochs=0))
+    torch.cuda.synchronize()
+    got, ref = r["label"].cpu().numpy(), plain["label"].cpu().numpy()
+    pts = r["points"].cpu().numpy()
+    assert len(set(pts.tolist())) == len(pts) == r["integrated"]
+    assert np.array_equal(got[pts], ref[pts])
+    drawn = M.gate(np.zeros((wl.n, 2)), 0.0, audit, 9)[1]          # the oracle's audit draw
+    assert set(drawn.tolist()) <= set(pts.tolist())
+    if margin > 1e29:
+        assert r["integrated"] == wl.n and np.array_equal(got, ref)
+    if margin == 0.0:
+        assert np.array_equal(np.sort(pts), drawn)
+    assert all(x >= 0 for x in r["phase_ms"])
