@@ -57,7 +57,59 @@ struct GemmArgs {
     uint16_t* Cb;              // bfloat16 result or null
     int64_t ldcb;
     int relu;
+    int amode, bmode;          // operand staging: 0 element-wise, 1 K contiguous, 2 M (N) contiguous
 };
+
+// Staging modes of an operand whose element (r, k) -- r the row of the
+// output tile (m for A, n for B) -- sits at p[r * sr + k * sk]:
+//   1: K contiguous (sk = 1, sr a multiple of 8, 16-byte aligned base):
+//      one 16-byte load of 8 K values per thread;
+//   2: r contiguous (sr = 1, sk a multiple of 8, aligned): one 16-byte load
+//      of 8 rows at one K per thread, transposed into LDS;
+//   0: element by element.
+int stage_mode(const uint16_t* p, int64_t sr, int64_t sk) {
+    const bool aligned = (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+    if (aligned && sk == 1 && sr % 8 == 0) return 1;
+    if (aligned && sr == 1 && sk % 8 == 0) return 2;
+    return 0;
+}
+
+// Fill tile[64][LDSK] (row r, K offset c) with element (r0 + r, k0 + c) of
+// the operand, zero outside [0, R) x [0, K).
+__device__ __forceinline__ void stage_tile(uint16_t (*tile)[LDSK], const uint16_t* p, int64_t sr, int64_t sk,
+                                           int mode, int64_t r0, int64_t R, int64_t k0, int64_t K, int tid) {
+    if (mode == 1) {
+        const int r = tid >> 2, c = (tid & 3) * 8;
+        const int64_t row = r0 + r, k = k0 + c;
+        union { uint4 v; uint16_t e[8]; } u;
+        if (row < R && k + 8 <= K) {
+            u.v = *reinterpret_cast<const uint4*>(p + row * sr + k);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) u.e[t] = (row < R && k + t < K) ? p[row * sr + (k + t)] : (uint16_t)0;
+        }
+        *reinterpret_cast<uint4*>(&tile[r][c]) = u.v;
+    } else if (mode == 2) {
+        const int c = tid >> 3, r = (tid & 7) * 8;
+        const int64_t row = r0 + r, k = k0 + c;
+        union { uint4 v; uint16_t e[8]; } u;
+        if (k < K && row + 8 <= R) {
+            u.v = *reinterpret_cast<const uint4*>(p + row + k * sk);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) u.e[t] = (k < K && row + t < R) ? p[(row + t) + k * sk] : (uint16_t)0;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) tile[r + t][c] = u.e[t];
+    } else {
+#pragma unroll
+        for (int e = tid; e < 64 * BK; e += 256) {
+            const int r = e / BK, c = e % BK;
+            const int64_t row = r0 + r, k = k0 + c;
+            tile[r][c] = (row < R && k < K) ? p[row * sr + k * sk] : (uint16_t)0;
+        }
+    }
+}
 
 // C = A B (+ bias) (ReLU) (* mask), M x N, FP32 accumulation.
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
@@ -73,18 +125,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < g.K; k0 += BK) {
-#pragma unroll
-        for (int e = tid; e < BM * BK; e += 256) {
-            const int r = e / BK, c = e % BK;
-            const int64_t m = m0 + r, k = k0 + c;
-            As[r][c] = (m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : (uint16_t)0;
-        }
-#pragma unroll
-        for (int e = tid; e < BN * BK; e += 256) {
-            const int r = e / BK, c = e % BK;
-            const int64_t n = n0 + r, k = k0 + c;
-            Bt[r][c] = (n < g.N && k < g.K) ? g.B[k * g.sbk + n * g.sbn] : (uint16_t)0;
-        }
+        stage_tile(As, g.A, g.sam, g.sak, g.amode, m0, g.M, k0, g.K, tid);
+        stage_tile(Bt, g.B, g.sbn, g.sbk, g.bmode, n0, g.N, k0, g.K, tid);
         __syncthreads();
         bf16x8 a[2], b[2];
 #pragma unroll
@@ -452,6 +494,8 @@ void gemm(hipStream_t s, int M, int N, int K, const uint16_t* A, int64_t sam, in
     g.B = B; g.sbk = sbk; g.sbn = sbn;
     g.bias = bias; g.relu = relu; g.mask = mask; g.ldm = ldm;
     g.Cf = Cf; g.ldcf = ldcf; g.Cb = Cb; g.ldcb = ldcb;
+    g.amode = stage_mode(A, sam, sak);
+    g.bmode = stage_mode(B, sbn, sbk);
     hipLaunchKernelGGL(k_gemm_bf16, dim3(blocks_for(N, BN), blocks_for(M, BM)), dim3(256), 0, s, g);
 }
 
@@ -683,7 +727,7 @@ void pn_default_surrogate_cfg(pn_surrogate_cfg* c) {
     c->margin = 0.5f;
     c->audit_frac = 0.01;
     c->seed = 5;
-    c->refine_epochs = 3;
+    c->refine_epochs = 10;
     c->refine_batch = 2048;
     c->refine_lr = 5e-4f;
     c->refine_seed = 51;

@@ -35,10 +35,14 @@ def bf16_bits(x):
     return t.view(torch.int16).to(DEV), t.to(torch.float64).numpy()
 
 
-@pytest.mark.parametrize("M_,N_,K_,trans_a", [(37, 5, 7, False), (64, 64, 32, False), (130, 257, 300, False),
-                                               (256, 7, 1000, True), (3, 256, 2, False), (1, 1, 1, False)])
-def test_gemm_matches_fp64_of_bf16_operands(pn, M_, N_, K_, trans_a):
-    rng = np.random.default_rng(M_ * 1000 + N_)
+@pytest.mark.parametrize("M_,N_,K_,trans_a,trans_b", [
+    (37, 5, 7, False, False), (64, 64, 32, False, False), (130, 257, 300, False, False),
+    (256, 7, 1000, True, False), (3, 256, 2, False, False), (1, 1, 1, False, False),
+    # 16-byte staging along K (A and B), along M/N (transposed A and B), ragged tails of both
+    (200, 136, 264, False, False), (256, 256, 2048, True, True), (72, 88, 100, True, True),
+    (130, 256, 256, False, True), (2, 256, 4096, True, False), (256, 2, 4096, True, True)])
+def test_gemm_matches_fp64_of_bf16_operands(pn, M_, N_, K_, trans_a, trans_b):
+    rng = np.random.default_rng(M_ * 1000 + N_ + K_)
     A = rng.normal(size=(M_, K_))
     B = rng.normal(size=(K_, N_))
     if trans_a:    # A stored as [K, M]: A(m, k) = At[k, m]
@@ -47,9 +51,13 @@ def test_gemm_matches_fp64_of_bf16_operands(pn, M_, N_, K_, trans_a):
     else:
         a_bits, Aq = bf16_bits(A)
         sam, sak = K_, 1
-    # B stored as Wt [N, K]: B(k, n) = Wt[n, k]
-    w_bits, Wq = bf16_bits(B.T.copy())
-    Cf, _ = pn.gemm_bf16(a_bits, sam, sak, w_bits, 1, K_, M_, N_, K_)
+    if trans_b:    # B stored as [K, N]: B(k, n) = Bs[k, n]
+        w_bits, Bq = bf16_bits(B)
+        Wq, sbk, sbn = Bq.T, N_, 1
+    else:          # B stored as Wt [N, K]: B(k, n) = Wt[n, k]
+        w_bits, Wq = bf16_bits(B.T.copy())
+        sbk, sbn = 1, K_
+    Cf, _ = pn.gemm_bf16(a_bits, sam, sak, w_bits, sbk, sbn, M_, N_, K_)
     ref = Aq @ Wq.T
     bound = 1e-5 * (np.abs(Aq) @ np.abs(Wq.T)) + 1e-30
     assert np.all(np.abs(Cf.cpu().numpy() - ref) <= bound)
