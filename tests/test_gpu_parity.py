@@ -258,3 +258,34 @@ def test_scan_grid64_full_size_sampled(pn):
     # Whole-grid properties: every orbit bound and corrected to rounding level.
     dH = out["dH"].cpu().numpy()
     assert np.all(st == 0) and np.nanmax(dH) < 1e-13
+
+
+@pytest.mark.parametrize("beta,qm", [(1.0, 1), (1.0, 0), (0.5, 1), (0.5, 0)])
+def test_scan_grid314_full_size_sampled(pn, beta, qm):
+    """The 314 x 314 (r0, p-scale) grid at t = 1e6, each of its four variants
+    (mass ratio 1 or 1/2, quadrupole-monopole on or off) at full size in the
+    benchmark's launch configuration; 8 seeded points recomputed by the
+    oracle.  Statuses exact; labels exact away from the threshold (6.8 at
+    t = 1e6), at most 0.5 % different in all; regular FLIs within 3e-4."""
+    from paper_1802_00147_amd import workloads as W
+    wl = W.grid314(beta=beta, quad_mono=qm)
+    model = dict(quad_mono=qm)
+    y0 = pn.init_state(*[dev(getattr(wl, k)) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")], beta, 1.0, 1.0,
+                       model=model)
+    out = pn.fli_scan(y0, wl.t_end, beta, 1.0, 1.0, model=model, full=False)
+    torch.cuda.synchronize()
+    idx = W.strided_sample(wl.n, 8, seed=13 + int(4 * beta) + qm)
+    sub = wl.subset(idx)
+    y0o = O.init_state(sub.r0, sub.p0, sub.th1, sub.ph1, sub.th2, sub.ph2, beta, 1.0, 1.0, model=model)
+    exp = O.fli_scan(y0o, wl.t_end, beta, 1.0, 1.0, model=model, nthreads=16)
+    st = out["status"].cpu().numpy()
+    lab = out["label"].cpu().numpy()
+    fli = out["fli"].cpu().numpy()
+    assert np.array_equal(st[idx], exp["status"])
+    thr = 5.8 + np.log10(wl.t_end / 1e5)
+    far = (exp["status"] == 0) & (np.abs(exp["fli"] - thr) > 0.25)
+    assert np.array_equal(lab[idx][far], exp["label"][far])
+    reg = (exp["status"] == 0) & (exp["label"] == 0) & (lab[idx] == 0)
+    assert np.all(np.abs(fli[idx][reg] - exp["fli"][reg]) <= FLI_ABS_CORRECTED)
+    # Whole grid: labels are -1 exactly where an orbit was removed.
+    assert np.array_equal(lab == -1, (st & 0xFF) != 0)
