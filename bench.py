@@ -37,7 +37,7 @@ KERNEL_SOURCES = ["paper_1802_00147_amd/csrc/pn_kernels.hip", "paper_1802_00147_
 # grid64 launch: FETCH_SIZE 376.5 KiB x 1.99993 (a 1 GiB copy reads 524,307.8
 # KiB) + WRITE_SIZE 548.0 KiB x 1.0 (the copy writes 1,048,576 KiB).
 TRAFFIC = dict(workload="grid64", bytes_per_launch=771044 + 561152,
-               sources_sha256="832654361c75163b453ba561203563853df1f0832637e5cf4f173c6306d2985d")
+               sources_sha256="c274fb34556a893cd576c379a89f25c1a690cd43811b70d6a3a848fff21769a1")
 
 
 def sources_sha256():

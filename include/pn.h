@@ -13,6 +13,9 @@
  *   Sec. 2, eqs. (10)-(13) manifold correction (spin lengths; dual scaling)
  *   Sec. 3B               Newton iteration limit eps <= 1e-10
  *   Sec. 3C               FLI phase-space scans, chaos threshold 5.8 at t = 1e5
+ *   Sec. 4, eq. (14)      gravitational-wave polarisations of recorded orbits
+ * Beyond the paper: a persistent batch for orbits of uneven length, and a
+ * neural surrogate of the scan's chaos label with integration as fallback.
  *
  * Units (Sec. 2): G = c = M = 1 with M = m1 + m2; r in M, p = P/mu, t in M,
  * H is the Hamiltonian per unit reduced mass mu.  beta = m1/m2 in (0, 1],
@@ -24,9 +27,9 @@
  *
  * Memory: every array pointer is a DEVICE pointer (hipMalloc or a torch
  * CUDA tensor), 8-byte aligned; 256-byte alignment is recommended.  The
- * caller allocates and frees everything; the library keeps no per-call
- * allocation.  All work is enqueued on the given stream and is complete when
- * the stream is synchronised.  Inputs are not modified unless documented as
+ * caller allocates and frees all device memory; the library allocates none
+ * per call.  All work is enqueued on the given stream and is complete when
+ * the stream is synchronised (calls that block are marked as such).  Inputs are not modified unless documented as
  * in/out.  Results depend only on each orbit's inputs and the settings, never
  * on the launch shape.
  *

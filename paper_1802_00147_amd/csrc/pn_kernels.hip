@@ -1,8 +1,10 @@
-// pn_kernels.hip -- gfx950 kernels and the C ABI of include/pn.h.
+// pn_kernels.hip -- gfx950 kernels of the FP64 path and the C ABI of
+// include/pn.h (except the network's entry points, in pn_mlp.hip).
 //
-// One lane integrates one orbit (and, in the scan, its shadow): the whole
+// One lane integrates one trajectory: in the scans an orbit and its shadow
+// occupy two adjacent lanes and trade state through DPP; the whole
 // 12-component state, the Runge-Kutta stages and the correction live in
-// registers; global memory is touched only to read the initial state and to
+// registers; global memory is touched only to read initial states and to
 // write results, in structure-of-arrays rows (coalesced across a wavefront).
 // The physics path is scalar FP64 end to end.
 #include <hip/hip_runtime.h>

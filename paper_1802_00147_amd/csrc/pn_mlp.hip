@@ -1,13 +1,16 @@
 // pn_mlp.hip -- learned surrogate of the FLI scan: a 7-256-256-256-2 ReLU
 // multilayer perceptron trained and evaluated on gfx950 matrix cores.
 //
-// Every matrix product runs in one hand-written kernel, k_gemm_bf16: bfloat16
+// Training products run in one hand-written kernel, k_gemm_bf16: bfloat16
 // operands, FP32 accumulation on v_mfma_f32_16x16x32_bf16, 64x64 output tiles
 // per 256-thread workgroup (each wavefront a 32x32 quarter as 2x2 MFMA
 // tiles), operands staged through LDS with K contiguous so that a lane reads
 // its eight K values with one 16-byte LDS load, and fused epilogues (bias,
 // ReLU, ReLU-mask of the backward pass, FP32 and/or bfloat16 stores).
 // Arbitrary strides let the same kernel form X W^T, G W and G^T H.
+// Inference over scan grids runs all four layers in one persistent kernel,
+// k_mlp_fused, with the same arithmetic.  The surrogate-assisted scan
+// (pn_surrogate_scan) strings these together with the FP64 batch scan.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
