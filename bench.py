@@ -34,10 +34,10 @@ KERNEL_SOURCES = ["paper_1802_00147_amd/csrc/pn_kernels.hip", "paper_1802_00147_
 # HBM traffic of the scan kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
 # (KiB per dispatch, scaled by a copy kernel of known size), valid only for the
 # kernel source whose hash is recorded with it.
-# grid64 launch: FETCH_SIZE 376.5 KiB x 1.99993 (a 1 GiB copy reads 524,307.8
+# grid64 launch: FETCH_SIZE 365.125 KiB x 1.999923 (a 1 GiB copy reads 524,308.25
 # KiB) + WRITE_SIZE 548.0 KiB x 1.0 (the copy writes 1,048,576 KiB).
-TRAFFIC = dict(workload="grid64", bytes_per_launch=771044 + 561152,
-               sources_sha256="c274fb34556a893cd576c379a89f25c1a690cd43811b70d6a3a848fff21769a1")
+TRAFFIC = dict(workload="grid64", bytes_per_launch=747747 + 561152,
+               sources_sha256="5ddb457f66de8e3056dbffbe531039ebfe0bdcde91aa177fbacbd776b6f3189a")
 
 
 def sources_sha256():

@@ -284,7 +284,7 @@ __device__ __forceinline__ int pn_energy_scale(const PnCoef& k, double* y, doubl
         const double a2 = a * a, a3 = a2 * a;
         const double g = fma(fma(fma(e.K6, a2, e.K4), a2, e.K2), a2, fma(e.K1, a, e.K0)) - E0;
         const double dg = fma(fma(6.0 * e.K6, a2, 4.0 * e.K4), a3, fma(2.0 * e.K2, a, e.K1));
-        const double da = -g / dg;
+        const double da = -g * pn_rcp(dg);
         a += da;
         ++it;
         if (fabs(da) <= tol) { conv = true; break; }
@@ -327,7 +327,7 @@ __device__ __forceinline__ void pn_project_EJ(const PnCoef& k, double* y, const 
     const double z0 = c0, z1 = c1 - l10 * z0, z2 = c2 - l20 * z0 - l21 * z1;
     const double z3 = c3 - l30 * z0 - l31 * z1 - l32 * z2;
     const double damp = PN_SIX_MU * A33;
-    const double lam3 = z3 * d3 / fma(d3, d3, damp * damp);
+    const double lam3 = z3 * d3 * pn_rcp(fma(d3, d3, damp * damp));
     const double lam2 = z2 * i2 - l32 * lam3;
     const double lam1 = z1 * i1 - l21 * lam2 - l31 * lam3;
     const double lam0 = z0 * i0 - l10 * lam1 - l20 * lam2 - l30 * lam3;
@@ -488,12 +488,13 @@ __device__ __forceinline__ void pn_rk_step(const PnCoef& k, double* y, double h)
     for (int c = 0; c < 12; ++c) y[c] = fma(h * b6, kk[c], acc[c]);
 }
 
-// Orbit validity in the order: non-finite, merged, escaped.
+// Orbit validity in the order: non-finite, merged, escaped.  The sum of
+// y[c] * 0 is NaN exactly when some component is NaN or infinite.
 __device__ __forceinline__ int pn_validity(const double* y, double rmerge2, double resc2) {
-    bool fin = true;
+    double z = 0.0;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) fin = fin && isfinite(y[c]);
-    if (!fin) return PN_ORBIT_NONFINITE;
+    for (int c = 0; c < 12; ++c) z = fma(y[c], 0.0, z);
+    if (!isfinite(z)) return PN_ORBIT_NONFINITE;
     const double r2 = dot3(y[0], y[1], y[2], y[0], y[1], y[2]);
     if (r2 < rmerge2) return PN_ORBIT_MERGED;
     if (r2 > resc2) return PN_ORBIT_ESCAPED;

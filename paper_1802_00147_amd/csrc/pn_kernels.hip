@@ -262,13 +262,13 @@ struct PairState {
     bool any_nc;
 };
 
-// Separation of the pair, computed identically in both lanes.
-__device__ __forceinline__ double pair_d2(const double* y, bool shadow) {
+// Separation of the pair, computed identically in both lanes: the lanes form
+// e and -e exactly, so e * e and the sum carry the same bits.
+__device__ __forceinline__ double pair_d2(const double* y) {
     double d2 = 0.0;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-        const double yp = swap_pair(y[c]);
-        const double e = shadow ? y[c] - yp : yp - y[c];
+        const double e = y[c] - swap_pair(y[c]);
         d2 = fma(e, e, d2);
     }
     return d2;
@@ -317,7 +317,7 @@ __device__ __forceinline__ void pair_step(PairState& ps, const PnCoef& k, bool s
     const int vo = shadow ? other : mine, vs = shadow ? mine : other;
     ps.st = vo != PN_ORBIT_OK ? vo : vs;
     if (ps.st != PN_ORBIT_OK) return;
-    ps.d2 = pair_d2(ps.y, shadow);
+    ps.d2 = pair_d2(ps.y);
     if (ps.d2 >= fa.d_renorm2) {
         const double d = sqrt(ps.d2);
         ps.acc += log10(d / fa.d0);
@@ -332,7 +332,7 @@ __device__ __forceinline__ void pair_step(PairState& ps, const PnCoef& k, bool s
             capture_ref(k, ps.y, ps.ref);
         }
         ps.renorms += 1;
-        ps.d2 = pair_d2(ps.y, shadow);
+        ps.d2 = pair_d2(ps.y);
     }
     const int64_t tev = fa.out.trace_every;
     if (tev > 0 && (ps.t % tev) == 0 && !shadow) {
@@ -348,7 +348,7 @@ __device__ __forceinline__ bool pair_running(const PairState& ps) {
 // Final separation and outputs of orbit i (written by the orbit lane).
 __device__ __forceinline__ void pair_finish(PairState& ps, const PnCoef& k, bool shadow, const FliArgs& fa,
                                             int64_t i) {
-    const double d2 = pair_d2(ps.y, shadow);
+    const double d2 = pair_d2(ps.y);
     const int nmax_other = swap_pair_i32(ps.nmax);
     const int nc_other = swap_pair_i32(ps.any_nc ? 1 : 0);
     if (shadow) return;
