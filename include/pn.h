@@ -372,6 +372,17 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
                             const int32_t* idx, int32_t batch, int32_t step, float lr, float* loss,
                             void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* nbatch training steps in one call, as pn_mlp_train_step each: batch b
+ * (0 <= b < nbatch) trains on rows order[b * batch .. (b + 1) * batch) of
+ * feat/label/target, with Adam step *adam_step + 1 + b; *adam_step (host,
+ * in/out) is advanced by the steps done.  The batches' mean losses are ADDED
+ * to the device scalar *loss.  order: device int32 array of nbatch * batch
+ * row indices (the caller's data-loader order).  ws as for
+ * pn_mlp_train_step(batch).  The first failing step's status is returned. */
+pn_status pn_mlp_train(pn_mlp* net, int32_t* adam_step, const float* feat, const float* label,
+                       const float* target, const int32_t* order, int64_t nbatch, int32_t batch,
+                       float lr, float* loss, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Bytes of workspace for inference in chunks of `chunk` rows. */
 size_t pn_mlp_infer_workspace_size(int64_t chunk);
 
@@ -467,6 +478,16 @@ pn_status pn_init_state_gather(const pn_model* model, pn_params params, int64_t 
                                int64_t ld, hipStream_t stream);
 
 /* Library version and last error text (thread-local; "" when none). */
+/* Bytes of device workspace pn_fli_scan needs for n orbits: 0 (the fused scan
+ * keeps everything in registers; the call exists so that callers can size
+ * workspaces uniformly). */
+size_t pn_fli_scan_workspace_size(int64_t n);
+
+/* Forget the per-device autotune results kept by pn_autotune_batch (later
+ * batches use pn_default_tuning until the next autotune).  The library holds
+ * no other state. */
+void pn_shutdown(void);
+
 int32_t pn_version(void);
 const char* pn_status_string(pn_status s);
 const char* pn_last_error(void);

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "pn.h"
 #include "pn_device.h"
@@ -651,9 +652,32 @@ bool valid_tuning(const pn_tuning& t) {
            t.waves_per_simd <= 2 && t.chunk_steps >= 1 && t.chunk_steps <= (1 << 20);
 }
 
-// Last autotune result per device.
+// Last autotune result per device (guarded: calls on other threads may
+// autotune or read it concurrently).
 pn_tuning g_tuned[64];
 bool g_has_tuned[64] = {false};
+std::mutex g_tuned_mu;
+
+// The tuning a batch uses: the caller's, else the device's last autotune
+// result, else the defaults.
+pn_tuning chosen_tuning(const pn_tuning* tuning, int dev) {
+    pn_tuning tu;
+    if (tuning) return *tuning;
+    {
+        std::lock_guard<std::mutex> lock(g_tuned_mu);
+        if (dev >= 0 && dev < 64 && g_has_tuned[dev]) return g_tuned[dev];
+    }
+    pn_default_tuning(&tu);
+    return tu;
+}
+
+void remember_tuning(int dev, const pn_tuning& tu) {
+    std::lock_guard<std::mutex> lock(g_tuned_mu);
+    if (dev >= 0 && dev < 64) {
+        g_tuned[dev] = tu;
+        g_has_tuned[dev] = true;
+    }
+}
 
 int device_cus(int& dev) {
     if (hipGetDevice(&dev) != hipSuccess) return -1;
@@ -771,6 +795,16 @@ const char* pn_status_string(pn_status s) {
 }
 
 const char* pn_last_error(void) { return pn_detail::g_last_error; }
+
+void pn_shutdown(void) {
+    std::lock_guard<std::mutex> lock(g_tuned_mu);
+    for (int d = 0; d < 64; ++d) g_has_tuned[d] = false;
+}
+
+size_t pn_fli_scan_workspace_size(int64_t n) {
+    (void)n;
+    return 0;
+}
 
 pn_status pn_init_state(const pn_model* model, pn_params params, int64_t n, const double* r0,
                         const double* p0, const double* th1, const double* ph1, const double* th2,
@@ -947,10 +981,7 @@ pn_status pn_batch_scan(const pn_model* model, pn_params params, const pn_integr
     int dev = 0;
     const int ncu = device_cus(dev);
     if (ncu <= 0) { set_error("pn_batch_scan", hipErrorInvalidDevice); return PN_EDEVICE; }
-    pn_tuning tu;
-    if (tuning) tu = *tuning;
-    else if (dev < 64 && g_has_tuned[dev]) tu = g_tuned[dev];
-    else pn_default_tuning(&tu);
+    const pn_tuning tu = chosen_tuning(tuning, dev);
     PN_REQUIRE(valid_tuning(tu));
     if (n == 0) return PN_OK;
     if (ws == nullptr || ws_bytes < batch_ws_bytes(n)) return PN_ENOWS;
@@ -1002,7 +1033,7 @@ pn_status pn_autotune_batch(const pn_model* model, pn_params params, const pn_in
                 (void)hipEventElapsedTime(&ms, e0, e1);
                 if (ms < best_t) { best_t = ms; *best = tu; }
             }
-    if (dev < 64) { g_tuned[dev] = *best; g_has_tuned[dev] = true; }
+    remember_tuning(dev, *best);
     if (best_ms) *best_ms = best_t;
 done:
     (void)hipEventDestroy(e0);
@@ -1028,10 +1059,7 @@ pn_status pn_batch_graph_create(const pn_model* model, pn_params params, const p
     int dev = 0;
     const int ncu = device_cus(dev);
     if (ncu <= 0) { set_error("pn_batch_graph_create", hipErrorInvalidDevice); return PN_EDEVICE; }
-    pn_tuning tu;
-    if (tuning) tu = *tuning;
-    else if (dev < 64 && g_has_tuned[dev]) tu = g_tuned[dev];
-    else pn_default_tuning(&tu);
+    const pn_tuning tu = chosen_tuning(tuning, dev);
     PN_REQUIRE(valid_tuning(tu));
     if (ws == nullptr || ws_bytes < batch_ws_bytes(n)) return PN_ENOWS;
     hipStream_t cs;

@@ -616,6 +616,21 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
     return launched("pn_mlp_train_step");
 }
 
+pn_status pn_mlp_train(pn_mlp* net, int32_t* adam_step, const float* feat, const float* label, const float* target,
+                       const int32_t* order, int64_t nbatch, int32_t batch, float lr, float* loss, void* ws,
+                       size_t ws_bytes, hipStream_t stream) {
+    if (!adam_step || *adam_step < 0 || nbatch < 0 || batch <= 0) return PN_EINVAL;
+    if (nbatch > 0 && !order) return PN_EINVAL;
+    if ((int64_t)*adam_step + nbatch > 0x7fffffffLL) return PN_EINVAL;
+    for (int64_t b = 0; b < nbatch; ++b) {
+        const pn_status st = pn_mlp_train_step(net, feat, label, target, order + b * batch, batch, *adam_step + 1,
+                                               lr, loss, ws, ws_bytes, stream);
+        if (st != PN_OK) return st;
+        *adam_step += 1;
+    }
+    return PN_OK;
+}
+
 size_t pn_mlp_infer_workspace_size(int64_t chunk) {
     if (chunk <= 0) return 0;
     const size_t C = (size_t)chunk;
@@ -880,6 +895,7 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
         PN_HIP(hipStreamSynchronize(stream), what);
         std::sort(host.begin(), host.begin() + ma);
         PN_HIP(hipMemcpyAsync(listA, host.data(), (size_t)ma * 4, hipMemcpyHostToDevice, stream), what);
+        PN_HIP(hipStreamSynchronize(stream), what);        // host memory must outlive the copy
         // 2. Integrate the audit.
         PN_TRY(integrate(listA, ma));
     }
@@ -909,13 +925,13 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
                 std::swap(ord[k - 1], ord[r]);
             }
             PN_HIP(hipMemcpyAsync(order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, stream), what);
+            PN_HIP(hipStreamSynchronize(stream), what);    // ord is reshuffled next epoch
             for (int64_t b = 0; b < nb; ++b) {
                 *adam_step += 1;
                 PN_TRY(pn_mlp_train_step(net, featA, labA, tgtA, order + b * cfg->refine_batch, cfg->refine_batch,
                                          *adam_step, cfg->refine_lr, loss, tws,
                                          pn_mlp_train_workspace_size(cfg->refine_batch), stream));
             }
-            PN_HIP(hipStreamSynchronize(stream), what);        // ord is reshuffled next epoch
         }
     }
     PN_TRY(mark(2));

@@ -86,6 +86,7 @@ EXPORTS = ["pn_default_model", "pn_default_integrator", "pn_default_correction",
            "pn_surrogate_merge", "pn_gemm_bf16", "pn_init_state_gather", "pn_mlp_targets",
            "pn_trajectory", "pn_gw_polarizations", "pn_mlp_infer_fused",
            "pn_default_surrogate_cfg", "pn_surrogate_scan_workspace_size", "pn_surrogate_scan",
+           "pn_mlp_train", "pn_fli_scan_workspace_size", "pn_shutdown",
            "pn_version", "pn_status_string", "pn_last_error"]
 
 
@@ -104,8 +105,11 @@ def lib():
                      "pn_graph_launch", "pn_mlp_sync_bf16", "pn_mlp_features", "pn_mlp_train_step",
                      "pn_mlp_infer", "pn_surrogate_gate", "pn_surrogate_merge", "pn_gemm_bf16",
                      "pn_init_state_gather", "pn_mlp_targets", "pn_trajectory", "pn_gw_polarizations",
-                     "pn_mlp_infer_fused", "pn_surrogate_scan"):
+                     "pn_mlp_infer_fused", "pn_surrogate_scan", "pn_mlp_train"):
             getattr(L, name).restype = ctypes.c_int
+        L.pn_fli_scan_workspace_size.restype = ctypes.c_size_t
+        L.pn_fli_scan_workspace_size.argtypes = [ctypes.c_int64]
+        L.pn_shutdown.restype = None
         L.pn_surrogate_scan_workspace_size.restype = ctypes.c_size_t
         L.pn_surrogate_scan_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int32]
         for name in ("pn_mlp_param_count", "pn_mlp_train_workspace_size", "pn_mlp_infer_workspace_size"):
@@ -513,6 +517,21 @@ def mlp_train_step(net, feat, label, target, idx, lr, loss, ws=None):
                                  ctypes.c_int32(batch), ctypes.c_int32(net.step), ctypes.c_float(lr), _ptr(loss),
                                  _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(feat.device))
     _check("pn_mlp_train_step", st)
+    return ws
+
+
+def mlp_train(net, feat, label, target, order, batch, lr, loss, ws=None):
+    """pn_mlp_train: len(order) // batch steps over the rows in `order` (device
+    int32), advancing net.step; returns the workspace."""
+    nbatch = order.numel() // batch
+    if ws is None:
+        ws = torch.empty(int(lib().pn_mlp_train_workspace_size(batch)), dtype=torch.uint8, device=feat.device)
+    step = ctypes.c_int32(net.step)
+    st = lib().pn_mlp_train(ctypes.byref(net.struct), ctypes.byref(step), _ptr(feat), _ptr(label), _ptr(target),
+                            _ptr(order), ctypes.c_int64(nbatch), ctypes.c_int32(batch), ctypes.c_float(lr), _ptr(loss),
+                            _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(feat.device))
+    net.step = step.value
+    _check("pn_mlp_train", st)
     return ws
 
 

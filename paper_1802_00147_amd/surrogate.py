@@ -81,8 +81,7 @@ def train(ts, epochs=8, batch=4096, lr=1e-3, seed=50, init_seed=50, device="cuda
     for ep in range(epochs):
         order = torch.as_tensor(rng.permutation(ts.valid).astype(np.int32), device=device)
         loss.zero_()
-        for b in range(nb):
-            ws = pn.mlp_train_step(net, ts.feat, ts.label, ts.target, order[b * batch:(b + 1) * batch], lr, loss, ws)
+        ws = pn.mlp_train(net, ts.feat, ts.label, ts.target, order[:nb * batch], batch, lr, loss, ws)
         history.append(float(loss.item()) / max(nb, 1))
         if log:
             log(f"epoch {ep}: mean loss {history[-1]:.5f}")

@@ -179,6 +179,24 @@ def test_invalid_surrogate_scan_arguments_rejected(pn):
     assert L.pn_surrogate_scan_workspace_size(1000, 2048) > 1000 * (8 * 4 * 2 + 12 * 8)
 
 
+def test_workspace_sizes_and_shutdown(pn):
+    L = pn.lib()
+    assert L.pn_fli_scan_workspace_size(0) == 0 and L.pn_fli_scan_workspace_size(10 ** 6) == 0
+    L.pn_shutdown()          # forgets cached tunings; harmless when there are none
+    L.pn_shutdown()
+    step = ctypes.c_int32(0)
+    net = pn.Mlp(*[pn.P4(*([8] * 4)) for _ in range(7)])
+    one = ctypes.c_void_p(8)
+    def train(step_p=ctypes.byref(step), nbatch=2, batch=16, order=one):
+        return L.pn_mlp_train(ctypes.byref(net), step_p, one, one, one, order, ctypes.c_int64(nbatch),
+                              ctypes.c_int32(batch), ctypes.c_float(1e-3), one, one, ctypes.c_size_t(1 << 30), None)
+    assert train(step_p=None) == pn.PN_EINVAL
+    assert train(nbatch=-1) == pn.PN_EINVAL
+    assert train(batch=0) == pn.PN_EINVAL
+    assert train(order=None) == pn.PN_EINVAL
+    assert train(nbatch=0) == pn.PN_OK and step.value == 0
+
+
 def test_missing_library_fails_loudly(monkeypatch):
     from paper_1802_00147_amd import pn as P
     monkeypatch.setattr(P, "_lib", None)

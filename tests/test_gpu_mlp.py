@@ -277,3 +277,28 @@ def test_native_surrogate_scan_per_point_parameters(pn, margin, audit):
     if margin == 0.0:
         assert np.array_equal(np.sort(pts), drawn)
     assert all(x >= 0 for x in r["phase_ms"])
+
+
+def test_multi_step_training_equals_single_steps(pn):
+    """pn_mlp_train over an order equals the same pn_mlp_train_step calls, bit
+    for bit (weights, Adam moments, accumulated loss, step counter)."""
+    rng = np.random.default_rng(90)
+    n = 5000
+    feat = np.zeros((n, 8), dtype=np.float32)
+    feat[:, :7] = rng.normal(size=(n, 7))
+    f_d = dev(feat, torch.float32)
+    l_d = dev((rng.random(n) > 0.7).astype(np.float32), torch.float32)
+    t_d = dev(rng.normal(size=n).astype(np.float32), torch.float32)
+    order = dev(rng.permutation(n)[:7 * 512].astype(np.int32), torch.int32)
+    nets = [_network(pn, seed=91)[0] for _ in range(2)]
+    losses = [torch.zeros(1, dtype=torch.float32, device=DEV) for _ in range(2)]
+    pn.mlp_train(nets[0], f_d, l_d, t_d, order, 512, 1e-3, losses[0])
+    ws = None
+    for b in range(7):
+        ws = pn.mlp_train_step(nets[1], f_d, l_d, t_d, order[b * 512:(b + 1) * 512], 1e-3, losses[1], ws)
+    torch.cuda.synchronize()
+    assert nets[0].step == nets[1].step == 7
+    assert torch.equal(losses[0], losses[1])
+    for attr in ("w", "b", "wb", "mw", "vw", "mb", "vb"):
+        for x, y in zip(getattr(nets[0], attr), getattr(nets[1], attr)):
+            assert torch.equal(x, y), attr
