@@ -281,7 +281,9 @@ def test_native_surrogate_scan_per_point_parameters(pn, margin, audit):
 
 def test_multi_step_training_equals_single_steps(pn):
     """pn_mlp_train over an order equals the same pn_mlp_train_step calls, bit
-    for bit (weights, Adam moments, accumulated loss, step counter)."""
+    for bit in the weights, their bfloat16 copies, the Adam moments and the
+    step counter.  The reported loss adds per-workgroup partial sums with
+    atomics, so only it may differ, in the last bits."""
     rng = np.random.default_rng(90)
     n = 5000
     feat = np.zeros((n, 8), dtype=np.float32)
@@ -298,7 +300,7 @@ def test_multi_step_training_equals_single_steps(pn):
         ws = pn.mlp_train_step(nets[1], f_d, l_d, t_d, order[b * 512:(b + 1) * 512], 1e-3, losses[1], ws)
     torch.cuda.synchronize()
     assert nets[0].step == nets[1].step == 7
-    assert torch.equal(losses[0], losses[1])
+    assert abs(losses[0].item() - losses[1].item()) <= 1e-6 * abs(losses[1].item())
     for attr in ("w", "b", "wb", "mw", "vw", "mb", "vb"):
         for x, y in zip(getattr(nets[0], attr), getattr(nets[1], attr)):
             assert torch.equal(x, y), attr
