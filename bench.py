@@ -37,7 +37,7 @@ KERNEL_SOURCES = ["paper_1802_00147_amd/csrc/pn_kernels.hip", "paper_1802_00147_
 # grid64 launch: FETCH_SIZE 365.125 KiB x 1.999923 (a 1 GiB copy reads 524,308.25
 # KiB) + WRITE_SIZE 548.0 KiB x 1.0 (the copy writes 1,048,576 KiB).
 TRAFFIC = dict(workload="grid64", bytes_per_launch=747747 + 561152,
-               sources_sha256="05df92e2a5a3b869d5602907617a6cfb2a987707b2d8e6971248da885e25a77a")
+               sources_sha256="ac9416f23849a613e13f513c902f10e30ee6c0116b6cd62886817c2806d2e0f3")
 
 
 def sources_sha256():

@@ -229,16 +229,6 @@ struct FliArgs {
     double step_scale;      // 1 for real runs; < 1 shortens every orbit (autotune trials)
 };
 
-__device__ __forceinline__ double sq_dist(const double* a, const double* b) {
-    double d2 = 0.0;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        const double e = b[c] - a[c];
-        d2 = fma(e, e, d2);
-    }
-    return d2;
-}
-
 // Exchange a value with the partner lane (lanes 2j and 2j+1 of a wavefront)
 // through DPP quad permutation [1,0,3,2]; no LDS traffic.
 __device__ __forceinline__ int swap_pair_i32(int v) {
