@@ -58,10 +58,16 @@ def make_workload(name):
         return W.batch()
     if name == "fig7":
         return W.fig7()
+    if name == "single":
+        return W.single()
     raise SystemExit(f"unknown workload {name}")
 
 
 def describe(wl):
+    if wl.name == "single":
+        return {"workload": f"single: one orbit and its shadow (d0 = 1e-8), r0=20, p0 from seed 1, beta=1, chi=1, "
+                            f"isotropic spins (seed 1), t={wl.t_end:g}, RK4 h=1, six-integral correction, QM on",
+                "orbits": 1, "t_end": wl.t_end, "orbit_steps": wl.steps()}
     if wl.shape is None:
         return {"workload": f"{wl.name}: {wl.n} orbits, per-orbit beta in [0.1,1], chi in [0,1], isotropic "
                             "spins, r0 in [8,60], t_end log-uniform in [1e3,1e6]; persistent work-stealing "
@@ -324,7 +330,7 @@ def main():
     n = wl.n
     out = pn.scan_outputs(n, n, dev, full=True)
     stream = torch.cuda.current_stream(dev)
-    batched = wl.shape is None
+    batched = wl.shape is None and wl.name != "single"
     as_dev = (lambda v: torch.as_tensor(v, device=dev) if isinstance(v, np.ndarray) else v)
     beta, chi1, chi2, t_end = as_dev(wl.beta), as_dev(wl.chi1), as_dev(wl.chi2), as_dev(wl.t_end)
     kernel = "k_fli_scan<RK4,SIX>"
@@ -373,6 +379,13 @@ def main():
     line["grid_pts_per_s"] = n * args.steps / elapsed
     line["chaotic_fraction"] = float(np.mean(labels == 1))
     line["invalid_orbits"] = int(np.sum((status & 0xFF) != 0))
+    if not batched:
+        # Latency view of one launch: time per step of the time loop and the
+        # share of the chip's SIMDs the trajectories can occupy.
+        waves = (2 * n + 63) // 64
+        simds = 4 * torch.cuda.get_device_properties(dev).multi_processor_count
+        line["latency"] = dict(us_per_step=1e3 * kernel_ms / float(np.max(wl.t_end)), wavefronts=waves,
+                               simd_fraction=min(1.0, waves / simds))
 
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, args.cpu_sample)
