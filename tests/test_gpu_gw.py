@@ -9,6 +9,8 @@ that partly cancel); from the two sides' own trajectories they agree to
 1e-9 of the largest |h| (the trajectory bound times the field's
 sensitivity, ~2/|v| per unit relative change of v).
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -130,3 +132,49 @@ def test_fig10_waveforms(pn, orbit):
     # The waveform oscillates at twice the orbital frequency: h_plus changes
     # sign several times over 1000 M for these orbits (periods ~ 200-300 M).
     assert np.sum(np.diff(np.sign(ep)) != 0) >= 4
+
+
+def _gw_raw(pn, traj, n, ns, ld, hp, hx, dist=3.0):
+    """pn_gw_polarizations called directly (explicit n, ns, ld)."""
+    N3 = (ctypes.c_double * 3)(0.0, 0.0, 1.0)
+    P3 = (ctypes.c_double * 3)(1.0, 0.0, 0.0)
+    p, keep = pn.params_struct(1.0, 0.8, 0.6)
+    return pn.lib().pn_gw_polarizations(ctypes.byref(pn.model_struct()), p, ctypes.c_int64(n), ctypes.c_int64(ns),
+                                        pn._ptr(traj), ctypes.c_int64(ld), N3, P3, ctypes.c_double(dist), pn._ptr(hp),
+                                        pn._ptr(hx), pn._stream(traj.device))
+
+
+def test_trajectory_and_gw_padded_layout_and_edges(pn):
+    """Columns beyond n (ld > n) are never written; every > nsteps records no
+    row and still advances the state; n = 0 and ns = 0 are no-ops."""
+    rng = np.random.default_rng(44)
+    n, ld = 37, 48
+    ys = random_states(rng, n, rscale=20.0)
+    sentinel = -12345.0
+    y = to_soa(ys, ld=ld)
+    y[:, n:] = sentinel
+    traj = pn.trajectory(y, 1.0, 0.8, 0.6, 9, 4, correction=dict(mode="spin"), n=n)
+    torch.cuda.synchronize()
+    assert traj.shape == (2, 12, ld)
+    assert torch.all(y[:, n:] == sentinel)
+    y2 = to_soa(ys, ld=ld)
+    pn.step(y2, 1.0, 0.8, 0.6, 8, correction=dict(mode="spin"), n=n)
+    torch.cuda.synchronize()
+    assert torch.equal(traj[1][:, :n], y2[:, :n])
+    # every > nsteps: no rows, the state still advances.
+    y3 = to_soa(ys, ld=ld)
+    t0 = pn.trajectory(y3, 1.0, 0.8, 0.6, 3, 5, n=n)
+    torch.cuda.synchronize()
+    assert t0.shape[0] == 0 and not torch.equal(y3[:, :n], to_soa(ys, ld=ld)[:, :n])
+    # Polarisations of the padded layout: only the first n columns are written.
+    hp = torch.full((2, ld), sentinel, dtype=torch.float64, device=DEV)
+    hx = torch.full((2, ld), sentinel, dtype=torch.float64, device=DEV)
+    assert _gw_raw(pn, traj, n, 2, ld, hp, hx) == pn.PN_OK
+    torch.cuda.synchronize()
+    assert torch.all(hp[:, n:] == sentinel) and torch.all(hx[:, n:] == sentinel)
+    ep, ex = O.gw_polarizations(from_soa(traj[1], n), 1.0, 0.8, 0.6, [0, 0, 1], [1, 0, 0], 3.0)
+    scale = max(np.abs(ep).max(), np.abs(ex).max())
+    assert np.abs(hp[1, :n].cpu().numpy() - ep).max() <= 1e-13 * scale
+    assert np.abs(hx[1, :n].cpu().numpy() - ex).max() <= 1e-13 * scale
+    assert _gw_raw(pn, traj, 0, 2, ld, hp, hx) == pn.PN_OK
+    assert _gw_raw(pn, traj, n, 0, ld, hp, hx) == pn.PN_OK
