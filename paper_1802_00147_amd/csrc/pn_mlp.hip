@@ -61,6 +61,8 @@ struct GemmArgs {
     int64_t ldcb;
     int relu;
     int amode, bmode;          // operand staging: 0 element-wise, 1 K contiguous, 2 M (N) contiguous
+    int kchunk;                // K range of one workgroup layer (blockIdx.z); K when not split
+    int64_t split_stride;      // Cf offset between K splits (0 when not split)
 };
 
 // Staging modes of an operand whose element (r, k) -- r the row of the
@@ -127,9 +129,13 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
-        stage_tile(As, g.A, g.sam, g.sak, g.amode, m0, g.M, k0, g.K, tid);
-        stage_tile(Bt, g.B, g.sbn, g.sbk, g.bmode, n0, g.N, k0, g.K, tid);
+    // Split K: layer z of the grid sums K range [kb, ke) into its own partial.
+    const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
+    const int64_t ke = (kb + g.kchunk < g.K) ? kb + g.kchunk : g.K;
+    float* const Cf = g.Cf ? g.Cf + (int64_t)blockIdx.z * g.split_stride : nullptr;
+    for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+        stage_tile(As, g.A, g.sam, g.sak, g.amode, m0, g.M, k0, ke, tid);
+        stage_tile(Bt, g.B, g.sbn, g.sbk, g.bmode, n0, g.N, k0, ke, tid);
         __syncthreads();
         bf16x8 a[2], b[2];
 #pragma unroll
@@ -156,9 +162,20 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
                 if (g.bias) x += g.bias[n];
                 if (g.relu) x = fmaxf(x, 0.0f);
                 if (g.mask && !(bf2f(g.mask[m * g.ldm + n]) > 0.0f)) x = 0.0f;
-                if (g.Cf) g.Cf[m * g.ldcf + n] = x;
+                if (Cf) Cf[m * g.ldcf + n] = x;
                 if (g.Cb) g.Cb[m * g.ldcb + n] = f2bf(x);
             }
+}
+
+// C[m][n] (ld ldc) = sum over z = 0 .. splits-1, in that order, of part[z][m][n].
+__global__ __launch_bounds__(256) void k_sum_splits(const float* part, int splits, int M, int N, float* C,
+                                                    int64_t ldc) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t mn = (int64_t)M * N;
+    if (e >= mn) return;
+    float x = 0.0f;
+    for (int z = 0; z < splits; ++z) x += part[z * mn + e];
+    C[(e / N) * ldc + e % N] = x;
 }
 
 // Rows idx[b] (or b) of the FP32 features -> bfloat16 [rows x 8].
@@ -488,9 +505,16 @@ __global__ __launch_bounds__(256) void k_merge(const int32_t* list, int64_t m, c
 
 unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
+constexpr int64_t kSplitFloats = (int64_t)1 << 20;   // partial-sum buffer of a split product (4 MB)
+
+// C = A B.  A product with few output tiles and a long K (the weight
+// gradients: K = batch rows) is split along K over up to 256 workgroups when
+// `part` (kSplitFloats floats) is given and the result is a plain FP32
+// store; the partials are summed in a fixed order, so the result does not
+// depend on scheduling.
 void gemm(hipStream_t s, int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B,
           int64_t sbk, int64_t sbn, const float* bias, int relu, const uint16_t* mask, int64_t ldm, float* Cf,
-          int64_t ldcf, uint16_t* Cb, int64_t ldcb) {
+          int64_t ldcf, uint16_t* Cb, int64_t ldcb, float* part = nullptr) {
     GemmArgs g;
     g.M = M; g.N = N; g.K = K;
     g.A = A; g.sam = sam; g.sak = sak;
@@ -499,7 +523,30 @@ void gemm(hipStream_t s, int M, int N, int K, const uint16_t* A, int64_t sam, in
     g.Cf = Cf; g.ldcf = ldcf; g.Cb = Cb; g.ldcb = ldcb;
     g.amode = stage_mode(A, sam, sak);
     g.bmode = stage_mode(B, sbn, sbk);
-    hipLaunchKernelGGL(k_gemm_bf16, dim3(blocks_for(N, BN), blocks_for(M, BM)), dim3(256), 0, s, g);
+    g.kchunk = K > 0 ? K : 1;
+    g.split_stride = 0;
+    const int64_t tiles = (int64_t)blocks_for(N, BN) * blocks_for(M, BM);
+    int splits = 1;
+    if (part && Cf && !Cb && !bias && !relu && !mask && tiles < 64 && K >= 512) {
+        int64_t sp = 256 / tiles;
+        if (sp > K / 128) sp = K / 128;
+        if (sp > kSplitFloats / ((int64_t)M * N)) sp = kSplitFloats / ((int64_t)M * N);
+        if (sp > 1) {
+            const int64_t chunk = ((K + sp - 1) / sp + BK - 1) / BK * BK;
+            splits = (int)((K + chunk - 1) / chunk);
+            g.kchunk = (int)chunk;
+        }
+    }
+    if (splits == 1) {
+        hipLaunchKernelGGL(k_gemm_bf16, dim3(blocks_for(N, BN), blocks_for(M, BM)), dim3(256), 0, s, g);
+        return;
+    }
+    g.Cf = part;
+    g.ldcf = N;
+    g.split_stride = (int64_t)M * N;
+    hipLaunchKernelGGL(k_gemm_bf16, dim3(blocks_for(N, BN), blocks_for(M, BM), splits), dim3(256), 0, s, g);
+    hipLaunchKernelGGL(k_sum_splits, dim3(blocks_for((int64_t)M * N, 256)), dim3(256), 0, s, part, splits, M, N, Cf,
+                       ldcf);
 }
 
 pn_status launched(const char* what) {
@@ -545,7 +592,8 @@ size_t pn_mlp_train_workspace_size(int32_t batch) {
     if (batch <= 0) return 0;
     const size_t B = (size_t)batch;
     return al(B * kFeatLd * 2) + 3 * al(B * 256 * 2) + al(B * 2 * 4) + al(B * 2 * 2) + 2 * al(B * 256 * 2) +
-           al(256 * 256 * 4) * 2 + al(256 * 7 * 4) + al(2 * 256 * 4) + 4 * al(256 * 4);
+           al(256 * 256 * 4) * 2 + al(256 * 7 * 4) + al(2 * 256 * 4) + 4 * al(256 * 4) +
+           al((size_t)kSplitFloats * 4);
 }
 
 pn_status pn_mlp_sync_bf16(pn_mlp* net, hipStream_t stream) {
@@ -580,6 +628,7 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
     dW[3] = (float*)take(2 * 256 * 4);
     float* db[4];
     for (int l = 0; l < 4; ++l) db[l] = (float*)take(256 * 4);
+    float* part = (float*)take((size_t)kSplitFloats * 4);
     hipStream_t s = stream;
 
     hipLaunchKernelGGL(k_gather_rows, dim3(blocks_for((int64_t)B * kFeatLd, 256)), dim3(256), 0, s, feat, idx,
@@ -587,19 +636,19 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
     forward(s, net, B, X, h[0], h[1], h[2], out);
     hipLaunchKernelGGL(k_loss, dim3(blocks_for(B, 256)), dim3(256), 0, s, out, label, target, idx, B, g4, loss);
     // Layer 4: dW4 = g4^T h3, db4, g3 = (g4 W4) * (h3 > 0).
-    gemm(s, 2, 256, B, g4, 1, 2, h[2], 256, 1, nullptr, 0, nullptr, 0, dW[3], 256, nullptr, 0);
+    gemm(s, 2, 256, B, g4, 1, 2, h[2], 256, 1, nullptr, 0, nullptr, 0, dW[3], 256, nullptr, 0, part);
     hipLaunchKernelGGL(k_bias_grad, dim3(2), dim3(256), 0, s, g4, (int64_t)B, 2, (int64_t)2, db[3]);
     gemm(s, B, 256, 2, g4, 2, 1, net->wb[3], 256, 1, nullptr, 0, h[2], 256, nullptr, 0, gA, 256);
     // Layer 3.
-    gemm(s, 256, 256, B, gA, 1, 256, h[1], 256, 1, nullptr, 0, nullptr, 0, dW[2], 256, nullptr, 0);
+    gemm(s, 256, 256, B, gA, 1, 256, h[1], 256, 1, nullptr, 0, nullptr, 0, dW[2], 256, nullptr, 0, part);
     hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, s, gA, (int64_t)B, 256, (int64_t)256, db[2]);
     gemm(s, B, 256, 256, gA, 256, 1, net->wb[2], 256, 1, nullptr, 0, h[1], 256, nullptr, 0, gB, 256);
     // Layer 2.
-    gemm(s, 256, 256, B, gB, 1, 256, h[0], 256, 1, nullptr, 0, nullptr, 0, dW[1], 256, nullptr, 0);
+    gemm(s, 256, 256, B, gB, 1, 256, h[0], 256, 1, nullptr, 0, nullptr, 0, dW[1], 256, nullptr, 0, part);
     hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, s, gB, (int64_t)B, 256, (int64_t)256, db[1]);
     gemm(s, B, 256, 256, gB, 256, 1, net->wb[1], 256, 1, nullptr, 0, h[0], 256, nullptr, 0, gA, 256);
     // Layer 1.
-    gemm(s, 256, 7, B, gA, 1, 256, X, kFeatLd, 1, nullptr, 0, nullptr, 0, dW[0], 7, nullptr, 0);
+    gemm(s, 256, 7, B, gA, 1, 256, X, kFeatLd, 1, nullptr, 0, nullptr, 0, dW[0], 7, nullptr, 0, part);
     hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, s, gA, (int64_t)B, 256, (int64_t)256, db[0]);
     // Adam on the FP32 master weights, refreshing the bfloat16 copies.
     const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);

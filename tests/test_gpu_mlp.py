@@ -129,10 +129,11 @@ def test_fused_inference_equals_layer_by_layer(pn, n):
     assert np.median(err) <= 1e-5 * np.abs(ref).max()
 
 
-def test_train_step_matches_oracle(pn):
+@pytest.mark.parametrize("B", [100, 1024, 4096])   # weight gradients unsplit, split 8 ways, split 16-32 ways
+def test_train_step_matches_oracle(pn, B):
     rng = np.random.default_rng(9)
     net, params = _network(pn)
-    n, B = 5000, 1024
+    n = 5000
     X = rng.normal(size=(n, 7))
     feat = np.zeros((n, 8), dtype=np.float32)
     feat[:, :7] = X
