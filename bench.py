@@ -297,7 +297,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--epochs", type=int, default=4, help="surrogate workload: training epochs")
     ap.add_argument("--plain-sample", type=int, default=65536, help="surrogate workload: plain-scan sample")
-    ap.add_argument("--refine", type=int, default=10, help="surrogate workload: refinement epochs on the audit")
+    ap.add_argument("--refine", type=int, default=40, help="surrogate workload: refinement epochs on the audit")
     ap.add_argument("--margin", type=float, default=0.5, help="surrogate workload: logit margin of the gate")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of this many MiB (a kernel of known traffic "

@@ -423,7 +423,7 @@ typedef struct {
     float margin;            /* points with |logit| < margin are integrated (0.5) */
     double audit_frac;       /* audit: SplitMix64(seed + i) / 2^64 < audit_frac (0.01) */
     uint64_t seed;           /* audit seed (5) */
-    int32_t refine_epochs;   /* passes of training on the integrated audit (10; 0: none) */
+    int32_t refine_epochs;   /* passes of training on the integrated audit (40; 0: none) */
     int32_t refine_batch;    /* samples per refinement step (2048) */
     float refine_lr;         /* Adam learning rate of the refinement (5e-4) */
     uint64_t refine_seed;    /* SplitMix64 seed of the sample order (51) */

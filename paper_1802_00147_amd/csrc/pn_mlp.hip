@@ -794,7 +794,7 @@ void pn_default_surrogate_cfg(pn_surrogate_cfg* c) {
     c->margin = 0.5f;
     c->audit_frac = 0.01;
     c->seed = 5;
-    c->refine_epochs = 10;
+    c->refine_epochs = 40;
     c->refine_batch = 2048;
     c->refine_lr = 5e-4f;
     c->refine_seed = 51;
