@@ -427,6 +427,8 @@ typedef struct {
     int32_t refine_batch;    /* samples per refinement step (2048) */
     float refine_lr;         /* Adam learning rate of the refinement (5e-4) */
     uint64_t refine_seed;    /* SplitMix64 seed of the sample order (51) */
+    int32_t refine_cosine;   /* 1: learning rate refine_lr (1 + cos(pi e / epochs)) / 2 in
+                                epoch e; 0: constant (0) */
 } pn_surrogate_cfg;
 
 void pn_default_surrogate_cfg(pn_surrogate_cfg* cfg);

@@ -798,6 +798,7 @@ void pn_default_surrogate_cfg(pn_surrogate_cfg* c) {
     c->refine_batch = 2048;
     c->refine_lr = 5e-4f;
     c->refine_seed = 51;
+    c->refine_cosine = 0;
 }
 
 size_t pn_surrogate_scan_workspace_size(int64_t n, int32_t refine_batch) {
@@ -853,6 +854,7 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
     if (!cfg || !label || !integrated || n < 0 || n > 0x7fffffffLL) return PN_EINVAL;
     if (!(cfg->margin >= 0.0f) || !(cfg->audit_frac >= 0.0 && cfg->audit_frac <= 1.0)) return PN_EINVAL;
     if (cfg->refine_epochs < 0 || cfg->refine_batch <= 0) return PN_EINVAL;
+    if (cfg->refine_cosine != 0 && cfg->refine_cosine != 1) return PN_EINVAL;
     if (cfg->refine_epochs > 0 && (!adam_step || *adam_step < 0 || !(cfg->refine_lr > 0.0f))) return PN_EINVAL;
     if (!net_ok(net, cfg->refine_epochs > 0)) return PN_EINVAL;
     if (!r0 || !p0 || !th1 || !ph1 || !th2 || !ph2 || !mean || !stdv) return PN_EINVAL;
@@ -969,6 +971,9 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
         SplitMix rng{cfg->refine_seed};
         std::vector<int32_t> ord(valid);
         for (int32_t e = 0; e < cfg->refine_epochs && nb > 0; ++e) {
+            const float lr_e = cfg->refine_cosine
+                                   ? cfg->refine_lr * 0.5f * (1.0f + cosf(3.14159265358979f * e / cfg->refine_epochs))
+                                   : cfg->refine_lr;
             for (size_t k = ord.size(); k > 1; --k) {          // Fisher-Yates
                 const size_t r = (size_t)(rng.next() % k);
                 std::swap(ord[k - 1], ord[r]);
@@ -978,7 +983,7 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
             for (int64_t b = 0; b < nb; ++b) {
                 *adam_step += 1;
                 PN_TRY(pn_mlp_train_step(net, featA, labA, tgtA, order + b * cfg->refine_batch, cfg->refine_batch,
-                                         *adam_step, cfg->refine_lr, loss, tws,
+                                         *adam_step, lr_e, loss, tws,
                                          pn_mlp_train_workspace_size(cfg->refine_batch), stream));
             }
         }

@@ -67,7 +67,7 @@ class ScanOut(ctypes.Structure):
 class SurrogateCfg(ctypes.Structure):
     _fields_ = [("margin", ctypes.c_float), ("audit_frac", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("refine_epochs", ctypes.c_int32), ("refine_batch", ctypes.c_int32), ("refine_lr", ctypes.c_float),
-                ("refine_seed", ctypes.c_uint64)]
+                ("refine_seed", ctypes.c_uint64), ("refine_cosine", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
