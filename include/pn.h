@@ -393,7 +393,8 @@ pn_status pn_mlp_infer(const pn_mlp* net, const float* feat, int64_t n, float* o
 /* The same outputs as pn_mlp_infer, bit for bit, from one persistent kernel
  * that runs all four layers on 64-row tiles with the activations in LDS and
  * the layer-2/3 weights in registers (a12: fused inference).  No workspace;
- * feat [n][8], out [n][2] device arrays owned by the caller. */
+ * feat [n][8] (16-byte aligned, else PN_EINVAL), out [n][2] device arrays
+ * owned by the caller. */
 pn_status pn_mlp_infer_fused(const pn_mlp* net, const float* feat, int64_t n, float* out,
                              hipStream_t stream);
 

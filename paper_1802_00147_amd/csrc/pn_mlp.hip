@@ -37,12 +37,8 @@ constexpr int kOut[4] = {256, 256, 256, 2};
 constexpr int kFeatLd = 8;     // feature rows are padded to 8 values
 
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;   // NaN stays NaN
-    u += 0x7fffu + ((u >> 16) & 1u);                        // round to nearest, ties to even
-    return (uint16_t)(u >> 16);
-}
+// FP32 -> bfloat16, round to nearest even (one v_cvt_pk_bf16_f32 on gfx950).
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
@@ -250,17 +246,35 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
     const float bias3 = lr < 2 ? b3[lr] : 0.0f;
 
     const int64_t ntiles = (n + FT - 1) / FT;
+    // Feature rows of a tile for the lanes of K-group 0 (16-byte loads; the
+    // next tile's rows are requested before this tile's layers 2-4 run, so
+    // their latency hides behind the matrix work).
+    float4 fcur[4][2], fnext[4][2];
+    auto load_feat = [&](int64_t t, float4 (&dst)[4][2]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t row = t * FT + 16 * i + lr;
+            if (lq == 0 && t < ntiles && row < n) {
+                dst[i][0] = *reinterpret_cast<const float4*>(feat + row * kFeatLd);
+                dst[i][1] = *reinterpret_cast<const float4*>(feat + row * kFeatLd + 4);
+            } else {
+                dst[i][0] = make_float4(0.f, 0.f, 0.f, 0.f);
+                dst[i][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+    };
+    load_feat(blockIdx.x, fcur);
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t r0 = tile * FT;
         f32x4 acc[4][2];
-        // Layer 1: A fragment of row block i straight from the FP32 features.
+        // Layer 1: A fragment of row block i from the features (7 values, the
+        // eighth is the zero padding of the feature row).
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int64_t row = r0 + 16 * i + lr;
             uint16_t v[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t)
-                v[t] = (lq == 0 && t < 7 && row < n) ? f2bf(feat[row * kFeatLd + t]) : (uint16_t)0;
+            v[0] = f2bf(fcur[i][0].x); v[1] = f2bf(fcur[i][0].y); v[2] = f2bf(fcur[i][0].z);
+            v[3] = f2bf(fcur[i][0].w); v[4] = f2bf(fcur[i][1].x); v[5] = f2bf(fcur[i][1].y);
+            v[6] = f2bf(fcur[i][1].z); v[7] = 0;
             const bf16x8 a = *reinterpret_cast<const bf16x8*>(v);
 #pragma unroll
             for (int j = 0; j < 2; ++j)
@@ -277,6 +291,7 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                         h[16 * i + 4 * lq + v][c0 + 16 * j + lr] = f2bf(fmaxf(acc[i][j][v] + bias[layer][j], 0.0f));
         };
         store(hA, 0);
+        load_feat(tile + gridDim.x, fnext);
         __syncthreads();
         // Layers 2 and 3: A fragments from LDS, B fragments from registers.
 #pragma unroll
@@ -324,6 +339,11 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
             }
         }
         __syncthreads();   // hA is rewritten by the next tile's layer 1
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            fcur[i][0] = fnext[i][0];
+            fcur[i][1] = fnext[i][1];
+        }
     }
 }
 
@@ -709,7 +729,7 @@ pn_status pn_mlp_infer(const pn_mlp* net, const float* feat, int64_t n, float* o
 pn_status pn_mlp_infer_fused(const pn_mlp* net, const float* feat, int64_t n, float* out, hipStream_t stream) {
     if (!net_ok(net, false) || n < 0) return PN_EINVAL;
     if (n == 0) return PN_OK;
-    if (!feat || !out) return PN_EINVAL;
+    if (!feat || !out || (reinterpret_cast<uintptr_t>(feat) & 15u) != 0) return PN_EINVAL;
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0) {
