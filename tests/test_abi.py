@@ -179,6 +179,16 @@ def test_invalid_surrogate_scan_arguments_rejected(pn):
     assert L.pn_surrogate_scan_workspace_size(1000, 2048) > 1000 * (8 * 4 * 2 + 12 * 8)
 
 
+def test_fused_inference_rejects_misaligned_features(pn):
+    L = pn.lib()
+    net = pn.Mlp(*[pn.P4(*([256] * 4)) for _ in range(7)])
+    out = ctypes.c_void_p(256)
+    assert L.pn_mlp_infer_fused(ctypes.byref(net), ctypes.c_void_p(8), ctypes.c_int64(10), out, None) == pn.PN_EINVAL
+    assert L.pn_mlp_infer_fused(ctypes.byref(net), None, ctypes.c_int64(10), out, None) == pn.PN_EINVAL
+    assert L.pn_mlp_infer_fused(ctypes.byref(net), ctypes.c_void_p(8), ctypes.c_int64(0), out, None) == pn.PN_OK
+    assert L.pn_mlp_infer_fused(ctypes.byref(net), ctypes.c_void_p(256), ctypes.c_int64(-1), out, None) == pn.PN_EINVAL
+
+
 def test_workspace_sizes_and_shutdown(pn):
     L = pn.lib()
     assert L.pn_fli_scan_workspace_size(0) == 0 and L.pn_fli_scan_workspace_size(10 ** 6) == 0
