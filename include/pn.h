@@ -362,7 +362,8 @@ pn_status pn_mlp_targets(const double* fli, const int8_t* label, const double* t
 /* Bytes of workspace for one training step of `batch` samples. */
 size_t pn_mlp_train_workspace_size(int32_t batch);
 
-/* One training step on rows idx[0..batch) of feat [rows][8], label [rows]
+/* One training step on rows idx[0..batch) of feat [rows][8] (16-byte aligned,
+ * else PN_EINVAL), label [rows]
  * (1 chaotic, 0 regular) and target [rows] (FLI - log10 t_end): forward,
  * loss (binary cross-entropy of output 0 + Huber, delta 1, of output 1,
  * mean over the batch), backward, and an Adam update (beta1 0.9, beta2 0.999,

@@ -204,11 +204,32 @@ __device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t* p) {
     return *reinterpret_cast<const bf16x8*>(p);
 }
 
+// Optional extras of the fused pass, used by training: rows idx[r] of the
+// features instead of row r, and the bfloat16 inputs and hidden activations
+// written out ([n][8] and [n][256], 16-byte aligned) for the backward pass.
+struct FusedIO {
+    const int32_t* idx;
+    uint16_t* x_out;
+    uint16_t* h_out[3];
+};
+
+// Copy the valid rows of an LDS activation tile to global memory, 16 bytes
+// per access.
+__device__ __forceinline__ void copy_tile(const uint16_t (*h)[FLD], uint16_t* dst, int64_t r0, int64_t n, int tid) {
+#pragma unroll
+    for (int e = tid; e < FT * 32; e += 512) {
+        const int r = e >> 5, c = (e & 31) * 8;
+        if (r0 + r < n) *reinterpret_cast<uint4*>(dst + (r0 + r) * 256 + c) = *reinterpret_cast<const uint4*>(&h[r][c]);
+    }
+}
+
+template <bool IO>
 __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ w0, const uint16_t* __restrict__ w1,
                                                    const uint16_t* __restrict__ w2, const uint16_t* __restrict__ w3,
                                                    const float* __restrict__ b0, const float* __restrict__ b1,
                                                    const float* __restrict__ b2, const float* __restrict__ b3,
-                                                   const float* __restrict__ feat, int64_t n, float* __restrict__ out) {
+                                                   const float* __restrict__ feat, int64_t n, float* __restrict__ out,
+                                                   FusedIO io) {
     __shared__ __attribute__((aligned(16))) uint16_t hA[FT][FLD];
     __shared__ __attribute__((aligned(16))) uint16_t hB[FT][FLD];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -255,8 +276,9 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
         for (int i = 0; i < 4; ++i) {
             const int64_t row = t * FT + 16 * i + lr;
             if (lq == 0 && t < ntiles && row < n) {
-                dst[i][0] = *reinterpret_cast<const float4*>(feat + row * kFeatLd);
-                dst[i][1] = *reinterpret_cast<const float4*>(feat + row * kFeatLd + 4);
+                const int64_t src = (IO && io.idx) ? (int64_t)io.idx[row] : row;
+                dst[i][0] = *reinterpret_cast<const float4*>(feat + src * kFeatLd);
+                dst[i][1] = *reinterpret_cast<const float4*>(feat + src * kFeatLd + 4);
             } else {
                 dst[i][0] = make_float4(0.f, 0.f, 0.f, 0.f);
                 dst[i][1] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -276,6 +298,8 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
             v[3] = f2bf(fcur[i][0].w); v[4] = f2bf(fcur[i][1].x); v[5] = f2bf(fcur[i][1].y);
             v[6] = f2bf(fcur[i][1].z); v[7] = 0;
             const bf16x8 a = *reinterpret_cast<const bf16x8*>(v);
+            if (IO && io.x_out && lq == 0 && r0 + 16 * i + lr < n)
+                *reinterpret_cast<bf16x8*>(io.x_out + (r0 + 16 * i + lr) * kFeatLd) = a;
 #pragma unroll
             for (int j = 0; j < 2; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wf0[j], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
@@ -291,8 +315,9 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                         h[16 * i + 4 * lq + v][c0 + 16 * j + lr] = f2bf(fmaxf(acc[i][j][v] + bias[layer][j], 0.0f));
         };
         store(hA, 0);
-        load_feat(tile + gridDim.x, fnext);
+        if (!IO) load_feat(tile + gridDim.x, fnext);   // training batches give each workgroup about one tile
         __syncthreads();
+        if (IO && io.h_out[0]) copy_tile(hA, io.h_out[0], r0, n, tid);
         // Layers 2 and 3: A fragments from LDS, B fragments from registers.
 #pragma unroll
         for (int layer = 1; layer < 3; ++layer) {
@@ -314,6 +339,7 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
             }
             store(hout, layer);
             __syncthreads();
+            if (IO && io.h_out[layer]) copy_tile(hout, io.h_out[layer], r0, n, tid);
         }
         // Layer 4 on wavefronts 0-3 (row block = wavefront), outputs 0 and 1.
         if (wave < 4) {
@@ -339,10 +365,14 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
             }
         }
         __syncthreads();   // hA is rewritten by the next tile's layer 1
+        if (IO) {
+            load_feat(tile + gridDim.x, fcur);
+        } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            fcur[i][0] = fnext[i][0];
-            fcur[i][1] = fnext[i][1];
+            for (int i = 0; i < 4; ++i) {
+                fcur[i][0] = fnext[i][0];
+                fcur[i][1] = fnext[i][1];
+            }
         }
     }
 }
@@ -389,27 +419,32 @@ __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* G, int64_t ro
     if (threadIdx.x == 0) db[n] = part[0];
 }
 
+// Adam over all eight parameter tensors in one launch: tensor t holds
+// elements [off[t], off[t+1]) of the flat index.
 struct AdamArgs {
-    float* w;
-    const float* g;
-    float* m;
-    float* v;
-    uint16_t* wb;   // bfloat16 copy (null for biases)
-    int64_t n;
+    float* w[8];
+    const float* g[8];
+    float* m[8];
+    float* v[8];
+    uint16_t* wb[8];    // bfloat16 copy (null for biases)
+    int64_t off[9];
     float lr, c1, c2;   // c1 = 1 - b1^t, c2 = 1 - b2^t
 };
-
 __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= a.n) return;
-    const float g = a.g[e];
-    const float m = 0.9f * a.m[e] + 0.1f * g;
-    const float v = 0.999f * a.v[e] + 0.001f * g * g;
-    a.m[e] = m;
-    a.v[e] = v;
-    const float w = a.w[e] - a.lr * (m / a.c1) / (sqrtf(v / a.c2) + 1e-8f);
-    a.w[e] = w;
-    if (a.wb) a.wb[e] = f2bf(w);
+    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (f >= a.off[8]) return;
+    int t = 0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) t += (f >= a.off[k]) ? 1 : 0;
+    const int64_t e = f - a.off[t];
+    const float g = a.g[t][e];
+    const float m = 0.9f * a.m[t][e] + 0.1f * g;
+    const float v = 0.999f * a.v[t][e] + 0.001f * g * g;
+    a.m[t][e] = m;
+    a.v[t][e] = v;
+    const float w = a.w[t][e] - a.lr * (m / a.c1) / (sqrtf(v / a.c2) + 1e-8f);
+    a.w[t][e] = w;
+    if (a.wb[t]) a.wb[t][e] = f2bf(w);
 }
 
 __global__ __launch_bounds__(256) void k_to_bf16(const float* x, int64_t n, uint16_t* y) {
@@ -589,6 +624,28 @@ bool net_ok(const pn_mlp* net, bool training) {
     return true;
 }
 
+// One fused pass over n rows on a persistent grid of at most one workgroup per CU.
+void launch_fused(hipStream_t s, const pn_mlp* net, const float* feat, int64_t n, float* out, const FusedIO& io,
+                  int ncu) {
+    const int64_t ntiles = (n + FT - 1) / FT;
+    const unsigned grid = (unsigned)(ntiles < ncu ? ntiles : ncu);
+    const bool with_io = io.idx || io.x_out || io.h_out[0] || io.h_out[1] || io.h_out[2];
+    if (with_io)
+        hipLaunchKernelGGL(k_mlp_fused<true>, dim3(grid), dim3(512), 0, s, net->wb[0], net->wb[1], net->wb[2],
+                           net->wb[3], net->b[0], net->b[1], net->b[2], net->b[3], feat, n, out, io);
+    else
+        hipLaunchKernelGGL(k_mlp_fused<false>, dim3(grid), dim3(512), 0, s, net->wb[0], net->wb[1], net->wb[2],
+                           net->wb[3], net->b[0], net->b[1], net->b[2], net->b[3], feat, n, out, io);
+}
+
+int device_cu_count() {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return ncu;
+}
+
 // Forward pass of rows [0, rows) whose bfloat16 inputs are in X (ld 8).
 void forward(hipStream_t s, const pn_mlp* net, int64_t rows, const uint16_t* X, uint16_t* h1, uint16_t* h2,
              uint16_t* h3, float* out) {
@@ -629,8 +686,14 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
                             const int32_t* idx, int32_t batch, int32_t step, float lr, float* loss,
                             void* ws, size_t ws_bytes, hipStream_t stream) {
     if (!net_ok(net, true) || !feat || !label || !target || !idx || !loss) return PN_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(feat) & 15u) != 0) return PN_EINVAL;
     if (batch <= 0 || step < 1 || !(lr > 0.0f) || !std::isfinite(lr)) return PN_EINVAL;
     if (!ws || ws_bytes < pn_mlp_train_workspace_size(batch)) return PN_ENOWS;
+    const int ncu = device_cu_count();
+    if (ncu <= 0) {
+        pn_detail::set_last_error("pn_mlp_train_step", "no device");
+        return PN_EDEVICE;
+    }
     const int B = batch;
     char* p = static_cast<char*>(ws);
     auto take = [&](size_t bytes) { char* q = p; p += al(bytes); return q; };
@@ -651,9 +714,9 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
     float* part = (float*)take((size_t)kSplitFloats * 4);
     hipStream_t s = stream;
 
-    hipLaunchKernelGGL(k_gather_rows, dim3(blocks_for((int64_t)B * kFeatLd, 256)), dim3(256), 0, s, feat, idx,
-                       (int64_t)B, (int64_t)0, X);
-    forward(s, net, B, X, h[0], h[1], h[2], out);
+    // Forward: one fused pass over the batch rows idx[], keeping the inputs
+    // and hidden activations for the backward pass.
+    launch_fused(s, net, feat, B, out, FusedIO{idx, X, {h[0], h[1], h[2]}}, ncu);
     hipLaunchKernelGGL(k_loss, dim3(blocks_for(B, 256)), dim3(256), 0, s, out, label, target, idx, B, g4, loss);
     // Layer 4: dW4 = g4^T h3, db4, g3 = (g4 W4) * (h3 > 0).
     gemm(s, 2, 256, B, g4, 1, 2, h[2], 256, 1, nullptr, 0, nullptr, 0, dW[3], 256, nullptr, 0, part);
@@ -671,17 +734,19 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
     gemm(s, 256, 7, B, gA, 1, 256, X, kFeatLd, 1, nullptr, 0, nullptr, 0, dW[0], 7, nullptr, 0, part);
     hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, s, gA, (int64_t)B, 256, (int64_t)256, db[0]);
     // Adam on the FP32 master weights, refreshing the bfloat16 copies.
-    const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
+    AdamArgs a;
+    a.lr = lr;
+    a.c1 = 1.0f - powf(0.9f, (float)step);
+    a.c2 = 1.0f - powf(0.999f, (float)step);
+    a.off[0] = 0;
     for (int l = 0; l < 4; ++l) {
-        AdamArgs a;
-        a.w = net->w[l]; a.g = dW[l]; a.m = net->mw[l]; a.v = net->vw[l]; a.wb = net->wb[l];
-        a.n = (int64_t)kIn[l] * kOut[l]; a.lr = lr; a.c1 = c1; a.c2 = c2;
-        hipLaunchKernelGGL(k_adam, dim3(blocks_for(a.n, 256)), dim3(256), 0, s, a);
-        AdamArgs c;
-        c.w = net->b[l]; c.g = db[l]; c.m = net->mb[l]; c.v = net->vb[l]; c.wb = nullptr;
-        c.n = kOut[l]; c.lr = lr; c.c1 = c1; c.c2 = c2;
-        hipLaunchKernelGGL(k_adam, dim3(blocks_for(c.n, 256)), dim3(256), 0, s, c);
+        const int tw = 2 * l, tb = 2 * l + 1;
+        a.w[tw] = net->w[l]; a.g[tw] = dW[l]; a.m[tw] = net->mw[l]; a.v[tw] = net->vw[l]; a.wb[tw] = net->wb[l];
+        a.off[tw + 1] = a.off[tw] + (int64_t)kIn[l] * kOut[l];
+        a.w[tb] = net->b[l]; a.g[tb] = db[l]; a.m[tb] = net->mb[l]; a.v[tb] = net->vb[l]; a.wb[tb] = nullptr;
+        a.off[tb + 1] = a.off[tb] + kOut[l];
     }
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(a.off[8], 256)), dim3(256), 0, s, a);
     return launched("pn_mlp_train_step");
 }
 
@@ -730,16 +795,12 @@ pn_status pn_mlp_infer_fused(const pn_mlp* net, const float* feat, int64_t n, fl
     if (!net_ok(net, false) || n < 0) return PN_EINVAL;
     if (n == 0) return PN_OK;
     if (!feat || !out || (reinterpret_cast<uintptr_t>(feat) & 15u) != 0) return PN_EINVAL;
-    int dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0) {
+    const int ncu = device_cu_count();
+    if (ncu <= 0) {
         pn_detail::set_last_error("pn_mlp_infer_fused", "no device");
         return PN_EDEVICE;
     }
-    const int64_t ntiles = (n + FT - 1) / FT;
-    const unsigned grid = (unsigned)(ntiles < ncu ? ntiles : ncu);
-    hipLaunchKernelGGL(k_mlp_fused, dim3(grid), dim3(512), 0, stream, net->wb[0], net->wb[1], net->wb[2],
-                       net->wb[3], net->b[0], net->b[1], net->b[2], net->b[3], feat, n, out);
+    launch_fused(stream, net, feat, n, out, FusedIO{nullptr, nullptr, {nullptr, nullptr, nullptr}}, ncu);
     return launched("pn_mlp_infer_fused");
 }
 
