@@ -36,8 +36,8 @@ KERNEL_SOURCES = ["paper_1802_00147_amd/csrc/pn_kernels.hip", "paper_1802_00147_
 # kernel source whose hash is recorded with it.
 # grid64 launch: FETCH_SIZE 365.125 KiB x 1.999923 (a 1 GiB copy reads 524,308.25
 # KiB) + WRITE_SIZE 548.0 KiB x 1.0 (the copy writes 1,048,576 KiB).
-TRAFFIC = dict(workload="grid64", bytes_per_launch=747747 + 561152,
-               sources_sha256="ac9416f23849a613e13f513c902f10e30ee6c0116b6cd62886817c2806d2e0f3")
+TRAFFIC = dict(workload="grid64", bytes_per_launch=753508 + 593920,
+               sources_sha256="94a216361b992af96ab6dacd3142a562c8e12040894cfd981db7081751549bdf")
 
 
 def sources_sha256():
@@ -60,6 +60,8 @@ def make_workload(name):
         return W.fig7()
     if name == "single":
         return W.single()
+    if name == "fig6":
+        return W.fig6()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -67,21 +69,26 @@ def describe(wl):
     if wl.name == "single":
         return {"workload": f"single: one orbit and its shadow (d0 = 1e-8), r0=20, p0 from seed 1, beta=1, chi=1, "
                             f"isotropic spins (seed 1), t={wl.t_end:g}, RK4 h=1, six-integral correction, QM on",
-                "orbits": 1, "t_end": wl.t_end, "orbit_steps": wl.steps()}
+                "orbits": 1, "t_end": wl.t_end, "orbit_steps_scheduled": wl.steps()}
     if wl.shape is None:
         return {"workload": f"{wl.name}: {wl.n} orbits, per-orbit beta in [0.1,1], chi in [0,1], isotropic "
                             "spins, r0 in [8,60], t_end log-uniform in [1e3,1e6]; persistent work-stealing "
                             "scan, autotuned; RK4 h=1, six-integral correction, QM on",
-                "orbits": wl.n, "orbit_steps": wl.steps()}
+                "orbits": wl.n, "orbit_steps_scheduled": wl.steps()}
+    if wl.name.startswith("fig6"):
+        return {"workload": "fig6: the paper's theta2 line, 314 orbits, theta2 = 0.01k, theta1 = pi/2, "
+                            f"(beta, r0, p_y) = (1/3, 5.65, 0.765) as printed (unbound states removed at t = 0), "
+                            f"chi=1, QM on, t={wl.t_end:g}, RK4 h=1, six-integral correction, threshold 5.8",
+                "orbits": wl.n, "t_end": wl.t_end, "orbit_steps_scheduled": wl.steps()}
     if wl.name == "fig7":
         return {"workload": "fig7: the paper's 314x314 (theta1, theta2) spin-angle plane, theta_i = 0.01k, "
                             f"r0=10.14, p_y=0.365, beta=1, chi=1, QM on, t={wl.t_end:g}, RK4 h=1, "
                             "six-integral correction, threshold 5.8",
-                "orbits": wl.n, "t_end": wl.t_end, "orbit_steps": wl.steps()}
+                "orbits": wl.n, "t_end": wl.t_end, "orbit_steps_scheduled": wl.steps()}
     return {"workload": f"{wl.name}: {wl.shape[0]}x{wl.shape[1]} FLI scan, t={wl.t_end:g}, RK4 h=1, "
                         f"six-integral correction, beta={wl.beta:g}, chi={wl.chi1:g}, QM "
                         f"{'on' if wl.model.get('quad_mono', 1) else 'off'}",
-            "orbits": wl.n, "t_end": wl.t_end, "orbit_steps": wl.steps()}
+            "orbits": wl.n, "t_end": wl.t_end, "orbit_steps_scheduled": wl.steps()}
 
 
 def cpu_baseline(wl, sample, flop_sample_steps=2000):
@@ -97,10 +104,12 @@ def cpu_baseline(wl, sample, flop_sample_steps=2000):
     t0 = time.perf_counter()
     res = O.fli_scan(y0, sub.t_end, sub.beta, sub.chi1, sub.chi2, model=wl.model, nthreads=cores)
     dt = time.perf_counter() - t0
-    steps = sub.steps()
+    steps = int(res["steps"].sum())
     flops = []
     pick = (lambda v, k: v[k] if isinstance(v, np.ndarray) else v)
-    for k in range(min(8, len(idx))):
+    # Flops per orbit-step from up to 8 sample orbits that take steps (a state
+    # removed at t = 0 has none to count).
+    for k in [k for k in range(len(idx)) if res["steps"][k] > 0][:8]:
         c = O.count_flops(y0[k], float(flop_sample_steps), pick(sub.beta, k), pick(sub.chi1, k),
                           pick(sub.chi2, k), model=wl.model)
         flops.append(c["run_total"] / c["steps"])
@@ -368,7 +377,9 @@ def main():
     elapsed = time.perf_counter() - t0
     kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
 
-    orbit_steps = wl.steps()
+    # Orbit-steps actually integrated: an orbit removed early (unbound start,
+    # merger, escape) stops counting where it stopped.
+    orbit_steps = int(out["steps"].sum())
     value = orbit_steps * args.steps / elapsed
     labels = out["label"].cpu().numpy()
     status = out["status"].cpu().numpy()
@@ -376,6 +387,7 @@ def main():
     line = dict(metric=METRIC, value=value, unit="orbit-steps/s", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=1e3 * elapsed / args.steps, higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="f64", data="synthetic", config=describe(wl))
+    line["config"]["orbit_steps"] = orbit_steps
     line["grid_pts_per_s"] = n * args.steps / elapsed
     line["chaotic_fraction"] = float(np.mean(labels == 1))
     line["invalid_orbits"] = int(np.sum((status & 0xFF) != 0))

@@ -162,7 +162,9 @@ typedef struct {
  *   newton_max[n]   largest Newton iteration count of any correction
  *   renorms[n]      number of shadow renormalisations
  *   trace[ntrace][ld] FLI after every trace_every steps (trace_every > 0;
- *                   entries past an orbit's last step are left untouched) */
+ *                   entries past an orbit's last step are left untouched)
+ *   steps[n]        steps the orbit completed (ceil(t_end / h) unless it was
+ *                   removed; 0 for a state removed at t = 0) */
 typedef struct {
     double* fli;
     int8_t* label;
@@ -175,6 +177,7 @@ typedef struct {
     double* trace;
     int64_t trace_every;
     int64_t ntrace;
+    int64_t* steps;
 } pn_scan_out;
 
 /* Defaults used by the tests and benchmark (filled into caller structs). */

@@ -226,7 +226,8 @@ def fli_scan(y0, t_end, beta, chi1, chi2, model=None, integrator=None, correctio
     integ = _fill(_Integrator, INTEGRATOR, integrator)
     out = dict(fli=np.zeros(n), label=np.zeros(n, np.int8), status=np.zeros(n, np.int32),
                y_final=np.zeros((n, 12)), dH=np.zeros(n), dJ=np.zeros(n),
-               newton_max=np.zeros(n, np.int32), renorms=np.zeros(n, np.int64))
+               newton_max=np.zeros(n, np.int32), renorms=np.zeros(n, np.int64),
+               steps=np.zeros(n, np.int64))
     ntrace = 0
     trace = None
     if trace_every > 0:
@@ -239,7 +240,8 @@ def fli_scan(y0, t_end, beta, chi1, chi2, model=None, integrator=None, correctio
                       ctypes.c_int64(ts), _p(out["fli"]), _p(out["label"], ctypes.c_int8),
                       _p(out["status"], ctypes.c_int32), _p(out["y_final"]), _p(out["dH"]),
                       _p(out["dJ"]), _p(out["newton_max"], ctypes.c_int32),
-                      _p(out["renorms"], ctypes.c_int64), _p(trace), ctypes.c_int64(trace_every),
+                      _p(out["renorms"], ctypes.c_int64), _p(out["steps"], ctypes.c_int64), _p(trace),
+                      ctypes.c_int64(trace_every),
                       ctypes.c_int64(ntrace), ctypes.c_int32(nthreads))
     if trace is not None:
         out["trace"] = trace

@@ -878,14 +878,15 @@ double or_rk_linear_step(int32_t method, double z) {
 
 // Full FLI run for n orbits, parallel over orbits with nthreads std::threads.
 // Outputs (each nullable except fli/label/status): y_final[12*n], dH[n], dJ[n],
-// newton_max[n], renorms[n], trace[n * ntrace] with ntrace = nsteps/trace_every.
+// newton_max[n], renorms[n], steps[n] (steps the orbit completed before its
+// run ended), trace[n * ntrace] with ntrace = nsteps/trace_every.
 void or_fli_scan(const or_model* m, const double* beta, const double* chi1, const double* chi2,
                  int64_t pstride, const or_integrator* in, const or_correction* cc,
                  const or_fli_cfg* fc, int64_t n, const double* y0, const double* t_end,
                  int64_t tstride, double* fli, int8_t* label, int32_t* status,
                  double* y_final, double* dH, double* dJ, int32_t* newton_max,
-                 int64_t* renorms, double* trace, int64_t trace_every, int64_t ntrace,
-                 int32_t nthreads) {
+                 int64_t* renorms, int64_t* steps, double* trace, int64_t trace_every,
+                 int64_t ntrace, int32_t nthreads) {
     std::atomic<int64_t> next(0);
     auto worker = [&]() {
         for (;;) {
@@ -900,6 +901,7 @@ void or_fli_scan(const or_model* m, const double* beta, const double* chi1, cons
                 if (dJ) dJ[i] = NAN;
                 if (newton_max) newton_max[i] = 0;
                 if (renorms) renorms[i] = 0;
+                if (steps) steps[i] = 0;
                 continue;
             }
             const Coef c = make_coef(*m, pick(beta, pstride, i), pick(chi1, pstride, i), pick(chi2, pstride, i));
@@ -913,6 +915,7 @@ void or_fli_scan(const or_model* m, const double* beta, const double* chi1, cons
             if (dJ) dJ[i] = r.dJ;
             if (newton_max) newton_max[i] = r.newton_max;
             if (renorms) renorms[i] = r.renorms;
+            if (steps) steps[i] = r.steps_done;
         }
     };
     if (nthreads <= 1) {

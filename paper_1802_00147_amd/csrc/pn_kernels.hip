@@ -371,6 +371,7 @@ __device__ __forceinline__ void pair_finish(PairState& ps, const PnCoef& k, bool
     o.status[i] = ps.st | ((ps.any_nc || nc_other) ? PN_ORBIT_NEWTON_NOCONV : 0);
     if (o.newton_max) o.newton_max[i] = max(ps.nmax, nmax_other);
     if (o.renorms) o.renorms[i] = ps.renorms;
+    if (o.steps) o.steps[i] = ps.t;
 }
 
 // Fused scan: orbit i on lanes (2i, 2i+1) from t = 0 to t_end.

@@ -61,7 +61,8 @@ class ScanOut(ctypes.Structure):
     _fields_ = [("fli", ctypes.c_void_p), ("label", ctypes.c_void_p), ("status", ctypes.c_void_p),
                 ("y_final", ctypes.c_void_p), ("dH", ctypes.c_void_p), ("dJ", ctypes.c_void_p),
                 ("newton_max", ctypes.c_void_p), ("renorms", ctypes.c_void_p),
-                ("trace", ctypes.c_void_p), ("trace_every", ctypes.c_int64), ("ntrace", ctypes.c_int64)]
+                ("trace", ctypes.c_void_p), ("trace_every", ctypes.c_int64), ("ntrace", ctypes.c_int64),
+                ("steps", ctypes.c_void_p)]
 
 
 class SurrogateCfg(ctypes.Structure):
@@ -268,7 +269,8 @@ def scan_outputs(n, ld, device, full=True, trace_every=0, nsteps_max=0):
                  dH=torch.empty(ld, dtype=torch.float64, device=device),
                  dJ=torch.empty(ld, dtype=torch.float64, device=device),
                  newton_max=torch.empty(ld, dtype=torch.int32, device=device),
-                 renorms=torch.empty(ld, dtype=torch.int64, device=device))
+                 renorms=torch.empty(ld, dtype=torch.int64, device=device),
+                 steps=torch.empty(ld, dtype=torch.int64, device=device))
     if trace_every > 0:
         ntrace = nsteps_max // trace_every
         o["trace"] = torch.full((ntrace, ld), float("nan"), dtype=torch.float64, device=device)
@@ -326,9 +328,7 @@ def fli_scan(y0, t_end, beta, chi1, chi2, model=None, integrator=None, correctio
         tmax = float(t_end.max()) if isinstance(t_end, torch.Tensor) else float(t_end)
         nmax = int(-(-tmax // integ.h)) if tmax > 0 else 0
         out = scan_outputs(n, ld, y0.device, full=full, trace_every=trace_every, nsteps_max=nmax)
-    so = ScanOut(*[out[k].data_ptr() if k in out else None
-                   for k in ("fli", "label", "status", "y_final", "dH", "dJ", "newton_max", "renorms", "trace")],
-                 int(out.get("trace_every", 0)), int(out["trace"].shape[0]) if "trace" in out else 0)
+    so = _scan_out_struct(out)
     p, keep = params_struct(beta, chi1, chi2)
     if isinstance(t_end, torch.Tensor):
         tptr, tall = _ptr(_dev_f64(t_end, n)), 0.0
@@ -357,7 +357,8 @@ def batch_workspace(n, device):
 def _scan_out_struct(out):
     return ScanOut(*[out[k].data_ptr() if k in out else None
                      for k in ("fli", "label", "status", "y_final", "dH", "dJ", "newton_max", "renorms", "trace")],
-                   int(out.get("trace_every", 0)), int(out["trace"].shape[0]) if "trace" in out else 0)
+                   int(out.get("trace_every", 0)), int(out["trace"].shape[0]) if "trace" in out else 0,
+                   out["steps"].data_ptr() if "steps" in out else None)
 
 
 def _batch_common(y0, t_end, beta, chi1, chi2, model, integrator, correction, fli, out, n, full, trace_every, ws):

@@ -12,7 +12,7 @@ from gpu_helpers import DEV, dev, rel_err_rows
 pytestmark = pytest.mark.gpu
 
 FLI_ABS_CORRECTED = 3e-4
-KEYS = ("fli", "label", "status", "y_final", "dH", "dJ", "newton_max", "renorms")
+KEYS = ("fli", "label", "status", "y_final", "dH", "dJ", "newton_max", "renorms", "steps")
 
 
 @pytest.fixture(scope="module")
@@ -49,6 +49,7 @@ def test_batch_equals_plain_scan(pn):
     assert np.array_equal(batch["status"], plain["status"])
     assert np.array_equal(batch["label"], plain["label"])
     assert np.array_equal(batch["renorms"], plain["renorms"])
+    assert np.array_equal(batch["steps"], plain["steps"])
     ok = plain["status"] == 0
     assert np.all(np.abs(batch["fli"][ok] - plain["fli"][ok]) <= 1e-12 * np.abs(plain["fli"][ok]) + 1e-12)
     assert np.all(rel_err_rows(batch["y_final"].T[ok], plain["y_final"].T[ok]) <= 1e-13)
@@ -97,7 +98,9 @@ def test_batch_parity_with_oracle(pn):
     exp = O.fli_scan(y0o, wl.t_end, wl.beta, wl.chi1, wl.chi2, nthreads=8)
     assert np.array_equal(got["status"], exp["status"])
     assert np.array_equal(got["label"], exp["label"])
+    assert np.array_equal(got["steps"], exp["steps"])
     ok = exp["status"] == 0
+    assert np.array_equal(got["steps"][ok], np.ceil(wl.t_end[ok]).astype(np.int64))
     assert np.all(rel_err_rows(got["y_final"].T[ok], exp["y_final"][ok]) <= 1e-9)
     # The FLI of short corrected runs has a noise floor of its own: the
     # oracle moves by as much when one initial momentum component changes by

@@ -231,9 +231,16 @@ def test_scan_status_edge_cases(pn):
     assert list(exp["status"] & 0xFF) == [4, 1, 2, 3, 0, 5]
     assert np.array_equal(got["status"], exp["status"])
     assert np.array_equal(got["label"], exp["label"])
+    # Steps completed: none for the states removed at t = 0 (unbound,
+    # non-finite, bad parameter), all 2000 for the orbit that stays, the
+    # removal step for the plunge and the escape.
+    assert np.array_equal(got["steps"], exp["steps"])
+    assert list(got["steps"][[0, 3, 5]]) == [0, 0, 0] and got["steps"][4] == 2000
+    assert np.all((got["steps"][1:3] > 0) & (got["steps"][1:3] < 2000))
     # Zero end time.
     exp0, got0 = _scan_both(pn, y0[4:5], 0.0, 1.0, 0.0, 0.0, 1, nthreads=1)
     assert got0["status"][0] == 0 and abs(got0["fli"][0] - exp0["fli"][0]) < 1e-12
+    assert got0["steps"][0] == 0 and exp0["steps"][0] == 0
 
 
 def test_scan_grid64_full_size_sampled(pn):

@@ -91,6 +91,26 @@ def test_status_codes(oracle):
     # Zero integration time: FLI = log10(d0/d0) = 0, regular.
     r = O.fli_scan(kepler_state(), 0.0, 1.0, 0, 0)
     assert r["status"][0] == 0 and abs(r["fli"][0]) < 1e-6 and r["label"][0] == 0
+    assert r["steps"][0] == 0
+
+
+def test_steps_completed(oracle):
+    """The steps output counts ceil(t_end / h) steps for an orbit that
+    stays, none for a state removed at t = 0, and for a removed orbit the
+    step of its removal: the same orbit run to one step less survives, run
+    to exactly that many steps it does not."""
+    O = oracle
+    r = O.fli_scan(kepler_state(), 100.5, 1.0, 0, 0)
+    assert r["status"][0] == 0 and r["steps"][0] == 101
+    r = O.fli_scan(kepler_state(10.0, 0.6), 100, 1.0, 0, 0)
+    assert r["steps"][0] == 0
+    for y, fli in ((kepler_state(6.0, 0.05), None), (kepler_state(10.0, 0.4), dict(r_esc=11.0))):
+        r = O.fli_scan(y, 2000, 1.0, 0, 0, fli=fli)
+        k = int(r["steps"][0])
+        assert r["status"][0] != 0 and 0 < k < 2000
+        assert O.fli_scan(y, float(k - 1), 1.0, 0, 0, fli=fli)["status"][0] == 0
+        again = O.fli_scan(y, float(k), 1.0, 0, 0, fli=fli)
+        assert again["status"][0] == r["status"][0] and again["steps"][0] == k
 
 
 def test_threads_do_not_change_results(oracle):
