@@ -404,10 +404,25 @@ __global__ __launch_bounds__(256) void k_loss(const float* out, const float* lab
     if (threadIdx.x == 0) atomicAdd(loss, part[0] / (float)B);
 }
 
-// db[n] = sum over rows of the bfloat16 gradient G [rows x N] (one block per n).
-__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* G, int64_t rows, int N, int64_t ldg, float* db) {
+// Bias gradients of the four layers in one launch: db_l[n] = sum over rows
+// of the bfloat16 gradient G_l [rows x N_l]; block b < first[4] serves layer
+// l with first[l] <= b < first[l+1], column n = b - first[l].
+struct BiasArgs {
+    const uint16_t* G[4];
+    int64_t ldg[4];
+    float* db[4];
+    int first[5];
+    int64_t rows;
+};
+__global__ __launch_bounds__(256) void k_bias_grads(BiasArgs a) {
     __shared__ float part[256];
-    const int n = blockIdx.x;
+    int l = 0;
+#pragma unroll
+    for (int k = 1; k < 4; ++k) l += ((int)blockIdx.x >= a.first[k]) ? 1 : 0;
+    const int n = (int)blockIdx.x - a.first[l];
+    const uint16_t* G = a.G[l];
+    const int64_t ldg = a.ldg[l], rows = a.rows;
+    float* db = a.db[l];
     float s = 0.0f;
     for (int64_t m = threadIdx.x; m < rows; m += 256) s += bf2f(G[m * ldg + n]);
     part[threadIdx.x] = s;
@@ -424,6 +439,8 @@ __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* G, int64_t ro
 struct AdamArgs {
     float* w[8];
     const float* g[8];
+    const float* part[8];   // splits[t] > 1: g = sum over z, in order, of part[t][z][e]
+    int splits[8];
     float* m[8];
     float* v[8];
     uint16_t* wb[8];    // bfloat16 copy (null for biases)
@@ -437,7 +454,17 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
 #pragma unroll
     for (int k = 1; k < 8; ++k) t += (f >= a.off[k]) ? 1 : 0;
     const int64_t e = f - a.off[t];
-    const float g = a.g[t][e];
+    float g;
+    if (a.splits[t] > 1) {
+        // The split weight gradient, summed in the order of k_sum_splits.
+        const int64_t mn = a.off[t + 1] - a.off[t];
+        const float* pp = a.part[t];
+        float x = 0.0f;
+        for (int z = 0; z < a.splits[t]; ++z) x += pp[z * mn + e];
+        g = x;
+    } else {
+        g = a.g[t][e];
+    }
     const float m = 0.9f * a.m[t][e] + 0.1f * g;
     const float v = 0.999f * a.v[t][e] + 0.001f * g * g;
     a.m[t][e] = m;
@@ -566,10 +593,12 @@ constexpr int64_t kSplitFloats = (int64_t)1 << 20;   // partial-sum buffer of a 
 // gradients: K = batch rows) is split along K over up to 256 workgroups when
 // `part` (kSplitFloats floats) is given and the result is a plain FP32
 // store; the partials are summed in a fixed order, so the result does not
-// depend on scheduling.
-void gemm(hipStream_t s, int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B,
-          int64_t sbk, int64_t sbn, const float* bias, int relu, const uint16_t* mask, int64_t ldm, float* Cf,
-          int64_t ldcf, uint16_t* Cb, int64_t ldcb, float* part = nullptr) {
+// depend on scheduling.  With sum_parts false and more than one split, the
+// partials part[z][M][N] are left for the consumer to sum (in the same
+// order) and C is not written.  Returns the number of splits.
+int gemm(hipStream_t s, int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B,
+         int64_t sbk, int64_t sbn, const float* bias, int relu, const uint16_t* mask, int64_t ldm, float* Cf,
+         int64_t ldcf, uint16_t* Cb, int64_t ldcb, float* part = nullptr, bool sum_parts = true) {
     GemmArgs g;
     g.M = M; g.N = N; g.K = K;
     g.A = A; g.sam = sam; g.sak = sak;
@@ -594,14 +623,16 @@ void gemm(hipStream_t s, int M, int N, int K, const uint16_t* A, int64_t sam, in
     }
     if (splits == 1) {
         hipLaunchKernelGGL(k_gemm_bf16, dim3(blocks_for(N, BN), blocks_for(M, BM)), dim3(256), 0, s, g);
-        return;
+        return 1;
     }
     g.Cf = part;
     g.ldcf = N;
     g.split_stride = (int64_t)M * N;
     hipLaunchKernelGGL(k_gemm_bf16, dim3(blocks_for(N, BN), blocks_for(M, BM), splits), dim3(256), 0, s, g);
-    hipLaunchKernelGGL(k_sum_splits, dim3(blocks_for((int64_t)M * N, 256)), dim3(256), 0, s, part, splits, M, N, Cf,
-                       ldcf);
+    if (sum_parts)
+        hipLaunchKernelGGL(k_sum_splits, dim3(blocks_for((int64_t)M * N, 256)), dim3(256), 0, s, part, splits, M, N,
+                           Cf, ldcf);
+    return splits;
 }
 
 pn_status launched(const char* what) {
@@ -668,9 +699,9 @@ size_t pn_mlp_param_count(int32_t layer, int32_t which) {
 size_t pn_mlp_train_workspace_size(int32_t batch) {
     if (batch <= 0) return 0;
     const size_t B = (size_t)batch;
-    return al(B * kFeatLd * 2) + 3 * al(B * 256 * 2) + al(B * 2 * 4) + al(B * 2 * 2) + 2 * al(B * 256 * 2) +
+    return al(B * kFeatLd * 2) + 3 * al(B * 256 * 2) + al(B * 2 * 4) + al(B * 2 * 2) + 3 * al(B * 256 * 2) +
            al(256 * 256 * 4) * 2 + al(256 * 7 * 4) + al(2 * 256 * 4) + 4 * al(256 * 4) +
-           al((size_t)kSplitFloats * 4);
+           4 * al((size_t)kSplitFloats * 4);
 }
 
 pn_status pn_mlp_sync_bf16(pn_mlp* net, hipStream_t stream) {
@@ -702,8 +733,9 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
     for (int l = 0; l < 3; ++l) h[l] = (uint16_t*)take((size_t)B * 256 * 2);
     float* out = (float*)take((size_t)B * 2 * 4);
     uint16_t* g4 = (uint16_t*)take((size_t)B * 2 * 2);
-    uint16_t* gA = (uint16_t*)take((size_t)B * 256 * 2);
-    uint16_t* gB = (uint16_t*)take((size_t)B * 256 * 2);
+    uint16_t* g3 = (uint16_t*)take((size_t)B * 256 * 2);
+    uint16_t* g2 = (uint16_t*)take((size_t)B * 256 * 2);
+    uint16_t* g1 = (uint16_t*)take((size_t)B * 256 * 2);
     float* dW[4];
     dW[1] = (float*)take(256 * 256 * 4);
     dW[2] = (float*)take(256 * 256 * 4);
@@ -711,28 +743,41 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
     dW[3] = (float*)take(2 * 256 * 4);
     float* db[4];
     for (int l = 0; l < 4; ++l) db[l] = (float*)take(256 * 4);
-    float* part = (float*)take((size_t)kSplitFloats * 4);
+    float* part[4];
+    for (int l = 0; l < 4; ++l) part[l] = (float*)take((size_t)kSplitFloats * 4);
     hipStream_t s = stream;
 
     // Forward: one fused pass over the batch rows idx[], keeping the inputs
     // and hidden activations for the backward pass.
     launch_fused(s, net, feat, B, out, FusedIO{idx, X, {h[0], h[1], h[2]}}, ncu);
     hipLaunchKernelGGL(k_loss, dim3(blocks_for(B, 256)), dim3(256), 0, s, out, label, target, idx, B, g4, loss);
-    // Layer 4: dW4 = g4^T h3, db4, g3 = (g4 W4) * (h3 > 0).
-    gemm(s, 2, 256, B, g4, 1, 2, h[2], 256, 1, nullptr, 0, nullptr, 0, dW[3], 256, nullptr, 0, part);
-    hipLaunchKernelGGL(k_bias_grad, dim3(2), dim3(256), 0, s, g4, (int64_t)B, 2, (int64_t)2, db[3]);
-    gemm(s, B, 256, 2, g4, 2, 1, net->wb[3], 256, 1, nullptr, 0, h[2], 256, nullptr, 0, gA, 256);
-    // Layer 3.
-    gemm(s, 256, 256, B, gA, 1, 256, h[1], 256, 1, nullptr, 0, nullptr, 0, dW[2], 256, nullptr, 0, part);
-    hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, s, gA, (int64_t)B, 256, (int64_t)256, db[2]);
-    gemm(s, B, 256, 256, gA, 256, 1, net->wb[2], 256, 1, nullptr, 0, h[1], 256, nullptr, 0, gB, 256);
-    // Layer 2.
-    gemm(s, 256, 256, B, gB, 1, 256, h[0], 256, 1, nullptr, 0, nullptr, 0, dW[1], 256, nullptr, 0, part);
-    hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, s, gB, (int64_t)B, 256, (int64_t)256, db[1]);
-    gemm(s, B, 256, 256, gB, 256, 1, net->wb[1], 256, 1, nullptr, 0, h[0], 256, nullptr, 0, gA, 256);
-    // Layer 1.
-    gemm(s, 256, 7, B, gA, 1, 256, X, kFeatLd, 1, nullptr, 0, nullptr, 0, dW[0], 7, nullptr, 0, part);
-    hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, s, gA, (int64_t)B, 256, (int64_t)256, db[0]);
+    // Backward.  Weight gradients dW_l = g_l^T h_(l-1) go to per-layer
+    // split-K partials that the Adam launch sums; the layer gradients
+    // g_(l-1) = (g_l W_l) * (h_(l-1) > 0) stay live for one launch that forms
+    // all bias gradients.
+    int splits[4];
+    splits[3] = gemm(s, 2, 256, B, g4, 1, 2, h[2], 256, 1, nullptr, 0, nullptr, 0, dW[3], 256, nullptr, 0, part[3],
+                     false);
+    gemm(s, B, 256, 2, g4, 2, 1, net->wb[3], 256, 1, nullptr, 0, h[2], 256, nullptr, 0, g3, 256);
+    splits[2] = gemm(s, 256, 256, B, g3, 1, 256, h[1], 256, 1, nullptr, 0, nullptr, 0, dW[2], 256, nullptr, 0,
+                     part[2], false);
+    gemm(s, B, 256, 256, g3, 256, 1, net->wb[2], 256, 1, nullptr, 0, h[1], 256, nullptr, 0, g2, 256);
+    splits[1] = gemm(s, 256, 256, B, g2, 1, 256, h[0], 256, 1, nullptr, 0, nullptr, 0, dW[1], 256, nullptr, 0,
+                     part[1], false);
+    gemm(s, B, 256, 256, g2, 256, 1, net->wb[1], 256, 1, nullptr, 0, h[0], 256, nullptr, 0, g1, 256);
+    splits[0] = gemm(s, 256, 7, B, g1, 1, 256, X, kFeatLd, 1, nullptr, 0, nullptr, 0, dW[0], 7, nullptr, 0, part[0],
+                     false);
+    BiasArgs ba;
+    const uint16_t* gl[4] = {g1, g2, g3, g4};
+    ba.rows = B;
+    ba.first[0] = 0;
+    for (int l = 0; l < 4; ++l) {
+        ba.G[l] = gl[l];
+        ba.ldg[l] = kOut[l];
+        ba.db[l] = db[l];
+        ba.first[l + 1] = ba.first[l] + kOut[l];
+    }
+    hipLaunchKernelGGL(k_bias_grads, dim3(ba.first[4]), dim3(256), 0, s, ba);
     // Adam on the FP32 master weights, refreshing the bfloat16 copies.
     AdamArgs a;
     a.lr = lr;
@@ -742,8 +787,10 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
     for (int l = 0; l < 4; ++l) {
         const int tw = 2 * l, tb = 2 * l + 1;
         a.w[tw] = net->w[l]; a.g[tw] = dW[l]; a.m[tw] = net->mw[l]; a.v[tw] = net->vw[l]; a.wb[tw] = net->wb[l];
+        a.part[tw] = part[l]; a.splits[tw] = splits[l];
         a.off[tw + 1] = a.off[tw] + (int64_t)kIn[l] * kOut[l];
         a.w[tb] = net->b[l]; a.g[tb] = db[l]; a.m[tb] = net->mb[l]; a.v[tb] = net->vb[l]; a.wb[tb] = nullptr;
+        a.part[tb] = nullptr; a.splits[tb] = 1;
         a.off[tb + 1] = a.off[tb] + kOut[l];
     }
     hipLaunchKernelGGL(k_adam, dim3(blocks_for(a.off[8], 256)), dim3(256), 0, s, a);
