@@ -112,12 +112,12 @@ __device__ __forceinline__ void stage_tile(uint16_t (*tile)[LDSK], const uint16_
     }
 }
 
-// C = A B (+ bias) (ReLU) (* mask), M x N, FP32 accumulation.
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[BM][LDSK];
-    __shared__ __attribute__((aligned(16))) uint16_t Bt[BN][LDSK];
+// One 64 x 64 output tile (column block bx, row block by, K split bz) of
+// C = A B (+ bias) (ReLU) (* mask), FP32 accumulation, staged through As/Bt.
+__device__ __forceinline__ void gemm_block(const GemmArgs& g, int bx, int by, int bz, uint16_t (*As)[LDSK],
+                                           uint16_t (*Bt)[LDSK]) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+    const int64_t m0 = (int64_t)by * BM, n0 = (int64_t)bx * BN;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int lr = lane & 15, lk = (lane >> 4) * 8;
     f32x4 acc[2][2];
@@ -126,9 +126,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     // Split K: layer z of the grid sums K range [kb, ke) into its own partial.
-    const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
+    const int64_t kb = (int64_t)bz * g.kchunk;
     const int64_t ke = (kb + g.kchunk < g.K) ? kb + g.kchunk : g.K;
-    float* const Cf = g.Cf ? g.Cf + (int64_t)blockIdx.z * g.split_stride : nullptr;
+    float* const Cf = g.Cf ? g.Cf + (int64_t)bz * g.split_stride : nullptr;
     for (int64_t k0 = kb; k0 < ke; k0 += BK) {
         stage_tile(As, g.A, g.sam, g.sak, g.amode, m0, g.M, k0, ke, tid);
         stage_tile(Bt, g.B, g.sbn, g.sbk, g.bmode, n0, g.N, k0, ke, tid);
@@ -161,6 +161,43 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
                 if (Cf) Cf[m * g.ldcf + n] = x;
                 if (g.Cb) g.Cb[m * g.ldcb + n] = f2bf(x);
             }
+}
+
+// C = A B (+ bias) (ReLU) (* mask), M x N: grid (N / 64, M / 64, K splits).
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[BM][LDSK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bt[BN][LDSK];
+    gemm_block(g, blockIdx.x, blockIdx.y, blockIdx.z, As, Bt);
+}
+
+// Up to four independent products in one launch (the weight gradients of a
+// training step): block b belongs to product l with first[l] <= b <
+// first[l+1] and takes its tile in x-fastest order of that product's
+// (tx, ty, splits) grid.  Each tile is computed as k_gemm_bf16 computes it.
+struct GemmGroup {
+    GemmArgs g[4];
+    int tx[4], ty[4];
+    int first[5];
+};
+__global__ __launch_bounds__(256) void k_gemm_group(GemmGroup gg) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[BM][LDSK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bt[BN][LDSK];
+    const int b = blockIdx.x;
+    int l = 0;
+#pragma unroll
+    for (int k = 1; k < 4; ++k) l += (b >= gg.first[k]) ? 1 : 0;
+    int tx = gg.tx[0], ty = gg.ty[0], f = gg.first[0];
+    if (l == 1) { tx = gg.tx[1]; ty = gg.ty[1]; f = gg.first[1]; }
+    if (l == 2) { tx = gg.tx[2]; ty = gg.ty[2]; f = gg.first[2]; }
+    if (l == 3) { tx = gg.tx[3]; ty = gg.ty[3]; f = gg.first[3]; }
+    const int local = b - f;
+    const int bx = local % tx, by = (local / tx) % ty, bz = local / (tx * ty);
+    switch (l) {
+        case 0: gemm_block(gg.g[0], bx, by, bz, As, Bt); break;
+        case 1: gemm_block(gg.g[1], bx, by, bz, As, Bt); break;
+        case 2: gemm_block(gg.g[2], bx, by, bz, As, Bt); break;
+        default: gemm_block(gg.g[3], bx, by, bz, As, Bt); break;
+    }
 }
 
 // C[m][n] (ld ldc) = sum over z = 0 .. splits-1, in that order, of part[z][m][n].
@@ -596,9 +633,14 @@ constexpr int64_t kSplitFloats = (int64_t)1 << 20;   // partial-sum buffer of a 
 // depend on scheduling.  With sum_parts false and more than one split, the
 // partials part[z][M][N] are left for the consumer to sum (in the same
 // order) and C is not written.  Returns the number of splits.
-int gemm(hipStream_t s, int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B,
-         int64_t sbk, int64_t sbn, const float* bias, int relu, const uint16_t* mask, int64_t ldm, float* Cf,
-         int64_t ldcf, uint16_t* Cb, int64_t ldcb, float* part = nullptr, bool sum_parts = true) {
+struct GemmPlan {
+    GemmArgs g;             // as launched (Cf = part when split)
+    int tx, ty, splits;     // grid
+};
+
+GemmPlan plan_gemm(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B,
+                   int64_t sbk, int64_t sbn, const float* bias, int relu, const uint16_t* mask, int64_t ldm,
+                   float* Cf, int64_t ldcf, uint16_t* Cb, int64_t ldcb, float* part) {
     GemmArgs g;
     g.M = M; g.N = N; g.K = K;
     g.A = A; g.sam = sam; g.sak = sak;
@@ -621,18 +663,23 @@ int gemm(hipStream_t s, int M, int N, int K, const uint16_t* A, int64_t sam, int
             g.kchunk = (int)chunk;
         }
     }
-    if (splits == 1) {
-        hipLaunchKernelGGL(k_gemm_bf16, dim3(blocks_for(N, BN), blocks_for(M, BM)), dim3(256), 0, s, g);
-        return 1;
+    if (splits > 1) {
+        g.Cf = part;
+        g.ldcf = N;
+        g.split_stride = (int64_t)M * N;
     }
-    g.Cf = part;
-    g.ldcf = N;
-    g.split_stride = (int64_t)M * N;
-    hipLaunchKernelGGL(k_gemm_bf16, dim3(blocks_for(N, BN), blocks_for(M, BM), splits), dim3(256), 0, s, g);
-    if (sum_parts)
-        hipLaunchKernelGGL(k_sum_splits, dim3(blocks_for((int64_t)M * N, 256)), dim3(256), 0, s, part, splits, M, N,
-                           Cf, ldcf);
-    return splits;
+    return GemmPlan{g, (int)blocks_for(N, BN), (int)blocks_for(M, BM), splits};
+}
+
+int gemm(hipStream_t s, int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B,
+         int64_t sbk, int64_t sbn, const float* bias, int relu, const uint16_t* mask, int64_t ldm, float* Cf,
+         int64_t ldcf, uint16_t* Cb, int64_t ldcb, float* part = nullptr, bool sum_parts = true) {
+    const GemmPlan pl = plan_gemm(M, N, K, A, sam, sak, B, sbk, sbn, bias, relu, mask, ldm, Cf, ldcf, Cb, ldcb, part);
+    hipLaunchKernelGGL(k_gemm_bf16, dim3(pl.tx, pl.ty, pl.splits), dim3(256), 0, s, pl.g);
+    if (pl.splits > 1 && sum_parts)
+        hipLaunchKernelGGL(k_sum_splits, dim3(blocks_for((int64_t)M * N, 256)), dim3(256), 0, s, part, pl.splits, M,
+                           N, Cf, ldcf);
+    return pl.splits;
 }
 
 pn_status launched(const char* what) {
@@ -755,18 +802,26 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
     // split-K partials that the Adam launch sums; the layer gradients
     // g_(l-1) = (g_l W_l) * (h_(l-1) > 0) stay live for one launch that forms
     // all bias gradients.
-    int splits[4];
-    splits[3] = gemm(s, 2, 256, B, g4, 1, 2, h[2], 256, 1, nullptr, 0, nullptr, 0, dW[3], 256, nullptr, 0, part[3],
-                     false);
     gemm(s, B, 256, 2, g4, 2, 1, net->wb[3], 256, 1, nullptr, 0, h[2], 256, nullptr, 0, g3, 256);
-    splits[2] = gemm(s, 256, 256, B, g3, 1, 256, h[1], 256, 1, nullptr, 0, nullptr, 0, dW[2], 256, nullptr, 0,
-                     part[2], false);
     gemm(s, B, 256, 256, g3, 256, 1, net->wb[2], 256, 1, nullptr, 0, h[1], 256, nullptr, 0, g2, 256);
-    splits[1] = gemm(s, 256, 256, B, g2, 1, 256, h[0], 256, 1, nullptr, 0, nullptr, 0, dW[1], 256, nullptr, 0,
-                     part[1], false);
     gemm(s, B, 256, 256, g2, 256, 1, net->wb[1], 256, 1, nullptr, 0, h[0], 256, nullptr, 0, g1, 256);
-    splits[0] = gemm(s, 256, 7, B, g1, 1, 256, X, kFeatLd, 1, nullptr, 0, nullptr, 0, dW[0], 7, nullptr, 0, part[0],
-                     false);
+    // The four weight gradients in one launch.
+    const GemmPlan pw[4] = {
+        plan_gemm(256, 7, B, g1, 1, 256, X, kFeatLd, 1, nullptr, 0, nullptr, 0, dW[0], 7, nullptr, 0, part[0]),
+        plan_gemm(256, 256, B, g2, 1, 256, h[0], 256, 1, nullptr, 0, nullptr, 0, dW[1], 256, nullptr, 0, part[1]),
+        plan_gemm(256, 256, B, g3, 1, 256, h[1], 256, 1, nullptr, 0, nullptr, 0, dW[2], 256, nullptr, 0, part[2]),
+        plan_gemm(2, 256, B, g4, 1, 2, h[2], 256, 1, nullptr, 0, nullptr, 0, dW[3], 256, nullptr, 0, part[3])};
+    GemmGroup gg;
+    int splits[4];
+    gg.first[0] = 0;
+    for (int l = 0; l < 4; ++l) {
+        gg.g[l] = pw[l].g;
+        gg.tx[l] = pw[l].tx;
+        gg.ty[l] = pw[l].ty;
+        gg.first[l + 1] = gg.first[l] + pw[l].tx * pw[l].ty * pw[l].splits;
+        splits[l] = pw[l].splits;
+    }
+    hipLaunchKernelGGL(k_gemm_group, dim3(gg.first[4]), dim3(256), 0, s, gg);
     BiasArgs ba;
     const uint16_t* gl[4] = {g1, g2, g3, g4};
     ba.rows = B;
