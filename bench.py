@@ -114,10 +114,23 @@ def cpu_baseline(wl, sample, flop_sample_steps=2000):
                           pick(sub.chi2, k), model=wl.model)
         flops.append(c["run_total"] / c["steps"])
     tdesc = f"full t={wl.t_end:g}" if wl.shape is not None else "full per-orbit t_end"
-    return dict(value=steps / dt, unit="orbit-steps/s", cores=cores, kind="oracle",
+    rate = steps / dt
+    return dict(value=rate, unit="orbit-steps/s", cores=cores, kind="oracle",
                 sample=f"{len(idx)} seeded orbits of {wl.name}, {tdesc} "
                        f"({steps} orbit-steps, {dt:.1f} s wall on {cores} threads)",
+                per_core=rate / cores, nproc=os.cpu_count(), cpu_model=cpu_model(),
                 labels=res["label"], flops_per_orbit_step=float(np.mean(flops)))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def gw_bench(args, dev):
@@ -278,7 +291,9 @@ def surrogate_bench(args, dev):
         cb.pop("labels")
         fpos = cb.pop("flops_per_orbit_step")
         cb["value"] = cb["value"] / grid.t_end   # orbit-steps/s -> grid-pts/s (1e5 steps per point)
+        cb["per_core"] = cb["per_core"] / grid.t_end
         cb["unit"] = "grid-pts/s"
+        cb["extrapolated_full_s"] = grid.n / cb["value"]   # plain scan of the whole grid, never run
         line["cpu_baseline"] = cb
         # Dominant kernel of the assisted scan: the FP64 batch scan of the audit
         # and of the uncertain points, timed by the call's own phase events
@@ -403,6 +418,9 @@ def main():
         cb = cpu_baseline(wl, args.cpu_sample)
         fpos = cb.pop("flops_per_orbit_step")
         cb.pop("labels")
+        # The whole workload on the same host threads, extrapolated from the
+        # sample's rate (never run).
+        cb["extrapolated_full_s"] = orbit_steps / cb["value"]
         line["cpu_baseline"] = cb
         achieved = fpos * orbit_steps / (kernel_ms * 1e-3) / 1e12
         traffic = None
