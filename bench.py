@@ -37,7 +37,7 @@ KERNEL_SOURCES = ["paper_1802_00147_amd/csrc/pn_kernels.hip", "paper_1802_00147_
 # grid64 launch: FETCH_SIZE 365.125 KiB x 1.999923 (a 1 GiB copy reads 524,308.25
 # KiB) + WRITE_SIZE 548.0 KiB x 1.0 (the copy writes 1,048,576 KiB).
 TRAFFIC = dict(workload="grid64", bytes_per_launch=753508 + 593920,
-               sources_sha256="94a216361b992af96ab6dacd3142a562c8e12040894cfd981db7081751549bdf")
+               sources_sha256="5d416b6b32d543a14038daaa6187bc215b7f7ba41b53ab412bd57c0cc68fa291")
 
 
 def sources_sha256():

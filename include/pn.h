@@ -317,6 +317,41 @@ pn_status pn_batch_graph_create(const pn_model* model, pn_params params, const p
 pn_status pn_graph_launch(pn_graph* graph, hipStream_t stream);
 void pn_graph_destroy(pn_graph* graph);
 
+/* Checkpoint and resume of a batch scan.  Long scans (t_end up to 1e6 steps
+ * per orbit) can be interrupted after a bounded amount of work, saved, and
+ * continued later, in the same process or after the workspace and outputs
+ * were copied to host memory and back, with results identical bit for bit to
+ * one uninterrupted pn_batch_scan (per-orbit arithmetic never depends on the
+ * schedule, and the saved state is the exact state of every orbit in flight).
+ *
+ * Bytes of workspace for n orbits: the batch queue plus two tables of
+ * min(n, 2^18) orbit records (324 bytes each). */
+size_t pn_batch_ckpt_workspace_size(int64_t n);
+
+/* pn_batch_scan with a checkpoint in ws (>= pn_batch_ckpt_workspace_size(n)
+ * bytes, device memory owned by the caller).
+ *   resume = 0: start the scan (the contents of ws on entry are irrelevant);
+ *   resume = 1: continue the scan whose state a previous call left in ws; the
+ *               model, parameters, settings, y0, t_end and out must be the
+ *               same arrays (or copies) as in the call that started it; the
+ *               tuning may differ.
+ *   max_chunks > 0: every wavefront stops after max_chunks refills of
+ *               tuning.chunk_steps steps; orbits still running are saved into
+ *               ws, finished orbits have their results in *out.
+ *   max_chunks = 0: run every remaining orbit to its end.
+ * The scan is complete when pn_batch_scan_pending reports 0.  Traces are not
+ * supported (out->trace_every must be 0).  Errors as pn_batch_scan, plus
+ * PN_EINVAL for resume outside {0, 1} or max_chunks < 0. */
+pn_status pn_batch_scan_resumable(const pn_model* model, pn_params params, const pn_integrator* integ,
+                                  const pn_correction* corr, const pn_fli_cfg* fli, int64_t n,
+                                  const double* y0, int64_t ld, const double* t_end,
+                                  const pn_scan_out* out, const pn_tuning* tuning, int32_t resume,
+                                  int32_t max_chunks, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Orbits of a resumable scan not finished yet (saved in flight plus never
+ * started), read from ws after synchronising the stream (blocks). */
+pn_status pn_batch_scan_pending(const void* ws, int64_t n, int64_t* pending, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Learned surrogate: a multilayer perceptron 7 -> 256 -> 256 -> 256 -> 2
  * (ReLU) that maps scan-point features to (chaos logit, FLI - log10 t_end),

@@ -442,13 +442,77 @@ __global__ __launch_bounds__(256) void k_batch_bin_scatter(BatchWs ws, const dou
     ws.order[pos] = (int32_t)i;
 }
 
+// Checkpoint of an interrupted batch scan: the exact state of every orbit in
+// flight, one record per orbit pair in each of two tables (the one a launch
+// resumes from and the one it saves into, swapped after every launch).  Lane
+// arrays hold two entries per record (2 r + 0 orbit, 2 r + 1 shadow).
+// hdr: [0], [1] records in table 0 / 1; [2] read cursor of the input table;
+// [3] index of the input table.
+struct CkptArgs {
+    unsigned long long* hdr;
+    int32_t* id[2];                 // [cap] orbit index
+    double* y[2];                   // [12][2 cap]
+    double* ref[2];                 // [4][2 cap]
+    double* acc[2];                 // [2 cap]
+    int64_t* t[2];                  // [2 cap]
+    int64_t* renorms[2];            // [2 cap]
+    int32_t* nmax[2];               // [2 cap]
+    int32_t* flags[2];              // [2 cap]: status | any_nc << 16
+    int64_t cap;                    // records per table
+    int32_t max_chunks;             // chunks per wavefront before it saves and leaves; 0: run to the end
+};
+
+__device__ __forceinline__ void ckpt_save(const CkptArgs& ck, int tab, unsigned long long r, const PairState& ps,
+                                          bool shadow, int64_t cur) {
+    const int64_t w = 2 * (int64_t)r + (shadow ? 1 : 0), L = 2 * ck.cap;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) ck.y[tab][c * L + w] = ps.y[c];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ck.ref[tab][c * L + w] = ps.ref[c];
+    ck.acc[tab][w] = ps.acc;
+    ck.t[tab][w] = ps.t;
+    ck.renorms[tab][w] = ps.renorms;
+    ck.nmax[tab][w] = ps.nmax;
+    ck.flags[tab][w] = ps.st | (ps.any_nc ? (1 << 16) : 0);
+    if (!shadow) ck.id[tab][r] = (int32_t)cur;
+}
+
+// Restores what ckpt_save kept; the end time and step count are recomputed
+// from the inputs as pair_begin computes them.
+__device__ __forceinline__ int64_t ckpt_load(const CkptArgs& ck, int tab, unsigned long long r, PairState& ps,
+                                             bool shadow, const FliArgs& fa) {
+    const int64_t w = 2 * (int64_t)r + (shadow ? 1 : 0), L = 2 * ck.cap;
+    const int64_t i = ck.id[tab][r];
+    if (i < 0 || i >= fa.n) return -1;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) ps.y[c] = ck.y[tab][c * L + w];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ps.ref[c] = ck.ref[tab][c * L + w];
+    ps.acc = ck.acc[tab][w];
+    ps.t = ck.t[tab][w];
+    ps.renorms = ck.renorms[tab][w];
+    ps.nmax = ck.nmax[tab][w];
+    const int f = ck.flags[tab][w];
+    ps.st = f & 0xFFFF;
+    ps.any_nc = (f >> 16) != 0;
+    ps.d2 = 0.0;
+    ps.t_end = fa.t_end ? fa.t_end[i] : fa.t_end_all;
+    ps.nsteps = ps.t_end > 0.0 ? (int64_t)ceil(ps.t_end / fa.h) : 0;
+    if (fa.step_scale != 1.0) ps.nsteps = (int64_t)ceil((double)ps.nsteps * fa.step_scale);
+    return i;
+}
+
 // Persistent kernel: every wavefront keeps 32 orbit slots busy.  Between
 // chunks of `chunk` steps, pairs whose orbit has ended write its results and
 // claim the next queue position (one atomic per wavefront), so long orbits,
 // started first, overlap with the short ones that fill the tail.  The
 // wavefront leaves when the queue is drained and all its slots are empty.
-template <int METHOD, int MODE, int OCC>
-__global__ __launch_bounds__(256, OCC) void k_batch_scan(ParamArgs pa, FliArgs fa, BatchWs ws, int32_t chunk) {
+// With CKPT, slots are first refilled from the orbits a previous launch
+// saved, and after ck.max_chunks chunks (if > 0) every pair still running
+// saves its state and the wavefront leaves.
+template <int METHOD, int MODE, int OCC, bool CKPT>
+__global__ __launch_bounds__(256, OCC) void k_batch_scan(ParamArgs pa, FliArgs fa, BatchWs ws, int32_t chunk,
+                                                          CkptArgs ck) {
     const int lane = threadIdx.x & 63;
     const bool shadow = (lane & 1) != 0;
     const unsigned long long n = (unsigned long long)fa.n;
@@ -456,7 +520,39 @@ __global__ __launch_bounds__(256, OCC) void k_batch_scan(ParamArgs pa, FliArgs f
     bool drained = false;
     PnCoef k;
     PairState ps;
+    int tin = 0;
+    unsigned long long saved = 0ull;
+    if (CKPT) {
+        // Bounded reads of the header, so that a workspace that holds no
+        // checkpoint cannot send a lane outside the tables.
+        tin = (int)(ck.hdr[3] & 1ull);
+        saved = ck.hdr[tin] < (unsigned long long)ck.cap ? ck.hdr[tin] : (unsigned long long)ck.cap;
+    }
+    int chunks = 0;
     for (;;) {
+        if (CKPT) {
+            // Saved orbits first: one atomic on the read cursor per wavefront.
+            const bool need = (cur < 0) && !drained;
+            const unsigned long long m = __ballot(need && !shadow);
+            if (m != 0ull) {
+                const int cnt = __popcll(m);
+                const int leader = __ffsll((long long)m) - 1;
+                unsigned long long base = 0ull;
+                if (lane == leader) base = atomicAdd(&ck.hdr[2], (unsigned long long)cnt);
+                base = __shfl(base, leader);
+                if (need) {
+                    const int even = lane & ~1;
+                    const unsigned long long r = base + __popcll(m & ((1ull << even) - 1ull));
+                    if (r < saved) {
+                        const int64_t i = ckpt_load(ck, tin, r, ps, shadow, fa);
+                        if (i >= 0 && i < fa.n) {
+                            cur = i;
+                            load_coef(pa, cur, k);
+                        }
+                    }
+                }
+            }
+        }
         // Refill empty slots: one atomic per wavefront for all claiming pairs.
         const bool need = (cur < 0) && !drained;
         const unsigned long long m = __ballot(need && !shadow);
@@ -471,8 +567,12 @@ __global__ __launch_bounds__(256, OCC) void k_batch_scan(ParamArgs pa, FliArgs f
                 const unsigned long long q = base + __popcll(m & ((1ull << even) - 1ull));
                 if (q < n) {
                     cur = ws.order[q];
-                    const bool ok = load_coef(pa, cur, k);
-                    pair_begin(ps, k, ok, shadow, fa, cur);
+                    if (CKPT && (cur < 0 || cur >= fa.n)) {
+                        cur = -1;       // not a queue this workspace set up: skip the position
+                    } else {
+                        const bool ok = load_coef(pa, cur, k);
+                        pair_begin(ps, k, ok, shadow, fa, cur);
+                    }
                 } else {
                     drained = true;
                 }
@@ -486,7 +586,66 @@ __global__ __launch_bounds__(256, OCC) void k_batch_scan(ParamArgs pa, FliArgs f
                 cur = -1;
             }
         }
+        if (CKPT && ck.max_chunks > 0 && ++chunks >= ck.max_chunks) {
+            // Interrupted: save the pairs still running into the other table.
+            const int tout = 1 - tin;
+            const bool keep = cur >= 0;
+            const unsigned long long m = __ballot(keep && !shadow);
+            if (m != 0ull) {
+                const int cnt = __popcll(m);
+                const int leader = __ffsll((long long)m) - 1;
+                unsigned long long base = 0ull;
+                if (lane == leader) base = atomicAdd(&ck.hdr[tout], (unsigned long long)cnt);
+                base = __shfl(base, leader);
+                if (keep) {
+                    const int even = lane & ~1;
+                    const unsigned long long r = base + __popcll(m & ((1ull << even) - 1ull));
+                    if (r < (unsigned long long)ck.cap) ckpt_save(ck, tout, r, ps, shadow, cur);
+                }
+            }
+            break;
+        }
     }
+}
+
+// After an interrupted launch (one workgroup): saved orbits of the input table
+// that no slot took are appended to the output table, which becomes the
+// input of the next launch.
+__global__ __launch_bounds__(256) void k_ckpt_carry(CkptArgs ck) {
+    const unsigned long long cap = (unsigned long long)ck.cap;
+    const int tin = (int)(ck.hdr[3] & 1ull), tout = 1 - tin;
+    const unsigned long long saved = ck.hdr[tin] < cap ? ck.hdr[tin] : cap;
+    const unsigned long long rd = ck.hdr[2] < saved ? ck.hdr[2] : saved;
+    const unsigned long long base = ck.hdr[tout] < cap ? ck.hdr[tout] : cap;
+    // The tables hold every orbit in flight (at most min(n, resident pairs));
+    // the bound below only keeps a corrupted header inside them.
+    const unsigned long long left = (saved - rd) < (cap - base) ? (saved - rd) : (cap - base);
+    const int64_t L = 2 * ck.cap;
+    for (unsigned long long r = rd + threadIdx.x; r < rd + left; r += 256) {
+        const unsigned long long d = base + (r - rd);
+        ck.id[tout][d] = ck.id[tin][r];
+        for (int h = 0; h < 2; ++h) {
+            const int64_t a = 2 * (int64_t)r + h, b = 2 * (int64_t)d + h;
+            for (int c = 0; c < 12; ++c) ck.y[tout][c * L + b] = ck.y[tin][c * L + a];
+            for (int c = 0; c < 4; ++c) ck.ref[tout][c * L + b] = ck.ref[tin][c * L + a];
+            ck.acc[tout][b] = ck.acc[tin][a];
+            ck.t[tout][b] = ck.t[tin][a];
+            ck.renorms[tout][b] = ck.renorms[tin][a];
+            ck.nmax[tout][b] = ck.nmax[tin][a];
+            ck.flags[tout][b] = ck.flags[tin][a];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ck.hdr[tout] = base + left;
+        ck.hdr[tin] = 0ull;
+        ck.hdr[2] = 0ull;
+        ck.hdr[3] = (unsigned long long)tout;
+    }
+}
+
+__global__ void k_ckpt_clear(CkptArgs ck) {
+    if (threadIdx.x < 4) ck.hdr[threadIdx.x] = 0ull;
 }
 
 // ---------------------------------------------------------------------------
@@ -590,32 +749,44 @@ void launch_scan_m(int mode, const ParamArgs& pa, const FliArgs& fa, hipStream_t
     }
 }
 
-template <int METHOD, int MODE>
-void launch_batch(const ParamArgs& pa, const FliArgs& fa, const BatchWs& ws, const pn_tuning& tu, int ncu,
-                  hipStream_t s) {
+// Orbit pairs a persistent launch keeps resident.
+int64_t batch_slots(const pn_tuning& tu, int ncu) { return (int64_t)ncu * 4 * tu.waves_per_simd * 32; }
+
+template <int METHOD, int MODE, bool CKPT>
+void launch_batch_c(const ParamArgs& pa, const FliArgs& fa, const BatchWs& ws, const pn_tuning& tu, int ncu,
+                    const CkptArgs& ck, hipStream_t s) {
     const unsigned blocks = (unsigned)((int64_t)ncu * 4 * tu.waves_per_simd * 64 / tu.block);
     // Two resident waves per SIMD need <= 256 registers per lane: RK4 fits
     // (a few bytes of spill at most); the six-stage RK5 would spill hundreds
     // of bytes, so it keeps the one-wave build and only the grid grows.
     if constexpr (METHOD == PN_RK4) {
         if (tu.waves_per_simd == 2) {
-            hipLaunchKernelGGL((k_batch_scan<METHOD, MODE, 2>), dim3(blocks), dim3(tu.block), 0, s, pa, fa, ws,
-                               tu.chunk_steps);
+            hipLaunchKernelGGL((k_batch_scan<METHOD, MODE, 2, CKPT>), dim3(blocks), dim3(tu.block), 0, s, pa, fa,
+                               ws, tu.chunk_steps, ck);
             return;
         }
     }
-    hipLaunchKernelGGL((k_batch_scan<METHOD, MODE, 1>), dim3(blocks), dim3(tu.block), 0, s, pa, fa, ws,
-                       tu.chunk_steps);
+    hipLaunchKernelGGL((k_batch_scan<METHOD, MODE, 1, CKPT>), dim3(blocks), dim3(tu.block), 0, s, pa, fa, ws,
+                       tu.chunk_steps, ck);
+}
+
+template <int METHOD, int MODE>
+void launch_batch(const ParamArgs& pa, const FliArgs& fa, const BatchWs& ws, const pn_tuning& tu, int ncu,
+                  const CkptArgs* ck, hipStream_t s) {
+    if (ck)
+        launch_batch_c<METHOD, MODE, true>(pa, fa, ws, tu, ncu, *ck, s);
+    else
+        launch_batch_c<METHOD, MODE, false>(pa, fa, ws, tu, ncu, CkptArgs{}, s);
 }
 
 template <int METHOD>
 void launch_batch_m(int mode, const ParamArgs& pa, const FliArgs& fa, const BatchWs& ws, const pn_tuning& tu,
-                    int ncu, hipStream_t s) {
+                    int ncu, const CkptArgs* ck, hipStream_t s) {
     switch (mode) {
-        case PN_CORR_NONE: launch_batch<METHOD, PN_CORR_NONE>(pa, fa, ws, tu, ncu, s); break;
-        case PN_CORR_SPIN: launch_batch<METHOD, PN_CORR_SPIN>(pa, fa, ws, tu, ncu, s); break;
-        case PN_CORR_SIX: launch_batch<METHOD, PN_CORR_SIX>(pa, fa, ws, tu, ncu, s); break;
-        default: launch_batch<METHOD, PN_CORR_DUAL>(pa, fa, ws, tu, ncu, s); break;
+        case PN_CORR_NONE: launch_batch<METHOD, PN_CORR_NONE>(pa, fa, ws, tu, ncu, ck, s); break;
+        case PN_CORR_SPIN: launch_batch<METHOD, PN_CORR_SPIN>(pa, fa, ws, tu, ncu, ck, s); break;
+        case PN_CORR_SIX: launch_batch<METHOD, PN_CORR_SIX>(pa, fa, ws, tu, ncu, ck, s); break;
+        default: launch_batch<METHOD, PN_CORR_DUAL>(pa, fa, ws, tu, ncu, ck, s); break;
     }
 }
 
@@ -636,6 +807,40 @@ BatchWs carve(void* ws, int64_t n) {
     w.order = reinterpret_cast<int32_t*>(b);
     (void)n;
     return w;
+}
+
+// Checkpoint tables: records per table, bytes per table.
+constexpr int64_t kCkptMaxPairs = (int64_t)1 << 18;
+
+int64_t ckpt_cap(int64_t n) { return n < kCkptMaxPairs ? n : kCkptMaxPairs; }
+
+size_t ckpt_table_bytes(int64_t cap) {
+    const size_t L = 2 * (size_t)cap;
+    return align256((size_t)cap * 4) + align256(12 * L * 8) + align256(4 * L * 8) + 3 * align256(L * 8) +
+           2 * align256(L * 4);
+}
+
+size_t ckpt_ws_bytes(int64_t n) { return batch_ws_bytes(n) + align256(4 * 8) + 2 * ckpt_table_bytes(ckpt_cap(n)); }
+
+CkptArgs carve_ckpt(void* ws, int64_t n, int32_t max_chunks) {
+    char* b = static_cast<char*>(ws) + batch_ws_bytes(n);
+    CkptArgs ck;
+    ck.cap = ckpt_cap(n);
+    ck.max_chunks = max_chunks;
+    ck.hdr = reinterpret_cast<unsigned long long*>(b);
+    b += align256(4 * 8);
+    const size_t L = 2 * (size_t)ck.cap;
+    for (int tab = 0; tab < 2; ++tab) {
+        ck.id[tab] = reinterpret_cast<int32_t*>(b);       b += align256((size_t)ck.cap * 4);
+        ck.y[tab] = reinterpret_cast<double*>(b);         b += align256(12 * L * 8);
+        ck.ref[tab] = reinterpret_cast<double*>(b);       b += align256(4 * L * 8);
+        ck.acc[tab] = reinterpret_cast<double*>(b);       b += align256(L * 8);
+        ck.t[tab] = reinterpret_cast<int64_t*>(b);        b += align256(L * 8);
+        ck.renorms[tab] = reinterpret_cast<int64_t*>(b);  b += align256(L * 8);
+        ck.nmax[tab] = reinterpret_cast<int32_t*>(b);     b += align256(L * 4);
+        ck.flags[tab] = reinterpret_cast<int32_t*>(b);    b += align256(L * 4);
+    }
+    return ck;
 }
 
 bool valid_tuning(const pn_tuning& t) {
@@ -717,17 +922,24 @@ pn_status prepare_scan(const pn_model* model, const pn_params& params, const pn_
 }
 
 // Enqueue the whole batch: clear, bin by step count, order, persistent scan.
+// With a checkpoint, `resume` skips the queue set-up and continues from the
+// saved orbits, and the launch is followed by the carry-over of saved orbits.
 void enqueue_batch(int method, int mode, const ParamArgs& pa, const FliArgs& fa, const BatchWs& w,
-                   const pn_tuning& tu, int ncu, hipStream_t stream) {
+                   const pn_tuning& tu, int ncu, hipStream_t stream, const CkptArgs* ck = nullptr,
+                   bool resume = false) {
     const unsigned g256 = (unsigned)((fa.n + 255) / 256);
-    hipLaunchKernelGGL(k_batch_clear, dim3(1), dim3(256), 0, stream, w);
-    hipLaunchKernelGGL(k_batch_bin_count, dim3(g256), dim3(256), 0, stream, w, fa.t_end, fa.h, fa.n);
-    hipLaunchKernelGGL(k_batch_bin_scan, dim3(1), dim3(kBins), 0, stream, w);
-    hipLaunchKernelGGL(k_batch_bin_scatter, dim3(g256), dim3(256), 0, stream, w, fa.t_end, fa.h, fa.n);
+    if (!resume) {
+        hipLaunchKernelGGL(k_batch_clear, dim3(1), dim3(256), 0, stream, w);
+        hipLaunchKernelGGL(k_batch_bin_count, dim3(g256), dim3(256), 0, stream, w, fa.t_end, fa.h, fa.n);
+        hipLaunchKernelGGL(k_batch_bin_scan, dim3(1), dim3(kBins), 0, stream, w);
+        hipLaunchKernelGGL(k_batch_bin_scatter, dim3(g256), dim3(256), 0, stream, w, fa.t_end, fa.h, fa.n);
+        if (ck) hipLaunchKernelGGL(k_ckpt_clear, dim3(1), dim3(64), 0, stream, *ck);
+    }
     if (method == PN_RK4)
-        launch_batch_m<PN_RK4>(mode, pa, fa, w, tu, ncu, stream);
+        launch_batch_m<PN_RK4>(mode, pa, fa, w, tu, ncu, ck, stream);
     else
-        launch_batch_m<PN_RK5>(mode, pa, fa, w, tu, ncu, stream);
+        launch_batch_m<PN_RK5>(mode, pa, fa, w, tu, ncu, ck, stream);
+    if (ck) hipLaunchKernelGGL(k_ckpt_carry, dim3(1), dim3(256), 0, stream, *ck);
 }
 
 }  // namespace
@@ -978,6 +1190,56 @@ pn_status pn_batch_scan(const pn_model* model, pn_params params, const pn_integr
     if (ws == nullptr || ws_bytes < batch_ws_bytes(n)) return PN_ENOWS;
     enqueue_batch(integ->method, corr->mode, pa, fa, carve(ws, n), tu, ncu, stream);
     return launched("pn_batch_scan");
+}
+
+size_t pn_batch_ckpt_workspace_size(int64_t n) { return n < 0 ? 0 : ckpt_ws_bytes(n); }
+
+pn_status pn_batch_scan_resumable(const pn_model* model, pn_params params, const pn_integrator* integ,
+                                  const pn_correction* corr, const pn_fli_cfg* fli, int64_t n, const double* y0,
+                                  int64_t ld, const double* t_end, const pn_scan_out* out,
+                                  const pn_tuning* tuning, int32_t resume, int32_t max_chunks, void* ws,
+                                  size_t ws_bytes, hipStream_t stream) {
+    ParamArgs pa;
+    FliArgs fa;
+    PN_REQUIRE(t_end != nullptr);
+    PN_REQUIRE(n < 0x7fffffffLL);
+    PN_REQUIRE(resume == 0 || resume == 1);
+    PN_REQUIRE(max_chunks >= 0);
+    PN_REQUIRE(prepare_scan(model, params, integ, corr, fli, n, y0, ld, t_end, 0.0, out, pa, fa) == PN_OK);
+    PN_REQUIRE(out->trace_every == 0);
+    int dev = 0;
+    const int ncu = device_cus(dev);
+    if (ncu <= 0) { set_error("pn_batch_scan_resumable", hipErrorInvalidDevice); return PN_EDEVICE; }
+    const pn_tuning tu = chosen_tuning(tuning, dev);
+    PN_REQUIRE(valid_tuning(tu));
+    if (n == 0) return PN_OK;
+    if (ws == nullptr || ws_bytes < ckpt_ws_bytes(n)) return PN_ENOWS;
+    // Orbits in flight never exceed the orbits or the resident pairs of a
+    // launch; the tables hold min(n, 2^18) records.
+    PN_REQUIRE(n <= kCkptMaxPairs || batch_slots(tu, ncu) <= kCkptMaxPairs);
+    const CkptArgs ck = carve_ckpt(ws, n, max_chunks);
+    enqueue_batch(integ->method, corr->mode, pa, fa, carve(ws, n), tu, ncu, stream, &ck, resume != 0);
+    return launched("pn_batch_scan_resumable");
+}
+
+pn_status pn_batch_scan_pending(const void* ws, int64_t n, int64_t* pending, hipStream_t stream) {
+    PN_REQUIRE(pending != nullptr && n >= 0);
+    *pending = 0;
+    if (n == 0) return PN_OK;
+    PN_REQUIRE(ws != nullptr);
+    hipError_t e = hipStreamSynchronize(stream);
+    unsigned long long head = 0ull, hdr[4] = {0ull, 0ull, 0ull, 0ull};
+    if (e == hipSuccess) e = hipMemcpy(&head, ws, sizeof(head), hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        e = hipMemcpy(hdr, static_cast<const char*>(ws) + batch_ws_bytes(n), sizeof(hdr), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        set_error("pn_batch_scan_pending", e);
+        return PN_EDEVICE;
+    }
+    const unsigned long long tin = hdr[3] & 1ull;
+    const unsigned long long queued = head < (unsigned long long)n ? (unsigned long long)n - head : 0ull;
+    *pending = (int64_t)(hdr[tin] + queued);
+    return PN_OK;
 }
 
 pn_status pn_autotune_batch(const pn_model* model, pn_params params, const pn_integrator* integ,

@@ -88,6 +88,7 @@ EXPORTS = ["pn_default_model", "pn_default_integrator", "pn_default_correction",
            "pn_trajectory", "pn_gw_polarizations", "pn_mlp_infer_fused",
            "pn_default_surrogate_cfg", "pn_surrogate_scan_workspace_size", "pn_surrogate_scan",
            "pn_mlp_train", "pn_fli_scan_workspace_size", "pn_shutdown",
+           "pn_batch_ckpt_workspace_size", "pn_batch_scan_resumable", "pn_batch_scan_pending",
            "pn_version", "pn_status_string", "pn_last_error"]
 
 
@@ -120,6 +121,8 @@ def lib():
         L.pn_mlp_infer_workspace_size.argtypes = [ctypes.c_int64]
         L.pn_batch_workspace_size.restype = ctypes.c_size_t
         L.pn_batch_workspace_size.argtypes = [ctypes.c_int64]
+        L.pn_batch_ckpt_workspace_size.restype = ctypes.c_size_t
+        L.pn_batch_ckpt_workspace_size.argtypes = [ctypes.c_int64]
         L.pn_graph_destroy.argtypes = [ctypes.c_void_p]
         _lib = L
     return _lib
@@ -393,6 +396,48 @@ def batch_scan(y0, t_end, beta, chi1, chi2, model=None, integrator=None, correct
                              _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(y0.device))
     _check("pn_batch_scan", st)
     return out
+
+
+def batch_ckpt_workspace(n, device):
+    nbytes = int(lib().pn_batch_ckpt_workspace_size(ctypes.c_int64(n)))
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+def batch_scan_resumable(y0, t_end, beta, chi1, chi2, ws, resume, max_chunks, model=None, integrator=None,
+                         correction=None, fli=None, out=None, n=None, full=True, tuning=None):
+    """pn_batch_scan_resumable: one launch of a checkpointed batch scan.  ws
+    (from batch_ckpt_workspace) holds the queue and the orbits in flight;
+    resume=False starts the scan, resume=True continues it; max_chunks > 0
+    interrupts every wavefront after that many chunks.  Returns the outputs;
+    batch_scan_pending tells whether orbits remain."""
+    ld = _state(y0)
+    n = ld if n is None else n
+    integ = integrator_struct(integrator)
+    assert isinstance(t_end, torch.Tensor), "batch scans take per-orbit end times"
+    t_end = _dev_f64(t_end, n)
+    if out is None:
+        out = scan_outputs(n, ld, y0.device, full=full)
+    p, keep = params_struct(beta, chi1, chi2)
+    tu = None
+    if tuning is not None:
+        tu = ctypes.byref(tuning if isinstance(tuning, Tuning) else tuning_struct(tuning))
+    so = _scan_out_struct(out)
+    st = lib().pn_batch_scan_resumable(ctypes.byref(model_struct(model)), p, ctypes.byref(integ),
+                                       ctypes.byref(correction_struct(correction)), ctypes.byref(fli_struct(fli)),
+                                       ctypes.c_int64(n), _ptr(y0), ctypes.c_int64(ld), _ptr(t_end),
+                                       ctypes.byref(so), tu, ctypes.c_int32(1 if resume else 0),
+                                       ctypes.c_int32(max_chunks), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                                       _stream(y0.device))
+    _check("pn_batch_scan_resumable", st)
+    return out
+
+
+def batch_scan_pending(ws, n):
+    """Orbits of a resumable scan not finished yet (synchronises the stream)."""
+    pending = ctypes.c_int64(0)
+    st = lib().pn_batch_scan_pending(_ptr(ws), ctypes.c_int64(n), ctypes.byref(pending), _stream(ws.device))
+    _check("pn_batch_scan_pending", st)
+    return int(pending.value)
 
 
 def autotune_batch(y0, t_end, beta, chi1, chi2, model=None, integrator=None, correction=None, fli=None,

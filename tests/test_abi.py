@@ -207,6 +207,41 @@ def test_workspace_sizes_and_shutdown(pn):
     assert train(nbatch=0) == pn.PN_OK and step.value == 0
 
 
+def test_resumable_batch_scan_arguments(pn):
+    """The checkpointed batch scan: workspace size (queue + two record tables
+    of min(n, 2^18) records of 324 bytes), and rejection of bad arguments
+    before anything is launched."""
+    L = pn.lib()
+    base = L.pn_batch_workspace_size(1000)
+    size = L.pn_batch_ckpt_workspace_size(1000)
+    assert size >= base + 256 + 2 * 1000 * 324 and size < base + 256 + 2 * 1000 * 324 + 20 * 256
+    assert L.pn_batch_ckpt_workspace_size(-1) == 0
+    big = L.pn_batch_ckpt_workspace_size(10 ** 7) - L.pn_batch_workspace_size(10 ** 7)
+    assert big < 2 * (1 << 18) * 324 + 21 * 256       # tables capped at 2^18 records
+    m = pn.model_struct()
+    p = pn.Params(None, None, None, 1.0, 1.0, 1.0)
+    one = ctypes.c_void_p(8)
+    so = pn.ScanOut(8, 8, 8, None, None, None, None, None, None, 0, 0)
+
+    def run(resume=0, max_chunks=1, t_end=one, out=so, n=4):
+        return L.pn_batch_scan_resumable(ctypes.byref(m), p, ctypes.byref(pn.integrator_struct()),
+                                         ctypes.byref(pn.correction_struct()), ctypes.byref(pn.fli_struct()),
+                                         ctypes.c_int64(n), one, ctypes.c_int64(4), t_end, ctypes.byref(out), None,
+                                         ctypes.c_int32(resume), ctypes.c_int32(max_chunks), one,
+                                         ctypes.c_size_t(1 << 30), None)
+    assert run(resume=2) == pn.PN_EINVAL
+    assert run(resume=-1) == pn.PN_EINVAL
+    assert run(max_chunks=-1) == pn.PN_EINVAL
+    assert run(t_end=None) == pn.PN_EINVAL
+    assert run(out=pn.ScanOut(8, 8, 8, None, None, None, None, None, 8, 10, 5)) == pn.PN_EINVAL
+    assert run(n=-1) == pn.PN_EINVAL
+    pending = ctypes.c_int64(7)
+    assert L.pn_batch_scan_pending(one, ctypes.c_int64(0), ctypes.byref(pending), None) == pn.PN_OK
+    assert pending.value == 0
+    assert L.pn_batch_scan_pending(one, ctypes.c_int64(4), None, None) == pn.PN_EINVAL
+    assert L.pn_batch_scan_pending(None, ctypes.c_int64(4), ctypes.byref(pending), None) == pn.PN_EINVAL
+
+
 def test_missing_library_fails_loudly(monkeypatch):
     from paper_1802_00147_amd import pn as P
     monkeypatch.setattr(P, "_lib", None)

@@ -145,6 +145,74 @@ def test_autotune_and_cached_tuning(pn):
         assert np.array_equal(a[k].view(np.uint8), c[k].view(np.uint8)), k
 
 
+def _run_resumable(pn, y0, t, b, c1, c2, n, tunings, max_chunks, through_host):
+    """Resumable scan to the end; returns (outputs, pending after each launch)."""
+    ws = pn.batch_ckpt_workspace(n, y0.device)
+    ws.fill_(0x5A)
+    out = pn.scan_outputs(n, n, y0.device, full=True)
+    for v in out.values():
+        v.fill_(-3)
+    pn.batch_scan_resumable(y0, t, b, c1, c2, ws, resume=False, max_chunks=max_chunks, out=out, tuning=tunings[0])
+    pending = [pn.batch_scan_pending(ws, n)]
+    while pending[-1] > 0:
+        assert len(pending) < 400, pending[-8:]
+        if through_host:
+            # Checkpoint to host memory, wipe the device copies, restore.
+            ws_h = ws.cpu()
+            out_h = {k: v.cpu() for k, v in out.items()}
+            ws.fill_(0xC3)
+            for v in out.values():
+                v.fill_(-5)
+            ws.copy_(ws_h)
+            for k, v in out.items():
+                v.copy_(out_h[k])
+        pn.batch_scan_resumable(y0, t, b, c1, c2, ws, resume=True, max_chunks=max_chunks, out=out,
+                                tuning=tunings[len(pending) % len(tunings)])
+        pending.append(pn.batch_scan_pending(ws, n))
+    torch.cuda.synchronize()
+    return host(out), pending
+
+
+def test_resumable_scan_equals_uninterrupted(pn):
+    """Checkpoint and resume: the batch interrupted every 3 chunks, its
+    workspace and outputs copied to host memory and back between launches
+    (the device copies overwritten meanwhile), resumed under changing launch
+    shapes, gives the uninterrupted scan's results bit for bit."""
+    wl = mixed_batch(3001, seed=31, tmin=50.0, tmax=3000.0)
+    y0, t, b, c1, c2 = device_inputs(pn, wl)
+    ref = host(pn.batch_scan(y0, t, b, c1, c2, tuning=dict(block=256, waves_per_simd=2, chunk_steps=64)))
+    tunings = [dict(block=64, waves_per_simd=1, chunk_steps=64), dict(block=256, waves_per_simd=2, chunk_steps=100),
+               dict(block=128, waves_per_simd=1, chunk_steps=37)]
+    got, pending = _run_resumable(pn, y0, t, b, c1, c2, wl.n, tunings, 3, through_host=True)
+    assert len(pending) > 5 and pending[0] > 0
+    assert all(x >= y for x, y in zip(pending, pending[1:]))     # never loses an orbit
+    for k in KEYS:
+        assert np.array_equal(got[k].view(np.uint8), ref[k].view(np.uint8)), k
+    # Run to the end in one launch (max_chunks = 0): same bits again.
+    got0, pending0 = _run_resumable(pn, y0, t, b, c1, c2, wl.n, tunings[1:2], 0, through_host=False)
+    assert pending0 == [0]
+    for k in KEYS:
+        assert np.array_equal(got0[k].view(np.uint8), ref[k].view(np.uint8)), k
+
+
+def test_resumable_scan_carries_orbits_a_smaller_grid_cannot_take(pn):
+    """40,000 orbits all in flight after a two-wave launch (more than the
+    one-wave grid's resident pairs on this chip) resume on one-wave grids:
+    the records no slot takes are carried to the next launch; results equal
+    the uninterrupted scan bit for bit."""
+    wl = mixed_batch(40000, seed=32, tmin=20.0, tmax=400.0)
+    y0, t, b, c1, c2 = device_inputs(pn, wl)
+    ref = host(pn.batch_scan(y0, t, b, c1, c2))
+    slots1 = torch.cuda.get_device_properties(y0.device).multi_processor_count * 4 * 32
+    tunings = [dict(block=256, waves_per_simd=2, chunk_steps=16), dict(block=256, waves_per_simd=1, chunk_steps=16)]
+    got, pending = _run_resumable(pn, y0, t, b, c1, c2, wl.n, tunings, 1, through_host=False)
+    if wl.n > slots1:
+        assert pending[0] > slots1          # the second launch cannot take every saved orbit
+    assert all(x >= y for x, y in zip(pending, pending[1:]))
+    for k in KEYS:
+        assert np.array_equal(got[k].view(np.uint8), ref[k].view(np.uint8)), k
+
+
 def test_batch_errors_and_empty(pn):
     wl = mixed_batch(10, seed=27)
     y0, t, b, c1, c2 = device_inputs(pn, wl)
