@@ -58,9 +58,11 @@ _lib = None
 
 
 def lib():
+    """The oracle library; PN_ORACLE_LIB names another build of the same
+    source (the sanitizer check loads an instrumented one)."""
     global _lib
     if _lib is None:
-        _lib = ctypes.CDLL(ensure_built())
+        _lib = ctypes.CDLL(os.environ.get("PN_ORACLE_LIB") or ensure_built())
     return _lib
 
 

@@ -14,15 +14,22 @@ CMD = ["g++", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c++17", "-Wall
        "-shared", "-fPIC", "-pthread", SRC, "-o", LIB]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile pn_oracle.cpp into libpn_oracle.so next to it; return the path."""
-    tmp = LIB + ".tmp"
-    cmd = CMD[:-1] + [tmp]
+# Host sanitizers for a checking build (plain g++, CPU code only).
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
+
+
+def build(verbose: bool = False, out: str = None, sanitize: bool = False) -> str:
+    """Compile pn_oracle.cpp into libpn_oracle.so next to it (or into `out`);
+    return the path.  sanitize=True adds AddressSanitizer and
+    UndefinedBehaviorSanitizer instrumentation."""
+    dst = out or LIB
+    tmp = dst + ".tmp"
+    cmd = CMD[:-2] + (SANITIZE if sanitize else []) + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, dst)
+    return dst
 
 
 def ensure_built() -> str:

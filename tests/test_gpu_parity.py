@@ -243,6 +243,22 @@ def test_scan_status_edge_cases(pn):
     assert got0["steps"][0] == 0 and exp0["steps"][0] == 0
 
 
+def test_scan_newton_nonconvergence_flag(pn):
+    """Forced non-convergence (one Newton iteration, tolerance 1e-300): the
+    GPU sets the NEWTON_NOCONV flag exactly where the oracle does, for the
+    six-integral and the dual correction, and keeps the orbits running."""
+    from paper_1802_00147_amd import workloads as W
+    wl = W.batch(n=24, seed=41, tmin=100.0, tmax=300.0)
+    y0 = O.init_state(wl.r0, wl.p0, wl.th1, wl.ph1, wl.th2, wl.ph2, wl.beta, wl.chi1, wl.chi2)
+    for mode in (2, 3):
+        corr = dict(mode=mode, max_iter=1, tol=1e-300)
+        exp, got = _scan_both(pn, y0, wl.t_end, wl.beta, wl.chi1, wl.chi2, wl.n, correction=corr)
+        assert np.array_equal(got["status"], exp["status"])
+        assert np.all((exp["status"] & 0x100) != 0)
+        assert np.array_equal(got["newton_max"], exp["newton_max"])
+        assert np.array_equal(got["steps"], exp["steps"])
+
+
 def test_scan_grid64_full_size_sampled(pn):
     """The 64 x 64 (r0, theta) grid at t = 1e5, in the benchmark's launch
     configuration; 24 seeded grid points recomputed by the oracle."""

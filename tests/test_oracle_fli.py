@@ -94,6 +94,21 @@ def test_status_codes(oracle):
     assert r["steps"][0] == 0
 
 
+def test_newton_nonconvergence_flag(oracle):
+    """One Newton iteration with a tolerance no update can meet: every orbit
+    carries the non-fatal NEWTON_NOCONV flag on top of its own status, and
+    its FLI and label are still produced; with the default settings the
+    flag stays clear."""
+    O = oracle
+    y = np.vstack([kepler_state(), kepler_state(12.0, 0.3)])
+    r = O.fli_scan(y, 200, 1.0, 0.5, 0.5, correction=dict(max_iter=1, tol=1e-300))
+    assert np.all(r["status"] == O.STATUS_NEWTON_NOCONV)
+    assert np.all(np.isfinite(r["fli"])) and np.all(r["label"] >= 0)
+    assert np.all(r["newton_max"] == 2)      # one iteration in each of the two sweeps of a correction
+    ok = O.fli_scan(y, 200, 1.0, 0.5, 0.5)
+    assert np.all(ok["status"] == 0)
+
+
 def test_steps_completed(oracle):
     """The steps output counts ceil(t_end / h) steps for an orbit that
     stays, none for a state removed at t = 0, and for a removed orbit the
