@@ -7,7 +7,8 @@
  * Source: Ran, Liu & Zhong, "GPU accelerated manifold correction method for
  * spinning compact binaries", arXiv:1802.00147.
  *   Sec. 2, eq. (1)       Hamiltonian H = H_N + H_1PN + H_2PN + H_SO + H_SS
- *                         (the 2.5PN radiation and 3PN terms are not modelled)
+ *                         (3PN is not modelled; the 2.5PN reaction of eq. (6)
+ *                         is optional, see pn_model)
  *   Sec. 2, eqs. (2)-(5)  spin-spin (S1S2) and quadrupole-monopole terms
  *   Sec. 2, eqs. (6)-(9)  Hamilton's equations and spin precession
  *   Sec. 2, eqs. (10)-(13) manifold correction (spin lengths; dual scaling)
@@ -92,13 +93,23 @@ typedef enum {
 
 typedef enum { PN_THR_LITERAL = 0, PN_THR_LOG_T = 1 } pn_thr_scaling;
 
-/* Terms of eq. (1).  pn_order: 0 Newtonian, 1 +1PN, 2 +1PN+2PN. */
+/* Terms of eq. (1).  pn_order: 0 Newtonian, 1 +1PN, 2 +1PN+2PN.
+ * rad_reaction: 1 adds the 2.5PN radiation-reaction acceleration to dp/dt
+ * (eq. 6; Sec. 3B, orbit 3).  The paper does not print it; this library uses
+ * the leading-order reaction of a point-mass binary in the Iyer-Will gauge
+ * family at (alpha, beta) = (4, 5), a = (8/5) eta / r^3 [(18 v^2 + 2/(3 r) -
+ * 25 rdot^2) rdot n - (6 v^2 - 2/r - 15 rdot^2) v] with v = dH/dp (M = 1),
+ * which radiates the quadrupole fluxes.  The system is then dissipative:
+ * pn_rhs, pn_step and pn_trajectory accept it (with advancing references,
+ * see pn_step); the FLI scans, batches and the surrogate integrate the
+ * conservative system and return PN_EINVAL for it. */
 typedef struct {
     int32_t pn_order;
     int32_t spin_orbit;  /* 1.5PN spin-orbit */
     int32_t spin_spin;   /* eq. (3) */
     int32_t quad_mono;   /* eqs. (4)-(5) */
     int32_t spin_units;  /* pn_spin_units */
+    int32_t rad_reaction; /* 0 or 1 */
 } pn_model;
 
 /* Mass ratio and dimensionless spins.  Either per-orbit DEVICE arrays of
@@ -213,10 +224,16 @@ pn_status pn_manifold_correct(const pn_model* model, pn_params params,
 /* nsteps integration steps of each state, each followed by the correction
  * (corr NULL or mode PN_CORR_NONE: no correction).  y: [12][ld] in/out.
  * ref: [4][ld] reference integrals, or NULL to capture them from y after its
- * spin lengths are set (only when a correction is requested). */
+ * spin lengths are set (only when a correction is requested).
+ * With model->rad_reaction = 1 the references follow the dissipation
+ * (integral-invariant relation, Sec. 3B): E and J advance with the state
+ * through dE/dt = v.a and dJ/dt = r x a in the same Runge-Kutta step, the
+ * correction targets the advanced values, and ref (when given) is in/out:
+ * it holds the references at the end of the call.  Otherwise ref is only
+ * read. */
 pn_status pn_step(const pn_model* model, pn_params params, const pn_integrator* integ,
                   const pn_correction* corr, int64_t n, double* y, int64_t ld,
-                  const double* ref, int64_t nsteps, hipStream_t stream);
+                  double* ref, int64_t nsteps, hipStream_t stream);
 
 /* Fused FLI scan: for every orbit, integrate the orbit and its shadow from y0
  * to t_end with a correction after every step, and report the FLI, the
@@ -239,7 +256,7 @@ pn_status pn_fli_scan(const pn_model* model, pn_params params, const pn_integrat
  * y, ref, nsteps and errors as in pn_step. */
 pn_status pn_trajectory(const pn_model* model, pn_params params, const pn_integrator* integ,
                         const pn_correction* corr, int64_t n, double* y, int64_t ld,
-                        const double* ref, int64_t nsteps, int64_t every, double* traj,
+                        double* ref, int64_t nsteps, int64_t every, double* traj,
                         hipStream_t stream);
 
 /* Gravitational-wave polarisations of eq. (14) from the leading

@@ -20,7 +20,7 @@ import numpy as np
 
 from .build import LIB, ensure_built
 
-MODEL = dict(pn_order=2, spin_orbit=1, spin_spin=1, quad_mono=1, spin_units=0)
+MODEL = dict(pn_order=2, spin_orbit=1, spin_spin=1, quad_mono=1, spin_units=0, rad_reaction=0)
 INTEGRATOR = dict(method=0, h=1.0)
 CORRECTION = dict(mode=2, tol=1e-10, max_iter=20, sweeps=2, w1=1.0, w2=1.0)
 FLI = dict(d0=1e-8, d_renorm=0.1, shadow_axis=0, thr_at_1e5=5.8, thr_scaling=1,
@@ -35,7 +35,7 @@ STATUS_NEWTON_NOCONV = 0x100
 class _Model(ctypes.Structure):
     _fields_ = [("pn_order", ctypes.c_int32), ("spin_orbit", ctypes.c_int32),
                 ("spin_spin", ctypes.c_int32), ("quad_mono", ctypes.c_int32),
-                ("spin_units", ctypes.c_int32)]
+                ("spin_units", ctypes.c_int32), ("rad_reaction", ctypes.c_int32)]
 
 
 class _Integrator(ctypes.Structure):
@@ -195,18 +195,20 @@ def manifold_correct(y, ref, beta, chi1, chi2, model=None, correction=None):
     return y, it
 
 
-def step(y, beta, chi1, chi2, nsteps, model=None, integrator=None, correction=None, ref=None):
-    """nsteps RK (+ correction unless correction is None) steps of copies of the states."""
+def step(y, beta, chi1, chi2, nsteps, model=None, integrator=None, correction=None, ref=None, return_ref=False):
+    """nsteps RK (+ correction unless correction is None) steps of copies of the states.
+    With radiation reaction the references (n, 4) advance with the states;
+    return_ref=True also returns them (a copy of ref when it was given)."""
     y = _states(y).copy()
     b, c1, c2, s = _params(len(y), beta, chi1, chi2)
     cc = ctypes.byref(_fill(_Correction, CORRECTION, correction)) if correction is not None else None
     r = None
     if ref is not None:
-        r = np.ascontiguousarray(np.asarray(ref, dtype=np.float64).reshape(len(y), 4))
+        r = np.array(np.asarray(ref, dtype=np.float64).reshape(len(y), 4), copy=True)
     lib().or_step(ctypes.byref(_fill(_Model, MODEL, model)), _p(b), _p(c1), _p(c2), ctypes.c_int64(s),
                   ctypes.byref(_fill(_Integrator, INTEGRATOR, integrator)), cc,
                   ctypes.c_int64(len(y)), _p(y), _p(r), ctypes.c_int64(nsteps))
-    return y
+    return (y, r) if return_ref else y
 
 
 def rk_linear_step(method, z):

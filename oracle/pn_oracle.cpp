@@ -16,9 +16,12 @@
 //
 // Sources (arXiv 1802.00147, "GPU accelerated manifold correction method for
 // spinning compact binaries"):
-//   Sec. 2, eq. (1)      H = H_N + H_PN + H_SO + H_SS (2.5PN and 3PN dropped)
+//   Sec. 2, eq. (1)      H = H_N + H_PN + H_SO + H_SS (3PN dropped; the 2.5PN
+//                        reaction of eq. (6) is an optional force on dp/dt)
 //   Sec. 2, eqs. (2)-(5) spin-spin and quadrupole-monopole terms
-//   Sec. 2, eq. (6)      dr/dt = dH/dp, dp/dt = -dH/dr (conservative part)
+//   Sec. 2, eq. (6)      dr/dt = dH/dp, dp/dt = -dH/dr (+ a_2.5PN, optional)
+//   Sec. 3B (orbit 3)    dissipative orbit corrected against references that
+//                        follow the integral-invariant relation
 //   Sec. 2, eqs. (7)-(9) dS_i/dt = Omega_i x S_i
 //   Sec. 2, eq. (10)     spin-length correction
 //   Sec. 2, eqs. (11)-(13) dual (momentum-position) scaling, Newton solve
@@ -101,6 +104,7 @@ typedef struct {
     int32_t spin_spin;   // S1-S2 coupling, eq. (3), on/off
     int32_t quad_mono;   // quadrupole-monopole S1S1, S2S2, eqs. (4)-(5), on/off
     int32_t spin_units;  // 0: physical spin flow (spins in mu*M), 1: eqs. (7)-(9) literal (spins in M^2)
+    int32_t rad_reaction; // 2.5PN radiation-reaction acceleration on dp/dt (eq. 6), on/off
 } or_model;
 
 typedef struct {
@@ -345,16 +349,57 @@ static Grad<T> gradient(const or_model& m, const Coef& c, const T* y, bool only_
     return g;
 }
 
-// Hamilton's equations (eq. 6 without a_2.5PN) and spin precession (eq. 7):
-//   dr/dt = dH/dp,  dp/dt = -dH/dr,  dS_i/dt = (dH/dS_i) x S_i.
+// The 2.5PN radiation-reaction acceleration of eq. (6).  The paper takes it
+// from Levin et al. (2011) without printing it; here it is the leading-order
+// reaction acceleration of a point-mass binary in the two-parameter gauge
+// family of Iyer and Will (1993),
+//   a = (8/5) eta / r^3 [ A rdot n - B v ],
+//   A = 3(1 + be) v^2 + (23 + 6 al - 9 be) / (3 r) - 5 be rdot^2,
+//   B = (2 + al) v^2 + (2 - al) / r - 3 (1 + al) rdot^2,
+// at al = 4, be = 5 (the harmonic-coordinate form of Damour and Deruelle),
+// with v = dH/dp the velocity of the Hamiltonian flow and rdot = n.v (M = 1).
+// Every member of the family radiates the quadrupole energy and angular
+// momentum fluxes on average over an orbit (-(32/5) eta^2 / r^5 on a circle).
+template <class T>
+static V3<T> rr_accel(const Coef& c, const T* y, const V3<T>& v) {
+    const V3<T> r = get3(y, 0);
+    const T rr = sqrt(dot(r, r));
+    const V3<T> n = scl(T(1.0) / rr, r);
+    const T rdot = dot(n, v), v2 = dot(v, v);
+    const double al = 4.0, be = 5.0;
+    const T A = 3.0 * (1.0 + be) * v2 + ((23.0 + 6.0 * al - 9.0 * be) / 3.0) / rr - 5.0 * be * rdot * rdot;
+    const T B = (2.0 + al) * v2 + (2.0 - al) / rr - 3.0 * (1.0 + al) * rdot * rdot;
+    const T pre = (8.0 / 5.0) * c.eta / (rr * rr * rr);
+    return sub(scl(pre * A * rdot, n), scl(pre * B, v));
+}
+
+// Hamilton's equations (eq. 6) and spin precession (eq. 7):
+//   dr/dt = dH/dp,  dp/dt = -dH/dr (+ a_2.5PN),  dS_i/dt = (dH/dS_i) x S_i.
 template <class T>
 static void rhs(const or_model& m, const Coef& c, const T* y, T* dydt) {
     const Grad<T> g = gradient(m, c, y);
     const V3<T> S1 = get3(y, 6), S2 = get3(y, 9);
     put3(dydt, 0, g.dp);
-    put3(dydt, 3, scl(-1.0, g.dr));
+    if (m.rad_reaction)
+        put3(dydt, 3, add(scl(-1.0, g.dr), rr_accel(c, y, g.dp)));
+    else
+        put3(dydt, 3, scl(-1.0, g.dr));
     put3(dydt, 6, cross(g.dS1, S1));
     put3(dydt, 9, cross(g.dS2, S2));
+}
+
+// The dissipative system with its reference integrals (Sec. 3B, integral
+// invariant relation): z = (y, E, J), dz/dt = (f(y), v.a, r x a).  The
+// Hamiltonian and total angular momentum change only through the reaction
+// acceleration (the spin flow conserves both), so E(t) and J(t) are the
+// values the corrected state must carry.
+static void rhs_with_refs(const or_model& m, const Coef& c, const double* z, double* dz) {
+    rhs<double>(m, c, z, dz);
+    const V3<double> v = get3(dz, 0);
+    const V3<double> a = rr_accel(c, z, v);
+    dz[12] = dot(v, a);
+    const V3<double> dJ = cross(get3(z, 0), a);
+    dz[13] = dJ.x; dz[14] = dJ.y; dz[15] = dJ.z;
 }
 
 // Total angular momentum J = r x p + S1 + S2.
@@ -614,6 +659,21 @@ static int step_once(const or_model& m, const Coef& c, const or_integrator& in,
     return correct(m, c, cc, y, ref, noconv);
 }
 
+// One step of the dissipative system: the state and its references advance
+// together with the same Runge-Kutta stages, then the state is corrected
+// against the advanced references.
+static int step_once_rr(const or_model& m, const Coef& c, const or_integrator& in,
+                        const or_correction& cc, double* y, double* ref, bool* noconv) {
+    double z[16];
+    for (int i = 0; i < 12; ++i) z[i] = y[i];
+    for (int i = 0; i < 4; ++i) z[12 + i] = ref[i];
+    auto f = [&](const double* zz, double* dd) { rhs_with_refs(m, c, zz, dd); };
+    rk_step<16>(in.method, in.h, f, z);
+    for (int i = 0; i < 12; ++i) y[i] = z[i];
+    for (int i = 0; i < 4; ++i) ref[i] = z[12 + i];
+    return correct(m, c, cc, y, ref, noconv);
+}
+
 // Orbit validity (Sec. 3C removes unbounded or merged orbits).
 template <class T>
 static int validity(const or_fli_cfg& fc, const T* y) {
@@ -843,10 +903,11 @@ void or_manifold_correct(const or_model* m, const double* beta, const double* ch
 
 // nsteps steps (RK + optional correction) of each state.  When ref is NULL
 // the references are captured from each state after its spin lengths are set
-// (only when a correction is requested).
+// (only when a correction is requested).  With radiation reaction the
+// references advance with the state and are written back to ref (when given).
 void or_step(const or_model* m, const double* beta, const double* chi1, const double* chi2,
              int64_t pstride, const or_integrator* in, const or_correction* cc,
-             int64_t n, double* y, const double* ref, int64_t nsteps) {
+             int64_t n, double* y, double* ref, int64_t nsteps) {
     or_correction none;
     std::memset(&none, 0, sizeof(none));
     const or_correction& use = cc ? *cc : none;
@@ -862,8 +923,13 @@ void or_step(const or_model* m, const double* beta, const double* chi1, const do
         }
         for (int64_t k = 0; k < nsteps; ++k) {
             bool nc = false;
-            step_once<double>(*m, c, *in, use, yi, r, &nc);
+            if (m->rad_reaction)
+                step_once_rr(*m, c, *in, use, yi, r, &nc);
+            else
+                step_once<double>(*m, c, *in, use, yi, r, &nc);
         }
+        if (ref && m->rad_reaction)
+            for (int k = 0; k < 4; ++k) ref[4 * i + k] = r[k];
     }
 }
 
@@ -892,7 +958,10 @@ void or_fli_scan(const or_model* m, const double* beta, const double* chi1, cons
         for (;;) {
             const int64_t i = next.fetch_add(1);
             if (i >= n) break;
-            if (!params_valid(pick(beta, pstride, i), pick(chi1, pstride, i), pick(chi2, pstride, i))) {
+            // Scans follow the conservative system (the paper's scans of
+            // Sec. 3C); a model with radiation reaction is refused per orbit.
+            if (m->rad_reaction ||
+                !params_valid(pick(beta, pstride, i), pick(chi1, pstride, i), pick(chi2, pstride, i))) {
                 fli[i] = NAN;
                 label[i] = -1;
                 status[i] = ST_BADPARAM;

@@ -488,6 +488,81 @@ __device__ __forceinline__ void pn_rk_step(const PnCoef& k, double* y, double h)
     for (int c = 0; c < 12; ++c) y[c] = fma(h * b6, kk[c], acc[c]);
 }
 
+// 2.5PN radiation-reaction acceleration of eq. (6) (M = 1): the
+// leading-order reaction of a point-mass binary in the Iyer-Will gauge family
+// at (alpha, beta) = (4, 5), the harmonic-coordinate form,
+//   a = (8/5) eta / r^3 [(18 v^2 + 2 / (3 r) - 25 rdot^2) rdot n
+//                        - (6 v^2 - 2 / r - 15 rdot^2) v],
+// with v = dH/dp and rdot = n.v.
+__device__ __forceinline__ void pn_rr_accel(double eta, const double* y, const double* v, double* a) {
+    const double r2 = dot3(y[0], y[1], y[2], y[0], y[1], y[2]);
+    const double u = pn_rsqrt(r2);
+    const double nx = y[0] * u, ny = y[1] * u, nz = y[2] * u;
+    const double rdot = dot3(nx, ny, nz, v[0], v[1], v[2]);
+    const double v2 = dot3(v[0], v[1], v[2], v[0], v[1], v[2]);
+    const double rd2 = rdot * rdot;
+    const double A = 18.0 * v2 + (2.0 / 3.0) * u - 25.0 * rd2;
+    const double B = 6.0 * v2 - 2.0 * u - 15.0 * rd2;
+    const double pre = 1.6 * eta * u * u * u;
+    const double cn = pre * A * rdot, cv = -pre * B;
+    a[0] = cn * nx + cv * v[0];
+    a[1] = cn * ny + cv * v[1];
+    a[2] = cn * nz + cv * v[2];
+}
+
+// The dissipative system with its reference integrals: z = (y, E, J) and
+// dz/dt = (f(y) with a_2.5PN on dp/dt, v.a, r x a).  The spin flow conserves
+// H and J, so the references change only through the reaction.
+__device__ __forceinline__ void pn_rhs_rr(const PnCoef& k, double eta, const double* z, double* f) {
+    pn_rhs_eval(k, z, f);
+    double a[3];
+    pn_rr_accel(eta, z, f, a);
+    f[3] += a[0]; f[4] += a[1]; f[5] += a[2];
+    f[12] = dot3(f[0], f[1], f[2], a[0], a[1], a[2]);
+    f[13] = z[1] * a[2] - z[2] * a[1];
+    f[14] = z[2] * a[0] - z[0] * a[2];
+    f[15] = z[0] * a[1] - z[1] * a[0];
+}
+
+// One fixed RK4 or Dormand-Prince fifth-order step of the 16-component
+// dissipative system (state and references together).
+template <int METHOD>
+__device__ void pn_rk_step_rr(const PnCoef& k, double eta, double* z, double h) {
+    constexpr int D = 16;
+    double k1[D], k2[D], k3[D], k4[D], t[D];
+    if (METHOD == PN_RK4) {
+        pn_rhs_rr(k, eta, z, k1);
+        for (int c = 0; c < D; ++c) t[c] = fma(0.5 * h, k1[c], z[c]);
+        pn_rhs_rr(k, eta, t, k2);
+        for (int c = 0; c < D; ++c) t[c] = fma(0.5 * h, k2[c], z[c]);
+        pn_rhs_rr(k, eta, t, k3);
+        for (int c = 0; c < D; ++c) t[c] = fma(h, k3[c], z[c]);
+        pn_rhs_rr(k, eta, t, k4);
+        for (int c = 0; c < D; ++c) z[c] = fma(h / 6.0, k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c], z[c]);
+        return;
+    }
+    double k5[D], k6[D];
+    pn_rhs_rr(k, eta, z, k1);
+    for (int c = 0; c < D; ++c) t[c] = z[c] + h * (1.0 / 5.0) * k1[c];
+    pn_rhs_rr(k, eta, t, k2);
+    for (int c = 0; c < D; ++c) t[c] = z[c] + h * ((3.0 / 40.0) * k1[c] + (9.0 / 40.0) * k2[c]);
+    pn_rhs_rr(k, eta, t, k3);
+    for (int c = 0; c < D; ++c)
+        t[c] = z[c] + h * ((44.0 / 45.0) * k1[c] + (-56.0 / 15.0) * k2[c] + (32.0 / 9.0) * k3[c]);
+    pn_rhs_rr(k, eta, t, k4);
+    for (int c = 0; c < D; ++c)
+        t[c] = z[c] + h * ((19372.0 / 6561.0) * k1[c] + (-25360.0 / 2187.0) * k2[c] + (64448.0 / 6561.0) * k3[c] +
+                           (-212.0 / 729.0) * k4[c]);
+    pn_rhs_rr(k, eta, t, k5);
+    for (int c = 0; c < D; ++c)
+        t[c] = z[c] + h * ((9017.0 / 3168.0) * k1[c] + (-355.0 / 33.0) * k2[c] + (46732.0 / 5247.0) * k3[c] +
+                           (49.0 / 176.0) * k4[c] + (-5103.0 / 18656.0) * k5[c]);
+    pn_rhs_rr(k, eta, t, k6);
+    for (int c = 0; c < D; ++c)
+        z[c] = z[c] + h * ((35.0 / 384.0) * k1[c] + (500.0 / 1113.0) * k3[c] + (125.0 / 192.0) * k4[c] +
+                           (-2187.0 / 6784.0) * k5[c] + (11.0 / 84.0) * k6[c]);
+}
+
 // Orbit validity in the order: non-finite, merged, escaped.  The sum of
 // y[c] * 0 is NaN exactly when some component is NaN or infinite.
 __device__ __forceinline__ int pn_validity(const double* y, double rmerge2, double resc2) {

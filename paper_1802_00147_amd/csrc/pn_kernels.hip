@@ -90,8 +90,15 @@ __global__ __launch_bounds__(kBlock) void k_init_state(ParamArgs pa, int64_t n, 
     store_state(y, ld, j, s);
 }
 
+// eta = m1 m2 (M = 1) of orbit i: from its mass ratio, or the shared value.
+__device__ __forceinline__ double orbit_eta(const ParamArgs& pa, int64_t i, double eta0) {
+    if (pa.beta == nullptr) return eta0;
+    const double b = pa.beta[i];
+    return b / ((1.0 + b) * (1.0 + b));
+}
+
 __global__ __launch_bounds__(kBlock) void k_rhs(ParamArgs pa, int64_t n, const double* y, int64_t ld,
-                                               double* f) {
+                                               double* f, double eta0) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     PnCoef k;
@@ -99,6 +106,11 @@ __global__ __launch_bounds__(kBlock) void k_rhs(ParamArgs pa, int64_t n, const d
     double s[12], d[12];
     load_state(y, ld, i, s);
     pn_rhs_eval(k, s, d);
+    if (pa.model.rad_reaction) {
+        double a[3];
+        pn_rr_accel(orbit_eta(pa, i, eta0), s, d, a);
+        d[3] += a[0]; d[4] += a[1]; d[5] += a[2];
+    }
     store_state(f, ld, i, d);
 }
 
@@ -142,15 +154,21 @@ __global__ __launch_bounds__(kBlock) void k_correct(ParamArgs pa, CorrArgs ca, i
 
 // nsteps corrected steps per orbit; with traj set, the state after every
 // `every` steps also goes to row (t / every - 1) of traj ([rows][12][ld]).
-template <int METHOD, int MODE>
+// RR: the dissipative system (2.5PN reaction); the references advance with
+// the state (z = (y, E, J), one RK step for all 16 components) and are
+// written back to ref when it is given.
+template <int METHOD, int MODE, bool RR>
 __global__ __launch_bounds__(kBlock) void k_step(ParamArgs pa, CorrArgs ca, double h, int64_t n,
-                                                double* y, int64_t ld, const double* ref,
-                                                int64_t nsteps, double* traj, int64_t every) {
+                                                double* y, int64_t ld, double* ref,
+                                                int64_t nsteps, double* traj, int64_t every, double eta0) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     PnCoef k;
     load_coef(pa, i, k);
-    double s[12], r[4];
+    double z[RR ? 16 : 12];
+    double* const s = z;
+    double rloc[4];
+    double* const r = RR ? z + 12 : rloc;
     load_state(y, ld, i, s);
     if (ref) {
 #pragma unroll
@@ -159,10 +177,14 @@ __global__ __launch_bounds__(kBlock) void k_step(ParamArgs pa, CorrArgs ca, doub
         if (MODE != PN_CORR_NONE) pn_correct_spins(k, s);
         capture_ref(k, s, r);
     }
+    const double eta = RR ? orbit_eta(pa, i, eta0) : 0.0;
     int64_t left = every;
     double* row = traj;
     for (int64_t t = 0; t < nsteps; ++t) {
-        pn_rk_step<METHOD>(k, s, h);
+        if constexpr (RR)
+            pn_rk_step_rr<METHOD>(k, eta, z, h);
+        else
+            pn_rk_step<METHOD>(k, s, h);
         bool nc;
         pn_correct<MODE>(k, s, r, ca.tol, ca.max_iter, ca.sweeps, nc);
         if (row != nullptr && --left == 0) {
@@ -172,6 +194,10 @@ __global__ __launch_bounds__(kBlock) void k_step(ParamArgs pa, CorrArgs ca, doub
         }
     }
     store_state(y, ld, i, s);
+    if (RR && ref) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ref[c * ld + i] = r[c];
+    }
 }
 
 // Gravitational-wave polarisations (Sec. 4, eq. 14) of the mass-quadrupole
@@ -658,6 +684,7 @@ pn_status check_model(const pn_model* m) {
     if (m->pn_order < 0 || m->pn_order > 2) return PN_EINVAL;
     if ((m->spin_orbit | m->spin_spin | m->quad_mono) & ~1) return PN_EINVAL;
     if (m->spin_units != PN_SPIN_PHYS && m->spin_units != PN_SPIN_PAPER_EQ8) return PN_EINVAL;
+    if (m->rad_reaction & ~1) return PN_EINVAL;
     return PN_OK;
 }
 
@@ -718,21 +745,33 @@ pn_status launched(const char* what) {
 
 template <int METHOD, int MODE>
 void launch_step(const ParamArgs& pa, const CorrArgs& ca, double h, int64_t n, double* y, int64_t ld,
-                 const double* ref, int64_t nsteps, double* traj, int64_t every, hipStream_t s) {
-    hipLaunchKernelGGL((k_step<METHOD, MODE>), dim3(grid_for(n)), dim3(kBlock), 0, s, pa, ca, h, n, y,
-                       ld, ref, nsteps, traj, every);
+                 double* ref, int64_t nsteps, double* traj, int64_t every, double eta0, hipStream_t s) {
+    if (pa.model.rad_reaction)
+        hipLaunchKernelGGL((k_step<METHOD, MODE, true>), dim3(grid_for(n)), dim3(kBlock), 0, s, pa, ca, h, n, y,
+                           ld, ref, nsteps, traj, every, eta0);
+    else
+        hipLaunchKernelGGL((k_step<METHOD, MODE, false>), dim3(grid_for(n)), dim3(kBlock), 0, s, pa, ca, h, n, y,
+                           ld, ref, nsteps, traj, every, eta0);
 }
 
 template <int METHOD>
 void launch_step_m(int mode, const ParamArgs& pa, const CorrArgs& ca, double h, int64_t n, double* y,
-                   int64_t ld, const double* ref, int64_t nsteps, double* traj, int64_t every, hipStream_t s) {
+                   int64_t ld, double* ref, int64_t nsteps, double* traj, int64_t every, double eta0,
+                   hipStream_t s) {
     switch (mode) {
-        case PN_CORR_NONE: launch_step<METHOD, PN_CORR_NONE>(pa, ca, h, n, y, ld, ref, nsteps, traj, every, s); break;
-        case PN_CORR_SPIN: launch_step<METHOD, PN_CORR_SPIN>(pa, ca, h, n, y, ld, ref, nsteps, traj, every, s); break;
-        case PN_CORR_SIX: launch_step<METHOD, PN_CORR_SIX>(pa, ca, h, n, y, ld, ref, nsteps, traj, every, s); break;
-        default: launch_step<METHOD, PN_CORR_DUAL>(pa, ca, h, n, y, ld, ref, nsteps, traj, every, s); break;
+        case PN_CORR_NONE:
+            launch_step<METHOD, PN_CORR_NONE>(pa, ca, h, n, y, ld, ref, nsteps, traj, every, eta0, s); break;
+        case PN_CORR_SPIN:
+            launch_step<METHOD, PN_CORR_SPIN>(pa, ca, h, n, y, ld, ref, nsteps, traj, every, eta0, s); break;
+        case PN_CORR_SIX:
+            launch_step<METHOD, PN_CORR_SIX>(pa, ca, h, n, y, ld, ref, nsteps, traj, every, eta0, s); break;
+        default:
+            launch_step<METHOD, PN_CORR_DUAL>(pa, ca, h, n, y, ld, ref, nsteps, traj, every, eta0, s); break;
     }
 }
+
+// eta of a shared parameter set (unused with per-orbit arrays).
+double shared_eta(const pn_params& p) { return p.beta ? 0.0 : p.beta0 / ((1.0 + p.beta0) * (1.0 + p.beta0)); }
 
 template <int METHOD, int MODE>
 void launch_scan(const ParamArgs& pa, const FliArgs& fa, hipStream_t s) {
@@ -888,6 +927,7 @@ pn_status prepare_scan(const pn_model* model, const pn_params& params, const pn_
                        const double* t_end, double t_end_all, const pn_scan_out* out, ParamArgs& pa,
                        FliArgs& fa) {
     if (check_model(model) != PN_OK || check_integ(integ) != PN_OK) return PN_EINVAL;
+    if (model->rad_reaction) return PN_EINVAL;      // scans integrate the conservative system
     if (corr == nullptr || check_corr(corr) != PN_OK) return PN_EINVAL;
     if (fli == nullptr || out == nullptr) return PN_EINVAL;
     if (!(n >= 0 && ld >= n)) return PN_EINVAL;
@@ -956,6 +996,7 @@ void pn_default_model(pn_model* m) {
     m->spin_spin = 1;
     m->quad_mono = 1;
     m->spin_units = PN_SPIN_PHYS;
+    m->rad_reaction = 0;
 }
 
 void pn_default_integrator(pn_integrator* in) {
@@ -1046,7 +1087,7 @@ pn_status pn_rhs(const pn_model* model, pn_params params, int64_t n, const doubl
     PN_REQUIRE(make_params(model, params, pa) == PN_OK);
     if (n == 0) return PN_OK;
     PN_REQUIRE(y && dydt);
-    hipLaunchKernelGGL(k_rhs, dim3(grid_for(n)), dim3(kBlock), 0, stream, pa, n, y, ld, dydt);
+    hipLaunchKernelGGL(k_rhs, dim3(grid_for(n)), dim3(kBlock), 0, stream, pa, n, y, ld, dydt, shared_eta(params));
     return launched("pn_rhs");
 }
 
@@ -1084,7 +1125,7 @@ pn_status pn_manifold_correct(const pn_model* model, pn_params params, const pn_
 }
 
 static pn_status step_impl(const char* what, const pn_model* model, pn_params params, const pn_integrator* integ,
-                           const pn_correction* corr, int64_t n, double* y, int64_t ld, const double* ref,
+                           const pn_correction* corr, int64_t n, double* y, int64_t ld, double* ref,
                            int64_t nsteps, double* traj, int64_t every, hipStream_t stream) {
     PN_REQUIRE(check_model(model) == PN_OK);
     PN_REQUIRE(check_integ(integ) == PN_OK);
@@ -1096,21 +1137,22 @@ static pn_status step_impl(const char* what, const pn_model* model, pn_params pa
     PN_REQUIRE(y);
     const int mode = corr ? corr->mode : PN_CORR_NONE;
     const CorrArgs ca = corr_args(corr);
+    const double eta0 = shared_eta(params);
     if (integ->method == PN_RK4)
-        launch_step_m<PN_RK4>(mode, pa, ca, integ->h, n, y, ld, ref, nsteps, traj, every, stream);
+        launch_step_m<PN_RK4>(mode, pa, ca, integ->h, n, y, ld, ref, nsteps, traj, every, eta0, stream);
     else
-        launch_step_m<PN_RK5>(mode, pa, ca, integ->h, n, y, ld, ref, nsteps, traj, every, stream);
+        launch_step_m<PN_RK5>(mode, pa, ca, integ->h, n, y, ld, ref, nsteps, traj, every, eta0, stream);
     return launched(what);
 }
 
 pn_status pn_step(const pn_model* model, pn_params params, const pn_integrator* integ,
-                  const pn_correction* corr, int64_t n, double* y, int64_t ld, const double* ref,
+                  const pn_correction* corr, int64_t n, double* y, int64_t ld, double* ref,
                   int64_t nsteps, hipStream_t stream) {
     return step_impl("pn_step", model, params, integ, corr, n, y, ld, ref, nsteps, nullptr, 1, stream);
 }
 
 pn_status pn_trajectory(const pn_model* model, pn_params params, const pn_integrator* integ,
-                        const pn_correction* corr, int64_t n, double* y, int64_t ld, const double* ref,
+                        const pn_correction* corr, int64_t n, double* y, int64_t ld, double* ref,
                         int64_t nsteps, int64_t every, double* traj, hipStream_t stream) {
     PN_REQUIRE(every >= 1);
     PN_REQUIRE(traj != nullptr || nsteps / every == 0 || n == 0);

@@ -34,7 +34,7 @@ class PnError(RuntimeError):
 class Model(ctypes.Structure):
     _fields_ = [("pn_order", ctypes.c_int32), ("spin_orbit", ctypes.c_int32),
                 ("spin_spin", ctypes.c_int32), ("quad_mono", ctypes.c_int32),
-                ("spin_units", ctypes.c_int32)]
+                ("spin_units", ctypes.c_int32), ("rad_reaction", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):
@@ -249,7 +249,8 @@ def manifold_correct(y, ref, beta, chi1, chi2, model=None, correction=None, n=No
 
 
 def step(y, beta, chi1, chi2, nsteps, model=None, integrator=None, correction=None, ref=None, n=None):
-    """nsteps steps of y (12, ld) in place; correction None means uncorrected."""
+    """nsteps steps of y (12, ld) in place; correction None means uncorrected.
+    With model rad_reaction=1 a given ref (4, ld) advances in place too."""
     ld = _state(y)
     n = ld if n is None else n
     if ref is not None:

@@ -242,6 +242,31 @@ def test_resumable_batch_scan_arguments(pn):
     assert L.pn_batch_scan_pending(None, ctypes.c_int64(4), ctypes.byref(pending), None) == pn.PN_EINVAL
 
 
+def test_radiation_reaction_flag(pn):
+    """rad_reaction must be 0 or 1; the scans refuse the dissipative model."""
+    L = pn.lib()
+    one = ctypes.c_void_p(8)
+    p = pn.Params(None, None, None, 1.0, 1.0, 1.0)
+    bad = pn.model_struct(dict(rad_reaction=2))
+    assert L.pn_rhs(ctypes.byref(bad), p, ctypes.c_int64(4), one, ctypes.c_int64(4), one, None) == pn.PN_EINVAL
+    rr = pn.model_struct(dict(rad_reaction=1))
+    so = pn.ScanOut(8, 8, 8, None, None, None, None, None, None, 0, 0)
+    assert L.pn_fli_scan(ctypes.byref(rr), p, ctypes.byref(pn.integrator_struct()),
+                         ctypes.byref(pn.correction_struct()), ctypes.byref(pn.fli_struct()), ctypes.c_int64(4), one,
+                         ctypes.c_int64(4), None, ctypes.c_double(1.0), ctypes.byref(so), None) == pn.PN_EINVAL
+    assert L.pn_batch_scan(ctypes.byref(rr), p, ctypes.byref(pn.integrator_struct()),
+                           ctypes.byref(pn.correction_struct()), ctypes.byref(pn.fli_struct()), ctypes.c_int64(4),
+                           one, ctypes.c_int64(4), one, ctypes.byref(so), None, one, ctypes.c_size_t(1 << 30),
+                           None) == pn.PN_EINVAL
+    assert L.pn_batch_scan_resumable(ctypes.byref(rr), p, ctypes.byref(pn.integrator_struct()),
+                                     ctypes.byref(pn.correction_struct()), ctypes.byref(pn.fli_struct()),
+                                     ctypes.c_int64(4), one, ctypes.c_int64(4), one, ctypes.byref(so), None,
+                                     ctypes.c_int32(0), ctypes.c_int32(0), one, ctypes.c_size_t(1 << 30),
+                                     None) == pn.PN_EINVAL
+    m = pn.model_struct()
+    assert m.rad_reaction == 0
+
+
 def test_missing_library_fails_loudly(monkeypatch):
     from paper_1802_00147_amd import pn as P
     monkeypatch.setattr(P, "_lib", None)
