@@ -48,6 +48,15 @@ def main():
         yc, it = O.manifold_correct(y2, refs, 1.0, 1.0, 1.0, correction=dict(mode=O.MODES[mode]))
         assert np.all(np.isfinite(yc))
     O.step(y, 1.0, 1.0, 1.0, 4, ref=refs)
+    # The dissipative system: references advanced and written back, both
+    # integrators, and a scan refusing it.
+    for method in (0, 1):
+        yr, rr = O.step(y, 1.0, 1.0, 1.0, 20, model=dict(rad_reaction=1), integrator=dict(method=method),
+                        correction=dict(mode=2), ref=refs, return_ref=True)
+        assert np.all(np.isfinite(yr)) and np.all(np.isfinite(rr))
+    O.step(y, 1.0, 1.0, 1.0, 5, model=dict(rad_reaction=1), correction=dict(mode=3))
+    O.rhs(y, beta, chi, chi, model=dict(rad_reaction=1))
+    assert O.fli_scan(y, 10.0, 1.0, 1.0, 1.0, model=dict(rad_reaction=1))["status"][0] == O.STATUS_BADPARAM
     for method in ("rk4", "rk5"):
         O.rk_linear_step(method, -0.5)
     O.gw_polarizations(y, 1.0, 1.0, 1.0, np.array([0.0, 0.0, 1.0]), np.array([1.0, 0.0, 0.0]), dist=10.0)
