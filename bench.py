@@ -176,6 +176,159 @@ def gw_bench(args, dev):
     print(json.dumps(line), flush=True)
 
 
+def _single_orbit_flops(wl, model, integrator, correction):
+    """Algorithmic flops of one corrected step of one trajectory (oracle
+    counting scalar)."""
+    import oracle as O
+    y0 = O.init_state(wl.r0, wl.p0, wl.th1, wl.ph1, wl.th2, wl.ph2, wl.beta, wl.chi1, wl.chi2, model=model)
+    c = O.count_flops(y0[0], 10.0, wl.beta, wl.chi1, wl.chi2, integrator=integrator, correction=correction)
+    return c["rk_step"] + c["correction"]
+
+
+def table2_bench(args, dev):
+    """The paper's Table 2 protocol (Sec. 3B): each of the four test orbits
+    (Cases I-II, orbits 1-2) integrated to t = 1e5 with RK5 (h = 1), corrected
+    by the dual scaling at eps = 1e-10 (the paper's correction) and
+    uncorrected; energy error max |H - E0| / |E0| over checkpoints every 1e4,
+    GPU elapsed time (one orbit, one lane: a latency-bound launch) against the
+    oracle on one host core.  One benchmark step = the four corrected runs."""
+    import torch
+    import oracle as O
+    from paper_1802_00147_amd import pn, workloads as W
+
+    integ = dict(method=1, h=1.0)
+    dual = dict(mode=3, tol=1e-10)
+    nchunk, chunk = 10, 10000
+    stream = torch.cuda.current_stream(dev)
+    rows, gpu_ms = [], 0.0
+    for name in ("I-1", "I-2", "II-1", "II-2"):
+        wl = W.paper_orbit(name)
+        args_p = (wl.beta, wl.chi1, wl.chi2)
+        y0 = pn.init_state(*[torch.as_tensor(getattr(wl, k), device=dev) for k in ("r0", "p0", "th1", "ph1", "th2",
+                                                                                     "ph2")], *args_p)
+        H0, J0 = pn.invariants(y0, *args_p)
+        ref = torch.cat([H0.reshape(1, 1), J0.reshape(3, 1)]).contiguous()
+        e0 = float(H0[0])
+        res = {}
+        for label, corr in (("corrected", dual), ("uncorrected", None)):
+            y = y0.clone()
+            err, ms = 0.0, 0.0
+            for _ in range(nchunk):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                pn.step(y, *args_p, chunk, integrator=integ, correction=corr, ref=ref)
+                b.record(stream)
+                H, _ = pn.invariants(y, *args_p)
+                torch.cuda.synchronize()
+                ms += a.elapsed_time(b)
+                err = max(err, abs(float(H[0]) - e0) / abs(e0))
+            res[label] = (err, ms)
+        gpu_ms += res["corrected"][1]
+        # The oracle's corrected run, one host core.
+        yo = O.init_state(wl.r0, wl.p0, wl.th1, wl.ph1, wl.th2, wl.ph2, *args_p)
+        Ho, Jo = O.invariants(yo, *args_p)
+        t0 = time.perf_counter()
+        yo = O.step(yo, *args_p, nchunk * chunk, integrator=integ, correction=dual)
+        cpu_s = time.perf_counter() - t0
+        rows.append(dict(orbit=name, dE_corrected=res["corrected"][0], dE_uncorrected=res["uncorrected"][0],
+                         gpu_s=res["corrected"][1] * 1e-3, gpu_s_uncorrected=res["uncorrected"][1] * 1e-3,
+                         oracle_s=cpu_s, us_per_step=1e3 * res["corrected"][1] / (nchunk * chunk)))
+    steps = 4 * nchunk * chunk
+    fps = float(np.mean([_single_orbit_flops(W.paper_orbit(r["orbit"]), None, integ, dual) for r in rows]))
+    achieved = fps * steps / (gpu_ms * 1e-3) / 1e12
+    cpu_total = sum(r["oracle_s"] for r in rows)
+    line = dict(metric="Table 2 protocol: corrected RK5 steps/s of one test orbit and its energy error",
+                value=steps / (gpu_ms * 1e-3), unit="steps/s", n_gpus=1, steps=1, warmup=0,
+                ms_per_step=gpu_ms, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+                data="synthetic",
+                config={"workload": "table2: the paper's Case I/II test orbits 1-2 (Sec. 3B), RK5 h=1 to t=1e5, "
+                                    "dual scaling eps=1e-10 (and uncorrected), energy error over checkpoints "
+                                    "every 1e4", "orbits": 4, "t_end": 1e5},
+                rows=rows,
+                latency=dict(us_per_step=1e3 * gpu_ms / steps, wavefronts=1, simd_fraction=1.0 / 1024),
+                cpu_baseline=dict(value=steps / cpu_total, unit="steps/s", cores=1, kind="oracle",
+                                  sample="the same four corrected runs on one host thread", cpu_model=cpu_model()),
+                roofline=dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                              frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=None, kernel="k_step<RK5,DUAL>",
+                              kernel_ms=gpu_ms / 4, flops_per_step=fps))
+    print(json.dumps(line), flush=True)
+
+
+def orbit3_bench(args, dev):
+    """The paper's dissipative orbit 3 (Sec. 3B, Fig. 5): the full Hamiltonian
+    with the 2.5PN reaction, RK5 (h = 1) corrected by the dual scaling
+    (eps = 1e-10) against references that follow the integral-invariant
+    relation, integrated in chunks (at most 2e4 steps) until r < 6 (or t = 1e6).
+    Reports the inspiral time, the energy error against the advancing
+    reference and the GPU time per step (one lane, latency-bound) beside the
+    oracle running the same inspiral on one host core."""
+    import torch
+    import oracle as O
+    from paper_1802_00147_amd import pn, workloads as W
+
+    model = dict(rad_reaction=1)
+    integ = dict(method=1, h=1.0)
+    dual = dict(mode=3, tol=1e-10)
+    chunk, r_stop, t_max = 20000, 6.0, 1_000_000
+    wl = W.paper_orbit("orbit3")
+    args_p = (wl.beta, wl.chi1, wl.chi2)
+    y = pn.init_state(*[torch.as_tensor(getattr(wl, k), device=dev) for k in ("r0", "p0", "th1", "ph1", "th2",
+                                                                               "ph2")], *args_p)
+    H0, J0 = pn.invariants(y, *args_p, model=model)
+    ref = torch.cat([H0.reshape(1, 1), J0.reshape(3, 1)]).contiguous()
+    stream = torch.cuda.current_stream(dev)
+    t, ms, err, r = 0, 0.0, 0.0, float(wl.r0[0])
+    chunks = []
+    while t < t_max:
+        # Chunks of 5% of the remaining quadrupole inspiral time at the current
+        # separation, (5/256) r^4 / eta, so that the run stops at r_stop and
+        # not in the plunge that follows.
+        eta = wl.beta / (1.0 + wl.beta) ** 2
+        n = int(min(chunk, max(20, 0.05 * (5.0 / 256.0) * r ** 4 / eta)))
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        pn.step(y, *args_p, n, model=model, integrator=integ, correction=dual, ref=ref)
+        b.record(stream)
+        H, _ = pn.invariants(y, *args_p, model=model)
+        torch.cuda.synchronize()
+        ms += a.elapsed_time(b)
+        t += n
+        chunks.append(n)
+        err = max(err, abs(float(H[0]) - float(ref[0, 0])) / abs(float(ref[0, 0])))
+        r = float(torch.linalg.norm(y[0:3, 0]))
+        if not np.isfinite(r) or r < r_stop:
+            break
+    # The oracle on the same inspiral (the same chunks), one host core.
+    yo = O.init_state(wl.r0, wl.p0, wl.th1, wl.ph1, wl.th2, wl.ph2, *args_p)
+    Ho, Jo = O.invariants(yo, *args_p, model=model)
+    refo = np.column_stack([Ho, Jo])
+    t0 = time.perf_counter()
+    for n in chunks:
+        yo, refo = O.step(yo, *args_p, n, model=model, integrator=integ, correction=dual, ref=refo,
+                          return_ref=True)
+    cpu_s = time.perf_counter() - t0
+    ro = float(np.linalg.norm(yo[0, 0:3]))
+    fps = _single_orbit_flops(wl, None, integ, dual)
+    achieved = fps * t / (ms * 1e-3) / 1e12
+    line = dict(metric="Dissipative orbit 3: corrected RK5 steps/s with the 2.5PN reaction",
+                value=t / (ms * 1e-3), unit="steps/s", n_gpus=1, steps=1, warmup=0, ms_per_step=ms,
+                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+                config={"workload": "orbit3: the paper's dissipative test orbit (beta=1, r=50, p_y=0.140, S1 at "
+                                    "45 deg, S2 at 30 deg, chi=(1, 0.85)), full Hamiltonian + 2.5PN reaction, "
+                                    "RK5 h=1, dual scaling eps=1e-10 against integral-invariant references, "
+                                    f"until r < {r_stop:g} (chunks of 5% of the remaining inspiral time)", "orbits": 1},
+                t_inspiral=t, r_final=r, r_final_oracle=ro, energy_error_vs_reference=err,
+                energy_radiated_fraction=float(ref[0, 0]) / float(H0[0]) - 1.0,
+                energy_ref_oracle_rel_diff=abs(float(ref[0, 0]) - float(refo[0, 0])) / abs(float(refo[0, 0])),
+                latency=dict(us_per_step=1e3 * ms / t, wavefronts=1, simd_fraction=1.0 / 1024),
+                cpu_baseline=dict(value=t / cpu_s, unit="steps/s", cores=1, kind="oracle",
+                                  sample="the same inspiral on one host thread", cpu_model=cpu_model()),
+                roofline=dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                              frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=None,
+                              kernel="k_step<RK5,DUAL,reaction>", kernel_ms=ms, flops_per_step_conservative=fps))
+    print(json.dumps(line), flush=True)
+
+
 def surrogate_bench(args, dev):
     """Surrogate-assisted scan of the 4096 x 4096 (r0, theta) grid at t = 1e5
     against the plain FP64 scan.  The network is trained on the FP64 scan of
@@ -348,6 +501,12 @@ def main():
         return
     if args.workload == "gw":
         gw_bench(args, dev)
+        return
+    if args.workload == "table2":
+        table2_bench(args, dev)
+        return
+    if args.workload == "orbit3":
+        orbit3_bench(args, dev)
         return
     wl = make_workload(args.workload)
     cols = {k: torch.as_tensor(getattr(wl, k), device=dev) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")}

@@ -26,6 +26,8 @@ and kinds of axes:
              orbital energy of that state is positive; the spin terms make it
              bound only at large theta2 (>= 2.21 in panel a, >= 2.51 in b),
              and the scan removes the rest as UNBOUND_INIT.
+* paper orbits: the single test orbits of Sec. 3B (Table 2 Cases I-II,
+             orbit 3 with the 2.5PN reaction), PAPER_ORBITS.
 * fig7     : the paper's (theta1, theta2) plane (Sec. 3C, Fig. 7, Table 3):
              314 x 314 points theta_i = 0.01 k, r = 10.14, p_y = 0.365,
              beta = 1 (orbit 2 of Sec. 3A), chi = 1, t = 1e5.
@@ -133,6 +135,34 @@ def fig7(t_end=1e5):
     n = T1.size
     return Workload("fig7", np.full(n, r), np.full(n, p), T1.ravel().copy(), np.zeros(n), T2.ravel().copy(),
                     np.zeros(n), beta, 1.0, 1.0, float(t_end), shape=T1.shape)
+
+
+# Single test orbits printed in the paper: (beta, r0, p_y, chi1, chi2, spin
+# unit vectors).  Case I orbits 1-2 and Case II orbits 1-2 of Sec. 3B (Table
+# 2; Case II inherits the (beta, r, p) of Case I), orbit 3 of Sec. 3B (the
+# dissipative run with the 2.5PN reaction, Fig. 5).
+PAPER_ORBITS = {
+    "I-1": (1.0 / 3.0, 20.0, 0.2461, 0.0, 0.0, (0.0, 0.0, 1.0), (0.0, 0.0, 1.0)),
+    "I-2": (1.0, 10.14, 0.365, 0.0, 0.0, (0.0, 0.0, 1.0), (0.0, 0.0, 1.0)),
+    "II-1": (1.0 / 3.0, 20.0, 0.2461, 0.75, 0.75, (np.sin(np.pi / 3), 0.0, np.cos(np.pi / 3)),
+             (np.sin(np.pi / 4), 0.0, np.cos(np.pi / 4))),
+    "II-2": (1.0, 10.14, 0.365, 1.0, 1.0, (0.13036, 0.262852, -0.955989), (0.118966, -0.13459, -0.983734)),
+    "orbit3": (1.0, 50.0, 0.140, 1.0, 0.85, (np.sin(np.pi / 4), 0.0, np.cos(np.pi / 4)),
+               (np.sin(np.pi / 6), 0.0, np.cos(np.pi / 6))),
+}
+
+
+def paper_orbit(name, t_end=1e5):
+    """One of the paper's test orbits as a one-orbit workload (spin
+    directions as polar and azimuthal angles)."""
+    beta, r0, py, chi1, chi2, s1, s2 = PAPER_ORBITS[name]
+    ang = []
+    for s in (s1, s2):
+        v = np.asarray(s, dtype=np.float64)
+        v = v / np.linalg.norm(v)
+        ang += [np.array([np.arccos(np.clip(v[2], -1.0, 1.0))]), np.array([np.arctan2(v[1], v[0])])]
+    return Workload(name, np.array([r0]), np.array([py]), ang[0], ang[1], ang[2], ang[3], float(beta),
+                    float(chi1), float(chi2), float(t_end))
 
 
 def batch(n=1_000_000, seed=4, tmin=1e3, tmax=1e6):
