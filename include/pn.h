@@ -55,7 +55,7 @@ extern "C" {
 
 typedef enum {
     PN_OK = 0,
-    PN_EINVAL = 1,   /* null pointer, n < 0, ld < n, parameter out of range, unknown enum */
+    PN_EINVAL = 1,   /* null pointer, n < 0 or n > 2^35, ld < n, parameter out of range, unknown enum */
     PN_ENOWS = 2,    /* workspace smaller than the documented size */
     PN_EDEVICE = 3   /* HIP error while launching */
 } pn_status;

@@ -732,6 +732,10 @@ CorrArgs corr_args(const pn_correction* c) {
 
 unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// Largest orbit count of a launch with one or two lanes per orbit: its grid
+// of 64-lane workgroups stays at or below 2^30.
+constexpr int64_t kMaxN = (int64_t)1 << 35;
+
 pn_status launched(const char* what) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -930,7 +934,7 @@ pn_status prepare_scan(const pn_model* model, const pn_params& params, const pn_
     if (model->rad_reaction) return PN_EINVAL;      // scans integrate the conservative system
     if (corr == nullptr || check_corr(corr) != PN_OK) return PN_EINVAL;
     if (fli == nullptr || out == nullptr) return PN_EINVAL;
-    if (!(n >= 0 && ld >= n)) return PN_EINVAL;
+    if (!(n >= 0 && n <= kMaxN && ld >= n)) return PN_EINVAL;
     if (!(fli->d0 > 0.0 && is_fin(fli->d0) && fli->d_renorm > fli->d0 && is_fin(fli->d_renorm))) return PN_EINVAL;
     if (fli->shadow_axis < 0 || fli->shadow_axis >= 12) return PN_EINVAL;
     if (!is_fin(fli->thr_at_1e5)) return PN_EINVAL;
@@ -1054,7 +1058,7 @@ pn_status pn_init_state(const pn_model* model, pn_params params, int64_t n, cons
                         const double* p0, const double* th1, const double* ph1, const double* th2,
                         const double* ph2, double* y0, int64_t ld, hipStream_t stream) {
     PN_REQUIRE(check_model(model) == PN_OK);
-    PN_REQUIRE(n >= 0 && ld >= n);
+    PN_REQUIRE(n >= 0 && n <= kMaxN && ld >= n);
     ParamArgs pa;
     PN_REQUIRE(make_params(model, params, pa) == PN_OK);
     if (n == 0) return PN_OK;
@@ -1069,7 +1073,7 @@ pn_status pn_init_state_gather(const pn_model* model, pn_params params, int64_t 
                                const double* th2, const double* ph2, double* y0, int64_t ld,
                                hipStream_t stream) {
     PN_REQUIRE(check_model(model) == PN_OK);
-    PN_REQUIRE(m >= 0 && ld >= m);
+    PN_REQUIRE(m >= 0 && m <= kMaxN && ld >= m);
     ParamArgs pa;
     PN_REQUIRE(make_params(model, params, pa) == PN_OK);
     if (m == 0) return PN_OK;
@@ -1082,7 +1086,7 @@ pn_status pn_init_state_gather(const pn_model* model, pn_params params, int64_t 
 pn_status pn_rhs(const pn_model* model, pn_params params, int64_t n, const double* y, int64_t ld,
                  double* dydt, hipStream_t stream) {
     PN_REQUIRE(check_model(model) == PN_OK);
-    PN_REQUIRE(n >= 0 && ld >= n);
+    PN_REQUIRE(n >= 0 && n <= kMaxN && ld >= n);
     ParamArgs pa;
     PN_REQUIRE(make_params(model, params, pa) == PN_OK);
     if (n == 0) return PN_OK;
@@ -1094,7 +1098,7 @@ pn_status pn_rhs(const pn_model* model, pn_params params, int64_t n, const doubl
 pn_status pn_invariants(const pn_model* model, pn_params params, int64_t n, const double* y, int64_t ld,
                         double* H, double* J, hipStream_t stream) {
     PN_REQUIRE(check_model(model) == PN_OK);
-    PN_REQUIRE(n >= 0 && ld >= n);
+    PN_REQUIRE(n >= 0 && n <= kMaxN && ld >= n);
     ParamArgs pa;
     PN_REQUIRE(make_params(model, params, pa) == PN_OK);
     if (n == 0) return PN_OK;
@@ -1108,7 +1112,7 @@ pn_status pn_manifold_correct(const pn_model* model, pn_params params, const pn_
                               hipStream_t stream) {
     PN_REQUIRE(check_model(model) == PN_OK);
     PN_REQUIRE(corr != nullptr && check_corr(corr) == PN_OK);
-    PN_REQUIRE(n >= 0 && ld >= n);
+    PN_REQUIRE(n >= 0 && n <= kMaxN && ld >= n);
     ParamArgs pa;
     PN_REQUIRE(make_params(model, params, pa) == PN_OK);
     if (n == 0) return PN_OK;
@@ -1130,7 +1134,7 @@ static pn_status step_impl(const char* what, const pn_model* model, pn_params pa
     PN_REQUIRE(check_model(model) == PN_OK);
     PN_REQUIRE(check_integ(integ) == PN_OK);
     PN_REQUIRE(check_corr(corr) == PN_OK);
-    PN_REQUIRE(n >= 0 && ld >= n && nsteps >= 0);
+    PN_REQUIRE(n >= 0 && n <= kMaxN && ld >= n && nsteps >= 0);
     ParamArgs pa;
     PN_REQUIRE(make_params(model, params, pa) == PN_OK);
     if (n == 0 || nsteps == 0) return PN_OK;

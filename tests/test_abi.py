@@ -267,6 +267,22 @@ def test_radiation_reaction_flag(pn):
     assert m.rad_reaction == 0
 
 
+def test_orbit_counts_beyond_the_launch_limit_rejected(pn):
+    """n above 2^35 would overflow a launch grid: refused before launch."""
+    L = pn.lib()
+    one = ctypes.c_void_p(8)
+    m = pn.model_struct()
+    p = pn.Params(None, None, None, 1.0, 1.0, 1.0)
+    big = ctypes.c_int64((1 << 35) + 1)
+    assert L.pn_rhs(ctypes.byref(m), p, big, one, big, one, None) == pn.PN_EINVAL
+    assert L.pn_step(ctypes.byref(m), p, ctypes.byref(pn.integrator_struct()), None, big, one, big, None,
+                     ctypes.c_int64(1), None) == pn.PN_EINVAL
+    so = pn.ScanOut(8, 8, 8, None, None, None, None, None, None, 0, 0)
+    assert L.pn_fli_scan(ctypes.byref(m), p, ctypes.byref(pn.integrator_struct()),
+                         ctypes.byref(pn.correction_struct()), ctypes.byref(pn.fli_struct()), big, one, big, None,
+                         ctypes.c_double(1.0), ctypes.byref(so), None) == pn.PN_EINVAL
+
+
 def test_missing_library_fails_loudly(monkeypatch):
     from paper_1802_00147_amd import pn as P
     monkeypatch.setattr(P, "_lib", None)
