@@ -481,7 +481,7 @@ def main():
                          "for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); the scan shards "
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); the scan shards "
               "by orbits with no exchange during integration, see the design notes.", file=sys.stderr)
         sys.exit(2)
 
