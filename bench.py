@@ -482,7 +482,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); the scan shards "
-              "by orbits with no exchange during integration, see the design notes.", file=sys.stderr)
+              "by orbits with no exchange during integration, one process per GPU on its share of the "
+              "orbits.", file=sys.stderr)
         sys.exit(2)
 
     import torch
