@@ -30,8 +30,9 @@
 //                        removal of unbounded / merged orbits
 //   Sec. 4, eq. (14)     gravitational-wave polarisations h_plus, h_cross
 // The orbital N/1PN/2PN and spin-orbit terms are not printed in the paper
-// (Sec. 2 cites them); the standard ADM-gauge expressions are used.  Every
-// reading of a silent or garbled passage is listed in the design notes.
+// (Sec. 2 cites them); the standard ADM-gauge expressions are used, and so
+// is one reading of every other silent or garbled passage, stated where it
+// is applied below.
 //
 // Parity pins that tie this file to the physics (not to itself) live in the
 // tests: Kepler closed forms, the 2PN circular-orbit energy E(x), the 2PN

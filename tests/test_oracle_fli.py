@@ -182,7 +182,8 @@ def test_paper_regular_orbits_are_regular(oracle):
     """Orbits the paper calls regular (Case II orbit 1, Fig. 3(b); orbit 4,
     Fig. 8(b)) stay below the 5.8 threshold at t = 1e5 with physical spin
     units.  The paper's chaotic Case II orbit 2 is run and must stay bound and
-    corrected; its FLI is not asserted (the design notes record the value)."""
+    corrected; its FLI is not asserted (the paper's label for it depends on
+    the spin-unit reading)."""
     for row in load_orbits():
         c = oracle.coefficients(row["beta"], row["chi1"], row["chi2"])
         y = np.zeros(12)
