@@ -182,8 +182,9 @@ def test_paper_regular_orbits_are_regular(oracle):
     """Orbits the paper calls regular (Case II orbit 1, Fig. 3(b); orbit 4,
     Fig. 8(b)) stay below the 5.8 threshold at t = 1e5 with physical spin
     units.  The paper's chaotic Case II orbit 2 is run and must stay bound and
-    corrected; its FLI is not asserted (the paper's label for it depends on
-    the spin-unit reading)."""
+    corrected; its FLI is not asserted (it reaches 4.41 at t = 1e5, below the
+    threshold, and the paper states neither the time nor the integrator of
+    its Fig. 3(d))."""
     for row in load_orbits():
         c = oracle.coefficients(row["beta"], row["chi1"], row["chi2"])
         y = np.zeros(12)
