@@ -472,7 +472,7 @@ def main():
     ap.add_argument("--workload", default="grid64")
     ap.add_argument("--cpu-sample", type=int, default=160)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--epochs", type=int, default=4, help="surrogate workload: training epochs")
+    ap.add_argument("--epochs", type=int, default=20, help="surrogate workload: training epochs (cosine decay)")
     ap.add_argument("--plain-sample", type=int, default=65536, help="surrogate workload: plain-scan sample")
     ap.add_argument("--refine", type=int, default=40, help="surrogate workload: refinement epochs on the audit")
     ap.add_argument("--margin", type=float, default=0.5, help="surrogate workload: logit margin of the gate")

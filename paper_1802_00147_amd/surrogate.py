@@ -8,6 +8,7 @@ on a finished scan is a loop of pn_mlp_train_step calls.  This module holds
 the host-side bookkeeping of a data loader: feature statistics and the seeded
 order of training samples.
 """
+import math
 import time
 from dataclasses import dataclass, field
 
@@ -68,9 +69,10 @@ def training_set(wl, scan_out, device):
     return TrainingSet(feat, label, target, valid, stats)
 
 
-def train(ts, epochs=8, batch=4096, lr=1e-3, seed=50, init_seed=50, device="cuda:0", log=None):
+def train(ts, epochs=20, batch=4096, lr=1e-3, cosine=True, seed=50, init_seed=50, device="cuda:0", log=None):
     """Train the network on the valid samples of `ts`; returns (network, mean
-    loss per epoch)."""
+    loss per epoch).  cosine: the learning rate of epoch e is
+    lr (1 + cos(pi e / epochs)) / 2, else constant."""
     params = W.mlp_init_weights(init_seed)
     net = pn.Network([W_ for W_, _ in params], [b for _, b in params], device)
     rng = np.random.default_rng(seed)
@@ -79,9 +81,10 @@ def train(ts, epochs=8, batch=4096, lr=1e-3, seed=50, init_seed=50, device="cuda
     history = []
     nb = len(ts.valid) // batch
     for ep in range(epochs):
+        lr_ep = lr * 0.5 * (1.0 + math.cos(math.pi * ep / epochs)) if cosine else lr
         order = torch.as_tensor(rng.permutation(ts.valid).astype(np.int32), device=device)
         loss.zero_()
-        ws = pn.mlp_train(net, ts.feat, ts.label, ts.target, order[:nb * batch], batch, lr, loss, ws)
+        ws = pn.mlp_train(net, ts.feat, ts.label, ts.target, order[:nb * batch], batch, lr_ep, loss, ws)
         history.append(float(loss.item()) / max(nb, 1))
         if log:
             log(f"epoch {ep}: mean loss {history[-1]:.5f}")
