@@ -37,7 +37,7 @@ KERNEL_SOURCES = ["paper_1802_00147_amd/csrc/pn_kernels.hip", "paper_1802_00147_
 # grid64 launch: FETCH_SIZE 365.125 KiB x 1.999923 (a 1 GiB copy reads 524,308.25
 # KiB) + WRITE_SIZE 548.0 KiB x 1.0 (the copy writes 1,048,576 KiB).
 TRAFFIC = dict(workload="grid64", bytes_per_launch=753508 + 593920,
-               sources_sha256="0f61652124a7021ceec3185b9cae65433a1a97b362d985e376c3c492b7a95d62")
+               sources_sha256="1197f061899a903c9ce46788adbfd372850f8f880f624a95646b42aae9ada876")
 
 
 def sources_sha256():

@@ -294,6 +294,12 @@ void pn_default_tuning(pn_tuning* t);
 /* Bytes of device workspace pn_batch_scan needs for n orbits. */
 size_t pn_batch_workspace_size(int64_t n);
 
+/* Orbit pairs a pn_batch_scan launch keeps resident on the current device
+ * with this tuning (NULL: the one pn_batch_scan would use): a batch of that
+ * many equal orbits is one scheduling round.  0 when no device or an
+ * invalid tuning. */
+int64_t pn_batch_resident_pairs(const pn_tuning* tuning);
+
 /* Same computation and outputs as pn_fli_scan (bitwise, for any tuning),
  * for orbits whose parameters and end times differ.  The orbits are ordered by
  * step count, longest first (binned, 8 bins per octave), into a queue in the
@@ -486,6 +492,13 @@ typedef struct {
     uint64_t refine_seed;    /* SplitMix64 seed of the sample order (51) */
     int32_t refine_cosine;   /* 1: learning rate refine_lr (1 + cos(pi e / epochs)) / 2 in
                                 epoch e; 0: constant (0) */
+    int64_t audit_split;     /* 0: the whole audit is integrated before the refinement (0);
+                                1: only the largest whole number of rounds of the batch
+                                kernel's resident orbit pairs (pn_batch_resident_pairs)
+                                is, and the refinement sees only those; the rest of the
+                                audit is integrated with the uncertain points, so that
+                                only one of the two integrations ends in a partly idle
+                                round; k > 1: as 1 with rounds of k points */
 } pn_surrogate_cfg;
 
 void pn_default_surrogate_cfg(pn_surrogate_cfg* cfg);

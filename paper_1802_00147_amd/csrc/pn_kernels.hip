@@ -1218,6 +1218,15 @@ void pn_default_tuning(pn_tuning* t) {
 
 size_t pn_batch_workspace_size(int64_t n) { return n < 0 ? 0 : batch_ws_bytes(n); }
 
+int64_t pn_batch_resident_pairs(const pn_tuning* tuning) {
+    int dev = 0;
+    const int ncu = device_cus(dev);
+    if (ncu <= 0) return 0;
+    const pn_tuning tu = chosen_tuning(tuning, dev);
+    if (!valid_tuning(tu)) return 0;
+    return batch_slots(tu, ncu);
+}
+
 pn_status pn_batch_scan(const pn_model* model, pn_params params, const pn_integrator* integ,
                         const pn_correction* corr, const pn_fli_cfg* fli, int64_t n, const double* y0,
                         int64_t ld, const double* t_end, const pn_scan_out* out, const pn_tuning* tuning,

@@ -982,6 +982,7 @@ void pn_default_surrogate_cfg(pn_surrogate_cfg* c) {
     c->refine_lr = 5e-4f;
     c->refine_seed = 51;
     c->refine_cosine = 0;
+    c->audit_split = 0;
 }
 
 size_t pn_surrogate_scan_workspace_size(int64_t n, int32_t refine_batch) {
@@ -1038,6 +1039,7 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
     if (!(cfg->margin >= 0.0f) || !(cfg->audit_frac >= 0.0 && cfg->audit_frac <= 1.0)) return PN_EINVAL;
     if (cfg->refine_epochs < 0 || cfg->refine_batch <= 0) return PN_EINVAL;
     if (cfg->refine_cosine != 0 && cfg->refine_cosine != 1) return PN_EINVAL;
+    if (cfg->audit_split < 0) return PN_EINVAL;
     if (cfg->refine_epochs > 0 && (!adam_step || *adam_step < 0 || !(cfg->refine_lr > 0.0f))) return PN_EINVAL;
     if (!net_ok(net, cfg->refine_epochs > 0)) return PN_EINVAL;
     if (!r0 || !p0 || !th1 || !ph1 || !th2 || !ph2 || !mean || !stdv) return PN_EINVAL;
@@ -1130,25 +1132,41 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
         std::sort(host.begin(), host.begin() + ma);
         PN_HIP(hipMemcpyAsync(listA, host.data(), (size_t)ma * 4, hipMemcpyHostToDevice, stream), what);
         PN_HIP(hipStreamSynchronize(stream), what);        // host memory must outlive the copy
-        // 2. Integrate the audit.
-        PN_TRY(integrate(listA, ma));
     }
-    PN_TRY(mark(1));
-    // 3. Refine the network on the integrated audit (valid orbits only), in a
-    //    SplitMix64-seeded order per epoch.
-    if (cfg->refine_epochs > 0 && ma >= cfg->refine_batch) {
-        PN_TRY(pn_mlp_features(params, ma, r0, th1, th2, t_end, t_end_all, listA, mean, stdv, featA, stream));
-        if (t_end) {
-            PN_TRY(pn_mlp_targets(sfli, slab, gp[3], 0.0, ma, labA, tgtA, stream));
-        } else {
-            PN_TRY(pn_mlp_targets(sfli, slab, nullptr, t_end_all, ma, labA, tgtA, stream));
+    // 2. Integrate the audit: all of it, or (audit_split) its first whole
+    //    number of scheduling rounds of the batch kernel; the rest of the
+    //    audit is then integrated with the uncertain points in step 5, so
+    //    that only one of the two integrations ends in a partial round.
+    int64_t round = 0;
+    if (cfg->audit_split == 1) {
+        round = pn_batch_resident_pairs(nullptr);
+        if (round <= 0) {
+            pn_detail::set_last_error(what, "no device");
+            return PN_EDEVICE;
         }
-        std::vector<int32_t> st((size_t)ma);
-        PN_HIP(hipMemcpyAsync(st.data(), sstat, (size_t)ma * 4, hipMemcpyDeviceToHost, stream), what);
+    } else if (cfg->audit_split > 1) {
+        round = cfg->audit_split;
+    }
+    int64_t m1 = ma;
+    if (round > 0 && ma >= round) m1 = (ma / round) * round;
+    const int64_t m2 = ma - m1;                            // audit points left for step 5
+    if (m1 > 0) PN_TRY(integrate(listA, m1));
+    PN_TRY(mark(1));
+    // 3. Refine the network on the integrated audit points (valid orbits
+    //    only), in a SplitMix64-seeded order per epoch.
+    if (cfg->refine_epochs > 0 && m1 >= cfg->refine_batch) {
+        PN_TRY(pn_mlp_features(params, m1, r0, th1, th2, t_end, t_end_all, listA, mean, stdv, featA, stream));
+        if (t_end) {
+            PN_TRY(pn_mlp_targets(sfli, slab, gp[3], 0.0, m1, labA, tgtA, stream));
+        } else {
+            PN_TRY(pn_mlp_targets(sfli, slab, nullptr, t_end_all, m1, labA, tgtA, stream));
+        }
+        std::vector<int32_t> st((size_t)m1);
+        PN_HIP(hipMemcpyAsync(st.data(), sstat, (size_t)m1 * 4, hipMemcpyDeviceToHost, stream), what);
         PN_HIP(hipStreamSynchronize(stream), what);
         std::vector<int32_t> valid;
-        valid.reserve((size_t)ma);
-        for (int64_t j = 0; j < ma; ++j)
+        valid.reserve((size_t)m1);
+        for (int64_t j = 0; j < m1; ++j)
             if ((st[(size_t)j] & 0xFF) == 0) valid.push_back((int32_t)j);
         const int64_t nb = (int64_t)valid.size() / cfg->refine_batch;
         SplitMix rng{cfg->refine_seed};
@@ -1177,16 +1195,26 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
     hipLaunchKernelGGL(k_gate_uncertain, dim3(blocks_for(n, 256)), dim3(256), 0, stream, out, n, cfg->margin,
                        cfg->audit_frac, (unsigned long long)cfg->seed, label, listU, counts + 1);
     PN_TRY(launched(what));
-    // The audit's labels (in slab) are merged before the next scan reuses it.
-    if (ma > 0) PN_TRY(pn_surrogate_merge(listA, ma, slab, label, stream));
+    // The integrated audit labels (in slab) are merged before the next scan
+    // reuses it.
+    if (m1 > 0) PN_TRY(pn_surrogate_merge(listA, m1, slab, label, stream));
     PN_HIP(hipMemcpyAsync(&cnt, counts + 1, 8, hipMemcpyDeviceToHost, stream), what);
     PN_HIP(hipStreamSynchronize(stream), what);
     const int64_t mu = (int64_t)cnt;
     PN_TRY(mark(3));
-    // 5. Integrate the uncertain points; their labels replace the network's.
-    if (mu > 0) {
-        PN_TRY(integrate(listU, mu));
-        PN_TRY(pn_surrogate_merge(listU, mu, slab, label, stream));
+    // 5. Integrate the rest of the audit and the uncertain points in one
+    //    batch (the training order buffer holds the joined list); their
+    //    labels replace the network's.
+    if (m2 + mu > 0) {
+        const int32_t* list5 = listU;
+        if (m2 > 0) {
+            PN_HIP(hipMemcpyAsync(order, listA + m1, (size_t)m2 * 4, hipMemcpyDeviceToDevice, stream), what);
+            if (mu > 0)
+                PN_HIP(hipMemcpyAsync(order + m2, listU, (size_t)mu * 4, hipMemcpyDeviceToDevice, stream), what);
+            list5 = order;
+        }
+        PN_TRY(integrate(list5, m2 + mu));
+        PN_TRY(pn_surrogate_merge(list5, m2 + mu, slab, label, stream));
     }
     if (points) {
         if (ma > 0) PN_HIP(hipMemcpyAsync(points, listA, (size_t)ma * 4, hipMemcpyDeviceToDevice, stream), what);

@@ -68,7 +68,7 @@ class ScanOut(ctypes.Structure):
 class SurrogateCfg(ctypes.Structure):
     _fields_ = [("margin", ctypes.c_float), ("audit_frac", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("refine_epochs", ctypes.c_int32), ("refine_batch", ctypes.c_int32), ("refine_lr", ctypes.c_float),
-                ("refine_seed", ctypes.c_uint64), ("refine_cosine", ctypes.c_int32)]
+                ("refine_seed", ctypes.c_uint64), ("refine_cosine", ctypes.c_int32), ("audit_split", ctypes.c_int64)]
 
 
 class Tuning(ctypes.Structure):
@@ -89,6 +89,7 @@ EXPORTS = ["pn_default_model", "pn_default_integrator", "pn_default_correction",
            "pn_default_surrogate_cfg", "pn_surrogate_scan_workspace_size", "pn_surrogate_scan",
            "pn_mlp_train", "pn_fli_scan_workspace_size", "pn_shutdown",
            "pn_batch_ckpt_workspace_size", "pn_batch_scan_resumable", "pn_batch_scan_pending",
+           "pn_batch_resident_pairs",
            "pn_version", "pn_status_string", "pn_last_error"]
 
 
@@ -121,6 +122,7 @@ def lib():
         L.pn_mlp_infer_workspace_size.argtypes = [ctypes.c_int64]
         L.pn_batch_workspace_size.restype = ctypes.c_size_t
         L.pn_batch_workspace_size.argtypes = [ctypes.c_int64]
+        L.pn_batch_resident_pairs.restype = ctypes.c_int64
         L.pn_batch_ckpt_workspace_size.restype = ctypes.c_size_t
         L.pn_batch_ckpt_workspace_size.argtypes = [ctypes.c_int64]
         L.pn_graph_destroy.argtypes = [ctypes.c_void_p]

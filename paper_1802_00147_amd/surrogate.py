@@ -101,20 +101,22 @@ class SurrogateResult:
 
 
 def surrogate_scan(net, wl, stats, margin=0.5, audit=0.01, seed=5, model=None,
-                   refine_epochs=0, refine_batch=2048, refine_lr=5e-4, refine_seed=51, refine_cosine=0, ws=None):
+                   refine_epochs=0, refine_batch=2048, refine_lr=5e-4, refine_seed=51, refine_cosine=0, audit_split=0,
+                   ws=None):
     """Labels of every point of the workload `wl` through pn_surrogate_scan:
 
-    1. the audit sample (SplitMix64(seed + i) / 2^64 < audit) is integrated;
+    1. the audit sample (SplitMix64(seed + i) / 2^64 < audit) is integrated
+       (with audit_split, its first whole number of batch-kernel rounds);
     2. with refine_epochs > 0 the network is first trained further on those
        integrated points (FLIs the method produced on this very scan);
     3. fused inference on every point; points with |logit| < margin are
-       integrated;
+       integrated, with the rest of the audit;
     4. integrated labels replace the network's wherever they exist.
     """
     device = net.w[0].device
     cols = {k: torch.as_tensor(getattr(wl, k), device=device) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")}
     cfg = dict(margin=margin, audit_frac=audit, seed=seed, refine_epochs=refine_epochs, refine_batch=refine_batch,
-               refine_lr=refine_lr, refine_seed=refine_seed, refine_cosine=refine_cosine)
+               refine_lr=refine_lr, refine_seed=refine_seed, refine_cosine=refine_cosine, audit_split=audit_split)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = pn.surrogate_scan(net, wl.n, cols["r0"], cols["p0"], cols["th1"], cols["ph1"], cols["th2"], cols["ph2"],

@@ -166,6 +166,10 @@ def test_invalid_surrogate_scan_arguments_rejected(pn):
     assert scan(cfg=dict(audit_frac=1.5)) == pn.PN_EINVAL
     assert scan(cfg=dict(refine_batch=0)) == pn.PN_EINVAL
     assert scan(cfg=dict(refine_lr=0.0)) == pn.PN_EINVAL
+    assert scan(cfg=dict(audit_split=-1)) == pn.PN_EINVAL
+    assert pn.surrogate_cfg().audit_split == 0
+    assert L.pn_batch_resident_pairs(ctypes.byref(pn.Tuning(7, 1, 64))) == 0   # invalid tuning
+    assert L.pn_batch_resident_pairs(None) >= 0
     assert scan(t_all=0.0) == pn.PN_EINVAL
     assert scan(std_=bad_std) == pn.PN_EINVAL
     assert scan(model=dict(pn_order=5)) == pn.PN_EINVAL

@@ -285,6 +285,44 @@ def test_native_surrogate_scan_per_point_parameters(pn, margin, audit):
     assert all(x >= 0 for x in r["phase_ms"])
 
 
+def test_audit_split_changes_only_the_batching(pn):
+    """With the audit split into whole rounds (here rounds of 256 points) and
+    no refinement, the same network gates the same points: the labels and the
+    set of integrated points equal those of the unsplit scan, every
+    integrated point carries the plain scan's label, and every audited point
+    is among them.  With refinement the split run stays exact on its
+    integrated points."""
+    from paper_1802_00147_amd import surrogate as S, workloads as W
+    wl = W.batch(n=3000, seed=34, tmin=200.0, tmax=1500.0)
+    cols = [dev(getattr(wl, k)) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")]
+    b, c1, c2, t = (dev(getattr(wl, k)) for k in ("beta", "chi1", "chi2", "t_end"))
+    plain = pn.batch_scan(pn.init_state(*cols, b, c1, c2), t, b, c1, c2, full=False)
+    ref = plain["label"].cpu().numpy()
+    stats = S.feature_stats(wl)
+    runs = {}
+    for split in (0, 256):
+        net, _ = _network(pn)
+        r = pn.surrogate_scan(net, wl.n, *cols, t, b, c1, c2, stats.mean, stats.std,
+                              cfg=dict(margin=0.3, audit_frac=0.2, seed=9, refine_epochs=0, audit_split=split))
+        torch.cuda.synchronize()
+        runs[split] = (r["label"].cpu().numpy(), np.sort(r["points"].cpu().numpy()), r["integrated"])
+    assert np.array_equal(runs[0][0], runs[256][0])
+    assert np.array_equal(runs[0][1], runs[256][1]) and runs[0][2] == runs[256][2]
+    got, pts, _ = runs[256]
+    assert np.array_equal(got[pts], ref[pts])
+    drawn = M.gate(np.zeros((wl.n, 2)), 0.0, 0.2, 9)[1]
+    assert len(drawn) > 256 and len(drawn) % 256 != 0      # the split leaves audit points for the second batch
+    assert set(drawn.tolist()) <= set(pts.tolist())
+    net, _ = _network(pn)
+    r = pn.surrogate_scan(net, wl.n, *cols, t, b, c1, c2, stats.mean, stats.std,
+                          cfg=dict(margin=0.3, audit_frac=0.2, seed=9, refine_epochs=3, refine_batch=128,
+                                   audit_split=256))
+    torch.cuda.synchronize()
+    got, pts = r["label"].cpu().numpy(), r["points"].cpu().numpy()
+    assert np.array_equal(got[pts], ref[pts])
+    assert set(drawn.tolist()) <= set(pts.tolist())
+
+
 def test_multi_step_training_equals_single_steps(pn):
     """pn_mlp_train over an order equals the same pn_mlp_train_step calls, bit
     for bit in the weights, their bfloat16 copies, the Adam moments and the
