@@ -37,7 +37,7 @@ KERNEL_SOURCES = ["paper_1802_00147_amd/csrc/pn_kernels.hip", "paper_1802_00147_
 # grid64 launch: FETCH_SIZE 365.125 KiB x 1.999923 (a 1 GiB copy reads 524,308.25
 # KiB) + WRITE_SIZE 548.0 KiB x 1.0 (the copy writes 1,048,576 KiB).
 TRAFFIC = dict(workload="grid64", bytes_per_launch=753508 + 593920,
-               sources_sha256="1197f061899a903c9ce46788adbfd372850f8f880f624a95646b42aae9ada876")
+               sources_sha256="d528492dba44ef6f5f2dedb52141f05d6a128ac11f32cefc6c94d2445ebf5a3c")
 
 
 def sources_sha256():
@@ -591,6 +591,14 @@ def main():
                                 frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=traffic,
                                 kernel=kernel, kernel_ms=kernel_ms,
                                 flops_per_orbit_step=fpos)
+        if not batched:
+            # Registers, spills and occupancy of the scan kernel as the
+            # runtime reports them, and the wavefronts per SIMD the launch
+            # actually keeps resident.
+            res = pn.scan_kernel_resources()
+            simds = 4 * torch.cuda.get_device_properties(dev).multi_processor_count
+            res["achieved_waves_per_simd"] = min(float(res["waves_per_simd"]), ((2 * n + 63) // 64) / simds)
+            line["roofline"]["resources"] = res
     print(json.dumps(line), flush=True)
 
 

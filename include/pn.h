@@ -294,6 +294,15 @@ void pn_default_tuning(pn_tuning* t);
 /* Bytes of device workspace pn_batch_scan needs for n orbits. */
 size_t pn_batch_workspace_size(int64_t n);
 
+/* Resources of the fused scan kernel (pn_fli_scan) for one integrator and
+ * correction mode on the current device, as the runtime reports them:
+ * vector registers per lane, scratch (spill) bytes per lane, and the
+ * wavefronts per SIMD its 64-lane workgroups can keep resident.  Any output
+ * pointer may be NULL (host memory).  PN_EINVAL for an unknown method or
+ * mode, PN_EDEVICE without a device. */
+pn_status pn_scan_kernel_resources(int32_t method, int32_t mode, int32_t* vgprs, int64_t* scratch_bytes,
+                                   int32_t* waves_per_simd);
+
 /* Orbit pairs a pn_batch_scan launch keeps resident on the current device
  * with this tuning (NULL: the one pn_batch_scan would use): a batch of that
  * many equal orbits is one scheduling round.  0 when no device or an

@@ -1218,6 +1218,35 @@ void pn_default_tuning(pn_tuning* t) {
 
 size_t pn_batch_workspace_size(int64_t n) { return n < 0 ? 0 : batch_ws_bytes(n); }
 
+pn_status pn_scan_kernel_resources(int32_t method, int32_t mode, int32_t* vgprs, int64_t* scratch_bytes,
+                                   int32_t* waves_per_simd) {
+    PN_REQUIRE(method == PN_RK4 || method == PN_RK5);
+    PN_REQUIRE(mode >= PN_CORR_NONE && mode <= PN_CORR_DUAL);
+    const void* f = nullptr;
+    switch (method * 4 + mode) {
+        case 0: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK4, PN_CORR_NONE>); break;
+        case 1: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK4, PN_CORR_SPIN>); break;
+        case 2: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK4, PN_CORR_SIX>); break;
+        case 3: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK4, PN_CORR_DUAL>); break;
+        case 4: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK5, PN_CORR_NONE>); break;
+        case 5: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK5, PN_CORR_SPIN>); break;
+        case 6: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK5, PN_CORR_SIX>); break;
+        default: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK5, PN_CORR_DUAL>); break;
+    }
+    hipFuncAttributes at;
+    hipError_t e = hipFuncGetAttributes(&at, f);
+    int blocks = 0;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, kBlock, 0);
+    if (e != hipSuccess) {
+        set_error("pn_scan_kernel_resources", e);
+        return PN_EDEVICE;
+    }
+    if (vgprs) *vgprs = at.numRegs;
+    if (scratch_bytes) *scratch_bytes = (int64_t)at.localSizeBytes;
+    if (waves_per_simd) *waves_per_simd = blocks / 4;     // one wavefront per workgroup, four SIMDs per CU
+    return PN_OK;
+}
+
 int64_t pn_batch_resident_pairs(const pn_tuning* tuning) {
     int dev = 0;
     const int ncu = device_cus(dev);

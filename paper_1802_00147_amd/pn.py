@@ -89,7 +89,7 @@ EXPORTS = ["pn_default_model", "pn_default_integrator", "pn_default_correction",
            "pn_default_surrogate_cfg", "pn_surrogate_scan_workspace_size", "pn_surrogate_scan",
            "pn_mlp_train", "pn_fli_scan_workspace_size", "pn_shutdown",
            "pn_batch_ckpt_workspace_size", "pn_batch_scan_resumable", "pn_batch_scan_pending",
-           "pn_batch_resident_pairs",
+           "pn_batch_resident_pairs", "pn_scan_kernel_resources",
            "pn_version", "pn_status_string", "pn_last_error"]
 
 
@@ -433,6 +433,19 @@ def batch_scan_resumable(y0, t_end, beta, chi1, chi2, ws, resume, max_chunks, mo
                                        _stream(y0.device))
     _check("pn_batch_scan_resumable", st)
     return out
+
+
+def scan_kernel_resources(integrator=None, correction=None):
+    """pn_scan_kernel_resources: dict(vgprs, scratch_bytes, waves_per_simd)
+    of the fused scan kernel for this integrator and correction mode."""
+    integ = integrator_struct(integrator)
+    mode = correction_struct(correction).mode
+    v, w = ctypes.c_int32(0), ctypes.c_int32(0)
+    sc = ctypes.c_int64(0)
+    st = lib().pn_scan_kernel_resources(ctypes.c_int32(integ.method), ctypes.c_int32(mode), ctypes.byref(v),
+                                        ctypes.byref(sc), ctypes.byref(w))
+    _check("pn_scan_kernel_resources", st)
+    return dict(vgprs=v.value, scratch_bytes=sc.value, waves_per_simd=w.value)
 
 
 def batch_scan_pending(ws, n):

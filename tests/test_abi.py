@@ -271,6 +271,12 @@ def test_radiation_reaction_flag(pn):
     assert m.rad_reaction == 0
 
 
+def test_scan_kernel_resources_arguments(pn):
+    L = pn.lib()
+    assert L.pn_scan_kernel_resources(ctypes.c_int32(7), ctypes.c_int32(2), None, None, None) == pn.PN_EINVAL
+    assert L.pn_scan_kernel_resources(ctypes.c_int32(0), ctypes.c_int32(9), None, None, None) == pn.PN_EINVAL
+
+
 def test_orbit_counts_beyond_the_launch_limit_rejected(pn):
     """n above 2^35 would overflow a launch grid: refused before launch."""
     L = pn.lib()

@@ -36,6 +36,9 @@ def test_default_line_has_every_field():
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in r, k
     assert r["bound"] == "alu" and r["peak"] == 78.6 and abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12
+    res = r["resources"]
+    assert 0 < res["vgprs"] <= 512 and res["scratch_bytes"] == 0 and res["waves_per_simd"] >= 1
+    assert abs(res["achieved_waves_per_simd"] - 128 / 1024) < 1e-12     # grid64: 128 wavefronts
     c = d["cpu_baseline"]
     for k in ("value", "unit", "cores", "kind", "sample"):
         assert k in c, k
