@@ -6,7 +6,10 @@ angle theta in [0, pi] (theta1 = pi/2, theta2 = theta), beta = 1, chi = 1, all
 Hamiltonian terms on (quadrupole-monopole included), RK4 with h = 1 to
 t = 1e5, the six-integral correction after every step, FLI threshold 5.8.
 One benchmark step is one pass of the whole path over the grid: initial
-states on the GPU (pn_init_state) and the fused scan (pn_fli_scan).
+states on the GPU (pn_init_state) and the fused scan (pn_fli_scan_balanced:
+the plain fused scan for this grid; full-chip grids such as 314 x 314 whose
+orbits fill a last round of resident wavefronts only partly take the balanced
+wrap-around schedule instead).
 
 Prints one JSON line.  value = orbit-steps per second (an orbit-step advances
 one orbit and its shadow by h, with both corrections and the FLI update).
@@ -37,7 +40,7 @@ KERNEL_SOURCES = ["paper_1802_00147_amd/csrc/pn_kernels.hip", "paper_1802_00147_
 # grid64 launch: FETCH_SIZE 365.125 KiB x 1.999923 (a 1 GiB copy reads 524,308.25
 # KiB) + WRITE_SIZE 548.0 KiB x 1.0 (the copy writes 1,048,576 KiB).
 TRAFFIC = dict(workload="grid64", bytes_per_launch=753508 + 593920,
-               sources_sha256="d528492dba44ef6f5f2dedb52141f05d6a128ac11f32cefc6c94d2445ebf5a3c")
+               sources_sha256="f74f4d532eb8c3ce8d34b073ef8b512ac29abfef2e625702c72af1d51c4b3b2f")
 
 
 def sources_sha256():
@@ -518,6 +521,16 @@ def main():
     as_dev = (lambda v: torch.as_tensor(v, device=dev) if isinstance(v, np.ndarray) else v)
     beta, chi1, chi2, t_end = as_dev(wl.beta), as_dev(wl.chi1), as_dev(wl.chi2), as_dev(wl.t_end)
     kernel = "k_fli_scan<RK4,SIX>"
+    sched, bws = None, None
+    if not batched:
+        # Equal-length grids: the balanced schedule where the library predicts
+        # it faster than the plain fused scan (full-chip grids whose resident
+        # rounds do not divide evenly), else the plain scan.
+        sched = pn.balanced_schedule(n, float(wl.t_end))
+        if sched["launches"] > 0:
+            bws = pn.balanced_workspace(sched["slots"], dev)
+            kernel = (f"k_wrap_scan<RK4,SIX> (balanced: {sched['slots']} slots x {sched['slot_len']} steps, "
+                      f"{sched['launches']} launches)")
     if batched:
         ws = pn.batch_workspace(n, dev)
         y = pn.init_state(cols["r0"], cols["p0"], cols["th1"], cols["ph1"], cols["th2"], cols["ph2"],
@@ -534,7 +547,7 @@ def main():
         if batched:
             pn.batch_scan(y, t_end, beta, chi1, chi2, model=wl.model, out=out, ws=ws)
         else:
-            pn.fli_scan(y, t_end, beta, chi1, chi2, model=wl.model, out=out)
+            pn.fli_scan_balanced(y, float(t_end), beta, chi1, chi2, model=wl.model, out=out, ws=bws)
         if ev is not None:
             ev[1].record(stream)
         return y
@@ -566,13 +579,16 @@ def main():
     line["grid_pts_per_s"] = n * args.steps / elapsed
     line["chaotic_fraction"] = float(np.mean(labels == 1))
     line["invalid_orbits"] = int(np.sum((status & 0xFF) != 0))
+    simds = 4 * torch.cuda.get_device_properties(dev).multi_processor_count
+    balanced = sched is not None and sched["launches"] > 0
     if not batched:
-        # Latency view of one launch: time per step of the time loop and the
-        # share of the chip's SIMDs the trajectories can occupy.
-        waves = (2 * n + 63) // 64
-        simds = 4 * torch.cuda.get_device_properties(dev).multi_processor_count
+        # Latency view: time per step of the time loop and the share of the
+        # chip's SIMDs the trajectories can occupy.
+        waves = (sched["slots"] + 31) // 32 if balanced else (2 * n + 63) // 64
         line["latency"] = dict(us_per_step=1e3 * kernel_ms / float(np.max(wl.t_end)), wavefronts=waves,
                                simd_fraction=min(1.0, waves / simds))
+        if balanced:
+            line["config"]["schedule"] = dict(kind="balanced", **sched)
 
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, args.cpu_sample)
@@ -595,9 +611,13 @@ def main():
             # Registers, spills and occupancy of the scan kernel as the
             # runtime reports them, and the wavefronts per SIMD the launch
             # actually keeps resident.
-            res = pn.scan_kernel_resources()
-            simds = 4 * torch.cuda.get_device_properties(dev).multi_processor_count
-            res["achieved_waves_per_simd"] = min(float(res["waves_per_simd"]), ((2 * n + 63) // 64) / simds)
+            if balanced:
+                res = pn.balanced_kernel_resources()
+                res["achieved_waves_per_simd"] = min(float(res["waves_per_simd"]),
+                                                     ((sched["slots"] + 31) // 32) / simds)
+            else:
+                res = pn.scan_kernel_resources()
+                res["achieved_waves_per_simd"] = min(float(res["waves_per_simd"]), ((2 * n + 63) // 64) / simds)
             line["roofline"]["resources"] = res
     print(json.dumps(line), flush=True)
 

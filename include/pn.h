@@ -246,6 +246,74 @@ pn_status pn_fli_scan(const pn_model* model, pn_params params, const pn_integrat
                       const pn_scan_out* out, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Balanced scan of a grid whose orbits all integrate to the same end time
+ * (the scans of Sec. 3C and Table 3).  Same computation and outputs as
+ * pn_fli_scan, bit for bit; only the schedule differs.  With S steps per
+ * orbit, the n orbits laid end to end form a tape of n S steps, and each of
+ * P slots (an orbit pair of lanes) integrates a stretch of C >= n S / P steps
+ * of it.  An orbit cut by the boundary between slots s and s + 1 is split as
+ * in McNaughton's wrap-around rule: slot s + 1 integrates its first steps at
+ * the start of its stretch and saves the pair state in the workspace, and
+ * slot s integrates the rest, from that state, at the end of its stretch.
+ * The stretches run in L launches of ceil(C / L) steps each; C - S >=
+ * ceil(C / L) puts the two parts of every split orbit in different launches,
+ * so no lane ever waits for another.  With P equal to the resident orbit
+ * pairs of the device, every SIMD carries the same work, where the plain scan
+ * of n > P equal orbits leaves a last round of resident wavefronts partly
+ * filled.
+ * ------------------------------------------------------------------------- */
+
+/* Host-only plan: slot length C and launch count L for n orbits of `steps`
+ * steps on `slots` slots.  C is the smallest length >= n steps / slots, raised
+ * to steps + ceil(steps / 15) when smaller (the last slots then stay empty);
+ * L is the smallest count in 2..16 with C - steps >= ceil(C / L).  PN_EINVAL
+ * for n, steps or slots <= 0, slots > 2^24, n steps or slots C above 2^62. */
+pn_status pn_balanced_plan(int64_t n, int64_t steps, int64_t slots, int64_t* slot_len, int32_t* launches);
+
+/* Host-only: the piece that slot `slot` integrates at slot time tau of its
+ * stretch (0 <= tau < its length, min(C, n steps - slot C)): steps
+ * [*first_step, *end_step) of orbit *orbit, starting at slot time *start.
+ * A piece with *first_step = 0 and *end_step < steps is the first part of a
+ * split orbit (only ever at *start = 0), one with *first_step > 0 its second
+ * part (the last piece of the stretch).  PN_EINVAL outside those ranges or
+ * for slot_len <= steps. */
+pn_status pn_balanced_piece(int64_t n, int64_t steps, int64_t slot_len, int64_t slot, int64_t tau,
+                            int64_t* orbit, int64_t* first_step, int64_t* end_step, int64_t* start);
+
+/* The schedule pn_fli_scan_balanced takes for n orbits to t_end_all:
+ * *slots_used = P, *slot_len = C, *launches = L (outputs nullable).
+ * slots = 0: P is the number of orbit pairs the balanced kernel keeps resident
+ * on the current device, and the balanced schedule is taken only where its
+ * predicted time (resident wavefronts per SIMD x C steps) is at least 2% below
+ * the plain scan's (rounds of resident wavefronts x S steps); otherwise L = 0
+ * and the call runs pn_fli_scan's kernel.  slots > 0: that many slots, always
+ * balanced (for tests of the schedule; slots beyond residency simply run
+ * later).  L = 0 also when n = 0 or S = 0.  PN_EINVAL for invalid arguments
+ * or slots > 0 without a plan; PN_EDEVICE when slots = 0 and no device. */
+pn_status pn_fli_scan_balanced_schedule(const pn_integrator* integ, const pn_correction* corr, int64_t n,
+                                        double t_end_all, int64_t slots, int64_t* slots_used,
+                                        int64_t* slot_len, int32_t* launches);
+
+/* Bytes of workspace for a balanced scan on `slots` slots (the *slots_used of
+ * pn_fli_scan_balanced_schedule): two tables of one pair record per slot,
+ * about 320 bytes each.  0 for slots outside 1..2^24. */
+size_t pn_fli_scan_balanced_workspace_size(int64_t slots);
+
+/* pn_fli_scan of n orbits that all end at t_end_all, on the schedule
+ * pn_fli_scan_balanced_schedule describes.  ws: device workspace of at least
+ * pn_fli_scan_balanced_workspace_size(P) bytes, owned by the caller, contents
+ * on entry irrelevant (the call first marks its records empty); may be NULL
+ * when the schedule is the plain scan (L = 0).  Calls that share a workspace
+ * must not overlap.  A saved part that is missing or names another orbit
+ * (impossible with the planned launches) gives that orbit
+ * PN_ORBIT_BADPARAM.  Errors as pn_fli_scan, plus PN_ENOWS for a short
+ * workspace and the errors of pn_fli_scan_balanced_schedule. */
+pn_status pn_fli_scan_balanced(const pn_model* model, pn_params params, const pn_integrator* integ,
+                               const pn_correction* corr, const pn_fli_cfg* fli, int64_t n,
+                               const double* y0, int64_t ld, double t_end_all, const pn_scan_out* out,
+                               int64_t slots, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Trajectories and gravitational waves (Sec. 4, eq. 14).
  * ------------------------------------------------------------------------- */
 
@@ -302,6 +370,11 @@ size_t pn_batch_workspace_size(int64_t n);
  * mode, PN_EDEVICE without a device. */
 pn_status pn_scan_kernel_resources(int32_t method, int32_t mode, int32_t* vgprs, int64_t* scratch_bytes,
                                    int32_t* waves_per_simd);
+
+/* The same figures for the balanced scan's kernel (pn_fli_scan_balanced),
+ * whose workgroups are 256 lanes (four wavefronts). */
+pn_status pn_balanced_kernel_resources(int32_t method, int32_t mode, int32_t* vgprs, int64_t* scratch_bytes,
+                                       int32_t* waves_per_simd);
 
 /* Orbit pairs a pn_batch_scan launch keeps resident on the current device
  * with this tuning (NULL: the one pn_batch_scan would use): a batch of that

@@ -279,6 +279,13 @@ struct PairState {
     bool any_nc;
 };
 
+// End time and step count of orbit i, from the inputs.
+__device__ __forceinline__ void pair_ends(PairState& ps, const FliArgs& fa, int64_t i) {
+    ps.t_end = fa.t_end ? fa.t_end[i] : fa.t_end_all;
+    ps.nsteps = ps.t_end > 0.0 ? (int64_t)ceil(ps.t_end / fa.h) : 0;
+    if (fa.step_scale != 1.0) ps.nsteps = (int64_t)ceil((double)ps.nsteps * fa.step_scale);
+}
+
 // Separation of the pair, computed identically in both lanes: the lanes form
 // e and -e exactly, so e * e and the sum carry the same bits.
 __device__ __forceinline__ double pair_d2(const double* y) {
@@ -302,9 +309,7 @@ __device__ __forceinline__ void pair_begin(PairState& ps, const PnCoef& k, bool 
         for (int c = 0; c < 12; ++c) ps.y[c] += (c == fa.shadow_axis) ? fa.d0 : 0.0;
     }
     capture_ref(k, ps.y, ps.ref);
-    ps.t_end = fa.t_end ? fa.t_end[i] : fa.t_end_all;
-    ps.nsteps = ps.t_end > 0.0 ? (int64_t)ceil(ps.t_end / fa.h) : 0;
-    if (fa.step_scale != 1.0) ps.nsteps = (int64_t)ceil((double)ps.nsteps * fa.step_scale);
+    pair_ends(ps, fa, i);
     int st = param_ok ? pn_validity(ps.y, fa.rmerge2, fa.resc2) : PN_ORBIT_BADPARAM;
     if (st == PN_ORBIT_OK && !(ps.ref[0] < 0.0)) st = PN_ORBIT_UNBOUND_INIT;
     const int other = swap_pair_i32(st);
@@ -468,65 +473,69 @@ __global__ __launch_bounds__(256) void k_batch_bin_scatter(BatchWs ws, const dou
     ws.order[pos] = (int32_t)i;
 }
 
+// A table of saved orbit pairs: record r holds the orbit index and the exact
+// state of lanes 2 r (orbit) and 2 r + 1 (shadow).
+struct RecTable {
+    int32_t* id;                    // [cap] orbit index
+    double* y;                      // [12][2 cap]
+    double* ref;                    // [4][2 cap]
+    double* acc;                    // [2 cap]
+    int64_t* t;                     // [2 cap]
+    int64_t* renorms;               // [2 cap]
+    int32_t* nmax;                  // [2 cap]
+    int32_t* flags;                 // [2 cap]: status | any_nc << 16
+    int64_t cap;                    // records
+};
+
+__device__ __forceinline__ void rec_save(const RecTable& T, int64_t r, const PairState& ps, bool shadow,
+                                         int64_t cur) {
+    const int64_t w = 2 * r + (shadow ? 1 : 0), L = 2 * T.cap;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) T.y[c * L + w] = ps.y[c];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) T.ref[c * L + w] = ps.ref[c];
+    T.acc[w] = ps.acc;
+    T.t[w] = ps.t;
+    T.renorms[w] = ps.renorms;
+    T.nmax[w] = ps.nmax;
+    T.flags[w] = ps.st | (ps.any_nc ? (1 << 16) : 0);
+    if (!shadow) T.id[r] = (int32_t)cur;
+}
+
+// Restores what rec_save kept; returns the orbit index of the record (-1 if
+// it names no orbit of this scan).
+__device__ __forceinline__ int64_t rec_load(const RecTable& T, int64_t r, PairState& ps, bool shadow,
+                                            const FliArgs& fa) {
+    const int64_t w = 2 * r + (shadow ? 1 : 0), L = 2 * T.cap;
+    const int64_t i = T.id[r];
+    if (i < 0 || i >= fa.n) return -1;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) ps.y[c] = T.y[c * L + w];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ps.ref[c] = T.ref[c * L + w];
+    ps.acc = T.acc[w];
+    ps.t = T.t[w];
+    ps.renorms = T.renorms[w];
+    ps.nmax = T.nmax[w];
+    const int f = T.flags[w];
+    ps.st = f & 0xFFFF;
+    ps.any_nc = (f >> 16) != 0;
+    ps.d2 = 0.0;
+    pair_ends(ps, fa, i);
+    return i;
+}
+
 // Checkpoint of an interrupted batch scan: the exact state of every orbit in
 // flight, one record per orbit pair in each of two tables (the one a launch
-// resumes from and the one it saves into, swapped after every launch).  Lane
-// arrays hold two entries per record (2 r + 0 orbit, 2 r + 1 shadow).
+// resumes from and the one it saves into, swapped after every launch).
 // hdr: [0], [1] records in table 0 / 1; [2] read cursor of the input table;
 // [3] index of the input table.
 struct CkptArgs {
     unsigned long long* hdr;
-    int32_t* id[2];                 // [cap] orbit index
-    double* y[2];                   // [12][2 cap]
-    double* ref[2];                 // [4][2 cap]
-    double* acc[2];                 // [2 cap]
-    int64_t* t[2];                  // [2 cap]
-    int64_t* renorms[2];            // [2 cap]
-    int32_t* nmax[2];               // [2 cap]
-    int32_t* flags[2];              // [2 cap]: status | any_nc << 16
+    RecTable tab[2];
     int64_t cap;                    // records per table
     int32_t max_chunks;             // chunks per wavefront before it saves and leaves; 0: run to the end
 };
-
-__device__ __forceinline__ void ckpt_save(const CkptArgs& ck, int tab, unsigned long long r, const PairState& ps,
-                                          bool shadow, int64_t cur) {
-    const int64_t w = 2 * (int64_t)r + (shadow ? 1 : 0), L = 2 * ck.cap;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) ck.y[tab][c * L + w] = ps.y[c];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) ck.ref[tab][c * L + w] = ps.ref[c];
-    ck.acc[tab][w] = ps.acc;
-    ck.t[tab][w] = ps.t;
-    ck.renorms[tab][w] = ps.renorms;
-    ck.nmax[tab][w] = ps.nmax;
-    ck.flags[tab][w] = ps.st | (ps.any_nc ? (1 << 16) : 0);
-    if (!shadow) ck.id[tab][r] = (int32_t)cur;
-}
-
-// Restores what ckpt_save kept; the end time and step count are recomputed
-// from the inputs as pair_begin computes them.
-__device__ __forceinline__ int64_t ckpt_load(const CkptArgs& ck, int tab, unsigned long long r, PairState& ps,
-                                             bool shadow, const FliArgs& fa) {
-    const int64_t w = 2 * (int64_t)r + (shadow ? 1 : 0), L = 2 * ck.cap;
-    const int64_t i = ck.id[tab][r];
-    if (i < 0 || i >= fa.n) return -1;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) ps.y[c] = ck.y[tab][c * L + w];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) ps.ref[c] = ck.ref[tab][c * L + w];
-    ps.acc = ck.acc[tab][w];
-    ps.t = ck.t[tab][w];
-    ps.renorms = ck.renorms[tab][w];
-    ps.nmax = ck.nmax[tab][w];
-    const int f = ck.flags[tab][w];
-    ps.st = f & 0xFFFF;
-    ps.any_nc = (f >> 16) != 0;
-    ps.d2 = 0.0;
-    ps.t_end = fa.t_end ? fa.t_end[i] : fa.t_end_all;
-    ps.nsteps = ps.t_end > 0.0 ? (int64_t)ceil(ps.t_end / fa.h) : 0;
-    if (fa.step_scale != 1.0) ps.nsteps = (int64_t)ceil((double)ps.nsteps * fa.step_scale);
-    return i;
-}
 
 // Persistent kernel: every wavefront keeps 32 orbit slots busy.  Between
 // chunks of `chunk` steps, pairs whose orbit has ended write its results and
@@ -570,7 +579,7 @@ __global__ __launch_bounds__(256, OCC) void k_batch_scan(ParamArgs pa, FliArgs f
                     const int even = lane & ~1;
                     const unsigned long long r = base + __popcll(m & ((1ull << even) - 1ull));
                     if (r < saved) {
-                        const int64_t i = ckpt_load(ck, tin, r, ps, shadow, fa);
+                        const int64_t i = rec_load(ck.tab[tin], (int64_t)r, ps, shadow, fa);
                         if (i >= 0 && i < fa.n) {
                             cur = i;
                             load_coef(pa, cur, k);
@@ -626,7 +635,7 @@ __global__ __launch_bounds__(256, OCC) void k_batch_scan(ParamArgs pa, FliArgs f
                 if (keep) {
                     const int even = lane & ~1;
                     const unsigned long long r = base + __popcll(m & ((1ull << even) - 1ull));
-                    if (r < (unsigned long long)ck.cap) ckpt_save(ck, tout, r, ps, shadow, cur);
+                    if (r < (unsigned long long)ck.cap) rec_save(ck.tab[tout], (int64_t)r, ps, shadow, cur);
                 }
             }
             break;
@@ -647,18 +656,20 @@ __global__ __launch_bounds__(256) void k_ckpt_carry(CkptArgs ck) {
     // the bound below only keeps a corrupted header inside them.
     const unsigned long long left = (saved - rd) < (cap - base) ? (saved - rd) : (cap - base);
     const int64_t L = 2 * ck.cap;
+    const RecTable& I = ck.tab[tin];
+    const RecTable& O = ck.tab[tout];
     for (unsigned long long r = rd + threadIdx.x; r < rd + left; r += 256) {
         const unsigned long long d = base + (r - rd);
-        ck.id[tout][d] = ck.id[tin][r];
+        O.id[d] = I.id[r];
         for (int h = 0; h < 2; ++h) {
             const int64_t a = 2 * (int64_t)r + h, b = 2 * (int64_t)d + h;
-            for (int c = 0; c < 12; ++c) ck.y[tout][c * L + b] = ck.y[tin][c * L + a];
-            for (int c = 0; c < 4; ++c) ck.ref[tout][c * L + b] = ck.ref[tin][c * L + a];
-            ck.acc[tout][b] = ck.acc[tin][a];
-            ck.t[tout][b] = ck.t[tin][a];
-            ck.renorms[tout][b] = ck.renorms[tin][a];
-            ck.nmax[tout][b] = ck.nmax[tin][a];
-            ck.flags[tout][b] = ck.flags[tin][a];
+            for (int c = 0; c < 12; ++c) O.y[c * L + b] = I.y[c * L + a];
+            for (int c = 0; c < 4; ++c) O.ref[c * L + b] = I.ref[c * L + a];
+            O.acc[b] = I.acc[a];
+            O.t[b] = I.t[a];
+            O.renorms[b] = I.renorms[a];
+            O.nmax[b] = I.nmax[a];
+            O.flags[b] = I.flags[a];
         }
     }
     __syncthreads();
@@ -672,6 +683,143 @@ __global__ __launch_bounds__(256) void k_ckpt_carry(CkptArgs ck) {
 
 __global__ void k_ckpt_clear(CkptArgs ck) {
     if (threadIdx.x < 4) ck.hdr[threadIdx.x] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// Balanced scan of orbits that all take S steps.  Laid end to end, the n
+// orbits form a tape of n S steps; slot s (one orbit pair of lanes) owns the
+// stretch [s C, (s + 1) C) of it, so every slot carries the same work.  An
+// orbit cut by the boundary between slots s and s + 1 is split the way
+// McNaughton's wrap-around rule splits a preempted job: slot s + 1 integrates
+// its first steps at the start of its stretch and saves the pair state
+// (record s + 1 of the split table); slot s integrates the remaining steps at
+// the end of its stretch, starting from that record.  The stretch runs in L
+// launches of c slot-time steps; with C - S >= c the first part of a split
+// orbit always ends in an earlier launch than the one in which its second part
+// starts, so records are read one launch or more after they are written and
+// no lane waits for another.  A piece cut by a launch boundary is saved in
+// the slot's record of the carry table and resumed by the next launch.
+// ---------------------------------------------------------------------------
+struct WrapPiece {
+    int64_t orbit;                  // orbit index
+    int64_t a, b;                   // the piece integrates steps [a, b) of the orbit
+    int64_t start;                  // slot time at which the piece starts
+};
+
+// The piece that slot s runs at slot time tau (0 <= tau < its stretch).
+__host__ __device__ inline WrapPiece wrap_piece(int64_t n, int64_t S, int64_t C, int64_t s, int64_t tau) {
+    const int64_t lo = s * C, total = n * S;
+    const int64_t hi = total - lo < C ? total : lo + C;
+    const int64_t j = (lo + tau) / S;
+    const int64_t o_lo = j * S, o_hi = o_lo + S;
+    const int64_t p_lo = o_lo > lo ? o_lo : lo, p_hi = o_hi < hi ? o_hi : hi;
+    WrapPiece p;
+    p.orbit = j;
+    p.start = p_lo - lo;
+    if (o_lo < lo) {                // begins in slot s - 1's stretch: run its first steps here
+        p.a = 0;
+        p.b = p_hi - p_lo;
+    } else if (o_hi > hi) {         // ends in slot s + 1's stretch: run its last steps here
+        p.a = S - (p_hi - p_lo);
+        p.b = S;
+    } else {
+        p.a = 0;
+        p.b = S;
+    }
+    return p;
+}
+
+struct WrapArgs {
+    int64_t steps;                  // S
+    int64_t slot_len;               // C
+    int64_t slots;                  // orbit pairs of the schedule
+    int64_t t0, t1;                 // slot-time window of this launch
+    int32_t chunk;                  // steps between checks for the end of a piece
+    RecTable carry, split;          // [slots] records each
+};
+
+// Where a piece's starting state comes from.
+constexpr int kFromInputs = 0, kFromCarry = 1, kFromSplit = 2;
+
+// Opens piece p in this pair: from the inputs when it starts at step 0, else
+// from record r of the carry or split table.  A record that does not hold
+// orbit p.orbit at step t_at (or stopped earlier with a final status) cannot
+// occur under a valid plan; the orbit then reports PN_ORBIT_BADPARAM.
+__device__ __forceinline__ void wrap_open(PairState& ps, PnCoef& k, const ParamArgs& pa, const FliArgs& fa,
+                                          const WrapArgs& wa, int from, int64_t r, const WrapPiece& p,
+                                          int64_t t_at, bool shadow) {
+    const bool ok = load_coef(pa, p.orbit, k);
+    if (from == kFromInputs) {
+        pair_begin(ps, k, ok, shadow, fa, p.orbit);
+        return;
+    }
+    const int64_t i = from == kFromCarry ? rec_load(wa.carry, r, ps, shadow, fa)
+                                         : rec_load(wa.split, r, ps, shadow, fa);
+    const bool match = i == p.orbit && (ps.st == PN_ORBIT_OK ? ps.t == t_at : ps.t <= t_at);
+    if (!match) {
+        pair_ends(ps, fa, p.orbit);
+        ps.st = PN_ORBIT_BADPARAM;
+    }
+}
+
+template <int METHOD, int MODE, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_wrap_scan(ParamArgs pa, FliArgs fa, WrapArgs wa) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t s = g >> 1;
+    const bool shadow = (g & 1) != 0;
+    const int64_t S = wa.steps, C = wa.slot_len;
+    const int64_t total = fa.n * S;
+    int64_t len = 0;
+    if (s < wa.slots && s * C < total) len = total - s * C < C ? total - s * C : C;
+    const int64_t tend = wa.t1 < len ? wa.t1 : len;    // this launch ends the slot's work at tend
+    int64_t tau = wa.t0;                               // slot time of the next piece to open
+    bool active = tau < tend, open = active;
+    int64_t orbit = 0, b = 0, pend = 0;                // open piece: orbit, last step + 1, end time
+    PnCoef k;
+    PairState ps;
+    for (;;) {
+        if (__ballot(active) == 0ull) break;
+        if (open) {
+            const WrapPiece p = wrap_piece(fa.n, S, C, s, tau);
+            orbit = p.orbit;
+            b = p.b;
+            pend = p.start + (p.b - p.a);
+            if (p.start < tau)          // cut by the previous launch's end
+                wrap_open(ps, k, pa, fa, wa, kFromCarry, s, p, p.a + (tau - p.start), shadow);
+            else
+                wrap_open(ps, k, pa, fa, wa, p.a > 0 ? kFromSplit : kFromInputs, s + 1, p, p.a, shadow);
+            open = false;
+        }
+        if (active) {
+            // Steps left in this launch: up to b, less what lies past tend.
+            const int64_t stop = pend <= tend ? b : b - (pend - tend);
+            for (int c = 0; c < wa.chunk && ps.st == PN_ORBIT_OK && ps.t < stop; ++c)
+                pair_step<METHOD, MODE>(ps, k, shadow, fa, orbit);
+            if (!(ps.st == PN_ORBIT_OK && ps.t < stop)) {
+                if (pend > tend) {
+                    rec_save(wa.carry, s, ps, shadow, orbit);
+                    active = false;
+                } else {
+                    if (b == S)
+                        pair_finish(ps, k, shadow, fa, orbit);
+                    else
+                        rec_save(wa.split, s, ps, shadow, orbit);      // first part of a split orbit
+                    tau = pend;
+                    active = open = pend < tend;
+                }
+            }
+        }
+    }
+}
+
+// Marks every record of both tables empty before the first launch, so that a
+// workspace's earlier contents can never be taken for this scan's records.
+__global__ __launch_bounds__(256) void k_wrap_clear(WrapArgs wa) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r < wa.slots) {
+        wa.carry.id[r] = -1;
+        wa.split.id[r] = -1;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -857,13 +1005,29 @@ constexpr int64_t kCkptMaxPairs = (int64_t)1 << 18;
 
 int64_t ckpt_cap(int64_t n) { return n < kCkptMaxPairs ? n : kCkptMaxPairs; }
 
-size_t ckpt_table_bytes(int64_t cap) {
+size_t rec_table_bytes(int64_t cap) {
     const size_t L = 2 * (size_t)cap;
     return align256((size_t)cap * 4) + align256(12 * L * 8) + align256(4 * L * 8) + 3 * align256(L * 8) +
            2 * align256(L * 4);
 }
 
-size_t ckpt_ws_bytes(int64_t n) { return batch_ws_bytes(n) + align256(4 * 8) + 2 * ckpt_table_bytes(ckpt_cap(n)); }
+// Carves one record table of cap records at b and advances b past it.
+RecTable carve_rec(char*& b, int64_t cap) {
+    RecTable T;
+    const size_t L = 2 * (size_t)cap;
+    T.cap = cap;
+    T.id = reinterpret_cast<int32_t*>(b);       b += align256((size_t)cap * 4);
+    T.y = reinterpret_cast<double*>(b);         b += align256(12 * L * 8);
+    T.ref = reinterpret_cast<double*>(b);       b += align256(4 * L * 8);
+    T.acc = reinterpret_cast<double*>(b);       b += align256(L * 8);
+    T.t = reinterpret_cast<int64_t*>(b);        b += align256(L * 8);
+    T.renorms = reinterpret_cast<int64_t*>(b);  b += align256(L * 8);
+    T.nmax = reinterpret_cast<int32_t*>(b);     b += align256(L * 4);
+    T.flags = reinterpret_cast<int32_t*>(b);    b += align256(L * 4);
+    return T;
+}
+
+size_t ckpt_ws_bytes(int64_t n) { return batch_ws_bytes(n) + align256(4 * 8) + 2 * rec_table_bytes(ckpt_cap(n)); }
 
 CkptArgs carve_ckpt(void* ws, int64_t n, int32_t max_chunks) {
     char* b = static_cast<char*>(ws) + batch_ws_bytes(n);
@@ -872,17 +1036,7 @@ CkptArgs carve_ckpt(void* ws, int64_t n, int32_t max_chunks) {
     ck.max_chunks = max_chunks;
     ck.hdr = reinterpret_cast<unsigned long long*>(b);
     b += align256(4 * 8);
-    const size_t L = 2 * (size_t)ck.cap;
-    for (int tab = 0; tab < 2; ++tab) {
-        ck.id[tab] = reinterpret_cast<int32_t*>(b);       b += align256((size_t)ck.cap * 4);
-        ck.y[tab] = reinterpret_cast<double*>(b);         b += align256(12 * L * 8);
-        ck.ref[tab] = reinterpret_cast<double*>(b);       b += align256(4 * L * 8);
-        ck.acc[tab] = reinterpret_cast<double*>(b);       b += align256(L * 8);
-        ck.t[tab] = reinterpret_cast<int64_t*>(b);        b += align256(L * 8);
-        ck.renorms[tab] = reinterpret_cast<int64_t*>(b);  b += align256(L * 8);
-        ck.nmax[tab] = reinterpret_cast<int32_t*>(b);     b += align256(L * 4);
-        ck.flags[tab] = reinterpret_cast<int32_t*>(b);    b += align256(L * 4);
-    }
+    for (int tab = 0; tab < 2; ++tab) ck.tab[tab] = carve_rec(b, ck.cap);
     return ck;
 }
 
@@ -985,6 +1139,144 @@ void enqueue_batch(int method, int mode, const ParamArgs& pa, const FliArgs& fa,
         launch_batch_m<PN_RK5>(mode, pa, fa, w, tu, ncu, ck, stream);
     if (ck) hipLaunchKernelGGL(k_ckpt_carry, dim3(1), dim3(256), 0, stream, *ck);
 }
+
+// Registers, private memory and resident wavefronts per SIMD of kernel f
+// launched with workgroups of `block` threads.
+pn_status func_resources(const char* what, const void* f, int block, int32_t* vgprs, int64_t* scratch_bytes,
+                         int32_t* waves_per_simd) {
+    hipFuncAttributes at;
+    hipError_t e = hipFuncGetAttributes(&at, f);
+    int blocks = 0;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, block, 0);
+    if (e != hipSuccess) {
+        set_error(what, e);
+        return PN_EDEVICE;
+    }
+    if (vgprs) *vgprs = at.numRegs;
+    if (scratch_bytes) *scratch_bytes = (int64_t)at.localSizeBytes;
+    if (waves_per_simd) *waves_per_simd = blocks * (block / 64) / 4;     // four SIMDs per CU
+    return PN_OK;
+}
+
+// Balanced scan: kernel per method and correction (RK4 keeps two resident
+// wavefronts per SIMD; the six-stage RK5 needs the registers of one).
+constexpr int32_t kWrapMaxLaunches = 16;
+constexpr int64_t kWrapMaxSlots = (int64_t)1 << 24;
+constexpr int64_t kWrapMaxTape = (int64_t)1 << 62;
+constexpr int32_t kWrapChunk = 256;
+
+template <int METHOD, int MODE>
+struct WrapK {
+    static constexpr int OCC = 1;
+    static const void* fn() { return reinterpret_cast<const void*>(&k_wrap_scan<METHOD, MODE, OCC>); }
+    static void launch(unsigned blocks, const ParamArgs& pa, const FliArgs& fa, const WrapArgs& wa,
+                       hipStream_t s) {
+        hipLaunchKernelGGL((k_wrap_scan<METHOD, MODE, OCC>), dim3(blocks), dim3(256), 0, s, pa, fa, wa);
+    }
+};
+
+const void* wrap_fn(int method, int mode) {
+    switch (method * 4 + mode) {
+        case 0: return WrapK<PN_RK4, PN_CORR_NONE>::fn();
+        case 1: return WrapK<PN_RK4, PN_CORR_SPIN>::fn();
+        case 2: return WrapK<PN_RK4, PN_CORR_SIX>::fn();
+        case 3: return WrapK<PN_RK4, PN_CORR_DUAL>::fn();
+        case 4: return WrapK<PN_RK5, PN_CORR_NONE>::fn();
+        case 5: return WrapK<PN_RK5, PN_CORR_SPIN>::fn();
+        case 6: return WrapK<PN_RK5, PN_CORR_SIX>::fn();
+        default: return WrapK<PN_RK5, PN_CORR_DUAL>::fn();
+    }
+}
+
+void wrap_launch(int method, int mode, unsigned blocks, const ParamArgs& pa, const FliArgs& fa,
+                 const WrapArgs& wa, hipStream_t s) {
+    switch (method * 4 + mode) {
+        case 0: WrapK<PN_RK4, PN_CORR_NONE>::launch(blocks, pa, fa, wa, s); break;
+        case 1: WrapK<PN_RK4, PN_CORR_SPIN>::launch(blocks, pa, fa, wa, s); break;
+        case 2: WrapK<PN_RK4, PN_CORR_SIX>::launch(blocks, pa, fa, wa, s); break;
+        case 3: WrapK<PN_RK4, PN_CORR_DUAL>::launch(blocks, pa, fa, wa, s); break;
+        case 4: WrapK<PN_RK5, PN_CORR_NONE>::launch(blocks, pa, fa, wa, s); break;
+        case 5: WrapK<PN_RK5, PN_CORR_SPIN>::launch(blocks, pa, fa, wa, s); break;
+        case 6: WrapK<PN_RK5, PN_CORR_SIX>::launch(blocks, pa, fa, wa, s); break;
+        default: WrapK<PN_RK5, PN_CORR_DUAL>::launch(blocks, pa, fa, wa, s); break;
+    }
+}
+
+// Slot length C and launch count L of the balanced schedule of n orbits of S
+// steps on P slots: C >= n S / P, and C - S >= ceil(C / L) so that the two
+// parts of every split orbit fall in different launches.  C is raised to
+// S + ceil(S / 15) when n S / P is smaller (the last slots then stay empty),
+// which keeps L <= 16.
+bool wrap_plan(int64_t n, int64_t S, int64_t P, int64_t& C, int32_t& L) {
+    if (n <= 0 || S <= 0 || P <= 0 || P > kWrapMaxSlots) return false;
+    if (n > kWrapMaxTape / S) return false;
+    const int64_t total = n * S;
+    C = total / P + (total % P != 0 ? 1 : 0);
+    const int64_t cmin = S + (S + kWrapMaxLaunches - 2) / (kWrapMaxLaunches - 1);
+    if (C < cmin) C = cmin;
+    if (C > kWrapMaxTape / P) return false;
+    for (L = 2; L <= kWrapMaxLaunches; ++L) {
+        const int64_t c = C / L + (C % L != 0 ? 1 : 0);
+        if (C - S >= c) return true;
+    }
+    return false;
+}
+
+// Orbit pairs the balanced kernel keeps resident on the current device (a
+// full grid of them places the same number of wavefronts on every SIMD).
+int64_t wrap_resident_pairs(int method, int mode, int64_t* waves_per_simd) {
+    int dev = 0;
+    const int ncu = device_cus(dev);
+    if (ncu <= 0) return 0;
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, wrap_fn(method, mode), 256, 0) != hipSuccess ||
+        blocks <= 0)
+        return 0;
+    if (waves_per_simd) *waves_per_simd = blocks;   // four wavefronts per workgroup, one per SIMD
+    return (int64_t)ncu * blocks * 128;
+}
+
+int64_t steps_of(double t_end_all, double h) { return t_end_all > 0.0 ? (int64_t)ceil(t_end_all / h) : 0; }
+
+// Schedule of pn_fli_scan_balanced: slots P, slot length C, launches L
+// (L = 0: the plain fused scan).  With slots = 0 the device's resident pairs
+// are used and the balanced schedule is taken only where its predicted time
+// (wavefronts per SIMD x C) is at least 2% below the plain scan's (rounds of
+// resident wavefronts x S); slots > 0 always takes it.
+pn_status wrap_choose(int method, int mode, int64_t n, int64_t S, int64_t slots, int64_t& P, int64_t& C,
+                      int32_t& L) {
+    C = 0;
+    L = 0;
+    P = slots;
+    if (slots < 0 || slots > kWrapMaxSlots) return PN_EINVAL;
+    int64_t W = 0;
+    if (slots == 0) {
+        P = wrap_resident_pairs(method, mode, &W);
+        if (P <= 0) {
+            set_error("pn_fli_scan_balanced", hipErrorNoDevice);
+            return PN_EDEVICE;
+        }
+    }
+    if (n == 0 || S == 0) return PN_OK;
+    if (!wrap_plan(n, S, P, C, L)) {
+        C = 0;
+        L = 0;
+        return slots > 0 ? PN_EINVAL : PN_OK;
+    }
+    if (slots == 0) {
+        const int64_t simds = P / (32 * W);
+        const int64_t waves = (2 * n + 63) / 64;
+        const double plain = (double)((waves + simds - 1) / simds) * (double)S;
+        const double wrap = (double)W * (double)C;
+        if (!(wrap * 1.02 < plain)) {
+            C = 0;
+            L = 0;
+        }
+    }
+    return PN_OK;
+}
+
+size_t wrap_ws_bytes(int64_t P) { return 2 * rec_table_bytes(P); }
 
 }  // namespace
 
@@ -1209,6 +1501,95 @@ pn_status pn_fli_scan(const pn_model* model, pn_params params, const pn_integrat
     return launched("pn_fli_scan");
 }
 
+pn_status pn_balanced_plan(int64_t n, int64_t steps, int64_t slots, int64_t* slot_len, int32_t* launches) {
+    PN_REQUIRE(slot_len != nullptr && launches != nullptr);
+    int64_t C = 0;
+    int32_t L = 0;
+    PN_REQUIRE(wrap_plan(n, steps, slots, C, L));
+    *slot_len = C;
+    *launches = L;
+    return PN_OK;
+}
+
+pn_status pn_balanced_piece(int64_t n, int64_t steps, int64_t slot_len, int64_t slot, int64_t tau,
+                            int64_t* orbit, int64_t* first_step, int64_t* end_step, int64_t* start) {
+    PN_REQUIRE(orbit && first_step && end_step && start);
+    PN_REQUIRE(n > 0 && steps > 0 && n <= kWrapMaxTape / steps && slot_len > steps && slot >= 0);
+    const int64_t total = n * steps;
+    PN_REQUIRE(slot <= total / slot_len && slot * slot_len < total);
+    const int64_t len = total - slot * slot_len < slot_len ? total - slot * slot_len : slot_len;
+    PN_REQUIRE(tau >= 0 && tau < len);
+    const WrapPiece p = wrap_piece(n, steps, slot_len, slot, tau);
+    *orbit = p.orbit;
+    *first_step = p.a;
+    *end_step = p.b;
+    *start = p.start;
+    return PN_OK;
+}
+
+pn_status pn_fli_scan_balanced_schedule(const pn_integrator* integ, const pn_correction* corr, int64_t n,
+                                        double t_end_all, int64_t slots, int64_t* slots_used,
+                                        int64_t* slot_len, int32_t* launches) {
+    PN_REQUIRE(check_integ(integ) == PN_OK && corr != nullptr && check_corr(corr) == PN_OK);
+    PN_REQUIRE(n >= 0 && n <= kMaxN && t_end_all >= 0.0 && is_fin(t_end_all) && t_end_all / integ->h < 4.0e18);
+    int64_t P = 0, C = 0;
+    int32_t L = 0;
+    const pn_status st = wrap_choose(integ->method, corr->mode, n, steps_of(t_end_all, integ->h), slots, P, C, L);
+    if (st != PN_OK) return st;
+    if (slots_used) *slots_used = P;
+    if (slot_len) *slot_len = C;
+    if (launches) *launches = L;
+    return PN_OK;
+}
+
+size_t pn_fli_scan_balanced_workspace_size(int64_t slots) {
+    return slots > 0 && slots <= kWrapMaxSlots ? wrap_ws_bytes(slots) : 0;
+}
+
+pn_status pn_fli_scan_balanced(const pn_model* model, pn_params params, const pn_integrator* integ,
+                               const pn_correction* corr, const pn_fli_cfg* fli, int64_t n, const double* y0,
+                               int64_t ld, double t_end_all, const pn_scan_out* out, int64_t slots, void* ws,
+                               size_t ws_bytes, hipStream_t stream) {
+    ParamArgs pa;
+    FliArgs fa;
+    PN_REQUIRE(prepare_scan(model, params, integ, corr, fli, n, y0, ld, nullptr, t_end_all, out, pa, fa) ==
+               PN_OK);
+    PN_REQUIRE(t_end_all / integ->h < 4.0e18);
+    PN_REQUIRE(slots >= 0 && slots <= kWrapMaxSlots);
+    if (n == 0) return PN_OK;
+    const int64_t S = steps_of(t_end_all, integ->h);
+    int64_t P = 0, C = 0;
+    int32_t L = 0;
+    const pn_status st = wrap_choose(integ->method, corr->mode, n, S, slots, P, C, L);
+    if (st != PN_OK) return st;
+    if (L == 0) {
+        if (integ->method == PN_RK4)
+            launch_scan_m<PN_RK4>(corr->mode, pa, fa, stream);
+        else
+            launch_scan_m<PN_RK5>(corr->mode, pa, fa, stream);
+        return launched("pn_fli_scan_balanced");
+    }
+    if (ws == nullptr || ws_bytes < wrap_ws_bytes(P)) return PN_ENOWS;
+    WrapArgs wa;
+    char* b = static_cast<char*>(ws);
+    wa.carry = carve_rec(b, P);
+    wa.split = carve_rec(b, P);
+    wa.steps = S;
+    wa.slot_len = C;
+    wa.slots = P;
+    wa.chunk = kWrapChunk;
+    wa.t0 = wa.t1 = 0;
+    hipLaunchKernelGGL(k_wrap_clear, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, stream, wa);
+    const int64_t c = C / L + (C % L != 0 ? 1 : 0);
+    const unsigned blocks = (unsigned)((2 * P + 255) / 256);
+    for (int32_t l = 0; l < L; ++l) {
+        wa.t0 = l * c;
+        wa.t1 = (l + 1) * c < C ? (l + 1) * c : C;
+        wrap_launch(integ->method, corr->mode, blocks, pa, fa, wa, stream);
+    }
+    return launched("pn_fli_scan_balanced");
+}
+
 void pn_default_tuning(pn_tuning* t) {
     if (!t) return;
     t->block = 256;
@@ -1233,18 +1614,15 @@ pn_status pn_scan_kernel_resources(int32_t method, int32_t mode, int32_t* vgprs,
         case 6: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK5, PN_CORR_SIX>); break;
         default: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK5, PN_CORR_DUAL>); break;
     }
-    hipFuncAttributes at;
-    hipError_t e = hipFuncGetAttributes(&at, f);
-    int blocks = 0;
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, kBlock, 0);
-    if (e != hipSuccess) {
-        set_error("pn_scan_kernel_resources", e);
-        return PN_EDEVICE;
-    }
-    if (vgprs) *vgprs = at.numRegs;
-    if (scratch_bytes) *scratch_bytes = (int64_t)at.localSizeBytes;
-    if (waves_per_simd) *waves_per_simd = blocks / 4;     // one wavefront per workgroup, four SIMDs per CU
-    return PN_OK;
+    return func_resources("pn_scan_kernel_resources", f, kBlock, vgprs, scratch_bytes, waves_per_simd);
+}
+
+pn_status pn_balanced_kernel_resources(int32_t method, int32_t mode, int32_t* vgprs, int64_t* scratch_bytes,
+                                       int32_t* waves_per_simd) {
+    PN_REQUIRE(method == PN_RK4 || method == PN_RK5);
+    PN_REQUIRE(mode >= PN_CORR_NONE && mode <= PN_CORR_DUAL);
+    return func_resources("pn_balanced_kernel_resources", wrap_fn(method, mode), 256, vgprs, scratch_bytes,
+                          waves_per_simd);
 }
 
 int64_t pn_batch_resident_pairs(const pn_tuning* tuning) {

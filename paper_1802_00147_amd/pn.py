@@ -90,6 +90,8 @@ EXPORTS = ["pn_default_model", "pn_default_integrator", "pn_default_correction",
            "pn_mlp_train", "pn_fli_scan_workspace_size", "pn_shutdown",
            "pn_batch_ckpt_workspace_size", "pn_batch_scan_resumable", "pn_batch_scan_pending",
            "pn_batch_resident_pairs", "pn_scan_kernel_resources",
+           "pn_balanced_plan", "pn_balanced_piece", "pn_fli_scan_balanced_schedule",
+           "pn_fli_scan_balanced_workspace_size", "pn_fli_scan_balanced", "pn_balanced_kernel_resources",
            "pn_version", "pn_status_string", "pn_last_error"]
 
 
@@ -123,6 +125,8 @@ def lib():
         L.pn_batch_workspace_size.restype = ctypes.c_size_t
         L.pn_batch_workspace_size.argtypes = [ctypes.c_int64]
         L.pn_batch_resident_pairs.restype = ctypes.c_int64
+        L.pn_fli_scan_balanced_workspace_size.restype = ctypes.c_size_t
+        L.pn_fli_scan_balanced_workspace_size.argtypes = [ctypes.c_int64]
         L.pn_batch_ckpt_workspace_size.restype = ctypes.c_size_t
         L.pn_batch_ckpt_workspace_size.argtypes = [ctypes.c_int64]
         L.pn_graph_destroy.argtypes = [ctypes.c_void_p]
@@ -446,6 +450,82 @@ def scan_kernel_resources(integrator=None, correction=None):
                                         ctypes.byref(sc), ctypes.byref(w))
     _check("pn_scan_kernel_resources", st)
     return dict(vgprs=v.value, scratch_bytes=sc.value, waves_per_simd=w.value)
+
+
+def balanced_kernel_resources(integrator=None, correction=None):
+    """pn_balanced_kernel_resources: dict(vgprs, scratch_bytes, waves_per_simd)
+    of the balanced scan's kernel for this integrator and correction mode."""
+    integ = integrator_struct(integrator)
+    mode = correction_struct(correction).mode
+    v, w = ctypes.c_int32(0), ctypes.c_int32(0)
+    sc = ctypes.c_int64(0)
+    st = lib().pn_balanced_kernel_resources(ctypes.c_int32(integ.method), ctypes.c_int32(mode), ctypes.byref(v),
+                                            ctypes.byref(sc), ctypes.byref(w))
+    _check("pn_balanced_kernel_resources", st)
+    return dict(vgprs=v.value, scratch_bytes=sc.value, waves_per_simd=w.value)
+
+
+def balanced_plan(n, steps, slots):
+    """pn_balanced_plan (host only): (slot length C, launches L)."""
+    c, l = ctypes.c_int64(0), ctypes.c_int32(0)
+    st = lib().pn_balanced_plan(ctypes.c_int64(n), ctypes.c_int64(steps), ctypes.c_int64(slots), ctypes.byref(c),
+                                ctypes.byref(l))
+    _check("pn_balanced_plan", st)
+    return int(c.value), int(l.value)
+
+
+def balanced_piece(n, steps, slot_len, slot, tau):
+    """pn_balanced_piece (host only): (orbit, first_step, end_step, start)."""
+    v = [ctypes.c_int64(0) for _ in range(4)]
+    st = lib().pn_balanced_piece(ctypes.c_int64(n), ctypes.c_int64(steps), ctypes.c_int64(slot_len),
+                                 ctypes.c_int64(slot), ctypes.c_int64(tau), *[ctypes.byref(x) for x in v])
+    _check("pn_balanced_piece", st)
+    return tuple(int(x.value) for x in v)
+
+
+def balanced_schedule(n, t_end, integrator=None, correction=None, slots=0):
+    """pn_fli_scan_balanced_schedule: dict(slots, slot_len, launches); launches
+    0 means the plain fused scan runs."""
+    p, c, l = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int32(0)
+    st = lib().pn_fli_scan_balanced_schedule(ctypes.byref(integrator_struct(integrator)),
+                                             ctypes.byref(correction_struct(correction)), ctypes.c_int64(n),
+                                             ctypes.c_double(float(t_end)), ctypes.c_int64(slots),
+                                             ctypes.byref(p), ctypes.byref(c), ctypes.byref(l))
+    _check("pn_fli_scan_balanced_schedule", st)
+    return dict(slots=int(p.value), slot_len=int(c.value), launches=int(l.value))
+
+
+def balanced_workspace(slots, device):
+    nbytes = int(lib().pn_fli_scan_balanced_workspace_size(ctypes.c_int64(slots)))
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+def fli_scan_balanced(y0, t_end, beta, chi1, chi2, model=None, integrator=None, correction=None, fli=None,
+                      out=None, n=None, full=True, trace_every=0, slots=0, ws=None):
+    """pn_fli_scan_balanced: the fused scan of orbits that all end at t_end
+    (a float), on the balanced schedule (slots = 0: the device's resident
+    orbit pairs, balanced only where predicted faster).  Same outputs as
+    fli_scan, bit for bit."""
+    ld = _state(y0)
+    n = ld if n is None else n
+    integ = integrator_struct(integrator)
+    corr = correction_struct(correction)
+    t_end = float(t_end)
+    if out is None:
+        nmax = int(-(-t_end // integ.h)) if t_end > 0 else 0
+        out = scan_outputs(n, ld, y0.device, full=full, trace_every=trace_every, nsteps_max=nmax)
+    if ws is None:
+        sch = balanced_schedule(n, t_end, integrator, correction, slots)
+        ws = balanced_workspace(sch["slots"], y0.device) if sch["launches"] > 0 else None
+    so = _scan_out_struct(out)
+    p, keep = params_struct(beta, chi1, chi2)
+    st = lib().pn_fli_scan_balanced(ctypes.byref(model_struct(model)), p, ctypes.byref(integ), ctypes.byref(corr),
+                                    ctypes.byref(fli_struct(fli)), ctypes.c_int64(n), _ptr(y0), ctypes.c_int64(ld),
+                                    ctypes.c_double(t_end), ctypes.byref(so), ctypes.c_int64(slots),
+                                    _ptr(ws) if ws is not None else None,
+                                    ctypes.c_size_t(ws.numel() if ws is not None else 0), _stream(y0.device))
+    _check("pn_fli_scan_balanced", st)
+    return out
 
 
 def batch_scan_pending(ws, n):
