@@ -451,14 +451,16 @@ def surrogate_bench(args, dev):
         cb["unit"] = "grid-pts/s"
         cb["extrapolated_full_s"] = grid.n / cb["value"]   # plain scan of the whole grid, never run
         line["cpu_baseline"] = cb
-        # Dominant kernel of the assisted scan: the FP64 batch scan of the audit
-        # and of the uncertain points, timed by the call's own phase events
-        # (the phases also hold their small gather/sort kernels).
+        # Dominant kernel of the assisted scan: the FP64 integration of the
+        # audit and of the uncertain points (balanced schedule where predicted
+        # faster, else the plain fused scan), timed by the call's own phase
+        # events (the phases also hold their small gather/sort kernels).
         scan_s = res.timings["audit_s"] + res.timings["fallback_s"]
         achieved = fpos * res.integrated * grid.t_end / scan_s / 1e12
         line["roofline"] = dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
                                 frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=None,
-                                kernel="k_batch_scan<RK4,SIX> (audit + fallback phases of pn_surrogate_scan)",
+                                kernel="k_wrap_scan / k_fli_scan <RK4,SIX> (audit + fallback phases of "
+                                       "pn_surrogate_scan, through pn_fli_scan_balanced)",
                                 kernel_ms=1e3 * scan_s, flops_per_orbit_step=fpos)
         plain = fpos * len(idx) * grid.t_end / (plain_ms * 1e-3) / 1e12
         line["plain_roofline"] = dict(bound="alu", achieved=plain, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",

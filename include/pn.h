@@ -592,8 +592,11 @@ size_t pn_surrogate_scan_workspace_size(int64_t n, int32_t refine_batch);
 /* The surrogate-assisted scan (a12) of n points, end to end on the stream:
  *  1. features of every point (pn_mlp_features with mean/stdv);
  *  2. the audit sample (SplitMix64(seed + i) / 2^64 < audit_frac), sorted by
- *     point index, integrated by the persistent batch scan (pn_batch_scan,
- *     cached tuning);
+ *     point index, integrated: with t_end NULL (every point ends at
+ *     t_end_all) by pn_fli_scan_balanced on the device's resident slots
+ *     (the plain fused scan where that is predicted faster), else by the
+ *     persistent batch scan (pn_batch_scan, cached tuning); the same for
+ *     step 5 (all three give the same results bit for bit);
  *  3. refine_epochs passes of training (pn_mlp_train_step, Adam steps counted
  *     in *adam_step) on the valid audited orbits, in an order drawn from
  *     SplitMix64(refine_seed) (Fisher-Yates per epoch), when at least

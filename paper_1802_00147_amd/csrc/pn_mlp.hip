@@ -985,12 +985,21 @@ void pn_default_surrogate_cfg(pn_surrogate_cfg* c) {
     c->audit_split = 0;
 }
 
+// Records of the balanced integrations: min(n, 2^17) slots.  The balanced
+// schedule is only taken for at least as many points as the device keeps
+// orbit pairs resident, and 2^17 pairs is four wavefronts on every SIMD of
+// 256 CUs.
+static size_t wrap_region_bytes(int64_t n) {
+    const int64_t cap = (int64_t)1 << 17;
+    return pn_fli_scan_balanced_workspace_size(n < cap ? n : cap);
+}
+
 size_t pn_surrogate_scan_workspace_size(int64_t n, int32_t refine_batch) {
     if (n <= 0 || n > 0x7fffffffLL || refine_batch <= 0) return 0;
     const size_t N = (size_t)n;
     return 2 * al(N * kFeatLd * 4) + al(N * 2 * 4) + 3 * al(N * 4) + al(2 * 8) + al(12 * N * 8) + 4 * al(N * 8) +
            al(N * 8) + al(N) + al(N * 4) + 2 * al(N * 4) + al(4) + pn_batch_workspace_size(n) +
-           pn_mlp_train_workspace_size(refine_batch);
+           al(wrap_region_bytes(n)) + pn_mlp_train_workspace_size(refine_batch);
 }
 
 }  // extern "C"
@@ -1075,11 +1084,15 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
     float* tgtA = (float*)take(N * 4);
     float* loss = (float*)take(4);
     void* bws = take(pn_batch_workspace_size(n));
+    const size_t wrap_bytes = wrap_region_bytes(n);
+    void* wws = take(wrap_bytes);
     void* tws = take(pn_mlp_train_workspace_size(cfg->refine_batch));
     const bool per_orbit = params.beta != nullptr;
 
-    // Integrate the m listed points with the persistent batch kernel (a10),
-    // labels into slab[0..m).
+    // Integrate the m listed points, labels into slab[0..m): points that all
+    // end at t_end_all through the balanced scan (which keeps the plain fused
+    // scan where that is predicted faster), others with the persistent batch
+    // kernel (a10).
     auto integrate = [&](const int32_t* list, int64_t m) -> pn_status {
         PN_TRY(pn_init_state_gather(model, params, m, list, r0, p0, th1, ph1, th2, ph2, y0, m, stream));
         const unsigned g = blocks_for(m, 256);
@@ -1095,6 +1108,13 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
         pn_scan_out so;
         std::memset(&so, 0, sizeof(so));
         so.fli = sfli; so.label = slab; so.status = sstat;
+        if (t_end == nullptr) {
+            int64_t slots = 0;
+            PN_TRY(pn_fli_scan_balanced_schedule(integ, corr, m, t_end_all, 0, &slots, nullptr, nullptr));
+            if (pn_fli_scan_balanced_workspace_size(slots) <= wrap_bytes)
+                return pn_fli_scan_balanced(model, q, integ, corr, fli, m, y0, m, t_end_all, &so, 0, wws,
+                                            wrap_bytes, stream);
+        }
         return pn_batch_scan(model, q, integ, corr, fli, m, y0, m, gp[3], &so, nullptr, bws,
                              pn_batch_workspace_size(m), stream);
     };
