@@ -75,47 +75,88 @@ int stage_mode(const uint16_t* p, int64_t sr, int64_t sk) {
     return 0;
 }
 
-// Fill tile[64][LDSK] (row r, K offset c) with element (r0 + r, k0 + c) of
-// the operand, zero outside [0, R) x [0, K).
-__device__ __forceinline__ void stage_tile(uint16_t (*tile)[LDSK], const uint16_t* p, int64_t sr, int64_t sk,
-                                           int mode, int64_t r0, int64_t R, int64_t k0, int64_t K, int tid) {
+// K slices staged in LDS between two barriers: their global loads are all
+// in flight before the first LDS store, so a K range of 256 waits for memory
+// twice instead of eight times.
+constexpr int kStageSlices = 4;
+
+// One 16-byte chunk of a tile: this thread's part of slice (r0.., k0..) of
+// the operand whose element (r, k) sits at p[r * sr + k * sk], zero outside
+// [0, R) x [0, K).  Mode 1 gives 8 K values of one row (row tid / 4, K offset
+// 8 (tid % 4)); mode 2 gives 8 rows at one K (K offset tid / 8, rows
+// 8 (tid % 8) ..); see stage_mode.
+__device__ __forceinline__ uint4 load_chunk(const uint16_t* p, int64_t sr, int64_t sk, int mode, int64_t r0,
+                                            int64_t R, int64_t k0, int64_t K, int tid) {
+    union { uint4 v; uint16_t e[8]; } u;
     if (mode == 1) {
-        const int r = tid >> 2, c = (tid & 3) * 8;
-        const int64_t row = r0 + r, k = k0 + c;
-        union { uint4 v; uint16_t e[8]; } u;
+        const int64_t row = r0 + (tid >> 2), k = k0 + (tid & 3) * 8;
         if (row < R && k + 8 <= K) {
             u.v = *reinterpret_cast<const uint4*>(p + row * sr + k);
         } else {
 #pragma unroll
             for (int t = 0; t < 8; ++t) u.e[t] = (row < R && k + t < K) ? p[row * sr + (k + t)] : (uint16_t)0;
         }
-        *reinterpret_cast<uint4*>(&tile[r][c]) = u.v;
-    } else if (mode == 2) {
-        const int c = tid >> 3, r = (tid & 7) * 8;
-        const int64_t row = r0 + r, k = k0 + c;
-        union { uint4 v; uint16_t e[8]; } u;
+    } else {
+        const int64_t k = k0 + (tid >> 3), row = r0 + (tid & 7) * 8;
         if (k < K && row + 8 <= R) {
             u.v = *reinterpret_cast<const uint4*>(p + row + k * sk);
         } else {
 #pragma unroll
             for (int t = 0; t < 8; ++t) u.e[t] = (k < K && row + t < R) ? p[(row + t) + k * sk] : (uint16_t)0;
         }
+    }
+    return u.v;
+}
+
+// Writes a chunk from load_chunk into tile[64][LDSK] (mode 2 transposes it).
+__device__ __forceinline__ void store_chunk(uint16_t (*tile)[LDSK], uint4 v, int mode, int tid) {
+    if (mode == 1) {
+        *reinterpret_cast<uint4*>(&tile[tid >> 2][(tid & 3) * 8]) = v;
+    } else {
+        union { uint4 v; uint16_t e[8]; } u;
+        u.v = v;
+        const int c = tid >> 3, r = (tid & 7) * 8;
 #pragma unroll
         for (int t = 0; t < 8; ++t) tile[r + t][c] = u.e[t];
-    } else {
-#pragma unroll
-        for (int e = tid; e < 64 * BK; e += 256) {
-            const int r = e / BK, c = e % BK;
-            const int64_t row = r0 + r, k = k0 + c;
-            tile[r][c] = (row < R && k < K) ? p[row * sr + k * sk] : (uint16_t)0;
-        }
     }
 }
 
+// Fill tiles[s][64][LDSK], s < ns, with element (r0 + r, k0 + s BK + c) of
+// the operand (row r, K offset c), zero outside [0, R) x [0, K).
+__device__ __forceinline__ void stage_tiles(uint16_t (*tiles)[BM][LDSK], int ns, const uint16_t* p, int64_t sr,
+                                            int64_t sk, int mode, int64_t r0, int64_t R, int64_t k0, int64_t K,
+                                            int tid) {
+    if (mode == 0) {
+        for (int s = 0; s < ns; ++s)
+            for (int e = tid; e < 64 * BK; e += 256) {
+                const int r = e / BK, c = e % BK;
+                const int64_t row = r0 + r, k = k0 + s * BK + c;
+                tiles[s][r][c] = (row < R && k < K) ? p[row * sr + k * sk] : (uint16_t)0;
+            }
+        return;
+    }
+    if (ns == kStageSlices && r0 + BM <= R && k0 + kStageSlices * BK <= K) {
+        // Whole tiles inside the operand (the same for every thread): the
+        // loads go out back to back, with no bounds branch between them.
+        const int64_t off = mode == 1 ? (r0 + (tid >> 2)) * sr + k0 + (tid & 3) * 8
+                                      : r0 + (tid & 7) * 8 + (k0 + (tid >> 3)) * sk;
+        const int64_t step = mode == 1 ? BK : BK * sk;
+        uint4 v[kStageSlices];
+#pragma unroll
+        for (int s = 0; s < kStageSlices; ++s) v[s] = *reinterpret_cast<const uint4*>(p + off + s * step);
+#pragma unroll
+        for (int s = 0; s < kStageSlices; ++s) store_chunk(tiles[s], v[s], mode, tid);
+        return;
+    }
+    for (int s = 0; s < ns; ++s) store_chunk(tiles[s], load_chunk(p, sr, sk, mode, r0, R, k0 + s * BK, K, tid), mode, tid);
+}
+
 // One 64 x 64 output tile (column block bx, row block by, K split bz) of
-// C = A B (+ bias) (ReLU) (* mask), FP32 accumulation, staged through As/Bt.
-__device__ __forceinline__ void gemm_block(const GemmArgs& g, int bx, int by, int bz, uint16_t (*As)[LDSK],
-                                           uint16_t (*Bt)[LDSK]) {
+// C = A B (+ bias) (ReLU) (* mask), FP32 accumulation, staged through As/Bt
+// (kStageSlices K slices each).  The MFMAs take the K slices in increasing
+// order, one 16x16x32 step per slice and output block.
+__device__ __forceinline__ void gemm_block(const GemmArgs& g, int bx, int by, int bz, uint16_t (*As)[BM][LDSK],
+                                           uint16_t (*Bt)[BN][LDSK]) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t m0 = (int64_t)by * BM, n0 = (int64_t)bx * BN;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -129,19 +170,27 @@ __device__ __forceinline__ void gemm_block(const GemmArgs& g, int bx, int by, in
     const int64_t kb = (int64_t)bz * g.kchunk;
     const int64_t ke = (kb + g.kchunk < g.K) ? kb + g.kchunk : g.K;
     float* const Cf = g.Cf ? g.Cf + (int64_t)bz * g.split_stride : nullptr;
-    for (int64_t k0 = kb; k0 < ke; k0 += BK) {
-        stage_tile(As, g.A, g.sam, g.sak, g.amode, m0, g.M, k0, ke, tid);
-        stage_tile(Bt, g.B, g.sbn, g.sbk, g.bmode, n0, g.N, k0, ke, tid);
+    for (int64_t k0 = kb; k0 < ke; k0 += kStageSlices * BK) {
+        const int64_t left = (ke - k0 + BK - 1) / BK;
+        const int ns = left < kStageSlices ? (int)left : kStageSlices;
+        stage_tiles(As, ns, g.A, g.sam, g.sak, g.amode, m0, g.M, k0, ke, tid);
+        stage_tiles(Bt, ns, g.B, g.sbn, g.sbk, g.bmode, n0, g.N, k0, ke, tid);
         __syncthreads();
-        bf16x8 a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * i + lr][lk]);
+        for (int s = 0; s < kStageSlices; ++s) {
+            if (s < ns) {
+                bf16x8 a[2], b[2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bt[wn + 16 * j + lr][lk]);
+                for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[s][wm + 16 * i + lr][lk]);
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bt[s][wn + 16 * j + lr][lk]);
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            }
+        }
         __syncthreads();
     }
     // Accumulator layout: element v of lane l is row 4 (l / 16) + v, column l % 16.
@@ -165,8 +214,8 @@ __device__ __forceinline__ void gemm_block(const GemmArgs& g, int bx, int by, in
 
 // C = A B (+ bias) (ReLU) (* mask), M x N: grid (N / 64, M / 64, K splits).
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[BM][LDSK];
-    __shared__ __attribute__((aligned(16))) uint16_t Bt[BN][LDSK];
+    __shared__ __attribute__((aligned(16))) uint16_t As[kStageSlices][BM][LDSK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bt[kStageSlices][BN][LDSK];
     gemm_block(g, blockIdx.x, blockIdx.y, blockIdx.z, As, Bt);
 }
 
@@ -180,8 +229,8 @@ struct GemmGroup {
     int first[5];
 };
 __global__ __launch_bounds__(256) void k_gemm_group(GemmGroup gg) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[BM][LDSK];
-    __shared__ __attribute__((aligned(16))) uint16_t Bt[BN][LDSK];
+    __shared__ __attribute__((aligned(16))) uint16_t As[kStageSlices][BM][LDSK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bt[kStageSlices][BN][LDSK];
     const int b = blockIdx.x;
     int l = 0;
 #pragma unroll
