@@ -299,3 +299,56 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(P, "LIB_PATH", "/nonexistent/libpn_hip.so")
     with pytest.raises(OSError):
         P.lib()
+
+
+def test_balanced_scan_arguments(pn):
+    """pn_fli_scan_balanced validates like pn_fli_scan (before any device
+    call) and also rejects negative or oversized slot counts; its schedule
+    query with explicit slots is host-only and agrees with pn_balanced_plan;
+    the workspace is two tables of one pair record per slot."""
+    L = pn.lib()
+    m = pn.model_struct()
+    p = pn.Params(None, None, None, 1.0, 1.0, 1.0)
+    one = ctypes.c_void_p(8)
+    so = pn.ScanOut(8, 8, 8, None, None, None, None, None, None, 0, 0)
+
+    def scan(integ=None, corr=None, fli=None, t_all=1.0, out=so, n=4, ld=4, slots=16):
+        return L.pn_fli_scan_balanced(ctypes.byref(m), p, ctypes.byref(pn.integrator_struct(integ)),
+                                      ctypes.byref(pn.correction_struct(corr)), ctypes.byref(pn.fli_struct(fli)),
+                                      ctypes.c_int64(n), one, ctypes.c_int64(ld), ctypes.c_double(t_all),
+                                      ctypes.byref(out), ctypes.c_int64(slots), None, ctypes.c_size_t(0), None)
+
+    assert scan(integ=dict(h=0.0)) == pn.PN_EINVAL
+    assert scan(corr=dict(mode=7)) == pn.PN_EINVAL
+    assert scan(fli=dict(d0=0.0)) == pn.PN_EINVAL
+    assert scan(t_all=float("nan")) == pn.PN_EINVAL
+    assert scan(t_all=1e30) == pn.PN_EINVAL                  # more than 4e18 steps
+    assert scan(n=-1) == pn.PN_EINVAL
+    assert scan(ld=3) == pn.PN_EINVAL
+    assert scan(slots=-1) == pn.PN_EINVAL
+    assert scan(slots=(1 << 24) + 1) == pn.PN_EINVAL
+    assert scan(out=pn.ScanOut(8, None, 8, None, None, None, None, None, None, 0, 0)) == pn.PN_EINVAL
+    m_rr = pn.model_struct(dict(rad_reaction=1))
+    assert L.pn_fli_scan_balanced(ctypes.byref(m_rr), p, ctypes.byref(pn.integrator_struct()),
+                                  ctypes.byref(pn.correction_struct()), ctypes.byref(pn.fli_struct()),
+                                  ctypes.c_int64(4), one, ctypes.c_int64(4), ctypes.c_double(1.0),
+                                  ctypes.byref(so), ctypes.c_int64(16), None, ctypes.c_size_t(0), None) == pn.PN_EINVAL
+    # A valid call with explicit slots and no workspace: PN_ENOWS, nothing launched.
+    assert scan(t_all=100.0, slots=2) == pn.PN_ENOWS
+    # Explicit slots: the host plan, no device needed.
+    sch = pn.balanced_schedule(1000, 300.0, slots=64)
+    assert (sch["slot_len"], sch["launches"]) == pn.balanced_plan(1000, 300, 64) and sch["slots"] == 64
+    assert pn.balanced_schedule(0, 300.0, slots=64)["launches"] == 0
+    assert pn.balanced_schedule(1000, 0.0, slots=64)["launches"] == 0
+    with pytest.raises(pn.PnError):
+        pn.balanced_schedule(1000, 300.0, slots=-5)
+    with pytest.raises(pn.PnError):
+        pn.balanced_schedule(1000, 300.0, integrator=dict(h=0.0), slots=4)
+    assert L.pn_fli_scan_balanced_workspace_size(0) == 0
+    assert L.pn_fli_scan_balanced_workspace_size((1 << 24) + 1) == 0
+    assert L.pn_fli_scan_balanced_workspace_size(1000) >= 2 * 1000 * 2 * (16 * 8 + 8 + 8 + 8 + 4 + 4)
+    for args in ((9, 0), (0, 9)):
+        v, w = ctypes.c_int32(0), ctypes.c_int32(0)
+        sc = ctypes.c_int64(0)
+        assert L.pn_balanced_kernel_resources(ctypes.c_int32(args[0]), ctypes.c_int32(args[1]), ctypes.byref(v),
+                                              ctypes.byref(sc), ctypes.byref(w)) == pn.PN_EINVAL
