@@ -33,9 +33,14 @@ def pn():
 
 
 def gpu_scan(pn, wl, model):
+    """The scan as the benchmark runs it: pn_fli_scan_balanced with the
+    device's schedule (the plain fused scan for the 314-orbit lines, the
+    balanced schedule for the 314 x 314 plane)."""
     y0 = pn.init_state(*[dev(getattr(wl, k)) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")],
                        wl.beta, wl.chi1, wl.chi2, model=model)
-    out = pn.fli_scan(y0, wl.t_end, wl.beta, wl.chi1, wl.chi2, model=model, full=False)
+    launches = pn.balanced_schedule(wl.n, wl.t_end)["launches"]
+    assert (launches >= 2) == (wl.n > 65536 // 2)
+    out = pn.fli_scan_balanced(y0, wl.t_end, wl.beta, wl.chi1, wl.chi2, model=model, full=False)
     torch.cuda.synchronize()
     return {k: out[k].cpu().numpy()[:wl.n] for k in ("fli", "label", "status")}
 

@@ -265,7 +265,8 @@ def test_scan_grid64_full_size_sampled(pn):
     from paper_1802_00147_amd import workloads as W
     wl = W.grid64()
     y0 = pn.init_state(*[dev(getattr(wl, k)) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")], 1.0, 1.0, 1.0)
-    out = pn.fli_scan(y0, wl.t_end, 1.0, 1.0, 1.0)
+    assert pn.balanced_schedule(wl.n, wl.t_end)["launches"] == 0        # the plain fused scan
+    out = pn.fli_scan_balanced(y0, wl.t_end, 1.0, 1.0, 1.0)
     torch.cuda.synchronize()
     idx = W.strided_sample(wl.n, 24, seed=7)
     sub = wl.subset(idx)
@@ -295,7 +296,8 @@ def test_scan_grid314_full_size_sampled(pn, beta, qm):
     model = dict(quad_mono=qm)
     y0 = pn.init_state(*[dev(getattr(wl, k)) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")], beta, 1.0, 1.0,
                        model=model)
-    out = pn.fli_scan(y0, wl.t_end, beta, 1.0, 1.0, model=model, full=False)
+    assert pn.balanced_schedule(wl.n, wl.t_end)["launches"] >= 2         # the balanced schedule
+    out = pn.fli_scan_balanced(y0, wl.t_end, beta, 1.0, 1.0, model=model, full=False)
     torch.cuda.synchronize()
     idx = W.strided_sample(wl.n, 8, seed=13 + int(4 * beta) + qm)
     sub = wl.subset(idx)
