@@ -343,13 +343,29 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
         for (int t = 0; t < 8; ++t) v[t] = (lq == 0 && t < 7) ? w0[col * 7 + t] : (uint16_t)0;
         wf0[j] = *reinterpret_cast<const bf16x8*>(v);
     }
-    float bias[3][2];
+    // Inference (TR) runs the products of layers 1-3 with the weights as the
+    // first MFMA operand, which yields the transposed 16 x 16 block: element
+    // v of lane l is row l % 16, column 4 (l / 16) + v, so a lane holds four
+    // consecutive outputs of one row and stores them with one 8-byte LDS
+    // write.  The training pass (IO), which has no registers to spare for the
+    // extra biases, keeps the MFMA's own layout (element v of lane l is row
+    // 4 (l / 16) + v, column l % 16) and 2-byte writes.  Each output is the
+    // same dot product either way.
+    constexpr bool TR = !IO;
+    float bias[3][2][4];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        bias[0][j] = b0[c0 + 16 * j + lr];
-        bias[1][j] = b1[c0 + 16 * j + lr];
-        bias[2][j] = b2[c0 + 16 * j + lr];
-    }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < (TR ? 4 : 1); ++v) {
+            const int col = TR ? c0 + 16 * j + 4 * lq + v : c0 + 16 * j + lr;
+            bias[0][j][v] = b0[col];
+            bias[1][j][v] = b1[col];
+            bias[2][j][v] = b2[col];
+        }
+    auto mfma = [](const bf16x8& a, const bf16x8& w, const f32x4& c) {
+        return TR ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, a, c, 0, 0, 0)
+                  : __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w, c, 0, 0, 0);
+    };
     const float bias3 = lr < 2 ? b3[lr] : 0.0f;
 
     const int64_t ntiles = (n + FT - 1) / FT;
@@ -388,17 +404,26 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                 *reinterpret_cast<bf16x8*>(io.x_out + (r0 + 16 * i + lr) * kFeatLd) = a;
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wf0[j], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                acc[i][j] = mfma(a, wf0[j], f32x4{0.f, 0.f, 0.f, 0.f});
         }
         // Epilogue: bias, ReLU, bfloat16 into an LDS buffer.
         auto store = [&](uint16_t (*h)[FLD], int layer) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < 2; ++j) {
+                    if (TR) {
+                        union { uint2 v; uint16_t e[4]; } u;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        h[16 * i + 4 * lq + v][c0 + 16 * j + lr] = f2bf(fmaxf(acc[i][j][v] + bias[layer][j], 0.0f));
+                        for (int v = 0; v < 4; ++v) u.e[v] = f2bf(fmaxf(acc[i][j][v] + bias[layer][j][v], 0.0f));
+                        *reinterpret_cast<uint2*>(&h[16 * i + lr][c0 + 16 * j + 4 * lq]) = u.v;
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            h[16 * i + 4 * lq + v][c0 + 16 * j + lr] =
+                                f2bf(fmaxf(acc[i][j][v] + bias[layer][j][0], 0.0f));
+                    }
+                }
         };
         store(hA, 0);
         if (!IO) load_feat(tile + gridDim.x, fnext);   // training batches give each workgroup about one tile
@@ -420,7 +445,7 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                     const bf16x8 a = load_bf16x8(&hin[16 * i + lr][32 * sl + lk]);
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wf[layer - 1][j][sl], acc[i][j], 0, 0, 0);
+                        acc[i][j] = mfma(a, wf[layer - 1][j][sl], acc[i][j]);
                 }
             }
             store(hout, layer);
