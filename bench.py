@@ -40,7 +40,7 @@ KERNEL_SOURCES = ["paper_1802_00147_amd/csrc/pn_kernels.hip", "paper_1802_00147_
 # grid64 launch: FETCH_SIZE 365.125 KiB x 1.999923 (a 1 GiB copy reads 524,308.25
 # KiB) + WRITE_SIZE 548.0 KiB x 1.0 (the copy writes 1,048,576 KiB).
 TRAFFIC = dict(workload="grid64", bytes_per_launch=753508 + 593920,
-               sources_sha256="21ffe57495b6abdcecf1c643eb4f0ca902d0868990281e9fbf684ca9e4ef1e31")
+               sources_sha256="bcaf5756935e5d2f61366c7c7213e39ab93a1b27e8f24acd2e679e2c72365e08")
 
 
 def sources_sha256():

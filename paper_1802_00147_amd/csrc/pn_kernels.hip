@@ -213,11 +213,12 @@ struct GwArgs {
     double eta0;                     // eta of a shared parameter set
 };
 
+// Orbit i = blockIdx.x * 256 + threadIdx.x, rows blockIdx.y, + gridDim.y, ...:
+// consecutive lanes read consecutive orbits of one recorded row.
 __global__ __launch_bounds__(256) void k_gw(ParamArgs pa, GwArgs ga, int64_t n, int64_t ns, const double* y,
                                             int64_t ld, double* hp, double* hx) {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= n * ns) return;
-    const int64_t row = j / n, i = j - row * n;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
     PnCoef k;
     const bool ok = load_coef(pa, i, k);
     double eta = ga.eta0;
@@ -225,19 +226,21 @@ __global__ __launch_bounds__(256) void k_gw(ParamArgs pa, GwArgs ga, int64_t n, 
         const double b = pa.beta[i];
         eta = b / ((1.0 + b) * (1.0 + b));
     }
-    double s[12], f[12];
-    load_state(y + row * 12 * ld, ld, i, s);
-    pn_rhs_eval(k, s, f);
-    const double u = pn_rsqrt(dot3(s[0], s[1], s[2], s[0], s[1], s[2]));
-    const double pv = dot3(ga.px, ga.py, ga.pz, f[0], f[1], f[2]);
-    const double qv = dot3(ga.qx, ga.qy, ga.qz, f[0], f[1], f[2]);
-    const double pr = dot3(ga.px, ga.py, ga.pz, s[0], s[1], s[2]) * u;
-    const double qr = dot3(ga.qx, ga.qy, ga.qz, s[0], s[1], s[2]) * u;
     const double a = eta * ga.inv_dist;
-    const double hplus = 2.0 * a * ((pv * pv - qv * qv) - (pr * pr - qr * qr) * u);
-    const double hcross = 4.0 * a * (pv * qv - pr * qr * u);
-    hp[row * ld + i] = ok ? hplus : __builtin_nan("");
-    hx[row * ld + i] = ok ? hcross : __builtin_nan("");
+    for (int64_t row = blockIdx.y; row < ns; row += gridDim.y) {
+        double s[12], f[12];
+        load_state(y + row * 12 * ld, ld, i, s);
+        pn_rhs_eval(k, s, f);
+        const double u = pn_rsqrt(dot3(s[0], s[1], s[2], s[0], s[1], s[2]));
+        const double pv = dot3(ga.px, ga.py, ga.pz, f[0], f[1], f[2]);
+        const double qv = dot3(ga.qx, ga.qy, ga.qz, f[0], f[1], f[2]);
+        const double pr = dot3(ga.px, ga.py, ga.pz, s[0], s[1], s[2]) * u;
+        const double qr = dot3(ga.qx, ga.qy, ga.qz, s[0], s[1], s[2]) * u;
+        const double hplus = 2.0 * a * ((pv * pv - qv * qv) - (pr * pr - qr * qr) * u);
+        const double hcross = 4.0 * a * (pv * qv - pr * qr * u);
+        hp[row * ld + i] = ok ? hplus : __builtin_nan("");
+        hx[row * ld + i] = ok ? hcross : __builtin_nan("");
+    }
 }
 
 struct FliArgs {
@@ -1483,10 +1486,10 @@ pn_status pn_gw_polarizations(const pn_model* model, pn_params params, int64_t n
     ga.qz = nhat[0] * phat[1] - nhat[1] * phat[0];
     ga.inv_dist = 1.0 / dist;
     ga.eta0 = params.beta0 / ((1.0 + params.beta0) * (1.0 + params.beta0));
-    const int64_t total = n * ns;
-    const int64_t blocks = (total + 255) / 256;
+    const int64_t blocks = (n + 255) / 256;
     PN_REQUIRE(blocks <= 0x7fffffffLL);
-    hipLaunchKernelGGL(k_gw, dim3((unsigned)blocks), dim3(256), 0, stream, pa, ga, n, ns, y, ld, hp, hx);
+    const unsigned rows = (unsigned)(ns < 65535 ? ns : 65535);
+    hipLaunchKernelGGL(k_gw, dim3((unsigned)blocks, rows), dim3(256), 0, stream, pa, ga, n, ns, y, ld, hp, hx);
     return launched("pn_gw_polarizations");
 }
 
