@@ -152,3 +152,19 @@ def test_balanced_workspace_contract(pn):
     # belong to the batch scan).
     with pytest.raises(pn.PnError):
         pn.fli_scan_balanced(y0, 300.0, b, c1, c2, slots=-1)
+
+
+@pytest.mark.parametrize("method", [0, 1], ids=["rk4", "rk5"])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3], ids=["none", "spin", "six", "dual"])
+def test_balanced_every_kernel_build(pn, method, mode):
+    """Each of the eight builds (integrator x correction) on 11 slots gives
+    the plain scan's outputs bit for bit, and the runtime reports its
+    resources (at least one resident wavefront per SIMD)."""
+    y0, b, c1, c2 = mixed_inputs(pn, 400, seed=40 + 4 * method + mode)
+    integ, corr = dict(method=method), dict(mode=mode)
+    plain = host(pn.fli_scan(y0, 250.0, b, c1, c2, integrator=integ, correction=corr))
+    got = host(pn.fli_scan_balanced(y0, 250.0, b, c1, c2, integrator=integ, correction=corr, slots=11))
+    torch.cuda.synchronize()
+    assert_same_as_plain(got, plain)
+    res = pn.balanced_kernel_resources(integ, corr)
+    assert res["waves_per_simd"] >= 1 and 0 < res["vgprs"] <= 512
