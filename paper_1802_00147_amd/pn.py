@@ -510,6 +510,11 @@ def fli_scan_balanced(y0, t_end, beta, chi1, chi2, model=None, integrator=None, 
     n = ld if n is None else n
     integ = integrator_struct(integrator)
     corr = correction_struct(correction)
+    if isinstance(t_end, torch.Tensor):
+        if t_end.numel() != 1:
+            raise ValueError("fli_scan_balanced takes one end time for all orbits; "
+                             "orbits of uneven length go to batch_scan")
+        t_end = t_end.item()
     t_end = float(t_end)
     if out is None:
         nmax = int(-(-t_end // integ.h)) if t_end > 0 else 0
