@@ -43,6 +43,10 @@ TRAFFIC = dict(workload="grid64", bytes_per_launch=753508 + 593920,
                sources_sha256="bcaf5756935e5d2f61366c7c7213e39ab93a1b27e8f24acd2e679e2c72365e08")
 
 
+# Table 3 of the paper: wall time of its GPU and CPU scans (seconds).
+PAPER_TABLE3 = {"fig6_th1_1.571": (75.0, 1020.0), "fig7": (2213.0, 25000.0)}
+
+
 def sources_sha256():
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
@@ -592,6 +596,13 @@ def main():
         if balanced:
             line["config"]["schedule"] = dict(kind="balanced", **sched)
 
+    if wl.name in PAPER_TABLE3:
+        # The paper's own wall times for the same scan (its Table 3, other
+        # hardware and integrator): context beside this run's time, never the
+        # target.
+        gpu_s, cpu_s = PAPER_TABLE3[wl.name]
+        line["paper_context"] = dict(table3_gpu_s=gpu_s, table3_cpu_core_s=cpu_s, this_run_s=1e-3 * kernel_ms,
+                                     note="GT 650M (RK5) and one i5-3230M core in the paper; context only")
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, args.cpu_sample)
         fpos = cb.pop("flops_per_orbit_step")
