@@ -100,3 +100,14 @@ def test_plan_and_piece_errors():
     for args in ((10, 7, C, 0, -1), (10, 7, C, 0, C), (10, 7, C, 3, 0), (10, 7, 7, 0, 0), (10, 7, C, -1, 0)):
         with pytest.raises(pn.PnError):
             pn.balanced_piece(*args)
+
+
+def test_plan_at_the_overflow_guards():
+    """Tapes up to 2^62 steps plan with both invariants; beyond the guards
+    (n S or P C above 2^62) the plan is refused instead of wrapping."""
+    for n, S, P in (((1 << 35), (1 << 26), 65536), (98596, 10 ** 12, 65536), (2, 3, 1 << 24)):
+        C, L = pn.balanced_plan(n, S, P)
+        assert C * P >= n * S and C - S >= -(-C // L) and 2 <= L <= 16
+    for n, S, P in (((1 << 35), (1 << 27) + 1, 65536), (1, 1 << 40, 1 << 24)):
+        with pytest.raises(pn.PnError):
+            pn.balanced_plan(n, S, P)
