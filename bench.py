@@ -34,13 +34,13 @@ METRIC = "FP64 orbit-steps/s + scan grid-pts/s (surrogate vs plain, ≥99% FLI l
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 128 FP64 flop/clk x 2.4 GHz
 KERNEL_SOURCES = ["paper_1802_00147_amd/csrc/pn_kernels.hip", "paper_1802_00147_amd/csrc/pn_device.h"]
 
-# HBM traffic of the scan kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
-# (KiB per dispatch, scaled by a copy kernel of known size), valid only for the
-# kernel source whose hash is recorded with it.
-# grid64 launch: FETCH_SIZE 365.125 KiB x 1.999923 (a 1 GiB copy reads 524,308.25
-# KiB) + WRITE_SIZE 548.0 KiB x 1.0 (the copy writes 1,048,576 KiB).
-TRAFFIC = dict(workload="grid64", bytes_per_launch=753508 + 593920,
-               sources_sha256="bcaf5756935e5d2f61366c7c7213e39ab93a1b27e8f24acd2e679e2c72365e08")
+# HBM bytes of one scan from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per
+# dispatch, scaled by a 1 GiB device copy: FETCH_SIZE x 1.99993, WRITE_SIZE
+# x 1.0), valid only for the kernel sources whose hash is recorded with them.
+# grid64, one k_fli_scan launch: 367.9375 KiB read, 580.0 KiB written.
+# fig7, three k_wrap_scan launches: 157,886.94 KiB read, 357,591.03 KiB written.
+TRAFFIC = dict(sources_sha256="bcaf5756935e5d2f61366c7c7213e39ab93a1b27e8f24acd2e679e2c72365e08",
+               bytes_per_scan={"grid64": 753508 + 593920, "fig7": 323340345 + 366173216})
 
 
 # Table 3 of the paper: wall time of its GPU and CPU scans (seconds).
@@ -613,9 +613,8 @@ def main():
         line["cpu_baseline"] = cb
         achieved = fpos * orbit_steps / (kernel_ms * 1e-3) / 1e12
         traffic = None
-        if (TRAFFIC is not None and TRAFFIC.get("workload") == wl.name
-                and TRAFFIC.get("sources_sha256") == sources_sha256()):
-            traffic = TRAFFIC["bytes_per_launch"]
+        if TRAFFIC["sources_sha256"] == sources_sha256():
+            traffic = TRAFFIC["bytes_per_scan"].get(wl.name)
         line["roofline"] = dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
                                 frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=traffic,
                                 kernel=kernel, kernel_ms=kernel_ms,
