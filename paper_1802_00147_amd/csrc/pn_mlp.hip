@@ -291,13 +291,25 @@ __device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t* p) {
 }
 
 // Optional extras of the fused pass, used by training: rows idx[r] of the
-// features instead of row r, and the bfloat16 inputs and hidden activations
-// written out ([n][8] and [n][256], 16-byte aligned) for the backward pass.
+// features instead of row r, the bfloat16 inputs and hidden activations
+// written out ([n][8] and [n][256], 16-byte aligned) for the backward pass,
+// and (gout non-null) the loss of the batch added to *loss and its gradient
+// with respect to the two outputs written to gout [n][2] (bfloat16).
 struct FusedIO {
     const int32_t* idx;
     uint16_t* x_out;
     uint16_t* h_out[3];
+    const float* label;
+    const float* target;
+    uint16_t* gout;
+    float* loss;
 };
+
+// Exchange with the adjacent lane (lanes 2j and 2j + 1), DPP quad permutation
+// [1, 0, 3, 2].
+__device__ __forceinline__ float swap_adjacent(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
 
 // Copy the valid rows of an LDS activation tile to global memory, 16 bytes
 // per access.
@@ -474,6 +486,33 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                     if (row < n) out[row * 2 + lr] = o[v] + bias3;
                 }
             }
+            if (IO && io.gout) {
+                // Loss of the batch: binary cross-entropy of the logit plus
+                // Huber (delta 1) of the FLI output, averaged over the n rows,
+                // and its gradient.  Lanes lr = 0 and 1 hold the two outputs of
+                // rows 4 lq + v and exchange them.
+                float lsum = 0.0f;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float mine = o[v] + bias3;
+                    const float other = swap_adjacent(mine);
+                    const int64_t row = r0 + 16 * wave + 4 * lq + v;
+                    if (lr == 0 && row < n) {
+                        const int32_t r = io.idx[row];
+                        const float z = mine, f = other, y = io.label[r], t = io.target[r];
+                        float l = fmaxf(z, 0.0f) - y * z + log1pf(expf(-fabsf(z)));
+                        const float d = f - t;
+                        l += fabsf(d) <= 1.0f ? 0.5f * d * d : fabsf(d) - 0.5f;
+                        const float sig = 1.0f / (1.0f + expf(-z));
+                        io.gout[2 * row] = f2bf((sig - y) / (float)n);
+                        io.gout[2 * row + 1] = f2bf(fminf(fmaxf(d, -1.0f), 1.0f) / (float)n);
+                        lsum += l;
+                    }
+                }
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
+                if (lane == 0) atomicAdd(io.loss, lsum / (float)n);
+            }
         }
         __syncthreads();   // hA is rewritten by the next tile's layer 1
         if (IO) {
@@ -486,33 +525,6 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
             }
         }
     }
-}
-
-// Loss of a batch and its gradient with respect to the two outputs:
-// binary cross-entropy of the logit + Huber (delta 1) of the FLI output.
-__global__ __launch_bounds__(256) void k_loss(const float* out, const float* label, const float* target,
-                                              const int32_t* idx, int B, uint16_t* gout, float* loss) {
-    __shared__ float part[256];
-    const int b = blockIdx.x * 256 + threadIdx.x;
-    float l = 0.0f;
-    if (b < B) {
-        const int r = idx[b];
-        const float z = out[2 * b], f = out[2 * b + 1];
-        const float y = label[r], t = target[r];
-        l = fmaxf(z, 0.0f) - y * z + log1pf(expf(-fabsf(z)));
-        const float d = f - t;
-        l += fabsf(d) <= 1.0f ? 0.5f * d * d : fabsf(d) - 0.5f;
-        const float sig = 1.0f / (1.0f + expf(-z));
-        gout[2 * b] = f2bf((sig - y) / (float)B);
-        gout[2 * b + 1] = f2bf(fminf(fmaxf(d, -1.0f), 1.0f) / (float)B);
-    }
-    part[threadIdx.x] = l;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicAdd(loss, part[0] / (float)B);
 }
 
 // Bias gradients of the four layers in one launch: db_l[n] = sum over rows
@@ -870,8 +882,8 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
 
     // Forward: one fused pass over the batch rows idx[], keeping the inputs
     // and hidden activations for the backward pass.
-    launch_fused(s, net, feat, B, out, FusedIO{idx, X, {h[0], h[1], h[2]}}, ncu);
-    hipLaunchKernelGGL(k_loss, dim3(blocks_for(B, 256)), dim3(256), 0, s, out, label, target, idx, B, g4, loss);
+    // Forward with the loss and its output gradient g4.
+    launch_fused(s, net, feat, B, out, FusedIO{idx, X, {h[0], h[1], h[2]}, label, target, g4, loss}, ncu);
     // Backward.  Weight gradients dW_l = g_l^T h_(l-1) go to per-layer
     // split-K partials that the Adam launch sums; the layer gradients
     // g_(l-1) = (g_l W_l) * (h_(l-1) > 0) stay live for one launch that forms
@@ -976,7 +988,8 @@ pn_status pn_mlp_infer_fused(const pn_mlp* net, const float* feat, int64_t n, fl
         pn_detail::set_last_error("pn_mlp_infer_fused", "no device");
         return PN_EDEVICE;
     }
-    launch_fused(stream, net, feat, n, out, FusedIO{nullptr, nullptr, {nullptr, nullptr, nullptr}}, ncu);
+    launch_fused(stream, net, feat, n, out,
+                 FusedIO{nullptr, nullptr, {nullptr, nullptr, nullptr}, nullptr, nullptr, nullptr, nullptr}, ncu);
     return launched("pn_mlp_infer_fused");
 }
 
