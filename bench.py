@@ -1,22 +1,30 @@
 #!/usr/bin/env python3
-"""Benchmark of the plain FP64 FLI phase-space scan on one MI355X.
+"""Benchmark of the FP64 FLI phase-space scan and its surrogate-assisted form
+on one MI355X.
 
-Workload (default): the 64 x 64 (r0, theta) grid -- r0 in [10, 40], spin polar
-angle theta in [0, pi] (theta1 = pi/2, theta2 = theta), beta = 1, chi = 1, all
-Hamiltonian terms on (quadrupole-monopole included), RK4 with h = 1 to
-t = 1e5, the six-integral correction after every step, FLI threshold 5.8.
-One benchmark step is one pass of the whole path over the grid: initial
-states on the GPU (pn_init_state) and the fused scan (pn_fli_scan_balanced:
-the plain fused scan for this grid; full-chip grids such as 314 x 314 whose
-orbits fill a last round of resident wavefronts only partly take the balanced
-wrap-around schedule instead).
+Default workload (surrogate4096): the surrogate-assisted scan of the
+4096 x 4096 (r0, theta) grid -- r0 in [10, 40], spin polar angle theta in
+[0, pi] (theta1 = pi/2, theta2 = theta), beta = 1, chi = 1, all Hamiltonian
+terms on, RK4 with h = 1 to t = 1e5, the six-integral correction after every
+step, FLI threshold 5.8.  The network (7-256-256-256-2, BF16 MFMA) is trained
+on the FP64 scan of the 10^6-orbit uneven batch (untimed setup); one benchmark
+step is one whole assisted scan of the 16.8 M points (audit integration,
+refinement, inference, gate, fallback integration, merge).  value =
+grid-pts/s of the assisted scan; plain_* fields give the plain FP64 scan of
+the same grid (rate measured on a seeded 65,536-point sample) and the label
+agreement between the two.
 
-Prints one JSON line.  value = orbit-steps per second (an orbit-step advances
-one orbit and its shadow by h, with both corrections and the FLI update).
-roofline: the scan kernel against the FP64 vector peak; its algorithmic flops
-per orbit-step come from the CPU oracle's counting scalar, measured in the
-cpu_baseline leg on sampled grid orbits.  cpu_baseline: the oracle as it is,
-timed on this host on a bounded sample of the same grid.
+Other workloads (--workload): grid64 (64 x 64, plain fused scan), grid314,
+fig7 (balanced schedule), batch1M (persistent work-stealing batch), single,
+fig6, table2, orbit3, gw.  value there = orbit-steps per second (an orbit-step
+advances one orbit and its shadow by h, with both corrections and the FLI
+update).
+
+roofline: the dominant kernel (the FP64 scan) against the FP64 vector peak,
+with the algorithmic work per orbit-step ALG_FLOPS_PER_ORBIT_STEP; hardware
+FP64 operations per orbit-step from rocprofv3 counters are reported beside
+it while the kernel sources are unchanged.  cpu_baseline: the oracle as it
+is, timed on this host on a bounded sample of the same workload.
 """
 import argparse
 import hashlib
@@ -32,6 +40,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FP64 orbit-steps/s + scan grid-pts/s (surrogate vs plain, ≥99% FLI label agree)"
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 128 FP64 flop/clk x 2.4 GHz
+
+# Algorithmic FP64 work of one orbit-step with RK4 and the six-integral
+# correction (two sweeps), the scope's per-unit figure: about 2 x (2.0k for
+# the RK4 step + 0.6k for the correction) + 40 for the separation.  The
+# oracle's counting scalar gives 7.7k: it evaluates H and its gradient
+# separately, and H again with dH/dp in every momentum-scaling iteration.
+# The kernel executes about 5.0k (FP64 instruction counters, FMA = 2).  The
+# oracle's count is reported beside the roofline as a secondary figure.
+ALG_FLOPS_PER_ORBIT_STEP = 5200.0
 KERNEL_SOURCES = ["paper_1802_00147_amd/csrc/pn_kernels.hip", "paper_1802_00147_amd/csrc/pn_device.h"]
 
 # HBM bytes of one scan from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per
@@ -45,6 +62,19 @@ TRAFFIC = dict(sources_sha256="bcaf5756935e5d2f61366c7c7213e39ab93a1b27e8f24acd2
 
 # Table 3 of the paper: wall time of its GPU and CPU scans (seconds).
 PAPER_TABLE3 = {"fig6_th1_1.571": (75.0, 1020.0), "fig7": (2213.0, 25000.0)}
+
+
+# FP64 operations per orbit-step that the scan kernels execute, from
+# rocprofv3 counters (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 x 64 lanes, FMA
+# counted twice, over the launch's orbit-steps), valid only for the kernel
+# sources whose hash is recorded with them.
+HW_FLOPS = dict(sources_sha256=None, per_orbit_step={})
+
+
+def hardware_flops(kernel):
+    if HW_FLOPS["sources_sha256"] != sources_sha256():
+        return None
+    return HW_FLOPS["per_orbit_step"].get(kernel)
 
 
 def sources_sha256():
@@ -100,11 +130,13 @@ def describe(wl):
 
 def cpu_baseline(wl, sample, flop_sample_steps=2000):
     """The oracle on a bounded sample of the workload: timing on this host's
-    cores, and algorithmic flops per orbit-step with the counting scalar."""
+    cores, and the oracle's own flops per orbit-step (counting scalar)."""
     import oracle as O
     from paper_1802_00147_amd import workloads as W
-    cores = min(os.cpu_count() or 1, 16)
     idx = W.strided_sample(wl.n, sample, seed=11)
+    # Threads that can work: the host's cores (at most 16, a GPU box's CPU
+    # share), and no more than the sample has orbits.
+    cores = max(1, min(os.cpu_count() or 1, 16, len(idx)))
     sub = wl.subset(idx)
     y0 = O.init_state(sub.r0, sub.p0, sub.th1, sub.ph1, sub.th2, sub.ph2, sub.beta, sub.chi1, sub.chi2,
                       model=wl.model)
@@ -126,7 +158,7 @@ def cpu_baseline(wl, sample, flop_sample_steps=2000):
                 sample=f"{len(idx)} seeded orbits of {wl.name}, {tdesc} "
                        f"({steps} orbit-steps, {dt:.1f} s wall on {cores} threads)",
                 per_core=rate / cores, nproc=os.cpu_count(), cpu_model=cpu_model(),
-                labels=res["label"], flops_per_orbit_step=float(np.mean(flops)))
+                labels=res["label"], oracle_flops_per_orbit_step=float(np.mean(flops)))
 
 
 def cpu_model():
@@ -371,22 +403,30 @@ def surrogate_bench(args, dev):
             dst.copy_(src)
         net.step = base_step
 
+    def one_scan(ws):
+        return S.surrogate_scan(net, grid, ts.stats, margin=args.margin, audit=0.01, seed=5,
+                                refine_epochs=args.refine, ws=ws)
+
     ws = None
     for _ in range(args.warmup):
         restore()
-        ws = S.surrogate_scan(net, grid, ts.stats, margin=args.margin, audit=0.01, seed=5,
-                              refine_epochs=args.refine, ws=ws).ws
+        ws = one_scan(ws).ws
+    # Timed region: K whole assisted scans, bracketed by device
+    # synchronisation; each scan also reports the duration of its FP64 scan
+    # launches (events on the launch stream, inside the library call).
     res = None
-    elapsed = 0.0
-    for _ in range(args.steps):
-        restore()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = S.surrogate_scan(net, grid, ts.stats, margin=args.margin, audit=0.01, seed=5,
-                               refine_epochs=args.refine, ws=ws)
+    scans = []
+    restore()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        if k > 0:
+            restore()
+        res = one_scan(ws)
         ws = res.ws
-        torch.cuda.synchronize()
-        elapsed += time.perf_counter() - t0
+        scans.append(res.scans)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
 
     # The network's own kernel: fused inference over every grid point against
     # its matrix-core roofline (2 x 133,376 multiply-adds per point), and the
@@ -409,17 +449,20 @@ def surrogate_bench(args, dev):
     inf_achieved = inf_flops / (inf["fused_ms"] * 1e-3) / 1e12
 
     # Plain scan on a seeded sample of the grid: rate and label agreement.
+    # 65,536 orbits fill every SIMD with two wavefronts, as the whole grid
+    # (256 times as many, an exact multiple) would.
     idx = W.strided_sample(grid.n, args.plain_sample, seed=17)
     sub = grid.subset(idx)
     scols = [torch.as_tensor(getattr(sub, k), device=dev) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")]
     ys = pn.init_state(*scols, 1.0, 1.0, 1.0)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    e0.record()
+    e0.record(stream)
     plain = pn.fli_scan(ys, grid.t_end, 1.0, 1.0, 1.0, full=False)
-    e1.record()
+    e1.record(stream)
     torch.cuda.synchronize()
     plain_ms = e0.elapsed_time(e1)
+    plain_steps = int(plain["steps"].sum().item())
     plain_pts_s = len(idx) / (plain_ms * 1e-3)
     got = res.label.cpu().numpy()[idx]
     ref = plain["label"].cpu().numpy()
@@ -429,47 +472,72 @@ def surrogate_bench(args, dev):
                 ms_per_step=1e3 * elapsed / args.steps, higher_is_better=True, scaling="weak", vs_baseline=None,
                 dtype="f64+bf16", data="synthetic",
                 config={"workload": "grid4096 surrogate-assisted FLI scan: 4096x4096 (r0, theta) grid, t=1e5, "
-                                    "beta=1, chi=1, QM on; MLP 7-256-256-256-2 (BF16 MFMA, FP32 accumulation) "
-                                    "trained on the FP64 scan of batch1M, refined on the integrated 1% "
-                                    "SplitMix64 audit of the grid; integration fallback for |logit| < margin",
-                        "grid_points": grid.n, "train_epochs": args.epochs, "refine_epochs": args.refine,
-                        "margin": args.margin})
+                                    "beta=1, chi=1, QM on, RK4 h=1, six-integral correction; MLP 7-256-256-256-2 "
+                                    "(BF16 MFMA, FP32 accumulation) trained on the FP64 scan of batch1M, refined "
+                                    "on the integrated 1% SplitMix64 audit of the grid; integration fallback for "
+                                    "|logit| < margin",
+                        "grid_points": grid.n, "t_end": grid.t_end, "train_epochs": args.epochs,
+                        "refine_epochs": args.refine, "margin": args.margin})
     line["plain_grid_pts_per_s"] = plain_pts_s
+    line["plain_orbit_steps_per_s"] = plain_steps / (plain_ms * 1e-3)
     line["speedup_vs_plain"] = value / plain_pts_s
     line["label_agreement"] = agree
     line["label_agreement_sample"] = len(idx)
     line["integrated_fraction"] = res.integrated / grid.n
     line["timings_s"] = dict(res.timings, training_data=data_s, training=train_s)
     line["train_loss"] = [round(h, 5) for h in hist]
+
+    # Dominant kernel of the assisted scan: the FP64 scan of the audit and of
+    # the uncertain points.  Per launch: the algorithmic work of the
+    # orbit-steps it integrated over its average duration, from the scan
+    # launches' own events over the timed scans.
+    per_kernel = {}
+    for sc_k in scans:
+        for ph in sc_k:
+            if ph["kernel"] is None:
+                continue
+            d = per_kernel.setdefault(ph["kernel"], dict(ms=0.0, launches=0, orbit_steps=0))
+            d["ms"] += ph["ms"]
+            d["launches"] += ph["launches"]
+            d["orbit_steps"] += ph["orbit_steps"]
+    kname, kd = max(per_kernel.items(), key=lambda kv: kv[1]["ms"])
+    launch_ms = kd["ms"] / kd["launches"]
+    flops_per_launch = ALG_FLOPS_PER_ORBIT_STEP * kd["orbit_steps"] / kd["launches"]
+    achieved = flops_per_launch / (launch_ms * 1e-3) / 1e12
+    line["roofline"] = dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                            frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=None,
+                            kernel=f"{kname}<RK4,SIX> (audit and fallback integrations of pn_surrogate_scan)",
+                            kernel_ms=launch_ms, launches_per_step=kd["launches"] / args.steps,
+                            orbit_steps_per_launch=kd["orbit_steps"] / kd["launches"],
+                            flops_per_orbit_step=ALG_FLOPS_PER_ORBIT_STEP,
+                            orbit_steps_per_s=kd["orbit_steps"] / (kd["ms"] * 1e-3),
+                            phases=res.scans)
+    hw = hardware_flops(kname)
+    if hw is not None:
+        line["roofline"]["hw_flops_per_orbit_step"] = hw
+        line["roofline"]["hw_frac"] = hw * kd["orbit_steps"] / (kd["ms"] * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS
+    if kname == "k_wrap_scan":
+        line["roofline"]["resources"] = pn.balanced_kernel_resources()
     line["inference_roofline"] = dict(bound="mfma", achieved=inf_achieved, peak=2500.0, unit="TFLOP/s",
                                       frac=inf_achieved / 2500.0, traffic=None, kernel="k_mlp_fused",
                                       kernel_ms=inf["fused_ms"], layered_ms=inf["layered_ms"],
                                       flops_per_point=inf_flops / grid.n)
+    plain_tf = ALG_FLOPS_PER_ORBIT_STEP * plain_steps / (plain_ms * 1e-3) / 1e12
+    line["plain_roofline"] = dict(bound="alu", achieved=plain_tf, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                                  frac=plain_tf / FP64_VECTOR_PEAK_TFLOPS,
+                                  kernel="k_fli_scan<RK4,SIX> (plain scan of the 65,536-point sample)",
+                                  kernel_ms=plain_ms)
     if not args.no_cpu_baseline:
-        sub_cpu = W.grid_r_theta(64, 64, grid.t_end, "grid64")   # same recipe at 4,096 points
-        cb = cpu_baseline(sub_cpu, args.cpu_sample)
+        # The oracle's plain scan of seeded points of the same grid, on this
+        # host's cores, in grid points per second.
+        cb = cpu_baseline(grid, args.cpu_sample)
         cb.pop("labels")
-        fpos = cb.pop("flops_per_orbit_step")
+        line["roofline"]["oracle_flops_per_orbit_step"] = cb.pop("oracle_flops_per_orbit_step")
         cb["value"] = cb["value"] / grid.t_end   # orbit-steps/s -> grid-pts/s (1e5 steps per point)
         cb["per_core"] = cb["per_core"] / grid.t_end
         cb["unit"] = "grid-pts/s"
         cb["extrapolated_full_s"] = grid.n / cb["value"]   # plain scan of the whole grid, never run
         line["cpu_baseline"] = cb
-        # Dominant kernel of the assisted scan: the FP64 integration of the
-        # audit and of the uncertain points (balanced schedule where predicted
-        # faster, else the plain fused scan), timed by the call's own phase
-        # events (the phases also hold their small gather/sort kernels).
-        scan_s = res.timings["audit_s"] + res.timings["fallback_s"]
-        achieved = fpos * res.integrated * grid.t_end / scan_s / 1e12
-        line["roofline"] = dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                                frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=None,
-                                kernel="k_wrap_scan / k_fli_scan <RK4,SIX> (audit + fallback phases of "
-                                       "pn_surrogate_scan, through pn_fli_scan_balanced)",
-                                kernel_ms=1e3 * scan_s, flops_per_orbit_step=fpos)
-        plain = fpos * len(idx) * grid.t_end / (plain_ms * 1e-3) / 1e12
-        line["plain_roofline"] = dict(bound="alu", achieved=plain, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                                      frac=plain / FP64_VECTOR_PEAK_TFLOPS, kernel="k_fli_scan<RK4,SIX> (plain sample)",
-                                      kernel_ms=plain_ms)
     print(json.dumps(line), flush=True)
 
 
@@ -478,7 +546,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="grid64")
+    ap.add_argument("--workload", default="surrogate4096")
     ap.add_argument("--cpu-sample", type=int, default=160)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--epochs", type=int, default=20, help="surrogate workload: training epochs (cosine decay)")
@@ -605,20 +673,26 @@ def main():
                                      note="GT 650M (RK5) and one i5-3230M core in the paper; context only")
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, args.cpu_sample)
-        fpos = cb.pop("flops_per_orbit_step")
+        oracle_fpos = cb.pop("oracle_flops_per_orbit_step")
         cb.pop("labels")
         # The whole workload on the same host threads, extrapolated from the
         # sample's rate (never run).
         cb["extrapolated_full_s"] = orbit_steps / cb["value"]
         line["cpu_baseline"] = cb
-        achieved = fpos * orbit_steps / (kernel_ms * 1e-3) / 1e12
+        achieved = ALG_FLOPS_PER_ORBIT_STEP * orbit_steps / (kernel_ms * 1e-3) / 1e12
         traffic = None
         if TRAFFIC["sources_sha256"] == sources_sha256():
             traffic = TRAFFIC["bytes_per_scan"].get(wl.name)
         line["roofline"] = dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
                                 frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=traffic,
                                 kernel=kernel, kernel_ms=kernel_ms,
-                                flops_per_orbit_step=fpos)
+                                flops_per_orbit_step=ALG_FLOPS_PER_ORBIT_STEP,
+                                oracle_flops_per_orbit_step=oracle_fpos)
+        hw = hardware_flops(kernel.split("<")[0])
+        if hw is not None:
+            line["roofline"]["hw_flops_per_orbit_step"] = hw
+            line["roofline"]["hw_frac"] = (hw * orbit_steps / (kernel_ms * 1e-3) / 1e12 /
+                                           FP64_VECTOR_PEAK_TFLOPS)
         if not batched:
             # Registers, spills and occupancy of the scan kernel as the
             # runtime reports them, and the wavefronts per SIMD the launch

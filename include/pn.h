@@ -55,7 +55,7 @@ extern "C" {
 
 typedef enum {
     PN_OK = 0,
-    PN_EINVAL = 1,   /* null pointer, n < 0 or n > 2^35, ld < n, parameter out of range, unknown enum */
+    PN_EINVAL = 1,   /* null pointer, n < 0 or n > 2^31 - 1, ld < n, parameter out of range, unknown enum */
     PN_ENOWS = 2,    /* workspace smaller than the documented size */
     PN_EDEVICE = 3   /* HIP error while launching */
 } pn_status;
@@ -585,6 +585,30 @@ typedef struct {
 
 void pn_default_surrogate_cfg(pn_surrogate_cfg* cfg);
 
+/* What one pn_surrogate_scan call did, from events on its stream and counts
+ * read back by the call.  Index 0 is the audit integration (step 2), index 1
+ * the fallback integration (step 5).
+ *   phase_ms[4]     milliseconds of the audit (features, draw, integration),
+ *                   the refinement, inference with the gate, and the
+ *                   fallback integration (gathers and merge included)
+ *   scan_ms[2]      milliseconds of the FP64 scan launches alone (the scan
+ *                   call of each integration, nothing else)
+ *   scan_kernel[2]  0 none, 1 the plain fused scan (k_fli_scan), 2 the
+ *                   balanced schedule (k_wrap_scan), 3 the persistent batch
+ *                   (k_batch_scan)
+ *   scan_launches[2] launches of that scan kernel
+ *   points[2]       points integrated
+ *   orbit_steps[2]  orbit-steps integrated (the sum of the points' completed
+ *                   steps; a removed orbit counts the steps it took) */
+typedef struct {
+    float phase_ms[4];
+    float scan_ms[2];
+    int32_t scan_kernel[2];
+    int32_t scan_launches[2];
+    int64_t points[2];
+    int64_t orbit_steps[2];
+} pn_surrogate_stats;
+
 /* Bytes of workspace for pn_surrogate_scan over n points (0 if n is out of
  * range or refine_batch <= 0). */
 size_t pn_surrogate_scan_workspace_size(int64_t n, int32_t refine_batch);
@@ -609,11 +633,9 @@ size_t pn_surrogate_scan_workspace_size(int64_t n, int32_t refine_batch);
  * t_end[i] or t_end_all.  label: [n] int8 device output; *integrated: host
  * output, the number of points integrated; points (nullable): [n] int32
  * device output whose first *integrated entries are the integrated points
- * (the sorted audit, then the uncertain ones); phase_ms (nullable): host
- * float[4], milliseconds of the audit (features, draw, integration), the
- * refinement, inference with the gate, and the fallback integration.  net is
- * updated by the
- * refinement.  ws: caller-owned device workspace of at least
+ * (the sorted audit, then the uncertain ones); stats (nullable): host
+ * output, timings and counts of the call (pn_surrogate_stats).  net is
+ * updated by the refinement.  ws: caller-owned device workspace of at least
  * pn_surrogate_scan_workspace_size(n, cfg->refine_batch) bytes.  Blocks the
  * calling thread (it reads the audit and gate counts back); calls sharing a
  * workspace or a network must not overlap.  Errors: PN_EINVAL for invalid
@@ -624,7 +646,7 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
                             const double* th1, const double* ph1, const double* th2,
                             const double* ph2, const double* t_end, double t_end_all,
                             const float* mean, const float* stdv, const pn_surrogate_cfg* cfg,
-                            int8_t* label, int32_t* points, int64_t* integrated, float* phase_ms,
+                            int8_t* label, int32_t* points, int64_t* integrated, pn_surrogate_stats* stats,
                             void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Initial states of selected points: like pn_init_state, but point j takes

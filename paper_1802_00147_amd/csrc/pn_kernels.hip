@@ -883,9 +883,10 @@ CorrArgs corr_args(const pn_correction* c) {
 
 unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-// Largest orbit count of a launch with one or two lanes per orbit: its grid
-// of 64-lane workgroups stays at or below 2^30.
-constexpr int64_t kMaxN = (int64_t)1 << 35;
+// Largest orbit count of a call: with two lanes per orbit a launch stays
+// below HIP's limit of 2^32 work-items in x, and the balanced scan's pair
+// records hold orbit indices in 32 bits.
+constexpr int64_t kMaxN = ((int64_t)1 << 31) - 1;
 
 pn_status launched(const char* what) {
     const hipError_t e = hipGetLastError();

@@ -708,6 +708,22 @@ __global__ __launch_bounds__(256) void k_merge(const int32_t* list, int64_t m, c
     if (j < m) label[list[j]] = integrated[j];
 }
 
+// *total += steps[0] + ... + steps[m - 1]: a grid-stride partial sum per
+// lane, a workgroup sum in LDS, one atomic per workgroup.
+__global__ __launch_bounds__(256) void k_sum_steps(const int64_t* steps, int64_t m, unsigned long long* total) {
+    __shared__ unsigned long long part[256];
+    unsigned long long s = 0;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < m; j += (int64_t)gridDim.x * 256)
+        s += (unsigned long long)steps[j];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(total, part[0]);
+}
+
 unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 constexpr int64_t kSplitFloats = (int64_t)1 << 20;   // partial-sum buffer of a split product (4 MB)
@@ -1084,8 +1100,8 @@ static size_t wrap_region_bytes(int64_t n) {
 size_t pn_surrogate_scan_workspace_size(int64_t n, int32_t refine_batch) {
     if (n <= 0 || n > 0x7fffffffLL || refine_batch <= 0) return 0;
     const size_t N = (size_t)n;
-    return 2 * al(N * kFeatLd * 4) + al(N * 2 * 4) + 3 * al(N * 4) + al(2 * 8) + al(12 * N * 8) + 4 * al(N * 8) +
-           al(N * 8) + al(N) + al(N * 4) + 2 * al(N * 4) + al(4) + pn_batch_workspace_size(n) +
+    return 2 * al(N * kFeatLd * 4) + al(N * 2 * 4) + 3 * al(N * 4) + al(4 * 8) + al(12 * N * 8) + 4 * al(N * 8) +
+           al(N * 8) + al(N) + al(N * 4) + al(N * 8) + 2 * al(N * 4) + al(4) + pn_batch_workspace_size(n) +
            al(wrap_region_bytes(n)) + pn_mlp_train_workspace_size(refine_batch);
 }
 
@@ -1128,8 +1144,8 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
                             int64_t n, const double* r0, const double* p0, const double* th1, const double* ph1,
                             const double* th2, const double* ph2, const double* t_end, double t_end_all,
                             const float* mean, const float* stdv, const pn_surrogate_cfg* cfg, int8_t* label,
-                            int32_t* points, int64_t* integrated, float* phase_ms, void* ws, size_t ws_bytes,
-                            hipStream_t stream) {
+                            int32_t* points, int64_t* integrated, pn_surrogate_stats* stats, void* ws,
+                            size_t ws_bytes, hipStream_t stream) {
     const char* what = "pn_surrogate_scan";
     if (!cfg || !label || !integrated || n < 0 || n > 0x7fffffffLL) return PN_EINVAL;
     if (!(cfg->margin >= 0.0f) || !(cfg->audit_frac >= 0.0 && cfg->audit_frac <= 1.0)) return PN_EINVAL;
@@ -1160,13 +1176,16 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
     int32_t* listA = (int32_t*)take(N * 4);
     int32_t* listU = (int32_t*)take(N * 4);
     int32_t* order = (int32_t*)take(N * 4);
-    unsigned long long* counts = (unsigned long long*)take(2 * 8);
+    // counts: [0] audit points, [1] uncertain points, [2], [3] orbit-steps
+    // integrated by the audit and by the fallback.
+    unsigned long long* counts = (unsigned long long*)take(4 * 8);
     double* y0 = (double*)take(12 * N * 8);
     double* gp[4];
     for (int c = 0; c < 4; ++c) gp[c] = (double*)take(N * 8);
     double* sfli = (double*)take(N * 8);
     int8_t* slab = (int8_t*)take(N);
     int32_t* sstat = (int32_t*)take(N * 4);
+    int64_t* ssteps = (int64_t*)take(N * 8);
     float* labA = (float*)take(N * 4);
     float* tgtA = (float*)take(N * 4);
     float* loss = (float*)take(4);
@@ -1176,11 +1195,29 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
     void* tws = take(pn_mlp_train_workspace_size(cfg->refine_batch));
     const bool per_orbit = params.beta != nullptr;
 
-    // Integrate the m listed points, labels into slab[0..m): points that all
-    // end at t_end_all through the balanced scan (which keeps the plain fused
-    // scan where that is predicted faster), others with the persistent batch
-    // kernel (a10).
-    auto integrate = [&](const int32_t* list, int64_t m) -> pn_status {
+    // Phase timing from events on the stream: ev[0..4] bound the four
+    // phases, ev[5..6] and ev[7..8] the scan call of the audit and of the
+    // fallback integration.
+    hipEvent_t ev[9] = {};
+    struct EventGuard {
+        hipEvent_t* e;
+        ~EventGuard() { for (int k = 0; k < 9; ++k) if (e[k]) (void)hipEventDestroy(e[k]); }
+    } guard{ev};
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        for (int k = 0; k < 9; ++k) PN_HIP(hipEventCreate(&ev[k]), what);
+    }
+    auto mark = [&](int k) -> pn_status {
+        if (stats) PN_HIP(hipEventRecord(ev[k], stream), what);
+        return PN_OK;
+    };
+
+    // Integrate the m listed points (phase 0: audit, 1: fallback), labels
+    // into slab[0..m), completed steps summed into counts[2 + phase]: points
+    // that all end at t_end_all through the balanced scan (which keeps the
+    // plain fused scan where that is predicted faster), others with the
+    // persistent batch kernel (a10).
+    auto integrate = [&](const int32_t* list, int64_t m, int phase) -> pn_status {
         PN_TRY(pn_init_state_gather(model, params, m, list, r0, p0, th1, ph1, th2, ph2, y0, m, stream));
         const unsigned g = blocks_for(m, 256);
         hipLaunchKernelGGL(k_gather_f64, dim3(g), dim3(256), 0, stream, t_end, t_end_all, list, m, gp[3]);
@@ -1194,37 +1231,44 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
         PN_TRY(launched(what));
         pn_scan_out so;
         std::memset(&so, 0, sizeof(so));
-        so.fli = sfli; so.label = slab; so.status = sstat;
+        so.fli = sfli; so.label = slab; so.status = sstat; so.steps = ssteps;
+        int32_t kind = 3, launches = 1;
+        bool balanced = false;
         if (t_end == nullptr) {
             int64_t slots = 0;
-            PN_TRY(pn_fli_scan_balanced_schedule(integ, corr, m, t_end_all, 0, &slots, nullptr, nullptr));
-            if (pn_fli_scan_balanced_workspace_size(slots) <= wrap_bytes)
-                return pn_fli_scan_balanced(model, q, integ, corr, fli, m, y0, m, t_end_all, &so, 0, wws,
-                                            wrap_bytes, stream);
+            int32_t nl = 0;
+            PN_TRY(pn_fli_scan_balanced_schedule(integ, corr, m, t_end_all, 0, &slots, nullptr, &nl));
+            if (pn_fli_scan_balanced_workspace_size(slots) <= wrap_bytes) {
+                balanced = true;
+                kind = nl > 0 ? 2 : 1;
+                launches = nl > 0 ? nl : 1;
+            }
         }
-        return pn_batch_scan(model, q, integ, corr, fli, m, y0, m, gp[3], &so, nullptr, bws,
-                             pn_batch_workspace_size(m), stream);
-    };
-
-    // Phase timing (host array phase_ms[4]: audit, refinement, inference and
-    // gate, fallback integration), from events on the stream.
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    struct EventGuard {
-        hipEvent_t* e;
-        ~EventGuard() { for (int k = 0; k < 5; ++k) if (e[k]) (void)hipEventDestroy(e[k]); }
-    } guard{ev};
-    if (phase_ms)
-        for (int k = 0; k < 5; ++k) PN_HIP(hipEventCreate(&ev[k]), what);
-    auto mark = [&](int k) -> pn_status {
-        if (phase_ms) PN_HIP(hipEventRecord(ev[k], stream), what);
+        PN_TRY(mark(5 + 2 * phase));
+        if (balanced) {
+            PN_TRY(pn_fli_scan_balanced(model, q, integ, corr, fli, m, y0, m, t_end_all, &so, 0, wws, wrap_bytes,
+                                        stream));
+        } else {
+            PN_TRY(pn_batch_scan(model, q, integ, corr, fli, m, y0, m, gp[3], &so, nullptr, bws,
+                                 pn_batch_workspace_size(m), stream));
+        }
+        PN_TRY(mark(6 + 2 * phase));
+        hipLaunchKernelGGL(k_sum_steps, dim3(g < 1024 ? g : 1024), dim3(256), 0, stream, ssteps, m,
+                           counts + 2 + phase);
+        PN_TRY(launched(what));
+        if (stats) {
+            stats->scan_kernel[phase] = kind;
+            stats->scan_launches[phase] = launches;
+            stats->points[phase] = m;
+        }
         return PN_OK;
     };
+
     PN_TRY(mark(0));
     // 1. Features of every point; the audit list, sorted so that everything
     //    derived from it is independent of the order of the atomic appends.
     PN_TRY(pn_mlp_features(params, n, r0, th1, th2, t_end, t_end_all, nullptr, mean, stdv, feat, stream));
-    hipLaunchKernelGGL(k_clear_count, dim3(1), dim3(1), 0, stream, counts);
-    hipLaunchKernelGGL(k_clear_count, dim3(1), dim3(1), 0, stream, counts + 1);
+    for (int c = 0; c < 4; ++c) hipLaunchKernelGGL(k_clear_count, dim3(1), dim3(1), 0, stream, counts + c);
     hipLaunchKernelGGL(k_audit, dim3(blocks_for(n, 256)), dim3(256), 0, stream, n, cfg->audit_frac,
                        (unsigned long long)cfg->seed, listA, counts);
     PN_TRY(launched(what));
@@ -1257,7 +1301,7 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
     int64_t m1 = ma;
     if (round > 0 && ma >= round) m1 = (ma / round) * round;
     const int64_t m2 = ma - m1;                            // audit points left for step 5
-    if (m1 > 0) PN_TRY(integrate(listA, m1));
+    if (m1 > 0) PN_TRY(integrate(listA, m1, 0));
     PN_TRY(mark(1));
     // 3. Refine the network on the integrated audit points (valid orbits
     //    only), in a SplitMix64-seeded order per epoch.
@@ -1320,7 +1364,7 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
                 PN_HIP(hipMemcpyAsync(order + m2, listU, (size_t)mu * 4, hipMemcpyDeviceToDevice, stream), what);
             list5 = order;
         }
-        PN_TRY(integrate(list5, m2 + mu));
+        PN_TRY(integrate(list5, m2 + mu, 1));
         PN_TRY(pn_surrogate_merge(list5, m2 + mu, slab, label, stream));
     }
     if (points) {
@@ -1328,9 +1372,16 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
         if (mu > 0) PN_HIP(hipMemcpyAsync(points + ma, listU, (size_t)mu * 4, hipMemcpyDeviceToDevice, stream), what);
     }
     PN_TRY(mark(4));
-    if (phase_ms) {
-        PN_HIP(hipEventSynchronize(ev[4]), what);
-        for (int k = 0; k < 4; ++k) PN_HIP(hipEventElapsedTime(&phase_ms[k], ev[k], ev[k + 1]), what);
+    if (stats) {
+        unsigned long long steps2[2] = {0, 0};
+        PN_HIP(hipMemcpyAsync(steps2, counts + 2, 16, hipMemcpyDeviceToHost, stream), what);
+        PN_HIP(hipStreamSynchronize(stream), what);
+        for (int k = 0; k < 4; ++k) PN_HIP(hipEventElapsedTime(&stats->phase_ms[k], ev[k], ev[k + 1]), what);
+        for (int k = 0; k < 2; ++k) {
+            if (stats->scan_launches[k] > 0)
+                PN_HIP(hipEventElapsedTime(&stats->scan_ms[k], ev[5 + 2 * k], ev[6 + 2 * k]), what);
+            stats->orbit_steps[k] = (int64_t)steps2[k];
+        }
     }
     *integrated = ma + mu;
     return PN_OK;

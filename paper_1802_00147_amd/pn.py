@@ -71,6 +71,15 @@ class SurrogateCfg(ctypes.Structure):
                 ("refine_seed", ctypes.c_uint64), ("refine_cosine", ctypes.c_int32), ("audit_split", ctypes.c_int64)]
 
 
+class SurrogateStats(ctypes.Structure):
+    _fields_ = [("phase_ms", ctypes.c_float * 4), ("scan_ms", ctypes.c_float * 2),
+                ("scan_kernel", ctypes.c_int32 * 2), ("scan_launches", ctypes.c_int32 * 2),
+                ("points", ctypes.c_int64 * 2), ("orbit_steps", ctypes.c_int64 * 2)]
+
+
+SCAN_KERNELS = {0: None, 1: "k_fli_scan", 2: "k_wrap_scan", 3: "k_batch_scan"}
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32), ("chunk_steps", ctypes.c_int32)]
 
@@ -717,8 +726,10 @@ def surrogate_cfg(over=None):
 def surrogate_scan(net, n, r0, p0, th1, ph1, th2, ph2, t_end, beta, chi1, chi2, mean, std, cfg=None, model=None,
                    integrator=None, correction=None, fli=None, ws=None):
     """pn_surrogate_scan: dict(label int8 [n], integrated, points int32 [integrated],
-    phase_ms [audit, refine, infer+gate, fallback], ws).  The network is refined
-    in place (net.step counts its Adam steps)."""
+    phase_ms [audit, refine, infer+gate, fallback], scans (per integration, audit
+    then fallback: kernel name, launches, points, orbit_steps, ms of the scan
+    launches alone), ws).  The network is refined in place (net.step counts its
+    Adam steps)."""
     dev_ = r0.device
     c = surrogate_cfg(cfg)
     need = int(lib().pn_surrogate_scan_workspace_size(n, c.refine_batch))
@@ -726,7 +737,7 @@ def surrogate_scan(net, n, r0, p0, th1, ph1, th2, ph2, t_end, beta, chi1, chi2, 
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev_)
     label = torch.empty(max(n, 1), dtype=torch.int8, device=dev_)
     points = torch.empty(max(n, 1), dtype=torch.int32, device=dev_)
-    phase = (ctypes.c_float * 4)()
+    stats = SurrogateStats()
     p, keep = params_struct(beta, chi1, chi2)
     mean = (ctypes.c_float * 7)(*[float(x) for x in mean])
     std = (ctypes.c_float * 7)(*[float(x) for x in std])
@@ -741,12 +752,14 @@ def surrogate_scan(net, n, r0, p0, th1, ph1, th2, ph2, t_end, beta, chi1, chi2, 
                                  ctypes.byref(integrator_struct(integrator)),
                                  ctypes.byref(correction_struct(correction)), ctypes.byref(fli_struct(fli)),
                                  ctypes.c_int64(n), *[_ptr(t) for t in cols], tptr, ctypes.c_double(tall), mean, std,
-                                 ctypes.byref(c), _ptr(label), _ptr(points), ctypes.byref(integrated), phase,
+                                 ctypes.byref(c), _ptr(label), _ptr(points), ctypes.byref(integrated), ctypes.byref(stats),
                                  _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(dev_))
     _check("pn_surrogate_scan", st)
     net.step = step.value
     m = integrated.value
-    return dict(label=label[:n], integrated=m, points=points[:m], phase_ms=list(phase), ws=ws)
+    scans = [dict(kernel=SCAN_KERNELS[stats.scan_kernel[k]], launches=stats.scan_launches[k],
+                  points=stats.points[k], orbit_steps=stats.orbit_steps[k], ms=stats.scan_ms[k]) for k in range(2)]
+    return dict(label=label[:n], integrated=m, points=points[:m], phase_ms=list(stats.phase_ms), scans=scans, ws=ws)
 
 
 def surrogate_gate(out, margin, audit_frac, seed):

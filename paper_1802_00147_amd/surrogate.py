@@ -98,6 +98,7 @@ class SurrogateResult:
     points: torch.Tensor         # their indices (int32)
     timings: dict = field(default_factory=dict)
     ws: object = None            # the device workspace, reusable by the next call
+    scans: list = field(default_factory=list)   # the audit's and the fallback's FP64 scan launches
 
 
 def surrogate_scan(net, wl, stats, margin=0.5, audit=0.01, seed=5, model=None,
@@ -126,4 +127,4 @@ def surrogate_scan(net, wl, stats, margin=0.5, audit=0.01, seed=5, model=None,
     ph = r["phase_ms"]
     t = dict(audit_s=ph[0] * 1e-3, refine_s=ph[1] * 1e-3, infer_gate_s=ph[2] * 1e-3, fallback_s=ph[3] * 1e-3,
              total_s=time.perf_counter() - t0)
-    return SurrogateResult(r["label"], r["integrated"], r["points"], t, r["ws"])
+    return SurrogateResult(r["label"], r["integrated"], r["points"], t, r["ws"], r["scans"])

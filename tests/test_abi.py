@@ -278,12 +278,14 @@ def test_scan_kernel_resources_arguments(pn):
 
 
 def test_orbit_counts_beyond_the_launch_limit_rejected(pn):
-    """n above 2^35 would overflow a launch grid: refused before launch."""
+    """n above 2^31 - 1 would overflow a launch grid of two lanes per orbit
+    (HIP allows fewer than 2^32 work-items in x) and the 32-bit orbit indices
+    of the balanced scan's records: refused before launch."""
     L = pn.lib()
     one = ctypes.c_void_p(8)
     m = pn.model_struct()
     p = pn.Params(None, None, None, 1.0, 1.0, 1.0)
-    big = ctypes.c_int64((1 << 35) + 1)
+    big = ctypes.c_int64(1 << 31)
     assert L.pn_rhs(ctypes.byref(m), p, big, one, big, one, None) == pn.PN_EINVAL
     assert L.pn_step(ctypes.byref(m), p, ctypes.byref(pn.integrator_struct()), None, big, one, big, None,
                      ctypes.c_int64(1), None) == pn.PN_EINVAL
