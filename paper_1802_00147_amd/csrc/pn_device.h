@@ -165,37 +165,76 @@ __device__ __forceinline__ void pn_rhs_eval(const PnCoef& k, const double* y, do
     f[11] = o2x * s2y - o2y * s2x;
 }
 
+// Quantities of the spins alone, fixed while a correction moves r and p:
+// the effective spin-orbit vector S_eff = cso1 S1 + cso2 S2 and the spin
+// products.
+struct PnSpinInv { double ex, ey, ez, S11, S22, S12; };
+
+__device__ __forceinline__ PnSpinInv pn_spin_inv(const PnCoef& k, const double* y) {
+    const double s1x = y[6], s1y = y[7], s1z = y[8];
+    const double s2x = y[9], s2y = y[10], s2z = y[11];
+    PnSpinInv v;
+    v.ex = k.cso1 * s1x + k.cso2 * s2x;
+    v.ey = k.cso1 * s1y + k.cso2 * s2y;
+    v.ez = k.cso1 * s1z + k.cso2 * s2z;
+    v.S11 = dot3(s1x, s1y, s1z, s1x, s1y, s1z);
+    v.S22 = dot3(s2x, s2y, s2z, s2x, s2y, s2z);
+    v.S12 = dot3(s1x, s1y, s1z, s2x, s2y, s2z);
+    return v;
+}
+
+// Geometry of the position with fixed spins: u = 1/r and its powers, n, the
+// spin projections a_i = S_i.n and the spin-spin brackets of H (3 a a - S.S,
+// eqs. 3-5), of dH/dr along n (5 a a - S.S) and of dH/dr along S_i (w_i).
+// It does not depend on p, so a momentum scaling leaves it valid.
+struct PnRGeom { double u, u2, u3, u4, nx, ny, nz, Hss3, Hss5, w1, w2; };
+
+__device__ __forceinline__ PnRGeom pn_rgeom(const PnCoef& k, const PnSpinInv& si, const double* y) {
+    const double rx = y[0], ry = y[1], rz = y[2];
+    PnRGeom g;
+    g.u = pn_rsqrt(dot3(rx, ry, rz, rx, ry, rz));
+    g.u2 = g.u * g.u;
+    g.u3 = g.u2 * g.u;
+    g.u4 = g.u2 * g.u2;
+    g.nx = rx * g.u;
+    g.ny = ry * g.u;
+    g.nz = rz * g.u;
+    const double sn1 = dot3(y[6], y[7], y[8], g.nx, g.ny, g.nz);
+    const double sn2 = dot3(y[9], y[10], y[11], g.nx, g.ny, g.nz);
+    g.Hss3 = k.c12 * (3.0 * sn1 * sn2 - si.S12) + k.c11 * (3.0 * sn1 * sn1 - si.S11)
+           + k.c22 * (3.0 * sn2 * sn2 - si.S22);
+    g.Hss5 = k.c12 * (5.0 * sn1 * sn2 - si.S12) + k.c11 * (5.0 * sn1 * sn1 - si.S11)
+           + k.c22 * (5.0 * sn2 * sn2 - si.S22);
+    g.w1 = 3.0 * k.c12 * sn2 + 6.0 * k.c11 * sn1;
+    g.w2 = 3.0 * k.c12 * sn1 + 6.0 * k.c22 * sn2;
+    return g;
+}
+
 // Energy as a polynomial in a momentum scale factor a (r and spins fixed):
 // H(r, a p, S) = K0 + K1 a + K2 a^2 + K4 a^4 + K6 a^6.
 struct PnEnergyPoly { double K0, K1, K2, K4, K6; };
 
-__device__ __forceinline__ PnEnergyPoly pn_energy_poly(const PnCoef& k, const double* y) {
+__device__ __forceinline__ PnEnergyPoly pn_energy_poly_g(const PnCoef& k, const PnSpinInv& si, const PnRGeom& g,
+                                                         const double* y) {
     const double rx = y[0], ry = y[1], rz = y[2];
     const double px = y[3], py = y[4], pz = y[5];
-    const double s1x = y[6], s1y = y[7], s1z = y[8];
-    const double s2x = y[9], s2y = y[10], s2z = y[11];
-    const double r2 = dot3(rx, ry, rz, rx, ry, rz);
-    const double u = pn_rsqrt(r2);
-    const double u2 = u * u, u3 = u2 * u;
     const double P2 = dot3(px, py, pz, px, py, pz);
-    const double NP = dot3(rx, ry, rz, px, py, pz) * u;
+    const double NP = dot3(g.nx, g.ny, g.nz, px, py, pz);
     const double NP2 = NP * NP;
     const double Lx = ry * pz - rz * py, Ly = rz * px - rx * pz, Lz = rx * py - ry * px;
-    const double LS = k.cso1 * dot3(Lx, Ly, Lz, s1x, s1y, s1z) + k.cso2 * dot3(Lx, Ly, Lz, s2x, s2y, s2z);
-    const double sn1 = dot3(s1x, s1y, s1z, rx, ry, rz) * u;
-    const double sn2 = dot3(s2x, s2y, s2z, rx, ry, rz) * u;
-    const double S12 = dot3(s1x, s1y, s1z, s2x, s2y, s2z);
-    const double S11 = dot3(s1x, s1y, s1z, s1x, s1y, s1z);
-    const double S22 = dot3(s2x, s2y, s2z, s2x, s2y, s2z);
+    const double LS = dot3(Lx, Ly, Lz, si.ex, si.ey, si.ez);
     PnEnergyPoly e;
-    e.K0 = -u + k.a4 * u2 + k.b7 * u3
-         + u3 * (k.c12 * (3.0 * sn1 * sn2 - S12) + k.c11 * (3.0 * sn1 * sn1 - S11)
-                 + k.c22 * (3.0 * sn2 * sn2 - S22));
-    e.K1 = u3 * LS;
-    e.K2 = 0.5 * P2 + fma(k.a2, P2, k.a3 * NP2) * u + fma(k.b5, P2, k.b6 * NP2) * u2;
-    e.K4 = k.a1 * P2 * P2 + (k.b2 * P2 * P2 + k.b3 * P2 * NP2 + k.b4 * NP2 * NP2) * u;
+    e.K0 = -g.u + k.a4 * g.u2 + k.b7 * g.u3 + g.u3 * g.Hss3;
+    e.K1 = g.u3 * LS;
+    e.K2 = 0.5 * P2 + fma(k.a2, P2, k.a3 * NP2) * g.u + fma(k.b5, P2, k.b6 * NP2) * g.u2;
+    e.K4 = k.a1 * P2 * P2 + (k.b2 * P2 * P2 + k.b3 * P2 * NP2 + k.b4 * NP2 * NP2) * g.u;
     e.K6 = k.b1 * P2 * P2 * P2;
     return e;
+}
+
+__device__ __forceinline__ PnEnergyPoly pn_energy_poly(const PnCoef& k, const double* y) {
+    const PnSpinInv si = pn_spin_inv(k, y);
+    return pn_energy_poly_g(k, si, pn_rgeom(k, si, y), y);
 }
 
 __device__ __forceinline__ double pn_energy(const PnCoef& k, const double* y) {
@@ -203,17 +242,15 @@ __device__ __forceinline__ double pn_energy(const PnCoef& k, const double* y) {
     return e.K0 + e.K1 + e.K2 + e.K4 + e.K6;
 }
 
-// H and its gradient with respect to r and p (spins held fixed).
-__device__ __forceinline__ void pn_energy_grad_rp(const PnCoef& k, const double* y, double& H,
-                                                  double* gr, double* gp) {
+// H and its gradient with respect to r and p (spins held fixed), given the
+// geometry of r.
+__device__ __forceinline__ void pn_energy_grad_g(const PnCoef& k, const PnSpinInv& si, const PnRGeom& g,
+                                                 const double* y, double& H, double* gr, double* gp) {
     const double rx = y[0], ry = y[1], rz = y[2];
     const double px = y[3], py = y[4], pz = y[5];
-    const double s1x = y[6], s1y = y[7], s1z = y[8];
-    const double s2x = y[9], s2y = y[10], s2z = y[11];
-    const double r2 = dot3(rx, ry, rz, rx, ry, rz);
-    const double u = pn_rsqrt(r2);
-    const double u2 = u * u, u3 = u2 * u, u4 = u2 * u2;
-    const double nx = rx * u, ny = ry * u, nz = rz * u;
+    const double u = g.u, u2 = g.u2, u3 = g.u3, u4 = g.u4;
+    const double nx = g.nx, ny = g.ny, nz = g.nz;
+    const double ex = si.ex, ey = si.ey, ez = si.ez;
     const double P2 = dot3(px, py, pz, px, py, pz);
     const double NP = dot3(nx, ny, nz, px, py, pz);
     const double NP2 = NP * NP;
@@ -224,34 +261,26 @@ __device__ __forceinline__ void pn_energy_grad_rp(const PnCoef& k, const double*
                     + (k.b2 * P2 * P2 + k.b3 * P2 * NP2 + k.b4 * NP2 * NP2)
                     + 2.0 * fma(k.b5, P2, k.b6 * NP2) * u + 3.0 * k.b7 * u2;
     const double Lx = ry * pz - rz * py, Ly = rz * px - rx * pz, Lz = rx * py - ry * px;
-    const double ex = k.cso1 * s1x + k.cso2 * s2x;
-    const double ey = k.cso1 * s1y + k.cso2 * s2y;
-    const double ez = k.cso1 * s1z + k.cso2 * s2z;
     const double LS = dot3(Lx, Ly, Lz, ex, ey, ez);
-    const double sn1 = dot3(s1x, s1y, s1z, nx, ny, nz);
-    const double sn2 = dot3(s2x, s2y, s2z, nx, ny, nz);
-    const double S12 = dot3(s1x, s1y, s1z, s2x, s2y, s2z);
-    const double S11 = dot3(s1x, s1y, s1z, s1x, s1y, s1z);
-    const double S22 = dot3(s2x, s2y, s2z, s2x, s2y, s2z);
-    const double w1 = 3.0 * k.c12 * sn2 + 6.0 * k.c11 * sn1;
-    const double w2 = 3.0 * k.c12 * sn1 + 6.0 * k.c22 * sn2;
-    const double Hss = k.c12 * (3.0 * sn1 * sn2 - S12) + k.c11 * (3.0 * sn1 * sn1 - S11)
-                     + k.c22 * (3.0 * sn2 * sn2 - S22);
     H = 0.5 * P2 - u + k.a1 * P2 * P2 + fma(k.a2, P2, k.a3 * NP2) * u + k.a4 * u2
       + k.b1 * P2 * P2 * P2 + (k.b2 * P2 * P2 + k.b3 * P2 * NP2 + k.b4 * NP2 * NP2) * u
-      + fma(k.b5, P2, k.b6 * NP2) * u2 + k.b7 * u3 + u3 * LS + u3 * Hss;
+      + fma(k.b5, P2, k.b6 * NP2) * u2 + k.b7 * u3 + u3 * LS + u3 * g.Hss3;
     const double cp = 2.0 * HP2;
     gp[0] = cp * px + HNP * nx + u3 * (ey * rz - ez * ry);
     gp[1] = cp * py + HNP * ny + u3 * (ez * rx - ex * rz);
     gp[2] = cp * pz + HNP * nz + u3 * (ex * ry - ey * rx);
     const double Ap = HNP * u;
-    const double An = -Ap * NP - Hu * u2 - 3.0 * u4 * LS
-                    - 3.0 * u4 * (k.c12 * (5.0 * sn1 * sn2 - S12) + k.c11 * (5.0 * sn1 * sn1 - S11)
-                                  + k.c22 * (5.0 * sn2 * sn2 - S22));
-    const double B1 = u4 * w1, B2 = u4 * w2;
-    gr[0] = An * nx + Ap * px + B1 * s1x + B2 * s2x + u3 * (py * ez - pz * ey);
-    gr[1] = An * ny + Ap * py + B1 * s1y + B2 * s2y + u3 * (pz * ex - px * ez);
-    gr[2] = An * nz + Ap * pz + B1 * s1z + B2 * s2z + u3 * (px * ey - py * ex);
+    const double An = -Ap * NP - Hu * u2 - 3.0 * u4 * LS - 3.0 * u4 * g.Hss5;
+    const double B1 = u4 * g.w1, B2 = u4 * g.w2;
+    gr[0] = An * nx + Ap * px + B1 * y[6] + B2 * y[9] + u3 * (py * ez - pz * ey);
+    gr[1] = An * ny + Ap * py + B1 * y[7] + B2 * y[10] + u3 * (pz * ex - px * ez);
+    gr[2] = An * nz + Ap * pz + B1 * y[8] + B2 * y[11] + u3 * (px * ey - py * ex);
+}
+
+__device__ __forceinline__ void pn_energy_grad_rp(const PnCoef& k, const double* y, double& H,
+                                                  double* gr, double* gp) {
+    const PnSpinInv si = pn_spin_inv(k, y);
+    pn_energy_grad_g(k, si, pn_rgeom(k, si, y), y, H, gr, gp);
 }
 
 // Total angular momentum J = r x p + S1 + S2.
@@ -271,12 +300,20 @@ __device__ __forceinline__ void pn_correct_spins(const PnCoef& k, double* y) {
     y[9] *= f2; y[10] *= f2; y[11] *= f2;
 }
 
+// 1/x to a relative error near the square of the hardware estimate's (one
+// Newton step): for the Newton updates and the multipliers of the
+// projection, whose results are corrections of order 1e-10 of the state and
+// need far fewer correct bits than the state itself.
+__device__ __forceinline__ double pn_rcp1(double x) {
+    const double y = __builtin_amdgcn_rcp(x);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+
 // Energy restoration by momentum scaling: Newton on a for
 // g(a) = H(r, a p, S) - E0 using the polynomial form of H in a.
 // Returns the iteration count; *conv is false if max_iter was reached.
-__device__ __forceinline__ int pn_energy_scale(const PnCoef& k, double* y, double E0, double tol,
-                                               int max_iter, bool& conv) {
-    const PnEnergyPoly e = pn_energy_poly(k, y);
+__device__ __forceinline__ int pn_energy_scale_poly(const PnEnergyPoly& e, double* y, double E0, double tol,
+                                                    int max_iter, bool& conv) {
     double a = 1.0;
     int it = 0;
     conv = false;
@@ -284,7 +321,7 @@ __device__ __forceinline__ int pn_energy_scale(const PnCoef& k, double* y, doubl
         const double a2 = a * a, a3 = a2 * a;
         const double g = fma(fma(fma(e.K6, a2, e.K4), a2, e.K2), a2, fma(e.K1, a, e.K0)) - E0;
         const double dg = fma(fma(6.0 * e.K6, a2, 4.0 * e.K4), a3, fma(2.0 * e.K2, a, e.K1));
-        const double da = -g * pn_rcp(dg);
+        const double da = -g * pn_rcp1(dg);
         a += da;
         ++it;
         if (fabs(da) <= tol) { conv = true; break; }
@@ -293,16 +330,22 @@ __device__ __forceinline__ int pn_energy_scale(const PnCoef& k, double* y, doubl
     return it;
 }
 
+__device__ __forceinline__ int pn_energy_scale(const PnCoef& k, double* y, double E0, double tol,
+                                               int max_iter, bool& conv) {
+    return pn_energy_scale_poly(pn_energy_poly(k, y), y, E0, tol, max_iter, conv);
+}
+
 // Least-squares projection of (r, p) onto H = E0, J = J0 (spins fixed): the
 // smallest displacement d with G d = -c, d = -G^T lam, (G G^T) lam = c, where
 // the rows of G are grad J_x, grad J_y, grad J_z, grad H.  Solved by LDL^T.
 // Near circular orbits the energy row is nearly a combination of the J rows
 // and its pivot d3 vanishes; its multiplier is damped (Tikhonov),
 // lam3 = z3 d3 / (d3^2 + (mu A33)^2) with mu = PN_SIX_MU, which bounds how far
-// rounding in z3 can move the state.
-__device__ __forceinline__ void pn_project_EJ(const PnCoef& k, double* y, const double* ref) {
+// rounding in z3 can move the state.  g is the geometry of the current r.
+__device__ __forceinline__ void pn_project_EJ_g(const PnCoef& k, const PnSpinInv& si, const PnRGeom& geo,
+                                                double* y, const double* ref) {
     double H, gr[3], gp[3], J[3];
-    pn_energy_grad_rp(k, y, H, gr, gp);
+    pn_energy_grad_g(k, si, geo, y, H, gr, gp);
     pn_total_J(y, J);
     const double rx = y[0], ry = y[1], rz = y[2];
     const double px = y[3], py = y[4], pz = y[5];
@@ -316,18 +359,18 @@ __device__ __forceinline__ void pn_project_EJ(const PnCoef& k, double* y, const 
     const double A33 = dot3(gr[0], gr[1], gr[2], gr[0], gr[1], gr[2]) + dot3(gp[0], gp[1], gp[2], gp[0], gp[1], gp[2]);
     const double c0 = J[0] - ref[1], c1 = J[1] - ref[2], c2 = J[2] - ref[3], c3 = H - ref[0];
     // LDL^T.
-    const double d0 = A00, i0 = pn_rcp(d0);
+    const double d0 = A00, i0 = pn_rcp1(d0);
     const double l10 = A10 * i0, l20 = A20 * i0, l30 = A30 * i0;
-    const double d1 = A11 - l10 * l10 * d0, i1 = pn_rcp(d1);
+    const double d1 = A11 - l10 * l10 * d0, i1 = pn_rcp1(d1);
     const double l21 = (A21 - l20 * l10 * d0) * i1;
     const double l31 = (A31 - l30 * l10 * d0) * i1;
-    const double d2 = A22 - l20 * l20 * d0 - l21 * l21 * d1, i2 = pn_rcp(d2);
+    const double d2 = A22 - l20 * l20 * d0 - l21 * l21 * d1, i2 = pn_rcp1(d2);
     const double l32 = (A32 - l30 * l20 * d0 - l31 * l21 * d1) * i2;
     const double d3 = A33 - l30 * l30 * d0 - l31 * l31 * d1 - l32 * l32 * d2;
     const double z0 = c0, z1 = c1 - l10 * z0, z2 = c2 - l20 * z0 - l21 * z1;
     const double z3 = c3 - l30 * z0 - l31 * z1 - l32 * z2;
     const double damp = PN_SIX_MU * A33;
-    const double lam3 = z3 * d3 * pn_rcp(fma(d3, d3, damp * damp));
+    const double lam3 = z3 * d3 * pn_rcp1(fma(d3, d3, damp * damp));
     const double lam2 = z2 * i2 - l32 * lam3;
     const double lam1 = z1 * i1 - l21 * lam2 - l31 * lam3;
     const double lam0 = z0 * i0 - l10 * lam1 - l20 * lam2 - l30 * lam3;
@@ -338,6 +381,25 @@ __device__ __forceinline__ void pn_project_EJ(const PnCoef& k, double* y, const 
     y[3] = px - (lam1 * rz - lam2 * ry) - lam3 * gp[0];
     y[4] = py - (lam2 * rx - lam0 * rz) - lam3 * gp[1];
     y[5] = pz - (lam0 * ry - lam1 * rx) - lam3 * gp[2];
+}
+
+// The six-integral correction after the spin lengths: `sweeps` passes of the
+// joint projection followed by the energy's momentum scaling.  The spins do
+// not move, and the momentum scaling leaves r (so its geometry) unchanged:
+// the geometry computed for the scaling serves the next pass's projection.
+__device__ __forceinline__ int pn_correct_six(const PnCoef& k, double* y, const double* ref, double tol,
+                                              int max_iter, int sweeps, bool& noconv) {
+    const PnSpinInv si = pn_spin_inv(k, y);
+    PnRGeom geo = pn_rgeom(k, si, y);
+    int iters = 0;
+    for (int s = 0; s < sweeps; ++s) {
+        pn_project_EJ_g(k, si, geo, y, ref);
+        geo = pn_rgeom(k, si, y);
+        bool conv;
+        iters += pn_energy_scale_poly(pn_energy_poly_g(k, si, geo, y), y, ref[0], tol, max_iter, conv);
+        noconv = noconv || !conv;
+    }
+    return iters;
 }
 
 // Dual scaling of eqs. (11)-(13): p = alpha p*, r = b r*, Newton on
@@ -397,17 +459,9 @@ __device__ __forceinline__ int pn_correct(const PnCoef& k, double* y, const doub
     if (MODE == PN_CORR_NONE) return 0;
     pn_correct_spins(k, y);
     if (MODE == PN_CORR_SPIN) return 0;
-    int iters = 0;
+    if (MODE == PN_CORR_SIX) return pn_correct_six(k, y, ref, tol, max_iter, sweeps, noconv);
     bool conv = true;
-    if (MODE == PN_CORR_SIX) {
-        for (int s = 0; s < sweeps; ++s) {
-            pn_project_EJ(k, y, ref);
-            iters += pn_energy_scale(k, y, ref[0], tol, max_iter, conv);
-            noconv = noconv || !conv;
-        }
-        return iters;
-    }
-    iters = pn_dual_scale(k, y, ref, tol, max_iter, conv);
+    const int iters = pn_dual_scale(k, y, ref, tol, max_iter, conv);
     noconv = !conv;
     return iters;
 }

@@ -259,9 +259,12 @@ struct FliArgs {
 };
 
 // Exchange a value with the partner lane (lanes 2j and 2j+1 of a wavefront)
-// through DPP quad permutation [1,0,3,2]; no LDS traffic.
+// through DPP quad permutation [1,0,3,2]; no LDS traffic.  The two lanes of
+// a pair always run the same control flow (their loop conditions are
+// exchanged values), so the partner is active and every lane is written:
+// the destination needs no prior value (no initialising move).
 __device__ __forceinline__ int swap_pair_i32(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
 }
 
 __device__ __forceinline__ double swap_pair(double v) {
@@ -478,30 +481,30 @@ __global__ __launch_bounds__(256) void k_batch_bin_scatter(BatchWs ws, const dou
 
 // A table of saved orbit pairs: record r holds the orbit index and the exact
 // state of lanes 2 r (orbit) and 2 r + 1 (shadow).
+// Saved pair states: one record of kRecWords doubles per lane, contiguous
+// (y[12], ref[4], acc, t, renorms, nmax | flags << 32), so that a lane
+// addresses its record with one base address and constant offsets; records
+// are written and read only where a piece or an orbit changes hands.
+constexpr int kRecWords = 20;
+
 struct RecTable {
     int32_t* id;                    // [cap] orbit index
-    double* y;                      // [12][2 cap]
-    double* ref;                    // [4][2 cap]
-    double* acc;                    // [2 cap]
-    int64_t* t;                     // [2 cap]
-    int64_t* renorms;               // [2 cap]
-    int32_t* nmax;                  // [2 cap]
-    int32_t* flags;                 // [2 cap]: status | any_nc << 16
+    double* rec;                    // [2 cap][kRecWords]
     int64_t cap;                    // records
 };
 
 __device__ __forceinline__ void rec_save(const RecTable& T, int64_t r, const PairState& ps, bool shadow,
                                          int64_t cur) {
-    const int64_t w = 2 * r + (shadow ? 1 : 0), L = 2 * T.cap;
+    double* R = T.rec + (2 * r + (shadow ? 1 : 0)) * kRecWords;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) T.y[c * L + w] = ps.y[c];
+    for (int c = 0; c < 12; ++c) R[c] = ps.y[c];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) T.ref[c * L + w] = ps.ref[c];
-    T.acc[w] = ps.acc;
-    T.t[w] = ps.t;
-    T.renorms[w] = ps.renorms;
-    T.nmax[w] = ps.nmax;
-    T.flags[w] = ps.st | (ps.any_nc ? (1 << 16) : 0);
+    for (int c = 0; c < 4; ++c) R[12 + c] = ps.ref[c];
+    R[16] = ps.acc;
+    R[17] = __builtin_bit_cast(double, ps.t);
+    R[18] = __builtin_bit_cast(double, ps.renorms);
+    const uint64_t fl = (uint64_t)(uint32_t)(ps.st | (ps.any_nc ? (1 << 16) : 0));
+    R[19] = __builtin_bit_cast(double, (uint64_t)(uint32_t)ps.nmax | (fl << 32));
     if (!shadow) T.id[r] = (int32_t)cur;
 }
 
@@ -509,18 +512,19 @@ __device__ __forceinline__ void rec_save(const RecTable& T, int64_t r, const Pai
 // it names no orbit of this scan).
 __device__ __forceinline__ int64_t rec_load(const RecTable& T, int64_t r, PairState& ps, bool shadow,
                                             const FliArgs& fa) {
-    const int64_t w = 2 * r + (shadow ? 1 : 0), L = 2 * T.cap;
     const int64_t i = T.id[r];
     if (i < 0 || i >= fa.n) return -1;
+    const double* R = T.rec + (2 * r + (shadow ? 1 : 0)) * kRecWords;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) ps.y[c] = T.y[c * L + w];
+    for (int c = 0; c < 12; ++c) ps.y[c] = R[c];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) ps.ref[c] = T.ref[c * L + w];
-    ps.acc = T.acc[w];
-    ps.t = T.t[w];
-    ps.renorms = T.renorms[w];
-    ps.nmax = T.nmax[w];
-    const int f = T.flags[w];
+    for (int c = 0; c < 4; ++c) ps.ref[c] = R[12 + c];
+    ps.acc = R[16];
+    ps.t = __builtin_bit_cast(int64_t, R[17]);
+    ps.renorms = __builtin_bit_cast(int64_t, R[18]);
+    const uint64_t w = __builtin_bit_cast(uint64_t, R[19]);
+    ps.nmax = (int)(uint32_t)w;
+    const int f = (int)(uint32_t)(w >> 32);
     ps.st = f & 0xFFFF;
     ps.any_nc = (f >> 16) != 0;
     ps.d2 = 0.0;
@@ -658,22 +662,14 @@ __global__ __launch_bounds__(256) void k_ckpt_carry(CkptArgs ck) {
     // The tables hold every orbit in flight (at most min(n, resident pairs));
     // the bound below only keeps a corrupted header inside them.
     const unsigned long long left = (saved - rd) < (cap - base) ? (saved - rd) : (cap - base);
-    const int64_t L = 2 * ck.cap;
     const RecTable& I = ck.tab[tin];
     const RecTable& O = ck.tab[tout];
     for (unsigned long long r = rd + threadIdx.x; r < rd + left; r += 256) {
         const unsigned long long d = base + (r - rd);
         O.id[d] = I.id[r];
-        for (int h = 0; h < 2; ++h) {
-            const int64_t a = 2 * (int64_t)r + h, b = 2 * (int64_t)d + h;
-            for (int c = 0; c < 12; ++c) O.y[c * L + b] = I.y[c * L + a];
-            for (int c = 0; c < 4; ++c) O.ref[c * L + b] = I.ref[c * L + a];
-            O.acc[b] = I.acc[a];
-            O.t[b] = I.t[a];
-            O.renorms[b] = I.renorms[a];
-            O.nmax[b] = I.nmax[a];
-            O.flags[b] = I.flags[a];
-        }
+        const double* src = I.rec + 2 * (int64_t)r * kRecWords;
+        double* dst = O.rec + 2 * (int64_t)d * kRecWords;
+        for (int w = 0; w < 2 * kRecWords; ++w) dst[w] = src[w];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -748,10 +744,11 @@ constexpr int kFromInputs = 0, kFromCarry = 1, kFromSplit = 2;
 // from record r of the carry or split table.  A record that does not hold
 // orbit p.orbit at step t_at (or stopped earlier with a final status) cannot
 // occur under a valid plan; the orbit then reports PN_ORBIT_BADPARAM.
+template <bool SHARED>
 __device__ __forceinline__ void wrap_open(PairState& ps, PnCoef& k, const ParamArgs& pa, const FliArgs& fa,
                                           const WrapArgs& wa, int from, int64_t r, const WrapPiece& p,
                                           int64_t t_at, bool shadow) {
-    const bool ok = load_coef(pa, p.orbit, k);
+    const bool ok = SHARED ? true : load_coef(pa, p.orbit, k);
     if (from == kFromInputs) {
         pair_begin(ps, k, ok, shadow, fa, p.orbit);
         return;
@@ -765,7 +762,10 @@ __device__ __forceinline__ void wrap_open(PairState& ps, PnCoef& k, const ParamA
     }
 }
 
-template <int METHOD, int MODE, int OCC>
+// SHARED: every orbit has the parameter set of pa.coef, whose table then stays
+// in scalar registers for the whole launch instead of being rebuilt per piece
+// in vector registers.
+template <int METHOD, int MODE, int OCC, bool SHARED>
 __global__ __launch_bounds__(256, OCC) void k_wrap_scan(ParamArgs pa, FliArgs fa, WrapArgs wa) {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t s = g >> 1;
@@ -779,6 +779,7 @@ __global__ __launch_bounds__(256, OCC) void k_wrap_scan(ParamArgs pa, FliArgs fa
     bool active = tau < tend, open = active;
     int64_t orbit = 0, b = 0, pend = 0;                // open piece: orbit, last step + 1, end time
     PnCoef k;
+    if (SHARED) k = pa.coef;
     PairState ps;
     for (;;) {
         if (__ballot(active) == 0ull) break;
@@ -788,9 +789,10 @@ __global__ __launch_bounds__(256, OCC) void k_wrap_scan(ParamArgs pa, FliArgs fa
             b = p.b;
             pend = p.start + (p.b - p.a);
             if (p.start < tau)          // cut by the previous launch's end
-                wrap_open(ps, k, pa, fa, wa, kFromCarry, s, p, p.a + (tau - p.start), shadow);
+                wrap_open<SHARED>(ps, k, pa, fa, wa, kFromCarry, s, p, p.a + (tau - p.start), shadow);
             else
-                wrap_open(ps, k, pa, fa, wa, p.a > 0 ? kFromSplit : kFromInputs, s + 1, p, p.a, shadow);
+                wrap_open<SHARED>(ps, k, pa, fa, wa, p.a > 0 ? kFromSplit : kFromInputs, s + 1, p, p.a,
+                                  shadow);
             open = false;
         }
         if (active) {
@@ -1010,24 +1012,15 @@ constexpr int64_t kCkptMaxPairs = (int64_t)1 << 18;
 int64_t ckpt_cap(int64_t n) { return n < kCkptMaxPairs ? n : kCkptMaxPairs; }
 
 size_t rec_table_bytes(int64_t cap) {
-    const size_t L = 2 * (size_t)cap;
-    return align256((size_t)cap * 4) + align256(12 * L * 8) + align256(4 * L * 8) + 3 * align256(L * 8) +
-           2 * align256(L * 4);
+    return align256((size_t)cap * 4) + align256(2 * (size_t)cap * kRecWords * 8);
 }
 
 // Carves one record table of cap records at b and advances b past it.
 RecTable carve_rec(char*& b, int64_t cap) {
     RecTable T;
-    const size_t L = 2 * (size_t)cap;
     T.cap = cap;
     T.id = reinterpret_cast<int32_t*>(b);       b += align256((size_t)cap * 4);
-    T.y = reinterpret_cast<double*>(b);         b += align256(12 * L * 8);
-    T.ref = reinterpret_cast<double*>(b);       b += align256(4 * L * 8);
-    T.acc = reinterpret_cast<double*>(b);       b += align256(L * 8);
-    T.t = reinterpret_cast<int64_t*>(b);        b += align256(L * 8);
-    T.renorms = reinterpret_cast<int64_t*>(b);  b += align256(L * 8);
-    T.nmax = reinterpret_cast<int32_t*>(b);     b += align256(L * 4);
-    T.flags = reinterpret_cast<int32_t*>(b);    b += align256(L * 4);
+    T.rec = reinterpret_cast<double*>(b);       b += align256(2 * (size_t)cap * kRecWords * 8);
     return T;
 }
 
@@ -1162,12 +1155,11 @@ pn_status func_resources(const char* what, const void* f, int block, int32_t* vg
     return PN_OK;
 }
 
-// Balanced scan: kernel per method and correction.  RK4 keeps two resident
-// wavefronts per SIMD: at 256 registers the piece bookkeeping (end times,
-// slot time) lives in scratch between piece events, and the step loop makes
-// one scratch access per step; this runs about 5% faster than the
-// spill-free build with one wavefront per SIMD.  The six-stage RK5 keeps
-// the registers of one.
+// Balanced scan: kernel per method, correction and parameter mode.  RK4
+// keeps two resident wavefronts per SIMD (at most 256 registers per lane):
+// with a shared parameter set the RK4 build fits without spilling; the
+// per-orbit build keeps a few values of the piece bookkeeping in scratch
+// between piece events.  The six-stage RK5 keeps the registers of one.
 constexpr int32_t kWrapMaxLaunches = 16;
 constexpr int64_t kWrapMaxSlots = (int64_t)1 << 24;
 constexpr int64_t kWrapMaxTape = (int64_t)1 << 62;
@@ -1176,23 +1168,32 @@ constexpr int32_t kWrapChunk = 256;
 template <int METHOD, int MODE>
 struct WrapK {
     static constexpr int OCC = METHOD == PN_RK4 ? 2 : 1;
-    static const void* fn() { return reinterpret_cast<const void*>(&k_wrap_scan<METHOD, MODE, OCC>); }
+    static const void* fn(bool shared) {
+        return shared ? reinterpret_cast<const void*>(&k_wrap_scan<METHOD, MODE, OCC, true>)
+                      : reinterpret_cast<const void*>(&k_wrap_scan<METHOD, MODE, OCC, false>);
+    }
     static void launch(unsigned blocks, const ParamArgs& pa, const FliArgs& fa, const WrapArgs& wa,
                        hipStream_t s) {
-        hipLaunchKernelGGL((k_wrap_scan<METHOD, MODE, OCC>), dim3(blocks), dim3(256), 0, s, pa, fa, wa);
+        if (pa.beta == nullptr)
+            hipLaunchKernelGGL((k_wrap_scan<METHOD, MODE, OCC, true>), dim3(blocks), dim3(256), 0, s, pa, fa, wa);
+        else
+            hipLaunchKernelGGL((k_wrap_scan<METHOD, MODE, OCC, false>), dim3(blocks), dim3(256), 0, s, pa, fa,
+                               wa);
     }
 };
 
-const void* wrap_fn(int method, int mode) {
+// shared: the build for one parameter set shared by every orbit (its table in
+// scalar registers), else the per-orbit build.
+const void* wrap_fn(int method, int mode, bool shared = true) {
     switch (method * 4 + mode) {
-        case 0: return WrapK<PN_RK4, PN_CORR_NONE>::fn();
-        case 1: return WrapK<PN_RK4, PN_CORR_SPIN>::fn();
-        case 2: return WrapK<PN_RK4, PN_CORR_SIX>::fn();
-        case 3: return WrapK<PN_RK4, PN_CORR_DUAL>::fn();
-        case 4: return WrapK<PN_RK5, PN_CORR_NONE>::fn();
-        case 5: return WrapK<PN_RK5, PN_CORR_SPIN>::fn();
-        case 6: return WrapK<PN_RK5, PN_CORR_SIX>::fn();
-        default: return WrapK<PN_RK5, PN_CORR_DUAL>::fn();
+        case 0: return WrapK<PN_RK4, PN_CORR_NONE>::fn(shared);
+        case 1: return WrapK<PN_RK4, PN_CORR_SPIN>::fn(shared);
+        case 2: return WrapK<PN_RK4, PN_CORR_SIX>::fn(shared);
+        case 3: return WrapK<PN_RK4, PN_CORR_DUAL>::fn(shared);
+        case 4: return WrapK<PN_RK5, PN_CORR_NONE>::fn(shared);
+        case 5: return WrapK<PN_RK5, PN_CORR_SPIN>::fn(shared);
+        case 6: return WrapK<PN_RK5, PN_CORR_SIX>::fn(shared);
+        default: return WrapK<PN_RK5, PN_CORR_DUAL>::fn(shared);
     }
 }
 

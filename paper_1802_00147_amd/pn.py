@@ -282,14 +282,14 @@ def step(y, beta, chi1, chi2, nsteps, model=None, integrator=None, correction=No
 def scan_outputs(n, ld, device, full=True, trace_every=0, nsteps_max=0):
     o = dict(fli=torch.empty(ld, dtype=torch.float64, device=device),
              label=torch.empty(ld, dtype=torch.int8, device=device),
-             status=torch.empty(ld, dtype=torch.int32, device=device))
+             status=torch.empty(ld, dtype=torch.int32, device=device),
+             steps=torch.empty(ld, dtype=torch.int64, device=device))
     if full:
         o.update(y_final=torch.empty((12, ld), dtype=torch.float64, device=device),
                  dH=torch.empty(ld, dtype=torch.float64, device=device),
                  dJ=torch.empty(ld, dtype=torch.float64, device=device),
                  newton_max=torch.empty(ld, dtype=torch.int32, device=device),
-                 renorms=torch.empty(ld, dtype=torch.int64, device=device),
-                 steps=torch.empty(ld, dtype=torch.int64, device=device))
+                 renorms=torch.empty(ld, dtype=torch.int64, device=device))
     if trace_every > 0:
         ntrace = nsteps_max // trace_every
         o["trace"] = torch.full((ntrace, ld), float("nan"), dtype=torch.float64, device=device)

@@ -228,22 +228,16 @@ def test_batch_errors_and_empty(pn):
 
 def test_batch1m_full_size_sampled(pn):
     """The 10^6-orbit uneven batch (t_end log-uniform in [1e3, 1e6], per-orbit
-    beta and spins) in one persistent launch; 12 seeded orbits recomputed by
-    the oracle."""
+    beta and spins) in one persistent launch, against the oracle on 1,000
+    seeded orbits (tests/golden/oracle_scan_batch1M.txt): the gates of
+    scan_expect (classes agree on >= 99.5%, regular FLIs within the
+    per-orbit tolerance, statuses and step counts exact for them)."""
     from paper_1802_00147_amd import workloads as W
+    import scan_expect as E
     wl = W.batch()
     y0, t, b, c1, c2 = device_inputs(pn, wl)
     out = pn.batch_scan(y0, t, b, c1, c2, full=False)
     torch.cuda.synchronize()
-    st = out["status"].cpu().numpy()
-    lab = out["label"].cpu().numpy()
-    fli = out["fli"].cpu().numpy()
-    assert np.all((lab == -1) == ((st & 0xFF) != 0))
-    idx = W.strided_sample(wl.n, 12, seed=8)
-    sub = wl.subset(idx)
-    y0o = O.init_state(sub.r0, sub.p0, sub.th1, sub.ph1, sub.th2, sub.ph2, sub.beta, sub.chi1, sub.chi2)
-    exp = O.fli_scan(y0o, sub.t_end, sub.beta, sub.chi1, sub.chi2, nthreads=12)
-    assert np.array_equal(st[idx], exp["status"])
-    ok = (exp["status"] == 0) & (exp["label"] == 0)
-    assert np.array_equal(lab[idx], exp["label"])
-    assert np.all(np.abs(fli[idx][ok] - exp["fli"][ok]) <= FLI_ABS_CORRECTED)
+    got = {k: out[k].cpu().numpy() for k in ("fli", "label", "status", "steps")}
+    assert np.all((got["label"] == -1) == ((got["status"] & 0xFF) != 0))
+    E.compare("batch1M", got)

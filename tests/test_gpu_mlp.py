@@ -352,19 +352,23 @@ def test_multi_step_training_equals_single_steps(pn):
 
 def test_surrogate_full_size_sampled(pn):
     """The assisted scan of the full 4096 x 4096 (r0, theta) grid at t = 1e5
-    in the benchmark's configuration (margin 0.5, 1% audit, 40 refinement
-    epochs; the network trained for 20 cosine epochs on the FP64 scan of a
-    200,000-orbit uneven batch).  Its cost: 1-3% of the grid integrated.
-    Sampled parity: 24 integrated points recomputed one by one by the oracle
-    carry the oracle's labels (away from the threshold: |FLI - 5.8| > 1e-3),
-    and the merged labels of 64 random grid points agree with the oracle's
-    on at least 60."""
+    in the benchmark's configuration: the network trained for 20 cosine
+    epochs on the FP64 scan of the 10^6-orbit uneven batch, margin 0.5, 1%
+    SplitMix64 audit, 40 refinement epochs on the audit.  Its cost: 1-3% of
+    the grid integrated.  Gates:
+      * labels agree with the plain FP64 GPU scan on >= 99% of a seeded
+        65,536-point sample (the plain scan run on those points), and the
+        integrated points among them carry the plain labels exactly;
+      * labels agree with the oracle on >= 99% of 1,000 seeded grid points
+        (tests/golden/oracle_scan_grid4096.txt)."""
     from paper_1802_00147_amd import surrogate as S, workloads as W
-    tr = W.batch(n=200_000, seed=35, tmin=1e3, tmax=1e5)
+    import scan_expect as E
+    tr = W.batch()
     cols = [dev(getattr(tr, k)) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")]
     b, c1, c2, t = (dev(getattr(tr, k)) for k in ("beta", "chi1", "chi2", "t_end"))
     sc = pn.batch_scan(pn.init_state(*cols, b, c1, c2), t, b, c1, c2, full=False)
     ts = S.training_set(tr, sc, DEV)
+    del sc
     net, hist = S.train(ts, epochs=20, batch=4096, lr=1e-3)
     grid = W.grid4096()
     res = S.surrogate_scan(net, grid, ts.stats, margin=0.5, audit=0.01, seed=5, refine_epochs=40)
@@ -373,17 +377,21 @@ def test_surrogate_full_size_sampled(pn):
     pts = res.points.cpu().numpy()
     assert 0.01 * grid.n <= res.integrated <= 0.03 * grid.n
     assert len(np.unique(pts)) == len(pts) == res.integrated
-
-    def oracle_fli(idx):
-        sub = grid.subset(idx)
-        y0 = O.init_state(sub.r0, sub.p0, sub.th1, sub.ph1, sub.th2, sub.ph2, 1.0, 1.0, 1.0)
-        return O.fli_scan(y0, grid.t_end, 1.0, 1.0, 1.0, nthreads=8)
-
-    rng = np.random.default_rng(36)
-    ipts = np.sort(rng.choice(pts, size=24, replace=False))
-    exp = oracle_fli(ipts)
-    clear = (exp["status"] == 0) & (np.abs(exp["fli"] - 5.8) > 1e-3)
-    assert np.array_equal(label[ipts][clear], exp["label"][clear])
-    rpts = np.sort(rng.choice(grid.n, size=64, replace=False))
-    exp2 = oracle_fli(rpts)
-    assert np.sum(label[rpts] == exp2["label"]) >= 60
+    # Plain FP64 scan of a seeded 65,536-point sample.
+    idx = W.strided_sample(grid.n, 65536, seed=17)
+    sub = grid.subset(idx)
+    ys = pn.init_state(*[dev(getattr(sub, k)) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")], 1.0, 1.0, 1.0)
+    plain = pn.fli_scan(ys, grid.t_end, 1.0, 1.0, 1.0, full=False)
+    torch.cuda.synchronize()
+    ref = plain["label"].cpu().numpy()
+    agree_plain = float(np.mean(label[idx] == ref))
+    inter, a_i, _ = np.intersect1d(idx, pts, return_indices=True)
+    assert len(inter) > 300
+    assert np.array_equal(label[inter], ref[a_i])
+    # Against the oracle on 1,000 seeded grid points.
+    exp = E.M.load("grid4096")
+    agree_oracle = float(np.mean(label[exp["index"]] == exp["label"]))
+    print(f"surrogate: integrated {res.integrated / grid.n:.4f}, agreement with the plain scan {agree_plain:.5f} "
+          f"(65,536 points), with the oracle {agree_oracle:.4f} (1,000 points)", flush=True)
+    assert agree_plain >= 0.99
+    assert agree_oracle >= 0.99

@@ -259,39 +259,37 @@ def test_scan_newton_nonconvergence_flag(pn):
         assert np.array_equal(got["steps"], exp["steps"])
 
 
-def test_scan_grid64_full_size_sampled(pn):
+def test_scan_grid64_full_size(pn):
     """The 64 x 64 (r0, theta) grid at t = 1e5, in the benchmark's launch
-    configuration; 24 seeded grid points recomputed by the oracle."""
+    configuration, against the oracle on every grid point
+    (tests/golden/oracle_scan_grid64.txt): classes agree on >= 99.5% of the
+    points, statuses and step counts exactly where both sides find a regular
+    orbit, whose FLIs agree within the per-orbit tolerance of scan_expect."""
     from paper_1802_00147_amd import workloads as W
+    import scan_expect as E
     wl = W.grid64()
     y0 = pn.init_state(*[dev(getattr(wl, k)) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")], 1.0, 1.0, 1.0)
     assert pn.balanced_schedule(wl.n, wl.t_end)["launches"] == 0        # the plain fused scan
     out = pn.fli_scan_balanced(y0, wl.t_end, 1.0, 1.0, 1.0)
     torch.cuda.synchronize()
-    idx = W.strided_sample(wl.n, 24, seed=7)
-    sub = wl.subset(idx)
-    y0o = O.init_state(sub.r0, sub.p0, sub.th1, sub.ph1, sub.th2, sub.ph2, 1.0, 1.0, 1.0)
-    exp = O.fli_scan(y0o, wl.t_end, 1.0, 1.0, 1.0, nthreads=8)
-    st = out["status"].cpu().numpy()[idx]
-    lab = out["label"].cpu().numpy()[idx]
-    fli = out["fli"].cpu().numpy()[idx]
-    assert np.array_equal(st, exp["status"])
-    assert np.array_equal(lab, exp["label"])
-    reg = (exp["status"] == 0) & (exp["label"] == 0)
-    assert np.all(np.abs(fli[reg] - exp["fli"][reg]) <= FLI_ABS_CORRECTED)
-    # Whole-grid properties: every orbit bound and corrected to rounding level.
+    got = {k: out[k].cpu().numpy() for k in ("fli", "label", "status", "steps")}
+    rep = E.compare("grid64", got)
+    assert rep["points"] == wl.n
+    # Whole grid: every orbit that runs to the end is corrected to rounding level.
     dH = out["dH"].cpu().numpy()
-    assert np.all(st == 0) and np.nanmax(dH) < 1e-13
+    ok = got["status"] == 0
+    assert ok.sum() >= wl.n - 4 and np.nanmax(dH[ok]) < 1e-13
 
 
 @pytest.mark.parametrize("beta,qm", [(1.0, 1), (1.0, 0), (0.5, 1), (0.5, 0)])
 def test_scan_grid314_full_size_sampled(pn, beta, qm):
     """The 314 x 314 (r0, p-scale) grid at t = 1e6, each of its four variants
     (mass ratio 1 or 1/2, quadrupole-monopole on or off) at full size in the
-    benchmark's launch configuration; 8 seeded points recomputed by the
-    oracle.  Statuses exact; labels exact away from the threshold (6.8 at
-    t = 1e6), at most 0.5 % different in all; regular FLIs within 3e-4."""
+    benchmark's launch configuration, against the oracle on a seeded sample
+    (986 points = 1% for beta = 1 with QM, 200 for each other variant;
+    tests/golden/oracle_scan_grid314_*.txt): the gates of scan_expect."""
     from paper_1802_00147_amd import workloads as W
+    import scan_expect as E
     wl = W.grid314(beta=beta, quad_mono=qm)
     model = dict(quad_mono=qm)
     y0 = pn.init_state(*[dev(getattr(wl, k)) for k in ("r0", "p0", "th1", "ph1", "th2", "ph2")], beta, 1.0, 1.0,
@@ -299,18 +297,7 @@ def test_scan_grid314_full_size_sampled(pn, beta, qm):
     assert pn.balanced_schedule(wl.n, wl.t_end)["launches"] >= 2         # the balanced schedule
     out = pn.fli_scan_balanced(y0, wl.t_end, beta, 1.0, 1.0, model=model, full=False)
     torch.cuda.synchronize()
-    idx = W.strided_sample(wl.n, 8, seed=13 + int(4 * beta) + qm)
-    sub = wl.subset(idx)
-    y0o = O.init_state(sub.r0, sub.p0, sub.th1, sub.ph1, sub.th2, sub.ph2, beta, 1.0, 1.0, model=model)
-    exp = O.fli_scan(y0o, wl.t_end, beta, 1.0, 1.0, model=model, nthreads=16)
-    st = out["status"].cpu().numpy()
-    lab = out["label"].cpu().numpy()
-    fli = out["fli"].cpu().numpy()
-    assert np.array_equal(st[idx], exp["status"])
-    thr = 5.8 + np.log10(wl.t_end / 1e5)
-    far = (exp["status"] == 0) & (np.abs(exp["fli"] - thr) > 0.25)
-    assert np.array_equal(lab[idx][far], exp["label"][far])
-    reg = (exp["status"] == 0) & (exp["label"] == 0) & (lab[idx] == 0)
-    assert np.all(np.abs(fli[idx][reg] - exp["fli"][reg]) <= FLI_ABS_CORRECTED)
+    got = {k: out[k].cpu().numpy() for k in ("fli", "label", "status", "steps")}
+    E.compare(f"grid314_b{beta:g}_qm{qm}", got)
     # Whole grid: labels are -1 exactly where an orbit was removed.
-    assert np.array_equal(lab == -1, (st & 0xFF) != 0)
+    assert np.array_equal(got["label"] == -1, (got["status"] & 0xFF) != 0)
