@@ -51,13 +51,13 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 128 FP64 flop/clk x 2.4 GH
 ALG_FLOPS_PER_ORBIT_STEP = 5200.0
 KERNEL_SOURCES = ["paper_1802_00147_amd/csrc/pn_kernels.hip", "paper_1802_00147_amd/csrc/pn_device.h"]
 
-# HBM bytes of one scan from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per
-# dispatch, scaled by a 1 GiB device copy: FETCH_SIZE x 1.99993, WRITE_SIZE
-# x 1.0), valid only for the kernel sources whose hash is recorded with them.
-# grid64, one k_fli_scan launch: 367.9375 KiB read, 580.0 KiB written.
-# fig7, three k_wrap_scan launches: 157,886.94 KiB read, 357,591.03 KiB written.
-TRAFFIC = dict(sources_sha256="bcaf5756935e5d2f61366c7c7213e39ab93a1b27e8f24acd2e679e2c72365e08",
-               bytes_per_scan={"grid64": 753508 + 593920, "fig7": 323340345 + 366173216})
+# HBM bytes from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per dispatch,
+# scaled by a 1 GiB device copy: FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0),
+# valid only for the kernel sources whose hash is recorded with them.
+# surrogate4096: the seven k_wrap_scan launches of one assisted scan, 206.4 MB
+# read + 158.7 MB written, 52.2 MB per launch.
+TRAFFIC = dict(sources_sha256="93f7a6e9b3191cd451681252ee59af220127e450e4ba785ed625c04b2663207a",
+               bytes_per_launch={"surrogate4096": 365164837 / 7})
 
 
 # Table 3 of the paper: wall time of its GPU and CPU scans (seconds).
@@ -68,13 +68,17 @@ PAPER_TABLE3 = {"fig6_th1_1.571": (75.0, 1020.0), "fig7": (2213.0, 25000.0)}
 # rocprofv3 counters (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 x 64 lanes, FMA
 # counted twice, over the launch's orbit-steps), valid only for the kernel
 # sources whose hash is recorded with them.
-HW_FLOPS = dict(sources_sha256=None, per_orbit_step={})
+HW_FLOPS = dict(sources_sha256="93f7a6e9b3191cd451681252ee59af220127e450e4ba785ed625c04b2663207a",
+                per_orbit_step={("k_wrap_scan", "surrogate4096"): 4934.2})
 
 
-def hardware_flops(kernel):
+def hardware_flops(kernel, workload):
+    """Hardware FP64 flops per orbit-step of `kernel` on `workload`, from the
+    counters recorded above (None when the sources changed or none were
+    taken)."""
     if HW_FLOPS["sources_sha256"] != sources_sha256():
         return None
-    return HW_FLOPS["per_orbit_step"].get(kernel)
+    return HW_FLOPS["per_orbit_step"].get((kernel, workload))
 
 
 def sources_sha256():
@@ -504,15 +508,18 @@ def surrogate_bench(args, dev):
     launch_ms = kd["ms"] / kd["launches"]
     flops_per_launch = ALG_FLOPS_PER_ORBIT_STEP * kd["orbit_steps"] / kd["launches"]
     achieved = flops_per_launch / (launch_ms * 1e-3) / 1e12
+    traffic = None
+    if TRAFFIC["sources_sha256"] == sources_sha256():
+        traffic = TRAFFIC["bytes_per_launch"].get("surrogate4096")
     line["roofline"] = dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                            frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=None,
+                            frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=traffic,
                             kernel=f"{kname}<RK4,SIX> (audit and fallback integrations of pn_surrogate_scan)",
                             kernel_ms=launch_ms, launches_per_step=kd["launches"] / args.steps,
                             orbit_steps_per_launch=kd["orbit_steps"] / kd["launches"],
                             flops_per_orbit_step=ALG_FLOPS_PER_ORBIT_STEP,
                             orbit_steps_per_s=kd["orbit_steps"] / (kd["ms"] * 1e-3),
                             phases=res.scans)
-    hw = hardware_flops(kname)
+    hw = hardware_flops(kname, "surrogate4096")
     if hw is not None:
         line["roofline"]["hw_flops_per_orbit_step"] = hw
         line["roofline"]["hw_frac"] = hw * kd["orbit_steps"] / (kd["ms"] * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS
@@ -682,13 +689,13 @@ def main():
         achieved = ALG_FLOPS_PER_ORBIT_STEP * orbit_steps / (kernel_ms * 1e-3) / 1e12
         traffic = None
         if TRAFFIC["sources_sha256"] == sources_sha256():
-            traffic = TRAFFIC["bytes_per_scan"].get(wl.name)
+            traffic = TRAFFIC["bytes_per_launch"].get(wl.name)
         line["roofline"] = dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
                                 frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=traffic,
                                 kernel=kernel, kernel_ms=kernel_ms,
                                 flops_per_orbit_step=ALG_FLOPS_PER_ORBIT_STEP,
                                 oracle_flops_per_orbit_step=oracle_fpos)
-        hw = hardware_flops(kernel.split("<")[0])
+        hw = hardware_flops(kernel.split("<")[0], wl.name)
         if hw is not None:
             line["roofline"]["hw_flops_per_orbit_step"] = hw
             line["roofline"]["hw_frac"] = (hw * orbit_steps / (kernel_ms * 1e-3) / 1e12 /

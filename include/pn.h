@@ -505,6 +505,21 @@ pn_status pn_mlp_targets(const double* fli, const int8_t* label, const double* t
 /* Bytes of workspace for one training step of `batch` samples. */
 size_t pn_mlp_train_workspace_size(int32_t batch);
 
+/* Byte offsets inside a pn_mlp_train_step workspace (of the same batch) of
+ * the tensors a step leaves there, readable once the step has completed on
+ * its stream (row-major, one row per batch sample):
+ *   off[0]     X: the gathered features as bfloat16 [batch][8] (column 7 zero);
+ *   off[1..3]  h1, h2, h3: the hidden activations after ReLU, bfloat16 [batch][256];
+ *   off[4]     out: the outputs (logit, FLI - log10 t_end), FP32 [batch][2];
+ *   off[5]     g4: d loss / d out, bfloat16 [batch][2];
+ *   off[6..8]  g3, g2, g1: d loss / d (pre-activation of hidden layer 3, 2, 1),
+ *              bfloat16 [batch][256].
+ * The weight gradient of layer l is g_(l+1)^T a_l (a_0 = X, a_l = h_l) and
+ * its bias gradient the column sums of g_(l+1); both are consumed by the
+ * step's Adam update (the first step's moments are 0.1 g and 0.001 g^2).
+ * off: 9 entries, caller-owned.  PN_EINVAL if batch <= 0 or off is NULL. */
+pn_status pn_mlp_train_workspace_layout(int32_t batch, size_t* off);
+
 /* One training step on rows idx[0..batch) of feat [rows][8] (16-byte aligned,
  * else PN_EINVAL), label [rows]
  * (1 chaotic, 0 regular) and target [rows] (FLI - log10 t_end): forward,

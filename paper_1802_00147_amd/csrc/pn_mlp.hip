@@ -853,6 +853,19 @@ size_t pn_mlp_train_workspace_size(int32_t batch) {
            4 * al((size_t)kSplitFloats * 4);
 }
 
+pn_status pn_mlp_train_workspace_layout(int32_t batch, size_t* off) {
+    if (batch <= 0 || !off) return PN_EINVAL;
+    const size_t B = (size_t)batch;
+    const size_t sizes[9] = {B * kFeatLd * 2, B * 256 * 2, B * 256 * 2, B * 256 * 2, B * 2 * 4, B * 2 * 2,
+                             B * 256 * 2, B * 256 * 2, B * 256 * 2};
+    size_t at = 0;
+    for (int k = 0; k < 9; ++k) {
+        off[k] = at;
+        at += al(sizes[k]);
+    }
+    return PN_OK;
+}
+
 pn_status pn_mlp_sync_bf16(pn_mlp* net, hipStream_t stream) {
     if (!net_ok(net, false)) return PN_EINVAL;
     for (int l = 0; l < 4; ++l) {
@@ -875,16 +888,20 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
         return PN_EDEVICE;
     }
     const int B = batch;
-    char* p = static_cast<char*>(ws);
+    // The tensors a step leaves in the workspace, at the offsets that
+    // pn_mlp_train_workspace_layout reports; the gradient buffers follow.
+    size_t off[9];
+    if (pn_mlp_train_workspace_layout(batch, off) != PN_OK) return PN_EINVAL;
+    char* const w0 = static_cast<char*>(ws);
+    uint16_t* X = (uint16_t*)(w0 + off[0]);
+    uint16_t* h[3] = {(uint16_t*)(w0 + off[1]), (uint16_t*)(w0 + off[2]), (uint16_t*)(w0 + off[3])};
+    float* out = (float*)(w0 + off[4]);
+    uint16_t* g4 = (uint16_t*)(w0 + off[5]);
+    uint16_t* g3 = (uint16_t*)(w0 + off[6]);
+    uint16_t* g2 = (uint16_t*)(w0 + off[7]);
+    uint16_t* g1 = (uint16_t*)(w0 + off[8]);
+    char* p = w0 + off[8] + al((size_t)B * 256 * 2);
     auto take = [&](size_t bytes) { char* q = p; p += al(bytes); return q; };
-    uint16_t* X = (uint16_t*)take((size_t)B * kFeatLd * 2);
-    uint16_t* h[3];
-    for (int l = 0; l < 3; ++l) h[l] = (uint16_t*)take((size_t)B * 256 * 2);
-    float* out = (float*)take((size_t)B * 2 * 4);
-    uint16_t* g4 = (uint16_t*)take((size_t)B * 2 * 2);
-    uint16_t* g3 = (uint16_t*)take((size_t)B * 256 * 2);
-    uint16_t* g2 = (uint16_t*)take((size_t)B * 256 * 2);
-    uint16_t* g1 = (uint16_t*)take((size_t)B * 256 * 2);
     float* dW[4];
     dW[1] = (float*)take(256 * 256 * 4);
     dW[2] = (float*)take(256 * 256 * 4);

@@ -92,6 +92,7 @@ EXPORTS = ["pn_default_model", "pn_default_integrator", "pn_default_correction",
            "pn_default_tuning", "pn_batch_workspace_size", "pn_batch_scan", "pn_autotune_batch",
            "pn_batch_graph_create", "pn_graph_launch", "pn_graph_destroy",
            "pn_mlp_param_count", "pn_mlp_sync_bf16", "pn_mlp_features", "pn_mlp_train_workspace_size",
+           "pn_mlp_train_workspace_layout",
            "pn_mlp_train_step", "pn_mlp_infer_workspace_size", "pn_mlp_infer", "pn_surrogate_gate",
            "pn_surrogate_merge", "pn_gemm_bf16", "pn_init_state_gather", "pn_mlp_targets",
            "pn_trajectory", "pn_gw_polarizations", "pn_mlp_infer_fused",
@@ -674,6 +675,28 @@ def mlp_train_step(net, feat, label, target, idx, lr, loss, ws=None):
                                  _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(feat.device))
     _check("pn_mlp_train_step", st)
     return ws
+
+
+def mlp_train_workspace_layout(batch):
+    """Byte offsets of (X, h1, h2, h3, out, g4, g3, g2, g1) in a training-step
+    workspace (pn_mlp_train_workspace_layout)."""
+    off = (ctypes.c_size_t * 9)()
+    _check("pn_mlp_train_workspace_layout", lib().pn_mlp_train_workspace_layout(ctypes.c_int32(batch), off))
+    return list(off)
+
+
+def mlp_train_step_tensors(ws, batch):
+    """Views of the tensors a completed training step left in its workspace:
+    dict X, h1, h2, h3 (bfloat16 bit patterns, int16), out (float32), g4, g3,
+    g2, g1 (int16)."""
+    off = mlp_train_workspace_layout(batch)
+    spec = [("X", 8, 2), ("h1", 256, 2), ("h2", 256, 2), ("h3", 256, 2), ("out", 2, 4), ("g4", 2, 2),
+            ("g3", 256, 2), ("g2", 256, 2), ("g1", 256, 2)]
+    res = {}
+    for (name, cols, size), o in zip(spec, off):
+        raw = ws[o:o + batch * cols * size]
+        res[name] = (raw.view(torch.float32) if size == 4 else raw.view(torch.int16)).view(batch, cols)
+    return res
 
 
 def mlp_train(net, feat, label, target, order, batch, lr, loss, ws=None):

@@ -354,3 +354,20 @@ def test_balanced_scan_arguments(pn):
         sc = ctypes.c_int64(0)
         assert L.pn_balanced_kernel_resources(ctypes.c_int32(args[0]), ctypes.c_int32(args[1]), ctypes.byref(v),
                                               ctypes.byref(sc), ctypes.byref(w)) == pn.PN_EINVAL
+
+
+def test_train_workspace_layout(pn):
+    """The tensors a training step leaves in its workspace lie inside it, in
+    order, 256-byte aligned, each large enough for its rows."""
+    for batch in (1, 100, 2048, 4096):
+        off = pn.mlp_train_workspace_layout(batch)
+        size = pn.lib().pn_mlp_train_workspace_size(batch)
+        need = [batch * 8 * 2, batch * 256 * 2, batch * 256 * 2, batch * 256 * 2, batch * 2 * 4,
+                batch * 2 * 2, batch * 256 * 2, batch * 256 * 2, batch * 256 * 2]
+        assert off[0] == 0 and all(o % 256 == 0 for o in off)
+        for k in range(8):
+            assert off[k + 1] >= off[k] + need[k]
+        assert off[8] + need[8] <= size
+    bad = (ctypes.c_size_t * 9)()
+    assert pn.lib().pn_mlp_train_workspace_layout(ctypes.c_int32(0), bad) == pn.PN_EINVAL
+    assert pn.lib().pn_mlp_train_workspace_layout(ctypes.c_int32(5), None) == pn.PN_EINVAL

@@ -167,6 +167,83 @@ def test_train_step_matches_oracle(pn, B):
         assert np.array_equal(wb, M.round_bf16(new_W)), l
 
 
+def _bf16(t):
+    """Device int16 bfloat16 bit patterns -> float64 numpy values."""
+    return t.cpu().view(torch.bfloat16).to(torch.float64).numpy()
+
+
+def _ulp_bf16(x):
+    """Spacing of bfloat16 values at |x| (8 significant bits)."""
+    e = np.floor(np.log2(np.maximum(np.abs(x), 1e-38)))
+    return 2.0 ** (e - 7)
+
+
+@pytest.mark.parametrize("B", [100, 1024, 4096])
+def test_train_step_elementwise(pn, B):
+    """One training step checked element by element, layer by layer, against
+    FP64 products of the step's own bfloat16 operands (the tensors it leaves
+    in its workspace): the pre-activations and output within 1e-5 of
+    sum |a w| (FP32 accumulation), each stored bfloat16 value within half a
+    bfloat16 ulp of that; the loss gradient of the outputs as the oracle's
+    (oracle/mlp.py) on the step's own outputs; the weight and bias gradients
+    -- the oracle's backward on the step's own activations and layer
+    gradients -- within 1e-5 of sum |g a| element by element; the Adam update
+    as the oracle's on the step's own gradients."""
+    rng = np.random.default_rng(19)
+    net, params = _network(pn)
+    p32 = _as_f32(params)
+    n = 5000
+    feat = np.zeros((n, 8), dtype=np.float32)
+    feat[:, :7] = rng.normal(size=(n, 7))
+    lab = (rng.uniform(size=n) < 0.3).astype(np.float32)
+    tgt = rng.normal(size=n).astype(np.float32)
+    idx = rng.choice(n, size=B, replace=False).astype(np.int32)
+    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+    ws = pn.mlp_train_step(net, dev(feat, torch.float32), dev(lab, torch.float32), dev(tgt, torch.float32),
+                           dev(idx, torch.int32), 1e-3, loss)
+    torch.cuda.synchronize()
+    T = pn.mlp_train_step_tensors(ws, B)
+    a = [_bf16(T["X"])[:, :7], _bf16(T["h1"]), _bf16(T["h2"]), _bf16(T["h3"])]
+    assert np.array_equal(a[0], M.round_bf16(feat[idx, :7]))
+    Wq = [M.round_bf16(W_) for W_, _ in p32]
+    # Forward, layer by layer from the step's own inputs.
+    for l in range(3):
+        z = a[l] @ Wq[l].T + p32[l][1]
+        scale = np.abs(a[l]) @ np.abs(Wq[l]).T + np.abs(p32[l][1])
+        h = a[l + 1]
+        assert np.all(np.abs(h - np.maximum(z, 0.0)) <= 0.5 * _ulp_bf16(h) + 1e-5 * scale + 1e-30), l
+    out = T["out"].cpu().double().numpy()
+    z = a[3] @ Wq[3].T + p32[3][1]
+    assert np.all(np.abs(out - z) <= 1e-5 * (np.abs(a[3]) @ np.abs(Wq[3]).T + np.abs(p32[3][1])) + 1e-30)
+    # Loss and its output gradient on the step's own outputs.
+    ref_loss, g_out = M.loss_and_grad_out(out, lab[idx].astype(np.float64), tgt[idx].astype(np.float64))
+    assert abs(loss.item() - ref_loss) <= 1e-5 * abs(ref_loss)
+    g = {4: _bf16(T["g4"]), 3: _bf16(T["g3"]), 2: _bf16(T["g2"]), 1: _bf16(T["g1"])}
+    assert np.all(np.abs(g[4] - g_out) <= 0.5 * _ulp_bf16(g[4]) + 1e-6 / B)     # FP32 sigmoid and Huber
+    # Layer gradients from the step's own next-layer gradients and masks.
+    for l in (3, 2, 1):
+        zg = (g[l + 1] @ Wq[l]) * (a[l] > 0.0)
+        scale = np.abs(g[l + 1]) @ np.abs(Wq[l])
+        assert np.all(np.abs(g[l] - zg) <= 0.5 * _ulp_bf16(g[l]) + 1e-5 * scale + 1e-30), l
+    # Weight and bias gradients: the oracle's backward of one layer on the
+    # step's own tensors; the first Adam step stores m = 0.1 g (FP32).
+    for l in range(4):
+        (rW, rb), = M.backward([p32[l]], [a[l]], g[l + 1], bf16=False)
+        gW = net.mw[l].cpu().double().numpy() / 0.1
+        gb = net.mb[l].cpu().double().numpy() / 0.1
+        sW = np.abs(g[l + 1]).T @ np.abs(a[l])
+        sb = np.abs(g[l + 1]).sum(axis=0)
+        assert np.all(np.abs(gW - rW) <= 1e-5 * sW + 1e-7 * np.abs(rW) + 1e-30), l
+        assert np.all(np.abs(gb - rb) <= 1e-5 * sb + 1e-7 * np.abs(rb) + 1e-30), l
+        # Adam: the oracle's update on the step's own gradients.
+        (nW, nb), = M.adam_step([p32[l]], [(gW, gb)], [(np.zeros_like(gW), np.zeros_like(gb))],
+                                [(np.zeros_like(gW), np.zeros_like(gb))], 1, lr=1e-3)[0]
+        new_W = net.w[l].cpu().double().numpy()
+        new_b = net.b[l].cpu().double().numpy()
+        assert np.all(np.abs(new_W - nW) <= 1e-5 * np.abs(nW - p32[l][0]) + 2.0 ** -23 * np.abs(nW) + 1e-30), l
+        assert np.all(np.abs(new_b - nb) <= 1e-5 * np.abs(nb - p32[l][1]) + 2.0 ** -23 * np.abs(nb) + 1e-30), l
+
+
 def test_features_targets_gate_merge(pn):
     from paper_1802_00147_amd import workloads as W
     wl = W.batch(n=20000, seed=30, tmin=1e3, tmax=1e5)
