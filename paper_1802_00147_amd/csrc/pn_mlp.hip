@@ -223,15 +223,54 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
 // training step): block b belongs to product l with first[l] <= b <
 // first[l+1] and takes its tile in x-fastest order of that product's
 // (tx, ty, splits) grid.  Each tile is computed as k_gemm_bf16 computes it.
+// Bias gradients: db_l[n] = sum over rows of the bfloat16 gradient G_l
+// [rows x N_l]; blocks first[l] <= b < first[l+1] serve layer l, column
+// n = b - first[l], one column per 256-thread block.
+struct BiasArgs {
+    const uint16_t* G[4];
+    int64_t ldg[4];
+    float* db[4];
+    int first[5];
+    int64_t rows;
+};
+
+__device__ __forceinline__ void bias_block(const BiasArgs& a, int b, float* part) {
+    int l = 0;
+#pragma unroll
+    for (int k = 1; k < 4; ++k) l += (b >= a.first[k]) ? 1 : 0;
+    const int n = b - a.first[l];
+    const uint16_t* G = a.G[l];
+    const int64_t ldg = a.ldg[l], rows = a.rows;
+    float* db = a.db[l];
+    float s = 0.0f;
+    for (int64_t m = threadIdx.x; m < rows; m += 256) s += bf2f(G[m * ldg + n]);
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) part[threadIdx.x] += part[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[n] = part[0];
+}
+
+// The weight-gradient products and, after their blocks (first[4] onwards),
+// the bias-gradient columns of BiasArgs: the whole backward reduction of a
+// training step in one launch.
 struct GemmGroup {
     GemmArgs g[4];
     int tx[4], ty[4];
     int first[5];
+    BiasArgs bias;
 };
 __global__ __launch_bounds__(256) void k_gemm_group(GemmGroup gg) {
     __shared__ __attribute__((aligned(16))) uint16_t As[kStageSlices][BM][LDSK];
     __shared__ __attribute__((aligned(16))) uint16_t Bt[kStageSlices][BN][LDSK];
+    __shared__ float part[256];
     const int b = blockIdx.x;
+    if (b >= gg.first[4]) {
+        bias_block(gg.bias, b - gg.first[4], part);
+        return;
+    }
     int l = 0;
 #pragma unroll
     for (int k = 1; k < 4; ++k) l += (b >= gg.first[k]) ? 1 : 0;
@@ -293,8 +332,11 @@ __device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t* p) {
 // Optional extras of the fused pass, used by training: rows idx[r] of the
 // features instead of row r, the bfloat16 inputs and hidden activations
 // written out ([n][8] and [n][256], 16-byte aligned) for the backward pass,
-// and (gout non-null) the loss of the batch added to *loss and its gradient
-// with respect to the two outputs written to gout [n][2] (bfloat16).
+// (gout non-null) the loss of the batch added to *loss and its gradient
+// with respect to the two outputs written to gout [n][2] (bfloat16), and
+// (g3_out non-null, with gout) the gradient of the last hidden layer's
+// pre-activation, (gout W4) * (h3 > 0), written to g3_out [n][256]
+// (bfloat16).
 struct FusedIO {
     const int32_t* idx;
     uint16_t* x_out;
@@ -303,6 +345,7 @@ struct FusedIO {
     const float* target;
     uint16_t* gout;
     float* loss;
+    uint16_t* g3_out;
 };
 
 // Exchange with the adjacent lane (lanes 2j and 2j + 1), DPP quad permutation
@@ -330,6 +373,7 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                                                    FusedIO io) {
     __shared__ __attribute__((aligned(16))) uint16_t hA[FT][FLD];
     __shared__ __attribute__((aligned(16))) uint16_t hB[FT][FLD];
+    __shared__ uint16_t g4s[IO ? FT : 1][2];          // the tile's output gradient (training)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lq = lane >> 4, lk = lq * 8;
     const int c0 = 32 * wave;                         // first output column of this wavefront
@@ -504,9 +548,16 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                         const float d = f - t;
                         l += fabsf(d) <= 1.0f ? 0.5f * d * d : fabsf(d) - 0.5f;
                         const float sig = 1.0f / (1.0f + expf(-z));
-                        io.gout[2 * row] = f2bf((sig - y) / (float)n);
-                        io.gout[2 * row + 1] = f2bf(fminf(fmaxf(d, -1.0f), 1.0f) / (float)n);
+                        const uint16_t g0 = f2bf((sig - y) / (float)n);
+                        const uint16_t g1 = f2bf(fminf(fmaxf(d, -1.0f), 1.0f) / (float)n);
+                        io.gout[2 * row] = g0;
+                        io.gout[2 * row + 1] = g1;
+                        g4s[16 * wave + 4 * lq + v][0] = g0;
+                        g4s[16 * wave + 4 * lq + v][1] = g1;
                         lsum += l;
+                    } else if (lr == 0) {
+                        g4s[16 * wave + 4 * lq + v][0] = 0;
+                        g4s[16 * wave + 4 * lq + v][1] = 0;
                     }
                 }
 #pragma unroll
@@ -515,6 +566,37 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
             }
         }
         __syncthreads();   // hA is rewritten by the next tile's layer 1
+        if (IO && io.gout && io.g3_out) {
+            // g3 = (g4 W4) * (h3 > 0) for this wavefront's 32 columns, as
+            // the product with K = 2 (padded to one 32-deep slice) and the
+            // ReLU mask of h3 (still in hA) that k_gemm_bf16 would form.
+            bf16x8 b[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = c0 + 16 * j + lr;
+                uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                if (lq == 0) { v[0] = w3[col]; v[1] = w3[256 + col]; }
+                b[j] = *reinterpret_cast<const bf16x8*>(v);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                if (lq == 0) { v[0] = g4s[16 * i + lr][0]; v[1] = g4s[16 * i + lr][1]; }
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(v);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const f32x4 g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], f32x4{0.f, 0.f, 0.f, 0.f},
+                                                                            0, 0, 0);
+#pragma unroll
+                    for (int v2 = 0; v2 < 4; ++v2) {
+                        const int rl = 16 * i + 4 * lq + v2, col = c0 + 16 * j + lr;
+                        const float x = bf2f(hA[rl][col]) > 0.0f ? g[v2] : 0.0f;
+                        if (r0 + rl < n) io.g3_out[(r0 + rl) * 256 + col] = f2bf(x);
+                    }
+                }
+            }
+            __syncthreads();
+        }
         if (IO) {
             load_feat(tile + gridDim.x, fcur);
         } else {
@@ -525,36 +607,6 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
             }
         }
     }
-}
-
-// Bias gradients of the four layers in one launch: db_l[n] = sum over rows
-// of the bfloat16 gradient G_l [rows x N_l]; block b < first[4] serves layer
-// l with first[l] <= b < first[l+1], column n = b - first[l].
-struct BiasArgs {
-    const uint16_t* G[4];
-    int64_t ldg[4];
-    float* db[4];
-    int first[5];
-    int64_t rows;
-};
-__global__ __launch_bounds__(256) void k_bias_grads(BiasArgs a) {
-    __shared__ float part[256];
-    int l = 0;
-#pragma unroll
-    for (int k = 1; k < 4; ++k) l += ((int)blockIdx.x >= a.first[k]) ? 1 : 0;
-    const int n = (int)blockIdx.x - a.first[l];
-    const uint16_t* G = a.G[l];
-    const int64_t ldg = a.ldg[l], rows = a.rows;
-    float* db = a.db[l];
-    float s = 0.0f;
-    for (int64_t m = threadIdx.x; m < rows; m += 256) s += bf2f(G[m * ldg + n]);
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if ((int)threadIdx.x < k) part[threadIdx.x] += part[threadIdx.x + k];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) db[n] = part[0];
 }
 
 // Adam over all eight parameter tensors in one launch: tensor t holds
@@ -915,13 +967,13 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
 
     // Forward: one fused pass over the batch rows idx[], keeping the inputs
     // and hidden activations for the backward pass.
-    // Forward with the loss and its output gradient g4.
-    launch_fused(s, net, feat, B, out, FusedIO{idx, X, {h[0], h[1], h[2]}, label, target, g4, loss}, ncu);
+    // Forward with the loss, its output gradient g4 and the last hidden
+    // layer's gradient g3 = (g4 W4) * (h3 > 0).
+    launch_fused(s, net, feat, B, out, FusedIO{idx, X, {h[0], h[1], h[2]}, label, target, g4, loss, g3}, ncu);
     // Backward.  Weight gradients dW_l = g_l^T h_(l-1) go to per-layer
     // split-K partials that the Adam launch sums; the layer gradients
-    // g_(l-1) = (g_l W_l) * (h_(l-1) > 0) stay live for one launch that forms
-    // all bias gradients.
-    gemm(s, B, 256, 2, g4, 2, 1, net->wb[3], 256, 1, nullptr, 0, h[2], 256, nullptr, 0, g3, 256);
+    // g_(l-1) = (g_l W_l) * (h_(l-1) > 0) stay live for the launch that forms
+    // the weight gradients and all bias gradients.
     gemm(s, B, 256, 256, g3, 256, 1, net->wb[2], 256, 1, nullptr, 0, h[1], 256, nullptr, 0, g2, 256);
     gemm(s, B, 256, 256, g2, 256, 1, net->wb[1], 256, 1, nullptr, 0, h[0], 256, nullptr, 0, g1, 256);
     // The four weight gradients in one launch.
@@ -940,8 +992,7 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
         gg.first[l + 1] = gg.first[l] + pw[l].tx * pw[l].ty * pw[l].splits;
         splits[l] = pw[l].splits;
     }
-    hipLaunchKernelGGL(k_gemm_group, dim3(gg.first[4]), dim3(256), 0, s, gg);
-    BiasArgs ba;
+    BiasArgs& ba = gg.bias;
     const uint16_t* gl[4] = {g1, g2, g3, g4};
     ba.rows = B;
     ba.first[0] = 0;
@@ -951,7 +1002,7 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
         ba.db[l] = db[l];
         ba.first[l + 1] = ba.first[l] + kOut[l];
     }
-    hipLaunchKernelGGL(k_bias_grads, dim3(ba.first[4]), dim3(256), 0, s, ba);
+    hipLaunchKernelGGL(k_gemm_group, dim3(gg.first[4] + ba.first[4]), dim3(256), 0, s, gg);
     // Adam on the FP32 master weights, refreshing the bfloat16 copies.
     AdamArgs a;
     a.lr = lr;
@@ -1022,7 +1073,8 @@ pn_status pn_mlp_infer_fused(const pn_mlp* net, const float* feat, int64_t n, fl
         return PN_EDEVICE;
     }
     launch_fused(stream, net, feat, n, out,
-                 FusedIO{nullptr, nullptr, {nullptr, nullptr, nullptr}, nullptr, nullptr, nullptr, nullptr}, ncu);
+                 FusedIO{nullptr, nullptr, {nullptr, nullptr, nullptr}, nullptr, nullptr, nullptr, nullptr, nullptr},
+                 ncu);
     return launched("pn_mlp_infer_fused");
 }
 
@@ -1336,25 +1388,40 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
         valid.reserve((size_t)m1);
         for (int64_t j = 0; j < m1; ++j)
             if ((st[(size_t)j] & 0xFF) == 0) valid.push_back((int32_t)j);
-        const int64_t nb = (int64_t)valid.size() / cfg->refine_batch;
+        const int64_t nv = (int64_t)valid.size();
+        const int64_t nb = nv / cfg->refine_batch;
         SplitMix rng{cfg->refine_seed};
         std::vector<int32_t> ord(valid);
-        for (int32_t e = 0; e < cfg->refine_epochs && nb > 0; ++e) {
-            const float lr_e = cfg->refine_cosine
-                                   ? cfg->refine_lr * 0.5f * (1.0f + cosf(3.14159265358979f * e / cfg->refine_epochs))
-                                   : cfg->refine_lr;
-            for (size_t k = ord.size(); k > 1; --k) {          // Fisher-Yates
-                const size_t r = (size_t)(rng.next() % k);
-                std::swap(ord[k - 1], ord[r]);
+        // The epochs' orders are drawn on the host in sequence and uploaded
+        // together, as many epochs per copy as the order buffer (n entries)
+        // holds, so the device waits for the host once per group of epochs.
+        const int64_t per_copy = nv > 0 ? std::max<int64_t>(1, (int64_t)N / nv) : 1;
+        std::vector<int32_t> orders;
+        for (int32_t e0 = 0; e0 < cfg->refine_epochs && nb > 0; e0 += (int32_t)per_copy) {
+            const int32_t ne = (int32_t)std::min<int64_t>(per_copy, cfg->refine_epochs - e0);
+            orders.resize((size_t)ne * (size_t)nv);
+            for (int32_t k = 0; k < ne; ++k) {
+                for (size_t q = ord.size(); q > 1; --q) {      // Fisher-Yates
+                    const size_t r = (size_t)(rng.next() % q);
+                    std::swap(ord[q - 1], ord[r]);
+                }
+                std::copy(ord.begin(), ord.end(), orders.begin() + (size_t)k * (size_t)nv);
             }
-            PN_HIP(hipMemcpyAsync(order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, stream), what);
-            PN_HIP(hipStreamSynchronize(stream), what);    // ord is reshuffled next epoch
-            for (int64_t b = 0; b < nb; ++b) {
-                *adam_step += 1;
-                PN_TRY(pn_mlp_train_step(net, featA, labA, tgtA, order + b * cfg->refine_batch, cfg->refine_batch,
-                                         *adam_step, lr_e, loss, tws,
-                                         pn_mlp_train_workspace_size(cfg->refine_batch), stream));
+            PN_HIP(hipMemcpyAsync(order, orders.data(), orders.size() * 4, hipMemcpyHostToDevice, stream), what);
+            for (int32_t k = 0; k < ne; ++k) {
+                const int32_t e = e0 + k;
+                const float lr_e = cfg->refine_cosine
+                                       ? cfg->refine_lr * 0.5f *
+                                             (1.0f + cosf(3.14159265358979f * e / cfg->refine_epochs))
+                                       : cfg->refine_lr;
+                for (int64_t b = 0; b < nb; ++b) {
+                    *adam_step += 1;
+                    PN_TRY(pn_mlp_train_step(net, featA, labA, tgtA, order + (size_t)k * nv + b * cfg->refine_batch,
+                                             cfg->refine_batch, *adam_step, lr_e, loss, tws,
+                                             pn_mlp_train_workspace_size(cfg->refine_batch), stream));
+                }
             }
+            PN_HIP(hipStreamSynchronize(stream), what);    // the host buffer is refilled next
         }
     }
     PN_TRY(mark(2));

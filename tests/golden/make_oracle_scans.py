@@ -1,17 +1,18 @@
 """Expected outputs of the full-size scans, written by the CPU oracle alone.
 
 Each configuration is a seeded sample of one of the scan workloads (the whole
-grid for the 64 x 64 scan).  For every sampled orbit the oracle runs three
-times: on the state as generated, with r0 moved up by one ulp, and with p0
-moved up by one ulp.  The spread of the three FLIs is the oracle's own
-rounding sensitivity at that orbit and end time; the GPU parity tests take
-their per-orbit FLI tolerance from it.
+grid for the 64 x 64 scan).  For every sampled orbit the oracle runs five
+times: on the state as generated, and with r0 or p0 moved up or down by one
+ulp.  The spread of the five FLIs is the oracle's own rounding sensitivity
+at that orbit and end time (a one-ulp change of the initial state changes
+every rounding that follows); the GPU parity tests take their per-orbit FLI
+tolerance from it.
 
 Run from the repository root:  python tests/golden/make_oracle_scans.py [name ...]
 It imports only the oracle and the seeded input generators, and writes
 tests/golden/oracle_scan_<name>.txt (one row per sampled orbit):
 
-    index status label steps fli fli_r0_ulp fli_p0_ulp
+    index status label steps fli fli_r0_up fli_r0_down fli_p0_up fli_p0_down
 
 `load(name)` reads a file back as a dict of arrays.
 """
@@ -47,6 +48,10 @@ CONFIGS = {
 }
 
 
+TWINS = ("fli_r", "fli_rm", "fli_p", "fli_pm")
+COLUMNS = ("index", "status", "label", "steps", "fli") + TWINS
+
+
 def sample(name):
     """(workload, sample indices) of a configuration."""
     make, k, seed, _ = CONFIGS[name]
@@ -72,15 +77,18 @@ def oracle_rows(name, idx_subset=None, nthreads=None):
     y0 = O.init_state(sub.r0, sub.p0, sub.th1, sub.ph1, sub.th2, sub.ph2, sub.beta, sub.chi1, sub.chi2,
                       model=model)
     runs = []
-    for comp in (None, 0, 4):          # as generated; r_x one ulp up; p_y one ulp up
+    # As generated; r_x one ulp up and down; p_y one ulp up and down.
+    for comp, to in ((None, 0.0), (0, np.inf), (0, -np.inf), (4, np.inf), (4, -np.inf)):
         y = y0.copy()
         if comp is not None:
-            y[:, comp] = np.nextafter(y[:, comp], np.inf)
+            y[:, comp] = np.nextafter(y[:, comp], to)
         runs.append(O.fli_scan(y, sub.t_end, sub.beta, sub.chi1, sub.chi2, model=model, nthreads=nthreads))
     base = runs[0]
-    return dict(index=idx.astype(np.int64), status=base["status"].astype(np.int64),
-                label=base["label"].astype(np.int64), steps=base["steps"].astype(np.int64),
-                fli=base["fli"], fli_r=runs[1]["fli"], fli_p=runs[2]["fli"])
+    rows = dict(index=idx.astype(np.int64), status=base["status"].astype(np.int64),
+                label=base["label"].astype(np.int64), steps=base["steps"].astype(np.int64), fli=base["fli"])
+    for k, key in enumerate(TWINS):
+        rows[key] = runs[1 + k]["fli"]
+    return rows
 
 
 def write(name, rows, seconds):
@@ -92,16 +100,15 @@ def write(name, rows, seconds):
                 f"t_end {'per orbit' if isinstance(wl.t_end, np.ndarray) else wl.t_end:}, RK4 h=1, "
                 f"six-integral correction\n")
         f.write(f"# written by tests/golden/make_oracle_scans.py in {seconds:.0f} s\n")
-        f.write("# index status label steps fli fli_r0_ulp fli_p0_ulp\n")
+        f.write("# index status label steps fli fli_r0_up fli_r0_down fli_p0_up fli_p0_down\n")
         for i in range(len(rows["index"])):
-            f.write(f"{rows['index'][i]} {rows['status'][i]} {rows['label'][i]} {rows['steps'][i]} "
-                    f"{float(rows['fli'][i])!r} {float(rows['fli_r'][i])!r} {float(rows['fli_p'][i])!r}\n")
+            f.write(f"{rows['index'][i]} {rows['status'][i]} {rows['label'][i]} {rows['steps'][i]} " +
+                    " ".join(repr(float(rows[k][i])) for k in ("fli",) + TWINS) + "\n")
 
 
 def load(name):
-    cols = ("index", "status", "label", "steps", "fli", "fli_r", "fli_p")
     data = np.loadtxt(path(name), comments="#", ndmin=2)
-    out = {c: data[:, k] for k, c in enumerate(cols)}
+    out = {c: data[:, k] for k, c in enumerate(COLUMNS)}
     for c in ("index", "status", "label", "steps"):
         out[c] = out[c].astype(np.int64)
     return out

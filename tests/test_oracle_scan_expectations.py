@@ -21,7 +21,7 @@ def test_expectations_are_current(name):
     rows = M.oracle_rows(name, idx_subset=exp["index"][pick], nthreads=2)
     for k in ("status", "label", "steps"):
         assert np.array_equal(rows[k], exp[k][pick]), k
-    for k in ("fli", "fli_r", "fli_p"):
+    for k in ("fli",) + M.TWINS:
         np.testing.assert_array_equal(rows[k], exp[k][pick], err_msg=k)    # NaN equals NaN
 
 
