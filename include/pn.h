@@ -422,6 +422,21 @@ pn_status pn_batch_graph_create(const pn_model* model, pn_params params, const p
 pn_status pn_graph_launch(pn_graph* graph, hipStream_t stream);
 void pn_graph_destroy(pn_graph* graph);
 
+/* pn_batch_scan without a workspace argument, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid allocation): the queue and the processing order live
+ * in a static device array of the library, one per device, sized for at most
+ * 2^20 orbits (4.2 MB); n above that returns PN_EINVAL (pn_last_error says
+ * why) before anything is launched.  The call allocates nothing.  Every call
+ * on a device shares that device's array: calls that overlap on one device
+ * (on different streams, or from several threads) race and must be
+ * serialised by the caller.  Arguments, outputs and results otherwise as
+ * pn_batch_scan. */
+pn_status pn_batch_scan_noalloc(const pn_model* model, pn_params params, const pn_integrator* integ,
+                                const pn_correction* corr, const pn_fli_cfg* fli, int64_t n, const double* y0,
+                                int64_t ld, const double* t_end, const pn_scan_out* out, const pn_tuning* tuning,
+                                hipStream_t stream);
+
 /* Checkpoint and resume of a batch scan.  Long scans (t_end up to 1e6 steps
  * per orbit) can be interrupted after a bounded amount of work, saved, and
  * continued later, in the same process or after the workspace and outputs

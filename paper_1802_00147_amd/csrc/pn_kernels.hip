@@ -1006,6 +1006,36 @@ BatchWs carve(void* ws, int64_t n) {
     return w;
 }
 
+// The batch scan's workspace for callers that cannot allocate: a file-scope
+// device array (every device the library runs on holds its own copy until
+// the process ends) sized for kStaticBatchMaxOrbits orbits.  Host code uses
+// only the device address that hipGetSymbolAddress reports for the current
+// device, never the array's name.
+constexpr int64_t kStaticBatchMaxOrbits = (int64_t)1 << 20;
+constexpr size_t kStaticBatchBytes = 256 + ((2 * 256 * sizeof(unsigned int) + 255) / 256) * 256 +
+                                     (((size_t)kStaticBatchMaxOrbits * sizeof(int32_t) + 255) / 256) * 256;
+static __device__ __align__(256) unsigned char scratch[kStaticBatchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (nullptr and the HIP error text on failure).
+void* static_scratch(int dev) {
+    if (dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            set_error("pn_batch_scan_noalloc", e);
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 // Checkpoint tables: records per table, bytes per table.
 constexpr int64_t kCkptMaxPairs = (int64_t)1 << 18;
 
@@ -1661,6 +1691,32 @@ pn_status pn_batch_scan(const pn_model* model, pn_params params, const pn_integr
     if (ws == nullptr || ws_bytes < batch_ws_bytes(n)) return PN_ENOWS;
     enqueue_batch(integ->method, corr->mode, pa, fa, carve(ws, n), tu, ncu, stream);
     return launched("pn_batch_scan");
+}
+
+pn_status pn_batch_scan_noalloc(const pn_model* model, pn_params params, const pn_integrator* integ,
+                                const pn_correction* corr, const pn_fli_cfg* fli, int64_t n, const double* y0,
+                                int64_t ld, const double* t_end, const pn_scan_out* out, const pn_tuning* tuning,
+                                hipStream_t stream) {
+    ParamArgs pa;
+    FliArgs fa;
+    PN_REQUIRE(t_end != nullptr);
+    PN_REQUIRE(prepare_scan(model, params, integ, corr, fli, n, y0, ld, t_end, 0.0, out, pa, fa) == PN_OK);
+    if (n > kStaticBatchMaxOrbits || batch_ws_bytes(n) > kStaticBatchBytes) {
+        pn_detail::set_last_error("pn_batch_scan_noalloc", "more orbits than the static workspace holds (2^20)");
+        return PN_EINVAL;
+    }
+    int dev = 0;
+    const int ncu = device_cus(dev);
+    if (ncu <= 0) { set_error("pn_batch_scan_noalloc", hipErrorInvalidDevice); return PN_EDEVICE; }
+    const pn_tuning tu = chosen_tuning(tuning, dev);
+    PN_REQUIRE(valid_tuning(tu));
+    if (n == 0) return PN_OK;
+    void* ws = static_scratch(dev);
+    if (ws == nullptr) return PN_EDEVICE;
+    // The queue head and bin counters start at zero: k_batch_clear (a kernel,
+    // not a memset) clears them at the start of every call.
+    enqueue_batch(integ->method, corr->mode, pa, fa, carve(ws, n), tu, ncu, stream);
+    return launched("pn_batch_scan_noalloc");
 }
 
 size_t pn_batch_ckpt_workspace_size(int64_t n) { return n < 0 ? 0 : ckpt_ws_bytes(n); }

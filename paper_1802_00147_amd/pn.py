@@ -99,6 +99,7 @@ EXPORTS = ["pn_default_model", "pn_default_integrator", "pn_default_correction",
            "pn_default_surrogate_cfg", "pn_surrogate_scan_workspace_size", "pn_surrogate_scan",
            "pn_mlp_train", "pn_fli_scan_workspace_size", "pn_shutdown",
            "pn_batch_ckpt_workspace_size", "pn_batch_scan_resumable", "pn_batch_scan_pending",
+           "pn_batch_scan_noalloc",
            "pn_batch_resident_pairs", "pn_scan_kernel_resources",
            "pn_balanced_plan", "pn_balanced_piece", "pn_fli_scan_balanced_schedule",
            "pn_fli_scan_balanced_workspace_size", "pn_fli_scan_balanced", "pn_balanced_kernel_resources",
@@ -412,6 +413,31 @@ def batch_scan(y0, t_end, beta, chi1, chi2, model=None, integrator=None, correct
                              ctypes.c_int64(n), _ptr(y0), ctypes.c_int64(ld), _ptr(t_end), ctypes.byref(so), tu,
                              _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(y0.device))
     _check("pn_batch_scan", st)
+    return out
+
+
+def batch_scan_noalloc(y0, t_end, beta, chi1, chi2, model=None, integrator=None, correction=None, fli=None,
+                       out=None, n=None, full=True, tuning=None):
+    """pn_batch_scan_noalloc: the persistent batch scan on the library's static
+    device workspace (at most 2^20 orbits; calls on one device must not
+    overlap).  Outputs as batch_scan."""
+    ld = _state(y0)
+    n = ld if n is None else n
+    integ = integrator_struct(integrator)
+    assert isinstance(t_end, torch.Tensor), "batch scans take per-orbit end times"
+    t_end = _dev_f64(t_end, n)
+    if out is None:
+        out = scan_outputs(n, ld, y0.device, full=full)
+    p, keep = params_struct(beta, chi1, chi2)
+    tu = None
+    if tuning is not None:
+        tu = ctypes.byref(tuning if isinstance(tuning, Tuning) else tuning_struct(tuning))
+    so = _scan_out_struct(out)
+    st = lib().pn_batch_scan_noalloc(ctypes.byref(model_struct(model)), p, ctypes.byref(integ),
+                                     ctypes.byref(correction_struct(correction)), ctypes.byref(fli_struct(fli)),
+                                     ctypes.c_int64(n), _ptr(y0), ctypes.c_int64(ld), _ptr(t_end), ctypes.byref(so),
+                                     tu, _stream(y0.device))
+    _check("pn_batch_scan_noalloc", st)
     return out
 
 

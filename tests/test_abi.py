@@ -371,3 +371,19 @@ def test_train_workspace_layout(pn):
     bad = (ctypes.c_size_t * 9)()
     assert pn.lib().pn_mlp_train_workspace_layout(ctypes.c_int32(0), bad) == pn.PN_EINVAL
     assert pn.lib().pn_mlp_train_workspace_layout(ctypes.c_int32(5), None) == pn.PN_EINVAL
+
+
+def test_noalloc_batch_scan_rejects_more_orbits_than_its_static_workspace(pn):
+    """pn_batch_scan_noalloc holds at most 2^20 orbits; more is refused with
+    PN_EINVAL before anything touches a device (fake non-null pointers)."""
+    m, integ, corr, fli = (pn.model_struct(), pn.integrator_struct(), pn.correction_struct(), pn.fli_struct())
+    so = pn.ScanOut()
+    for f in ("fli", "label", "status"):
+        setattr(so, f, 8)
+    p = pn.Params(None, None, None, 1.0, 1.0, 1.0)
+    n = (1 << 20) + 1
+    st = pn.lib().pn_batch_scan_noalloc(ctypes.byref(m), p, ctypes.byref(integ), ctypes.byref(corr),
+                                       ctypes.byref(fli), ctypes.c_int64(n), ctypes.c_void_p(8),
+                                       ctypes.c_int64(n), ctypes.c_void_p(8), ctypes.byref(so), None, None)
+    assert st == pn.PN_EINVAL
+    assert b"2^20" in pn.lib().pn_last_error()
