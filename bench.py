@@ -55,9 +55,10 @@ KERNEL_SOURCES = ["paper_1802_00147_amd/csrc/pn_kernels.hip", "paper_1802_00147_
 # scaled by a 1 GiB device copy: FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0),
 # valid only for the kernel sources whose hash is recorded with them.
 # surrogate4096: the seven k_wrap_scan launches of one assisted scan, 206.4 MB
-# read + 158.7 MB written, 52.2 MB per launch.
-TRAFFIC = dict(sources_sha256="93f7a6e9b3191cd451681252ee59af220127e450e4ba785ed625c04b2663207a",
-               bytes_per_launch={"surrogate4096": 365164837 / 7})
+# read + 158.7 MB written, 52.2 MB per launch; fig7: the three launches of
+# the balanced scan, 81.4 MB read + 81.1 MB written, 54.2 MB per launch.
+TRAFFIC = dict(sources_sha256="ac4398b9fe9527cef0145f2124114bebe25ba3738a75e69cee5c8ddc31faf07a",
+               bytes_per_launch={"surrogate4096": 365161758 / 7, "fig7": 162524699 / 3})
 
 
 # Table 3 of the paper: wall time of its GPU and CPU scans (seconds).
@@ -68,8 +69,10 @@ PAPER_TABLE3 = {"fig6_th1_1.571": (75.0, 1020.0), "fig7": (2213.0, 25000.0)}
 # rocprofv3 counters (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 x 64 lanes, FMA
 # counted twice, over the launch's orbit-steps), valid only for the kernel
 # sources whose hash is recorded with them.
-HW_FLOPS = dict(sources_sha256="93f7a6e9b3191cd451681252ee59af220127e450e4ba785ed625c04b2663207a",
-                per_orbit_step={("k_wrap_scan", "surrogate4096"): 4934.2})
+HW_FLOPS = dict(sources_sha256="ac4398b9fe9527cef0145f2124114bebe25ba3738a75e69cee5c8ddc31faf07a",
+                per_orbit_step={("k_wrap_scan", "surrogate4096"): 4934.2, ("k_wrap_scan", "grid314"): 4912.6,
+                                ("k_wrap_scan", "fig7"): 4962.0, ("k_batch_scan", "batch1M"): 4944.9,
+                                ("k_fli_scan", "grid64"): 4910.0})
 
 
 def hardware_flops(kernel, workload):
@@ -556,6 +559,9 @@ def main():
     ap.add_argument("--workload", default="surrogate4096")
     ap.add_argument("--cpu-sample", type=int, default=160)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--schedule", choices=("auto", "plain"), default="auto",
+                    help="equal-length grids: the library's choice (balanced where it predicts it faster) "
+                         "or always the plain fused scan")
     ap.add_argument("--epochs", type=int, default=20, help="surrogate workload: training epochs (cosine decay)")
     ap.add_argument("--plain-sample", type=int, default=65536, help="surrogate workload: plain-scan sample")
     ap.add_argument("--refine", type=int, default=40, help="surrogate workload: refinement epochs on the audit")
@@ -608,6 +614,8 @@ def main():
         # it faster than the plain fused scan (full-chip grids whose resident
         # rounds do not divide evenly), else the plain scan.
         sched = pn.balanced_schedule(n, float(wl.t_end))
+        if args.schedule == "plain":
+            sched = dict(sched, launches=0)
         if sched["launches"] > 0:
             bws = pn.balanced_workspace(sched["slots"], dev)
             kernel = (f"k_wrap_scan<RK4,SIX> (balanced: {sched['slots']} slots x {sched['slot_len']} steps, "
@@ -628,7 +636,10 @@ def main():
         if batched:
             pn.batch_scan(y, t_end, beta, chi1, chi2, model=wl.model, out=out, ws=ws)
         else:
-            pn.fli_scan_balanced(y, float(t_end), beta, chi1, chi2, model=wl.model, out=out, ws=bws)
+            if bws is not None:
+                pn.fli_scan_balanced(y, float(t_end), beta, chi1, chi2, model=wl.model, out=out, ws=bws)
+            else:
+                pn.fli_scan(y, float(t_end), beta, chi1, chi2, model=wl.model, out=out)
         if ev is not None:
             ev[1].record(stream)
         return y
@@ -670,6 +681,8 @@ def main():
                                simd_fraction=min(1.0, waves / simds))
         if balanced:
             line["config"]["schedule"] = dict(kind="balanced", **sched)
+        else:
+            line["config"]["schedule"] = dict(kind="plain")
 
     if wl.name in PAPER_TABLE3:
         # The paper's own wall times for the same scan (its Table 3, other
@@ -678,6 +691,7 @@ def main():
         gpu_s, cpu_s = PAPER_TABLE3[wl.name]
         line["paper_context"] = dict(table3_gpu_s=gpu_s, table3_cpu_core_s=cpu_s, this_run_s=1e-3 * kernel_ms,
                                      note="GT 650M (RK5) and one i5-3230M core in the paper; context only")
+    oracle_fpos = None
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, args.cpu_sample)
         oracle_fpos = cb.pop("oracle_flops_per_orbit_step")
@@ -686,32 +700,32 @@ def main():
         # sample's rate (never run).
         cb["extrapolated_full_s"] = orbit_steps / cb["value"]
         line["cpu_baseline"] = cb
-        achieved = ALG_FLOPS_PER_ORBIT_STEP * orbit_steps / (kernel_ms * 1e-3) / 1e12
-        traffic = None
-        if TRAFFIC["sources_sha256"] == sources_sha256():
-            traffic = TRAFFIC["bytes_per_launch"].get(wl.name)
-        line["roofline"] = dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                                frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=traffic,
-                                kernel=kernel, kernel_ms=kernel_ms,
-                                flops_per_orbit_step=ALG_FLOPS_PER_ORBIT_STEP,
-                                oracle_flops_per_orbit_step=oracle_fpos)
-        hw = hardware_flops(kernel.split("<")[0], wl.name)
-        if hw is not None:
-            line["roofline"]["hw_flops_per_orbit_step"] = hw
-            line["roofline"]["hw_frac"] = (hw * orbit_steps / (kernel_ms * 1e-3) / 1e12 /
-                                           FP64_VECTOR_PEAK_TFLOPS)
-        if not batched:
-            # Registers, spills and occupancy of the scan kernel as the
-            # runtime reports them, and the wavefronts per SIMD the launch
-            # actually keeps resident.
-            if balanced:
-                res = pn.balanced_kernel_resources()
-                res["achieved_waves_per_simd"] = min(float(res["waves_per_simd"]),
-                                                     ((sched["slots"] + 31) // 32) / simds)
-            else:
-                res = pn.scan_kernel_resources()
-                res["achieved_waves_per_simd"] = min(float(res["waves_per_simd"]), ((2 * n + 63) // 64) / simds)
-            line["roofline"]["resources"] = res
+    achieved = ALG_FLOPS_PER_ORBIT_STEP * orbit_steps / (kernel_ms * 1e-3) / 1e12
+    traffic = None
+    if TRAFFIC["sources_sha256"] == sources_sha256():
+        traffic = TRAFFIC["bytes_per_launch"].get(wl.name if args.schedule == "auto" else wl.name + "/plain")
+    line["roofline"] = dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                            frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=traffic,
+                            kernel=kernel, kernel_ms=kernel_ms,
+                            flops_per_orbit_step=ALG_FLOPS_PER_ORBIT_STEP,
+                            oracle_flops_per_orbit_step=oracle_fpos)
+    hw = hardware_flops(kernel.split("<")[0], wl.name)
+    if hw is not None:
+        line["roofline"]["hw_flops_per_orbit_step"] = hw
+        line["roofline"]["hw_frac"] = (hw * orbit_steps / (kernel_ms * 1e-3) / 1e12 /
+                                       FP64_VECTOR_PEAK_TFLOPS)
+    if not batched:
+        # Registers, spills and occupancy of the scan kernel as the
+        # runtime reports them, and the wavefronts per SIMD the launch
+        # actually keeps resident.
+        if balanced:
+            res = pn.balanced_kernel_resources()
+            res["achieved_waves_per_simd"] = min(float(res["waves_per_simd"]),
+                                                 ((sched["slots"] + 31) // 32) / simds)
+        else:
+            res = pn.scan_kernel_resources()
+            res["achieved_waves_per_simd"] = min(float(res["waves_per_simd"]), ((2 * n + 63) // 64) / simds)
+        line["roofline"]["resources"] = res
     print(json.dumps(line), flush=True)
 
 
