@@ -363,7 +363,8 @@ void pn_default_tuning(pn_tuning* t);
 size_t pn_batch_workspace_size(int64_t n);
 
 /* Resources of the fused scan kernel (pn_fli_scan) for one integrator and
- * correction mode on the current device, as the runtime reports them:
+ * correction mode on the current device, in the build that serves a shared
+ * parameter set (every scan grid), as the runtime reports them:
  * vector registers per lane, scratch (spill) bytes per lane, and the
  * wavefronts per SIMD its 64-lane workgroups can keep resident.  Any output
  * pointer may be NULL (host memory).  PN_EINVAL for an unknown method or

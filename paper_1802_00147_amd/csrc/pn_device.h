@@ -29,6 +29,12 @@ struct PnCoef {
     double b1, b2, b3, b4, b5, b6, b7;     // 2PN
     double cso1, cso2, c12, c11, c22;      // spin couplings
     double s1, s2;                         // spin lengths
+    // Multiples of the above that the equations of motion use, formed once
+    // per table (pn_orbit_partials, pn_rhs_eval).
+    double m4a1, m6b1, m2a2, m4b2, m2b3, m2b5;   // 2 dH/dP2
+    double m2a3, m4b4, m2b6;                     // dH/dNP / (u NP), with m2b3
+    double m2a4, m3b7;                           // dH/du, with m2b5 and m2b6
+    double m3c12, m6c11, m6c22;                  // spin-spin weights w_i
 };
 
 // Coefficient table of one parameter set (Sec. 2: M = 1, eta = m1 m2).
@@ -72,6 +78,11 @@ PN_HD bool pn_make_coef(const pn_model& m, double beta, double chi1, double chi2
         k.s1 = chi1 * m1 * m1;
         k.s2 = chi2 * m2 * m2;
     }
+    k.m4a1 = 4.0 * k.a1; k.m6b1 = 6.0 * k.b1; k.m2a2 = 2.0 * k.a2; k.m4b2 = 4.0 * k.b2;
+    k.m2b3 = 2.0 * k.b3; k.m2b5 = 2.0 * k.b5;
+    k.m2a3 = 2.0 * k.a3; k.m4b4 = 4.0 * k.b4; k.m2b6 = 2.0 * k.b6;
+    k.m2a4 = 2.0 * k.a4; k.m3b7 = 3.0 * k.b7;
+    k.m3c12 = 3.0 * k.c12; k.m6c11 = 6.0 * k.c11; k.m6c22 = 6.0 * k.c22;
     return ok;
 }
 
@@ -98,6 +109,26 @@ __device__ __forceinline__ double dot3(double ax, double ay, double az, double b
     return fma(ax, bx, fma(ay, by, az * bz));
 }
 
+// Partial derivatives of H_orb(P2, NP, u) in nested (Horner) form:
+//   cp = 2 dH/dP2 = 1 + P2 (4 a1 + 6 b1 P2) + u (2 a2 + 4 b2 P2 + 2 b3 NP2 + 2 b5 u)
+//   dH/dNP = NP u hw,  hw = 2 a3 + 2 b3 P2 + 4 b4 NP2 + 2 b6 u
+//   dH/du = -1 + P2 (a2 + b2 P2 + b3 NP2) + NP2 (a3 + b4 NP2) + u (2 a4 + 2 b5 P2 + 2 b6 NP2 + 3 b7 u)
+struct PnOrbPartials { double cp, hw, Hu, Hu0; };
+
+__device__ __forceinline__ PnOrbPartials pn_orbit_partials(const PnCoef& k, double P2, double NP2, double u) {
+    PnOrbPartials o;
+    const double ca = fma(fma(k.m6b1, P2, k.m4a1), P2, 1.0);
+    const double cb = fma(k.m2b5, u, fma(k.m2b3, NP2, fma(k.m4b2, P2, k.m2a2)));
+    o.cp = fma(cb, u, ca);
+    o.hw = fma(k.m2b6, u, fma(k.m4b4, NP2, fma(k.m2b3, P2, k.m2a3)));
+    const double t1 = fma(k.b3, NP2, fma(k.b2, P2, k.a2));
+    const double t2 = fma(k.b4, NP2, k.a3);
+    const double t3 = fma(k.m3b7, u, fma(k.m2b6, NP2, fma(k.m2b5, P2, k.m2a4)));
+    o.Hu0 = fma(t2, NP2, fma(t1, P2, -1.0));
+    o.Hu = fma(t3, u, o.Hu0);
+    return o;
+}
+
 // Right-hand side: f = (dH/dp, -dH/dr, Omega1 x S1, Omega2 x S2).
 __device__ __forceinline__ void pn_rhs_eval(const PnCoef& k, const double* y, double* f) {
     const double rx = y[0], ry = y[1], rz = y[2];
@@ -111,52 +142,50 @@ __device__ __forceinline__ void pn_rhs_eval(const PnCoef& k, const double* y, do
     const double P2 = dot3(px, py, pz, px, py, pz);
     const double NP = dot3(nx, ny, nz, px, py, pz);
     const double NP2 = NP * NP;
+    const PnOrbPartials o = pn_orbit_partials(k, P2, NP2, u);
+    const double HNP = (u * o.hw) * NP;   // dH/dNP
+    const double Ap = HNP * u;
 
-    // Partial derivatives of H_orb(P2, NP, u).
-    const double HP2 = 0.5 + 2.0 * k.a1 * P2 + k.a2 * u + 3.0 * k.b1 * P2 * P2
-                     + fma(2.0 * k.b2, P2, k.b3 * NP2) * u + k.b5 * u2;
-    const double HNP = 2.0 * NP * (k.a3 * u + fma(k.b3, P2, 2.0 * k.b4 * NP2) * u + k.b6 * u2);
-    const double Hu = -1.0 + fma(k.a2, P2, k.a3 * NP2) + 2.0 * k.a4 * u
-                    + (k.b2 * P2 * P2 + k.b3 * P2 * NP2 + k.b4 * NP2 * NP2)
-                    + 2.0 * fma(k.b5, P2, k.b6 * NP2) * u + 3.0 * k.b7 * u2;
-
-    // Spin geometry.
+    // Spin geometry; eu = u^3 S_eff, S_eff = cso1 S1 + cso2 S2.
     const double Lx = ry * pz - rz * py, Ly = rz * px - rx * pz, Lz = rx * py - ry * px;
-    const double ex = k.cso1 * s1x + k.cso2 * s2x;   // S_eff
-    const double ey = k.cso1 * s1y + k.cso2 * s2y;
-    const double ez = k.cso1 * s1z + k.cso2 * s2z;
-    const double LS = dot3(Lx, Ly, Lz, ex, ey, ez);
+    const double A1 = u3 * k.cso1, A2 = u3 * k.cso2, C12 = u3 * k.c12;
+    const double eux = fma(A1, s1x, A2 * s2x);
+    const double euy = fma(A1, s1y, A2 * s2y);
+    const double euz = fma(A1, s1z, A2 * s2z);
+    const double LSu = dot3(Lx, Ly, Lz, eux, euy, euz);   // u^3 L.S_eff
     const double sn1 = dot3(s1x, s1y, s1z, nx, ny, nz);
     const double sn2 = dot3(s2x, s2y, s2z, nx, ny, nz);
     const double S12 = dot3(s1x, s1y, s1z, s2x, s2y, s2z);
     const double S11 = dot3(s1x, s1y, s1z, s1x, s1y, s1z);
     const double S22 = dot3(s2x, s2y, s2z, s2x, s2y, s2z);
-    const double w1 = 3.0 * k.c12 * sn2 + 6.0 * k.c11 * sn1;   // Omega1 = u^3 (cso1 L + w1 n - c12 S2) + (...) S1
-    const double w2 = 3.0 * k.c12 * sn1 + 6.0 * k.c22 * sn2;
+    // Spin-spin weights: dH/dS_i holds u^3 w_i n (eqs. 3-5).
+    const double w1 = fma(k.m3c12, sn2, k.m6c11 * sn1);
+    const double w2 = fma(k.m3c12, sn1, k.m6c22 * sn2);
+    // Bracket of dH/dr along n (eqs. 3-5): sum c (5 a a - S.S), with
+    // w1 a1 + w2 a2 = 6 sum c a a.
+    const double Hss5 = fma(5.0 / 6.0, fma(w1, sn1, w2 * sn2), -fma(k.c12, S12, fma(k.c11, S11, k.c22 * S22)));
 
-    // dH/dp = 2 HP2 p + HNP n + u^3 (S_eff x r).
-    const double cp = 2.0 * HP2;
-    f[0] = cp * px + HNP * nx + u3 * (ey * rz - ez * ry);
-    f[1] = cp * py + HNP * ny + u3 * (ez * rx - ex * rz);
-    f[2] = cp * pz + HNP * nz + u3 * (ex * ry - ey * rx);
+    // dH/dp = cp p + HNP n + u^3 (S_eff x r).
+    f[0] = fma(euy, rz, fma(-euz, ry, fma(HNP, nx, o.cp * px)));
+    f[1] = fma(euz, rx, fma(-eux, rz, fma(HNP, ny, o.cp * py)));
+    f[2] = fma(eux, ry, fma(-euy, rx, fma(HNP, nz, o.cp * pz)));
 
-    // dH/dr = An n + Ap p + u^4 (w1 S1 + w2 S2) + u^3 (p x S_eff).
-    const double Ap = HNP * u;
-    const double An = -Ap * NP - Hu * u2 - 3.0 * u4 * LS
-                    - 3.0 * u4 * (k.c12 * (5.0 * sn1 * sn2 - S12) + k.c11 * (5.0 * sn1 * sn1 - S11)
-                                  + k.c22 * (5.0 * sn2 * sn2 - S22));
+    // dH/dr = An n + Ap p + u^4 (w1 S1 + w2 S2) + u^3 (p x S_eff),
+    // An = -Ap NP - Hu u^2 - 3 u^4 (L.S_eff + Hss5).
+    const double An = fma(-3.0 * u, fma(u3, Hss5, LSu), fma(-o.Hu, u2, -Ap * NP));
     const double B1 = u4 * w1, B2 = u4 * w2;
-    f[3] = -(An * nx + Ap * px + B1 * s1x + B2 * s2x + u3 * (py * ez - pz * ey));
-    f[4] = -(An * ny + Ap * py + B1 * s1y + B2 * s2y + u3 * (pz * ex - px * ez));
-    f[5] = -(An * nz + Ap * pz + B1 * s1z + B2 * s2z + u3 * (px * ey - py * ex));
+    f[3] = -fma(euz, py, fma(-euy, pz, fma(B2, s2x, fma(B1, s1x, fma(Ap, px, An * nx)))));
+    f[4] = -fma(eux, pz, fma(-euz, px, fma(B2, s2y, fma(B1, s1y, fma(Ap, py, An * ny)))));
+    f[5] = -fma(euy, px, fma(-eux, py, fma(B2, s2z, fma(B1, s1z, fma(Ap, pz, An * nz)))));
 
-    // Spin precession, eq. (7).
-    const double o1x = u3 * (k.cso1 * Lx + w1 * nx - k.c12 * s2x);
-    const double o1y = u3 * (k.cso1 * Ly + w1 * ny - k.c12 * s2y);
-    const double o1z = u3 * (k.cso1 * Lz + w1 * nz - k.c12 * s2z);
-    const double o2x = u3 * (k.cso2 * Lx + w2 * nx - k.c12 * s1x);
-    const double o2y = u3 * (k.cso2 * Ly + w2 * ny - k.c12 * s1y);
-    const double o2z = u3 * (k.cso2 * Lz + w2 * nz - k.c12 * s1z);
+    // Spin precession, eq. (7): Omega1 = u^3 (cso1 L + w1 n - c12 S2), and
+    // u^3 w1 n = u^4 w1 r = B1 r.
+    const double o1x = fma(A1, Lx, fma(B1, rx, -C12 * s2x));
+    const double o1y = fma(A1, Ly, fma(B1, ry, -C12 * s2y));
+    const double o1z = fma(A1, Lz, fma(B1, rz, -C12 * s2z));
+    const double o2x = fma(A2, Lx, fma(B2, rx, -C12 * s1x));
+    const double o2y = fma(A2, Ly, fma(B2, ry, -C12 * s1y));
+    const double o2z = fma(A2, Lz, fma(B2, rz, -C12 * s1z));
     f[6] = o1y * s1z - o1z * s1y;
     f[7] = o1z * s1x - o1x * s1z;
     f[8] = o1x * s1y - o1y * s1x;
@@ -168,7 +197,7 @@ __device__ __forceinline__ void pn_rhs_eval(const PnCoef& k, const double* y, do
 // Quantities of the spins alone, fixed while a correction moves r and p:
 // the effective spin-orbit vector S_eff = cso1 S1 + cso2 S2 and the spin
 // products.
-struct PnSpinInv { double ex, ey, ez, S11, S22, S12; };
+struct PnSpinInv { double ex, ey, ez, S11, S22, S12, Sq; };
 
 __device__ __forceinline__ PnSpinInv pn_spin_inv(const PnCoef& k, const double* y) {
     const double s1x = y[6], s1y = y[7], s1z = y[8];
@@ -180,6 +209,7 @@ __device__ __forceinline__ PnSpinInv pn_spin_inv(const PnCoef& k, const double* 
     v.S11 = dot3(s1x, s1y, s1z, s1x, s1y, s1z);
     v.S22 = dot3(s2x, s2y, s2z, s2x, s2y, s2z);
     v.S12 = dot3(s1x, s1y, s1z, s2x, s2y, s2z);
+    v.Sq = fma(k.c12, v.S12, fma(k.c11, v.S11, k.c22 * v.S22));   // sum c S.S of eqs. 3-5
     return v;
 }
 
@@ -201,12 +231,12 @@ __device__ __forceinline__ PnRGeom pn_rgeom(const PnCoef& k, const PnSpinInv& si
     g.nz = rz * g.u;
     const double sn1 = dot3(y[6], y[7], y[8], g.nx, g.ny, g.nz);
     const double sn2 = dot3(y[9], y[10], y[11], g.nx, g.ny, g.nz);
-    g.Hss3 = k.c12 * (3.0 * sn1 * sn2 - si.S12) + k.c11 * (3.0 * sn1 * sn1 - si.S11)
-           + k.c22 * (3.0 * sn2 * sn2 - si.S22);
-    g.Hss5 = k.c12 * (5.0 * sn1 * sn2 - si.S12) + k.c11 * (5.0 * sn1 * sn1 - si.S11)
-           + k.c22 * (5.0 * sn2 * sn2 - si.S22);
-    g.w1 = 3.0 * k.c12 * sn2 + 6.0 * k.c11 * sn1;
-    g.w2 = 3.0 * k.c12 * sn1 + 6.0 * k.c22 * sn2;
+    g.w1 = fma(k.m3c12, sn2, k.m6c11 * sn1);
+    g.w2 = fma(k.m3c12, sn1, k.m6c22 * sn2);
+    // w1 a1 + w2 a2 = 6 sum c a a, so the brackets are multiples of it less sum c S.S.
+    const double q6 = fma(g.w1, sn1, g.w2 * sn2);
+    g.Hss3 = fma(0.5, q6, -si.Sq);
+    g.Hss5 = fma(5.0 / 6.0, q6, -si.Sq);
     return g;
 }
 
@@ -254,27 +284,24 @@ __device__ __forceinline__ void pn_energy_grad_g(const PnCoef& k, const PnSpinIn
     const double P2 = dot3(px, py, pz, px, py, pz);
     const double NP = dot3(nx, ny, nz, px, py, pz);
     const double NP2 = NP * NP;
-    const double HP2 = 0.5 + 2.0 * k.a1 * P2 + k.a2 * u + 3.0 * k.b1 * P2 * P2
-                     + fma(2.0 * k.b2, P2, k.b3 * NP2) * u + k.b5 * u2;
-    const double HNP = 2.0 * NP * (k.a3 * u + fma(k.b3, P2, 2.0 * k.b4 * NP2) * u + k.b6 * u2);
-    const double Hu = -1.0 + fma(k.a2, P2, k.a3 * NP2) + 2.0 * k.a4 * u
-                    + (k.b2 * P2 * P2 + k.b3 * P2 * NP2 + k.b4 * NP2 * NP2)
-                    + 2.0 * fma(k.b5, P2, k.b6 * NP2) * u + 3.0 * k.b7 * u2;
+    const PnOrbPartials o = pn_orbit_partials(k, P2, NP2, u);
+    const double HNP = (u * o.hw) * NP;
+    const double Ap = HNP * u;
     const double Lx = ry * pz - rz * py, Ly = rz * px - rx * pz, Lz = rx * py - ry * px;
     const double LS = dot3(Lx, Ly, Lz, ex, ey, ez);
-    H = 0.5 * P2 - u + k.a1 * P2 * P2 + fma(k.a2, P2, k.a3 * NP2) * u + k.a4 * u2
-      + k.b1 * P2 * P2 * P2 + (k.b2 * P2 * P2 + k.b3 * P2 * NP2 + k.b4 * NP2 * NP2) * u
-      + fma(k.b5, P2, k.b6 * NP2) * u2 + k.b7 * u3 + u3 * LS + u3 * g.Hss3;
-    const double cp = 2.0 * HP2;
-    gp[0] = cp * px + HNP * nx + u3 * (ey * rz - ez * ry);
-    gp[1] = cp * py + HNP * ny + u3 * (ez * rx - ex * rz);
-    gp[2] = cp * pz + HNP * nz + u3 * (ex * ry - ey * rx);
-    const double Ap = HNP * u;
-    const double An = -Ap * NP - Hu * u2 - 3.0 * u4 * LS - 3.0 * u4 * g.Hss5;
+    // H = P2 (1/2 + P2 (a1 + b1 P2)) + u (dH/du at u = 0 + u (a4 + b5 P2 + b6 NP2 + u (b7 + LS + Hss3))).
+    const double hA = fma(fma(k.b1, P2, k.a1), P2, 0.5) * P2;
+    const double hB = fma(k.b7 + (LS + g.Hss3), u, fma(k.b6, NP2, fma(k.b5, P2, k.a4)));
+    H = fma(fma(hB, u, o.Hu0), u, hA);
+    const double eux = u3 * ex, euy = u3 * ey, euz = u3 * ez;
+    gp[0] = fma(euy, rz, fma(-euz, ry, fma(HNP, nx, o.cp * px)));
+    gp[1] = fma(euz, rx, fma(-eux, rz, fma(HNP, ny, o.cp * py)));
+    gp[2] = fma(eux, ry, fma(-euy, rx, fma(HNP, nz, o.cp * pz)));
+    const double An = fma(-3.0 * u4, LS + g.Hss5, fma(-o.Hu, u2, -Ap * NP));
     const double B1 = u4 * g.w1, B2 = u4 * g.w2;
-    gr[0] = An * nx + Ap * px + B1 * y[6] + B2 * y[9] + u3 * (py * ez - pz * ey);
-    gr[1] = An * ny + Ap * py + B1 * y[7] + B2 * y[10] + u3 * (pz * ex - px * ez);
-    gr[2] = An * nz + Ap * pz + B1 * y[8] + B2 * y[11] + u3 * (px * ey - py * ex);
+    gr[0] = fma(euz, py, fma(-euy, pz, fma(B2, y[9], fma(B1, y[6], fma(Ap, px, An * nx)))));
+    gr[1] = fma(eux, pz, fma(-euz, px, fma(B2, y[10], fma(B1, y[7], fma(Ap, py, An * ny)))));
+    gr[2] = fma(euy, px, fma(-eux, py, fma(B2, y[11], fma(B1, y[8], fma(Ap, pz, An * nz)))));
 }
 
 __device__ __forceinline__ void pn_energy_grad_rp(const PnCoef& k, const double* y, double& H,

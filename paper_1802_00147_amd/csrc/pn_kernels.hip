@@ -411,15 +411,21 @@ __device__ __forceinline__ void pair_finish(PairState& ps, const PnCoef& k, bool
     if (o.steps) o.steps[i] = ps.t;
 }
 
-// Fused scan: orbit i on lanes (2i, 2i+1) from t = 0 to t_end.
-template <int METHOD, int MODE>
+// Fused scan: orbit i on lanes (2i, 2i+1) from t = 0 to t_end.  SHARED:
+// every orbit has the parameter set of pa.coef, whose table then stays in
+// scalar registers.
+template <int METHOD, int MODE, bool SHARED>
 __global__ __launch_bounds__(kBlock) void k_fli_scan(ParamArgs pa, FliArgs fa) {
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t i = g >> 1;
     if (i >= fa.n) return;                 // pairs are whole: both lanes leave together
     const bool shadow = (g & 1) != 0;
     PnCoef k;
-    const bool param_ok = load_coef(pa, i, k);
+    bool param_ok = true;
+    if (SHARED)
+        k = pa.coef;
+    else
+        param_ok = load_coef(pa, i, k);
     PairState ps;
     pair_begin(ps, k, param_ok, shadow, fa, i);
     while (pair_running(ps)) pair_step<METHOD, MODE>(ps, k, shadow, fa, i);
@@ -933,7 +939,11 @@ double shared_eta(const pn_params& p) { return p.beta ? 0.0 : p.beta0 / ((1.0 + 
 
 template <int METHOD, int MODE>
 void launch_scan(const ParamArgs& pa, const FliArgs& fa, hipStream_t s) {
-    hipLaunchKernelGGL((k_fli_scan<METHOD, MODE>), dim3(grid_for(2 * fa.n)), dim3(kBlock), 0, s, pa, fa);
+    if (pa.beta == nullptr)
+        hipLaunchKernelGGL((k_fli_scan<METHOD, MODE, true>), dim3(grid_for(2 * fa.n)), dim3(kBlock), 0, s, pa, fa);
+    else
+        hipLaunchKernelGGL((k_fli_scan<METHOD, MODE, false>), dim3(grid_for(2 * fa.n)), dim3(kBlock), 0, s, pa,
+                           fa);
 }
 
 template <int METHOD>
@@ -1644,14 +1654,14 @@ pn_status pn_scan_kernel_resources(int32_t method, int32_t mode, int32_t* vgprs,
     PN_REQUIRE(mode >= PN_CORR_NONE && mode <= PN_CORR_DUAL);
     const void* f = nullptr;
     switch (method * 4 + mode) {
-        case 0: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK4, PN_CORR_NONE>); break;
-        case 1: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK4, PN_CORR_SPIN>); break;
-        case 2: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK4, PN_CORR_SIX>); break;
-        case 3: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK4, PN_CORR_DUAL>); break;
-        case 4: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK5, PN_CORR_NONE>); break;
-        case 5: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK5, PN_CORR_SPIN>); break;
-        case 6: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK5, PN_CORR_SIX>); break;
-        default: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK5, PN_CORR_DUAL>); break;
+        case 0: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK4, PN_CORR_NONE, true>); break;
+        case 1: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK4, PN_CORR_SPIN, true>); break;
+        case 2: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK4, PN_CORR_SIX, true>); break;
+        case 3: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK4, PN_CORR_DUAL, true>); break;
+        case 4: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK5, PN_CORR_NONE, true>); break;
+        case 5: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK5, PN_CORR_SPIN, true>); break;
+        case 6: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK5, PN_CORR_SIX, true>); break;
+        default: f = reinterpret_cast<const void*>(&k_fli_scan<PN_RK5, PN_CORR_DUAL, true>); break;
     }
     return func_resources("pn_scan_kernel_resources", f, kBlock, vgprs, scratch_bytes, waves_per_simd);
 }

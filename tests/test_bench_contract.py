@@ -68,7 +68,9 @@ def test_grid64_line():
     d = _run("--workload", "grid64")
     assert d["unit"] == "orbit-steps/s" and d["dtype"] == "f64"
     assert d["config"]["workload"].startswith("grid64")
-    assert d["config"]["orbit_steps"] == 4096 * 100000
+    # A chaotic orbit may come within r < 2 and stop before t = 1e5 (whether
+    # it does depends on rounding: the oracle's own run stops one of them).
+    assert 0.999 * 4096 * 100000 <= d["config"]["orbit_steps"] <= 4096 * 100000
     res = d["roofline"]["resources"]
     assert 0 < res["vgprs"] <= 512 and res["waves_per_simd"] >= 1
     assert abs(res["achieved_waves_per_simd"] - 128 / 1024) < 1e-12     # grid64: 128 wavefronts
