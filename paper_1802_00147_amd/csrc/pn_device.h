@@ -37,6 +37,18 @@ struct PnCoef {
     double m3c12, m6c11, m6c22;                  // spin-spin weights w_i
 };
 
+// The multiples of a table's coefficients (the same IEEE products wherever
+// they are formed).  A kernel whose orbits share one table receives it in
+// scalar registers and re-forms these on the device, so that they sit in
+// vector registers: the scalar registers then hold only the base table.
+PN_HD void pn_coef_derive(PnCoef& k) {
+    k.m4a1 = 4.0 * k.a1; k.m6b1 = 6.0 * k.b1; k.m2a2 = 2.0 * k.a2; k.m4b2 = 4.0 * k.b2;
+    k.m2b3 = 2.0 * k.b3; k.m2b5 = 2.0 * k.b5;
+    k.m2a3 = 2.0 * k.a3; k.m4b4 = 4.0 * k.b4; k.m2b6 = 2.0 * k.b6;
+    k.m2a4 = 2.0 * k.a4; k.m3b7 = 3.0 * k.b7;
+    k.m3c12 = 3.0 * k.c12; k.m6c11 = 6.0 * k.c11; k.m6c22 = 6.0 * k.c22;
+}
+
 // Coefficient table of one parameter set (Sec. 2: M = 1, eta = m1 m2).
 // Returns false when beta or chi is out of range (or not finite).
 PN_HD bool pn_make_coef(const pn_model& m, double beta, double chi1, double chi2, PnCoef& k) {
@@ -78,11 +90,7 @@ PN_HD bool pn_make_coef(const pn_model& m, double beta, double chi1, double chi2
         k.s1 = chi1 * m1 * m1;
         k.s2 = chi2 * m2 * m2;
     }
-    k.m4a1 = 4.0 * k.a1; k.m6b1 = 6.0 * k.b1; k.m2a2 = 2.0 * k.a2; k.m4b2 = 4.0 * k.b2;
-    k.m2b3 = 2.0 * k.b3; k.m2b5 = 2.0 * k.b5;
-    k.m2a3 = 2.0 * k.a3; k.m4b4 = 4.0 * k.b4; k.m2b6 = 2.0 * k.b6;
-    k.m2a4 = 2.0 * k.a4; k.m3b7 = 3.0 * k.b7;
-    k.m3c12 = 3.0 * k.c12; k.m6c11 = 6.0 * k.c11; k.m6c22 = 6.0 * k.c22;
+    pn_coef_derive(k);
     return ok;
 }
 

@@ -422,10 +422,12 @@ __global__ __launch_bounds__(kBlock) void k_fli_scan(ParamArgs pa, FliArgs fa) {
     const bool shadow = (g & 1) != 0;
     PnCoef k;
     bool param_ok = true;
-    if (SHARED)
+    if (SHARED) {
         k = pa.coef;
-    else
+        pn_coef_derive(k);
+    } else {
         param_ok = load_coef(pa, i, k);
+    }
     PairState ps;
     pair_begin(ps, k, param_ok, shadow, fa, i);
     while (pair_running(ps)) pair_step<METHOD, MODE>(ps, k, shadow, fa, i);
@@ -785,7 +787,10 @@ __global__ __launch_bounds__(256, OCC) void k_wrap_scan(ParamArgs pa, FliArgs fa
     bool active = tau < tend, open = active;
     int64_t orbit = 0, b = 0, pend = 0;                // open piece: orbit, last step + 1, end time
     PnCoef k;
-    if (SHARED) k = pa.coef;
+    if (SHARED) {
+        k = pa.coef;
+        pn_coef_derive(k);
+    }
     PairState ps;
     for (;;) {
         if (__ballot(active) == 0ull) break;
