@@ -54,11 +54,11 @@ KERNEL_SOURCES = ["paper_1802_00147_amd/csrc/pn_kernels.hip", "paper_1802_00147_
 # HBM bytes from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per dispatch,
 # scaled by a 1 GiB device copy: FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0),
 # valid only for the kernel sources whose hash is recorded with them.
-# surrogate4096: the seven k_wrap_scan launches of one assisted scan, 206.4 MB
-# read + 158.7 MB written, 52.2 MB per launch; fig7: the three launches of
-# the balanced scan, 81.4 MB read + 81.1 MB written, 54.2 MB per launch.
-TRAFFIC = dict(sources_sha256="ac4398b9fe9527cef0145f2124114bebe25ba3738a75e69cee5c8ddc31faf07a",
-               bytes_per_launch={"surrogate4096": 365161758 / 7, "fig7": 162524699 / 3})
+# surrogate4096: the eight k_wrap_scan launches of one assisted scan, 226.4 MB
+# read + 180.1 MB written, 50.8 MB per launch; fig7: the three launches of
+# the balanced scan, 81.3 MB read + 81.2 MB written, 54.2 MB per launch.
+TRAFFIC = dict(sources_sha256="a0a398ce521ad1cbb5af85f3f6c8a6f8a0e6b93ce527798f7dad9423e4a89349",
+               bytes_per_launch={"surrogate4096": 406514885 / 8, "fig7": 162541823 / 3})
 
 
 # Table 3 of the paper: wall time of its GPU and CPU scans (seconds).
@@ -69,10 +69,10 @@ PAPER_TABLE3 = {"fig6_th1_1.571": (75.0, 1020.0), "fig7": (2213.0, 25000.0)}
 # rocprofv3 counters (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 x 64 lanes, FMA
 # counted twice, over the launch's orbit-steps), valid only for the kernel
 # sources whose hash is recorded with them.
-HW_FLOPS = dict(sources_sha256="ac4398b9fe9527cef0145f2124114bebe25ba3738a75e69cee5c8ddc31faf07a",
-                per_orbit_step={("k_wrap_scan", "surrogate4096"): 4934.2, ("k_wrap_scan", "grid314"): 4912.6,
-                                ("k_wrap_scan", "fig7"): 4962.0, ("k_batch_scan", "batch1M"): 4944.9,
-                                ("k_fli_scan", "grid64"): 4910.0})
+HW_FLOPS = dict(sources_sha256="a0a398ce521ad1cbb5af85f3f6c8a6f8a0e6b93ce527798f7dad9423e4a89349",
+                per_orbit_step={("k_wrap_scan", "surrogate4096"): 4575.8, ("k_wrap_scan", "grid314"): 4552.4,
+                                ("k_wrap_scan", "fig7"): 4598.3, ("k_batch_scan", "batch1M"): 4582.4,
+                                ("k_fli_scan", "grid64"): 4550.4})
 
 
 def hardware_flops(kernel, workload):
