@@ -322,8 +322,16 @@ __global__ __launch_bounds__(256) void k_gather_rows(const float* feat, const in
 // accumulation over K-slices, the bias/ReLU epilogues and the bfloat16
 // rounding between layers are those of k_gemm_bf16, so the result equals the
 // layer-by-layer path bit for bit.
-constexpr int FT = 64;              // rows per tile
 constexpr int FLD = 256 + 8;        // LDS row stride of an activation buffer (elements)
+// Rows per tile: 64 for inference (a persistent grid walks many tiles per
+// workgroup); a training batch of a few thousand rows is a few dozen such
+// tiles, so the training pass takes tiles of kTrainFT rows and spreads one
+// step over more workgroups.  A row's products do not depend on the tile
+// height, so the outputs are the same bits either way.
+#ifndef PN_TRAIN_FT
+#define PN_TRAIN_FT 16
+#endif
+constexpr int kInferFT = 64, kTrainFT = PN_TRAIN_FT;
 
 __device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t* p) {
     return *reinterpret_cast<const bf16x8*>(p);
@@ -356,6 +364,7 @@ __device__ __forceinline__ float swap_adjacent(float v) {
 
 // Copy the valid rows of an LDS activation tile to global memory, 16 bytes
 // per access.
+template <int FT>
 __device__ __forceinline__ void copy_tile(const uint16_t (*h)[FLD], uint16_t* dst, int64_t r0, int64_t n, int tid) {
 #pragma unroll
     for (int e = tid; e < FT * 32; e += 512) {
@@ -364,7 +373,7 @@ __device__ __forceinline__ void copy_tile(const uint16_t (*h)[FLD], uint16_t* ds
     }
 }
 
-template <bool IO>
+template <bool IO, int FT>
 __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ w0, const uint16_t* __restrict__ w1,
                                                    const uint16_t* __restrict__ w2, const uint16_t* __restrict__ w3,
                                                    const float* __restrict__ b0, const float* __restrict__ b1,
@@ -377,6 +386,8 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lq = lane >> 4, lk = lq * 8;
     const int c0 = 32 * wave;                         // first output column of this wavefront
+    constexpr int RB = FT / 16;                       // 16-row blocks per tile
+    static_assert(FT % 16 == 0 && RB >= 1 && RB <= 8, "tile height");
 
     // Register-resident B fragments of layers 2 and 3: column c0 + 16 j + lr,
     // K values 32 s + lk .. + 8 (weights are [out][in], K contiguous).
@@ -428,10 +439,10 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
     // Feature rows of a tile for the lanes of K-group 0 (16-byte loads; the
     // next tile's rows are requested before this tile's layers 2-4 run, so
     // their latency hides behind the matrix work).
-    float4 fcur[4][2], fnext[4][2];
-    auto load_feat = [&](int64_t t, float4 (&dst)[4][2]) {
+    float4 fcur[RB][2], fnext[RB][2];
+    auto load_feat = [&](int64_t t, float4 (&dst)[RB][2]) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < RB; ++i) {
             const int64_t row = t * FT + 16 * i + lr;
             if (lq == 0 && t < ntiles && row < n) {
                 const int64_t src = (IO && io.idx) ? (int64_t)io.idx[row] : row;
@@ -446,11 +457,11 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
     load_feat(blockIdx.x, fcur);
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t r0 = tile * FT;
-        f32x4 acc[4][2];
+        f32x4 acc[RB][2];
         // Layer 1: A fragment of row block i from the features (7 values, the
         // eighth is the zero padding of the feature row).
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < RB; ++i) {
             uint16_t v[8];
             v[0] = f2bf(fcur[i][0].x); v[1] = f2bf(fcur[i][0].y); v[2] = f2bf(fcur[i][0].z);
             v[3] = f2bf(fcur[i][0].w); v[4] = f2bf(fcur[i][1].x); v[5] = f2bf(fcur[i][1].y);
@@ -465,7 +476,7 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
         // Epilogue: bias, ReLU, bfloat16 into an LDS buffer.
         auto store = [&](uint16_t (*h)[FLD], int layer) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < RB; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
                     if (TR) {
@@ -484,20 +495,20 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
         store(hA, 0);
         if (!IO) load_feat(tile + gridDim.x, fnext);   // training batches give each workgroup about one tile
         __syncthreads();
-        if (IO && io.h_out[0]) copy_tile(hA, io.h_out[0], r0, n, tid);
+        if (IO && io.h_out[0]) copy_tile<FT>(hA, io.h_out[0], r0, n, tid);
         // Layers 2 and 3: A fragments from LDS, B fragments from registers.
 #pragma unroll
         for (int layer = 1; layer < 3; ++layer) {
             uint16_t (*hin)[FLD] = layer == 1 ? hA : hB;
             uint16_t (*hout)[FLD] = layer == 1 ? hB : hA;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < RB; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int sl = 0; sl < 8; ++sl) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
+                for (int i = 0; i < RB; ++i) {
                     const bf16x8 a = load_bf16x8(&hin[16 * i + lr][32 * sl + lk]);
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
@@ -506,10 +517,10 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
             }
             store(hout, layer);
             __syncthreads();
-            if (IO && io.h_out[layer]) copy_tile(hout, io.h_out[layer], r0, n, tid);
+            if (IO && io.h_out[layer]) copy_tile<FT>(hout, io.h_out[layer], r0, n, tid);
         }
-        // Layer 4 on wavefronts 0-3 (row block = wavefront), outputs 0 and 1.
-        if (wave < 4) {
+        // Layer 4 on wavefronts 0 .. RB - 1 (row block = wavefront), outputs 0 and 1.
+        if (wave < RB) {
             f32x4 o = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int sl = 0; sl < 8; ++sl) {
@@ -579,7 +590,7 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                 b[j] = *reinterpret_cast<const bf16x8*>(v);
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < RB; ++i) {
                 uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                 if (lq == 0) { v[0] = g4s[16 * i + lr][0]; v[1] = g4s[16 * i + lr][1]; }
                 const bf16x8 a = *reinterpret_cast<const bf16x8*>(v);
@@ -601,7 +612,7 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
             load_feat(tile + gridDim.x, fcur);
         } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < RB; ++i) {
                 fcur[i][0] = fnext[i][0];
                 fcur[i][1] = fnext[i][1];
             }
@@ -859,15 +870,16 @@ bool net_ok(const pn_mlp* net, bool training) {
 // One fused pass over n rows on a persistent grid of at most one workgroup per CU.
 void launch_fused(hipStream_t s, const pn_mlp* net, const float* feat, int64_t n, float* out, const FusedIO& io,
                   int ncu) {
-    const int64_t ntiles = (n + FT - 1) / FT;
-    const unsigned grid = (unsigned)(ntiles < ncu ? ntiles : ncu);
     const bool with_io = io.idx || io.x_out || io.h_out[0] || io.h_out[1] || io.h_out[2];
+    const int ft = with_io ? kTrainFT : kInferFT;
+    const int64_t ntiles = (n + ft - 1) / ft;
+    const unsigned grid = (unsigned)(ntiles < ncu ? ntiles : ncu);
     if (with_io)
-        hipLaunchKernelGGL(k_mlp_fused<true>, dim3(grid), dim3(512), 0, s, net->wb[0], net->wb[1], net->wb[2],
-                           net->wb[3], net->b[0], net->b[1], net->b[2], net->b[3], feat, n, out, io);
+        hipLaunchKernelGGL((k_mlp_fused<true, kTrainFT>), dim3(grid), dim3(512), 0, s, net->wb[0], net->wb[1],
+                           net->wb[2], net->wb[3], net->b[0], net->b[1], net->b[2], net->b[3], feat, n, out, io);
     else
-        hipLaunchKernelGGL(k_mlp_fused<false>, dim3(grid), dim3(512), 0, s, net->wb[0], net->wb[1], net->wb[2],
-                           net->wb[3], net->b[0], net->b[1], net->b[2], net->b[3], feat, n, out, io);
+        hipLaunchKernelGGL((k_mlp_fused<false, kInferFT>), dim3(grid), dim3(512), 0, s, net->wb[0], net->wb[1],
+                           net->wb[2], net->wb[3], net->b[0], net->b[1], net->b[2], net->b[3], feat, n, out, io);
 }
 
 int device_cu_count() {
