@@ -344,7 +344,11 @@ __device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t* p) {
 // with respect to the two outputs written to gout [n][2] (bfloat16), and
 // (g3_out non-null, with gout) the gradient of the last hidden layer's
 // pre-activation, (gout W4) * (h3 > 0), written to g3_out [n][256]
-// (bfloat16).
+// (bfloat16), and (g2_out, g1_out non-null, with g3_out) the two earlier
+// layer gradients g2 = (g3 W3) * (h2 > 0) and g1 = (g2 W2) * (h1 > 0),
+// written to g2_out and g1_out [n][256] (bfloat16).  The backward products
+// take their B operands from wT[1] = W3^T and wT[0] = W2^T ([in][out]
+// bfloat16 copies, so that a fragment's K values are contiguous).
 struct FusedIO {
     const int32_t* idx;
     uint16_t* x_out;
@@ -354,6 +358,9 @@ struct FusedIO {
     uint16_t* gout;
     float* loss;
     uint16_t* g3_out;
+    uint16_t* g2_out;
+    uint16_t* g1_out;
+    const uint16_t* wT[2];
 };
 
 // Exchange with the adjacent lane (lanes 2j and 2j + 1), DPP quad permutation
@@ -382,7 +389,13 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                                                    FusedIO io) {
     __shared__ __attribute__((aligned(16))) uint16_t hA[FT][FLD];
     __shared__ __attribute__((aligned(16))) uint16_t hB[FT][FLD];
+    // Training keeps h1 in a third buffer for the backward pass's ReLU mask:
+    // layer 1 writes hC, layer 2 reads it, and g3, g2 later overwrite hA (h3)
+    // and hB (h2) in place, element by element, each by the lane that reads
+    // that element's mask.
+    __shared__ __attribute__((aligned(16))) uint16_t hC[IO ? FT : 1][IO ? FLD : 8];
     __shared__ uint16_t g4s[IO ? FT : 1][2];          // the tile's output gradient (training)
+    uint16_t (*const h1buf)[FLD] = IO ? reinterpret_cast<uint16_t (*)[FLD]>(&hC[0][0]) : hA;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lq = lane >> 4, lk = lq * 8;
     const int c0 = 32 * wave;                         // first output column of this wavefront
@@ -391,15 +404,21 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
 
     // Register-resident B fragments of layers 2 and 3: column c0 + 16 j + lr,
     // K values 32 s + lk .. + 8 (weights are [out][in], K contiguous).
+    // Training reloads them for every tile (a training batch gives each
+    // workgroup about one tile), which frees their registers for the
+    // backward products' fragments.
     bf16x8 wf[2][2][8];
+    auto load_wf = [&]() {
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int sl = 0; sl < 8; ++sl) {
-            const int col = c0 + 16 * j + lr;
-            wf[0][j][sl] = load_bf16x8(w1 + (int64_t)col * 256 + 32 * sl + lk);
-            wf[1][j][sl] = load_bf16x8(w2 + (int64_t)col * 256 + 32 * sl + lk);
-        }
+            for (int sl = 0; sl < 8; ++sl) {
+                const int col = c0 + 16 * j + lr;
+                wf[0][j][sl] = load_bf16x8(w1 + (int64_t)col * 256 + 32 * sl + lk);
+                wf[1][j][sl] = load_bf16x8(w2 + (int64_t)col * 256 + 32 * sl + lk);
+            }
+    };
+    if (!IO) load_wf();
     // Layer 1 fragments (K = 7; only the lanes of K-group 0 carry values).
     bf16x8 wf0[2];
 #pragma unroll
@@ -457,6 +476,7 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
     load_feat(blockIdx.x, fcur);
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t r0 = tile * FT;
+        if (IO) load_wf();
         f32x4 acc[RB][2];
         // Layer 1: A fragment of row block i from the features (7 values, the
         // eighth is the zero padding of the feature row).
@@ -492,14 +512,14 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                     }
                 }
         };
-        store(hA, 0);
+        store(h1buf, 0);
         if (!IO) load_feat(tile + gridDim.x, fnext);   // training batches give each workgroup about one tile
         __syncthreads();
-        if (IO && io.h_out[0]) copy_tile<FT>(hA, io.h_out[0], r0, n, tid);
+        if (IO && io.h_out[0]) copy_tile<FT>(h1buf, io.h_out[0], r0, n, tid);
         // Layers 2 and 3: A fragments from LDS, B fragments from registers.
 #pragma unroll
         for (int layer = 1; layer < 3; ++layer) {
-            uint16_t (*hin)[FLD] = layer == 1 ? hA : hB;
+            uint16_t (*hin)[FLD] = layer == 1 ? h1buf : hB;
             uint16_t (*hout)[FLD] = layer == 1 ? hB : hA;
 #pragma unroll
             for (int i = 0; i < RB; ++i)
@@ -602,11 +622,59 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                     for (int v2 = 0; v2 < 4; ++v2) {
                         const int rl = 16 * i + 4 * lq + v2, col = c0 + 16 * j + lr;
                         const float x = bf2f(hA[rl][col]) > 0.0f ? g[v2] : 0.0f;
-                        if (r0 + rl < n) io.g3_out[(r0 + rl) * 256 + col] = f2bf(x);
+                        const uint16_t y = f2bf(x);
+                        if (io.g2_out) hA[rl][col] = y;          // g3 replaces h3 for the next product
+                        if (r0 + rl < n) io.g3_out[(r0 + rl) * 256 + col] = y;
                     }
                 }
             }
             __syncthreads();
+            if (io.g2_out) {
+                // g2 = (g3 W3) * (h2 > 0) from g3 (hA) and the mask h2 (hB),
+                // then g1 = (g2 W2) * (h1 > 0) from g2 (now in hB) and h1
+                // (hC): the products k_gemm_bf16 forms, with the K slices in
+                // the same order, so the same bits.
+#pragma unroll
+                for (int phase = 0; phase < 2; ++phase) {
+                    uint16_t (*ain)[FLD] = phase == 0 ? hA : hB;
+                    uint16_t (*mask)[FLD] = phase == 0 ? hB : h1buf;
+                    const uint16_t* wt = io.wT[1 - phase];
+                    bf16x8 wbk[2][8];
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+#pragma unroll
+                        for (int sl = 0; sl < 8; ++sl)
+                            wbk[j][sl] = load_bf16x8(wt + (int64_t)(c0 + 16 * j + lr) * 256 + 32 * sl + lk);
+#pragma unroll
+                    for (int i = 0; i < RB; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int sl = 0; sl < 8; ++sl) {
+#pragma unroll
+                        for (int i = 0; i < RB; ++i) {
+                            const bf16x8 a = load_bf16x8(&ain[16 * i + lr][32 * sl + lk]);
+#pragma unroll
+                            for (int j = 0; j < 2; ++j)
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wbk[j][sl], acc[i][j], 0, 0, 0);
+                        }
+                    }
+                    uint16_t* gdst = phase == 0 ? io.g2_out : io.g1_out;
+#pragma unroll
+                    for (int i = 0; i < RB; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+#pragma unroll
+                            for (int v2 = 0; v2 < 4; ++v2) {
+                                const int rl = 16 * i + 4 * lq + v2, col = c0 + 16 * j + lr;
+                                const float x = bf2f(mask[rl][col]) > 0.0f ? acc[i][j][v2] : 0.0f;
+                                const uint16_t y = f2bf(x);
+                                if (phase == 0) hB[rl][col] = y;
+                                if (r0 + rl < n) gdst[(r0 + rl) * 256 + col] = y;
+                            }
+                    __syncthreads();
+                }
+            }
         }
         if (IO) {
             load_feat(tile + gridDim.x, fcur);
@@ -630,6 +698,7 @@ struct AdamArgs {
     float* m[8];
     float* v[8];
     uint16_t* wb[8];    // bfloat16 copy (null for biases)
+    uint16_t* wbT[8];   // transposed bfloat16 copy [in][out] (null where not kept)
     int64_t off[9];
     float lr, c1, c2;   // c1 = 1 - b1^t, c2 = 1 - b2^t
 };
@@ -658,6 +727,17 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
     const float w = a.w[t][e] - a.lr * (m / a.c1) / (sqrtf(v / a.c2) + 1e-8f);
     a.w[t][e] = w;
     if (a.wb[t]) a.wb[t][e] = f2bf(w);
+    if (a.wbT[t]) a.wbT[t][(e & 255) * 256 + (e >> 8)] = f2bf(w);   // 256 x 256 tensors only
+}
+
+// wT[t][i][o] = bfloat16 W[o][i] for the two 256 x 256 hidden weights.
+__global__ __launch_bounds__(256) void k_transpose_hidden(const uint16_t* w1, const uint16_t* w2, uint16_t* t1,
+                                                          uint16_t* t2) {
+    const int e = blockIdx.x * 256 + threadIdx.x;     // grid 512 x 256 threads
+    const uint16_t* src = e < 65536 ? w1 : w2;
+    uint16_t* dst = e < 65536 ? t1 : t2;
+    const int f = e & 65535;
+    dst[(f & 255) * 256 + (f >> 8)] = src[f];
 }
 
 __global__ __launch_bounds__(256) void k_to_bf16(const float* x, int64_t n, uint16_t* y) {
@@ -914,7 +994,7 @@ size_t pn_mlp_train_workspace_size(int32_t batch) {
     const size_t B = (size_t)batch;
     return al(B * kFeatLd * 2) + 3 * al(B * 256 * 2) + al(B * 2 * 4) + al(B * 2 * 2) + 3 * al(B * 256 * 2) +
            al(256 * 256 * 4) * 2 + al(256 * 7 * 4) + al(2 * 256 * 4) + 4 * al(256 * 4) +
-           4 * al((size_t)kSplitFloats * 4);
+           4 * al((size_t)kSplitFloats * 4) + 2 * al(256 * 256 * 2);
 }
 
 pn_status pn_mlp_train_workspace_layout(int32_t batch, size_t* off) {
@@ -939,9 +1019,17 @@ pn_status pn_mlp_sync_bf16(pn_mlp* net, hipStream_t stream) {
     return launched("pn_mlp_sync_bf16");
 }
 
-pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, const float* target,
-                            const int32_t* idx, int32_t batch, int32_t step, float lr, float* loss,
-                            void* ws, size_t ws_bytes, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// One training step (pn_mlp_train_step).  The workspace also holds bfloat16
+// copies of W2^T and W3^T for the backward products of the fused pass; each
+// Adam update rewrites them with the bfloat16 weights, so a run of steps on
+// one workspace forms them once (fresh_transposes) before its first step.
+pn_status train_step(pn_mlp* net, const float* feat, const float* label, const float* target, const int32_t* idx,
+                     int32_t batch, int32_t step, float lr, float* loss, void* ws, size_t ws_bytes,
+                     hipStream_t stream, bool fresh_transposes) {
     if (!net_ok(net, true) || !feat || !label || !target || !idx || !loss) return PN_EINVAL;
     if ((reinterpret_cast<uintptr_t>(feat) & 15u) != 0) return PN_EINVAL;
     if (batch <= 0 || step < 1 || !(lr > 0.0f) || !std::isfinite(lr)) return PN_EINVAL;
@@ -975,20 +1063,21 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
     for (int l = 0; l < 4; ++l) db[l] = (float*)take(256 * 4);
     float* part[4];
     for (int l = 0; l < 4; ++l) part[l] = (float*)take((size_t)kSplitFloats * 4);
+    uint16_t* wT[2];
+    for (int t = 0; t < 2; ++t) wT[t] = (uint16_t*)take(256 * 256 * 2);
     hipStream_t s = stream;
 
-    // Forward: one fused pass over the batch rows idx[], keeping the inputs
-    // and hidden activations for the backward pass.
-    // Forward with the loss, its output gradient g4 and the last hidden
-    // layer's gradient g3 = (g4 W4) * (h3 > 0).
-    launch_fused(s, net, feat, B, out, FusedIO{idx, X, {h[0], h[1], h[2]}, label, target, g4, loss, g3}, ncu);
+    if (fresh_transposes)
+        hipLaunchKernelGGL(k_transpose_hidden, dim3(512), dim3(256), 0, s, net->wb[1], net->wb[2], wT[0], wT[1]);
+    // Forward over the batch rows idx[], keeping the inputs and hidden
+    // activations, with the loss, its output gradient g4 and the layer
+    // gradients g3 = (g4 W4) * (h3 > 0), g2 = (g3 W3) * (h2 > 0) and
+    // g1 = (g2 W2) * (h1 > 0), all in one fused pass.
+    FusedIO io{idx, X, {h[0], h[1], h[2]}, label, target, g4, loss, g3, g2, g1, {wT[0], wT[1]}};
+    launch_fused(s, net, feat, B, out, io, ncu);
     // Backward.  Weight gradients dW_l = g_l^T h_(l-1) go to per-layer
-    // split-K partials that the Adam launch sums; the layer gradients
-    // g_(l-1) = (g_l W_l) * (h_(l-1) > 0) stay live for the launch that forms
-    // the weight gradients and all bias gradients.
-    gemm(s, B, 256, 256, g3, 256, 1, net->wb[2], 256, 1, nullptr, 0, h[1], 256, nullptr, 0, g2, 256);
-    gemm(s, B, 256, 256, g2, 256, 1, net->wb[1], 256, 1, nullptr, 0, h[0], 256, nullptr, 0, g1, 256);
-    // The four weight gradients in one launch.
+    // split-K partials that the Adam launch sums.
+    // The four weight gradients and all bias gradients in one launch.
     const GemmPlan pw[4] = {
         plan_gemm(256, 7, B, g1, 1, 256, X, kFeatLd, 1, nullptr, 0, nullptr, 0, dW[0], 7, nullptr, 0, part[0]),
         plan_gemm(256, 256, B, g2, 1, 256, h[0], 256, 1, nullptr, 0, nullptr, 0, dW[1], 256, nullptr, 0, part[1]),
@@ -1024,14 +1113,26 @@ pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, 
     for (int l = 0; l < 4; ++l) {
         const int tw = 2 * l, tb = 2 * l + 1;
         a.w[tw] = net->w[l]; a.g[tw] = dW[l]; a.m[tw] = net->mw[l]; a.v[tw] = net->vw[l]; a.wb[tw] = net->wb[l];
+        a.wbT[tw] = (l == 1 || l == 2) ? wT[l - 1] : nullptr;
         a.part[tw] = part[l]; a.splits[tw] = splits[l];
         a.off[tw + 1] = a.off[tw] + (int64_t)kIn[l] * kOut[l];
         a.w[tb] = net->b[l]; a.g[tb] = db[l]; a.m[tb] = net->mb[l]; a.v[tb] = net->vb[l]; a.wb[tb] = nullptr;
+        a.wbT[tb] = nullptr;
         a.part[tb] = nullptr; a.splits[tb] = 1;
         a.off[tb + 1] = a.off[tb] + kOut[l];
     }
     hipLaunchKernelGGL(k_adam, dim3(blocks_for(a.off[8], 256)), dim3(256), 0, s, a);
     return launched("pn_mlp_train_step");
+}
+
+}  // namespace
+
+extern "C" {
+
+pn_status pn_mlp_train_step(pn_mlp* net, const float* feat, const float* label, const float* target,
+                            const int32_t* idx, int32_t batch, int32_t step, float lr, float* loss,
+                            void* ws, size_t ws_bytes, hipStream_t stream) {
+    return train_step(net, feat, label, target, idx, batch, step, lr, loss, ws, ws_bytes, stream, true);
 }
 
 pn_status pn_mlp_train(pn_mlp* net, int32_t* adam_step, const float* feat, const float* label, const float* target,
@@ -1041,8 +1142,8 @@ pn_status pn_mlp_train(pn_mlp* net, int32_t* adam_step, const float* feat, const
     if (nbatch > 0 && !order) return PN_EINVAL;
     if ((int64_t)*adam_step + nbatch > 0x7fffffffLL) return PN_EINVAL;
     for (int64_t b = 0; b < nbatch; ++b) {
-        const pn_status st = pn_mlp_train_step(net, feat, label, target, order + b * batch, batch, *adam_step + 1,
-                                               lr, loss, ws, ws_bytes, stream);
+        const pn_status st = train_step(net, feat, label, target, order + b * batch, batch, *adam_step + 1, lr,
+                                        loss, ws, ws_bytes, stream, b == 0);
         if (st != PN_OK) return st;
         *adam_step += 1;
     }
@@ -1422,15 +1523,18 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
             PN_HIP(hipMemcpyAsync(order, orders.data(), orders.size() * 4, hipMemcpyHostToDevice, stream), what);
             for (int32_t k = 0; k < ne; ++k) {
                 const int32_t e = e0 + k;
+                // The transposed weight copies are formed before the first
+                // refinement step; each step's Adam update keeps them current.
                 const float lr_e = cfg->refine_cosine
                                        ? cfg->refine_lr * 0.5f *
                                              (1.0f + cosf(3.14159265358979f * e / cfg->refine_epochs))
                                        : cfg->refine_lr;
                 for (int64_t b = 0; b < nb; ++b) {
                     *adam_step += 1;
-                    PN_TRY(pn_mlp_train_step(net, featA, labA, tgtA, order + (size_t)k * nv + b * cfg->refine_batch,
-                                             cfg->refine_batch, *adam_step, lr_e, loss, tws,
-                                             pn_mlp_train_workspace_size(cfg->refine_batch), stream));
+                    PN_TRY(train_step(net, featA, labA, tgtA, order + (size_t)k * nv + b * cfg->refine_batch,
+                                      cfg->refine_batch, *adam_step, lr_e, loss, tws,
+                                      pn_mlp_train_workspace_size(cfg->refine_batch), stream,
+                                      e == 0 && b == 0));
                 }
             }
             PN_HIP(hipStreamSynchronize(stream), what);    // the host buffer is refilled next
