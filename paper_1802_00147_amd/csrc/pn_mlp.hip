@@ -42,6 +42,23 @@ __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(ui
 
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
+// ReLU applied after the rounding to bfloat16: a value with its sign bit set
+// (negative, or -0) becomes +0, any other stays.  For finite values this is
+// the rounding of max(x, 0); on a packed pair it is one signed 16-bit max
+// against zero (v_pk_max_i16).
+typedef short short2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint16_t relu_bf16(uint16_t b) { return (b & 0x8000u) ? (uint16_t)0 : b; }
+// Two FP32 values to a packed bfloat16 pair (a low), each rounded as f2bf.
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){a, b}, bf16x2v));
+}
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t p) {
+    const short2v v = __builtin_bit_cast(short2v, p);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(v, short2v{0, 0}));
+}
+
 struct GemmArgs {
     int M, N, K;
     const uint16_t* A;
@@ -161,11 +178,16 @@ __device__ __forceinline__ void gemm_block(const GemmArgs& g, int bx, int by, in
     const int64_t m0 = (int64_t)by * BM, n0 = (int64_t)bx * BN;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int lr = lane & 15, lk = (lane >> 4) * 8;
+    // The bias (never with split K) is the accumulators' starting value: the
+    // MFMAs add the K slices to it.
     f32x4 acc[2][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+        const int64_t n = n0 + wn + 16 * j + lr;
+        const float b0 = (g.bias && bz == 0 && n < g.N) ? g.bias[n] : 0.0f;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < 2; ++i) acc[i][j] = f32x4{b0, b0, b0, b0};
+    }
     // Split K: layer z of the grid sums K range [kb, ke) into its own partial.
     const int64_t kb = (int64_t)bz * g.kchunk;
     const int64_t ke = (kb + g.kchunk < g.K) ? kb + g.kchunk : g.K;
@@ -203,12 +225,13 @@ __device__ __forceinline__ void gemm_block(const GemmArgs& g, int bx, int by, in
                 const int64_t m = m0 + wm + 16 * i + (lane >> 4) * 4 + v;
                 const int64_t n = n0 + wn + 16 * j + lr;
                 if (m >= g.M || n >= g.N) continue;
-                float x = acc[i][j][v];
-                if (g.bias) x += g.bias[n];
-                if (g.relu) x = fmaxf(x, 0.0f);
-                if (g.mask && !(bf2f(g.mask[m * g.ldm + n]) > 0.0f)) x = 0.0f;
-                if (Cf) Cf[m * g.ldcf + n] = x;
-                if (g.Cb) g.Cb[m * g.ldcb + n] = f2bf(x);
+                const float x = acc[i][j][v];
+                const bool keep = !g.mask || bf2f(g.mask[m * g.ldm + n]) > 0.0f;
+                if (Cf) Cf[m * g.ldcf + n] = keep ? (g.relu ? fmaxf(x, 0.0f) : x) : 0.0f;
+                if (g.Cb) {
+                    const uint16_t y = g.relu ? relu_bf16(f2bf(x)) : f2bf(x);
+                    g.Cb[m * g.ldcb + n] = keep ? y : (uint16_t)0;
+                }
             }
 }
 
@@ -389,13 +412,14 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                                                    FusedIO io) {
     __shared__ __attribute__((aligned(16))) uint16_t hA[FT][FLD];
     __shared__ __attribute__((aligned(16))) uint16_t hB[FT][FLD];
-    // Training keeps h1 in a third buffer for the backward pass's ReLU mask:
-    // layer 1 writes hC, layer 2 reads it, and g3, g2 later overwrite hA (h3)
-    // and hB (h2) in place, element by element, each by the lane that reads
-    // that element's mask.
-    __shared__ __attribute__((aligned(16))) uint16_t hC[IO ? FT : 1][IO ? FLD : 8];
+    // h1 in hC, h2 in hB, h3 in hA: with three buffers a tile's layer 1 may
+    // start while wavefronts of the previous tile still read h3 in layer 4
+    // (inference), and training keeps h1 for the backward pass's ReLU mask --
+    // g3 and g2 later overwrite hA (h3) and hB (h2) in place, element by
+    // element, each by the lane that reads that element's mask.
+    __shared__ __attribute__((aligned(16))) uint16_t hC[FT][FLD];
     __shared__ uint16_t g4s[IO ? FT : 1][2];          // the tile's output gradient (training)
-    uint16_t (*const h1buf)[FLD] = IO ? reinterpret_cast<uint16_t (*)[FLD]>(&hC[0][0]) : hA;
+    uint16_t (*const h1buf)[FLD] = hC;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lq = lane >> 4, lk = lq * 8;
     const int c0 = 32 * wave;                         // first output column of this wavefront
@@ -452,25 +476,29 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
         return TR ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, a, c, 0, 0, 0)
                   : __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w, c, 0, 0, 0);
     };
+    // The bias is the accumulators' starting value, as in k_gemm_bf16.
+    auto bias_init = [&](int layer, int j) {
+        return TR ? f32x4{bias[layer][j][0], bias[layer][j][1], bias[layer][j][2], bias[layer][j][3]}
+                  : f32x4{bias[layer][j][0], bias[layer][j][0], bias[layer][j][0], bias[layer][j][0]};
+    };
     const float bias3 = lr < 2 ? b3[lr] : 0.0f;
 
     const int64_t ntiles = (n + FT - 1) / FT;
-    // Feature rows of a tile for the lanes of K-group 0 (16-byte loads; the
-    // next tile's rows are requested before this tile's layers 2-4 run, so
-    // their latency hides behind the matrix work).
+    // Feature rows of a tile (16-byte loads; the next tile's rows are
+    // requested before this tile's layers 2-4 run, so their latency hides
+    // behind the matrix work).  Every lane loads its row: the lanes of
+    // K-groups 1-3 meet zero weights in layer 1, so their copies add exact
+    // zeros (the features are finite); rows past n repeat row n - 1 and
+    // their results are never stored.
     float4 fcur[RB][2], fnext[RB][2];
     auto load_feat = [&](int64_t t, float4 (&dst)[RB][2]) {
 #pragma unroll
         for (int i = 0; i < RB; ++i) {
-            const int64_t row = t * FT + 16 * i + lr;
-            if (lq == 0 && t < ntiles && row < n) {
-                const int64_t src = (IO && io.idx) ? (int64_t)io.idx[row] : row;
-                dst[i][0] = *reinterpret_cast<const float4*>(feat + src * kFeatLd);
-                dst[i][1] = *reinterpret_cast<const float4*>(feat + src * kFeatLd + 4);
-            } else {
-                dst[i][0] = make_float4(0.f, 0.f, 0.f, 0.f);
-                dst[i][1] = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
+            int64_t row = t * FT + 16 * i + lr;
+            row = row < n ? row : n - 1;
+            const int64_t src = (IO && io.idx) ? (int64_t)io.idx[row] : row;
+            dst[i][0] = *reinterpret_cast<const float4*>(feat + src * kFeatLd);
+            dst[i][1] = *reinterpret_cast<const float4*>(feat + src * kFeatLd + 4);
         }
     };
     load_feat(blockIdx.x, fcur);
@@ -491,28 +519,27 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                 *reinterpret_cast<bf16x8*>(io.x_out + (r0 + 16 * i + lr) * kFeatLd) = a;
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                acc[i][j] = mfma(a, wf0[j], f32x4{0.f, 0.f, 0.f, 0.f});
+                acc[i][j] = mfma(a, wf0[j], bias_init(0, j));
         }
-        // Epilogue: bias, ReLU, bfloat16 into an LDS buffer.
-        auto store = [&](uint16_t (*h)[FLD], int layer) {
+        // Epilogue: bfloat16, ReLU, into an LDS buffer.
+        auto store = [&](uint16_t (*h)[FLD]) {
 #pragma unroll
             for (int i = 0; i < RB; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
                     if (TR) {
-                        union { uint2 v; uint16_t e[4]; } u;
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) u.e[v] = f2bf(fmaxf(acc[i][j][v] + bias[layer][j][v], 0.0f));
-                        *reinterpret_cast<uint2*>(&h[16 * i + lr][c0 + 16 * j + 4 * lq]) = u.v;
+                        uint2 u;
+                        u.x = relu_bf16x2(pack_bf16x2(acc[i][j][0], acc[i][j][1]));
+                        u.y = relu_bf16x2(pack_bf16x2(acc[i][j][2], acc[i][j][3]));
+                        *reinterpret_cast<uint2*>(&h[16 * i + lr][c0 + 16 * j + 4 * lq]) = u;
                     } else {
 #pragma unroll
                         for (int v = 0; v < 4; ++v)
-                            h[16 * i + 4 * lq + v][c0 + 16 * j + lr] =
-                                f2bf(fmaxf(acc[i][j][v] + bias[layer][j][0], 0.0f));
+                            h[16 * i + 4 * lq + v][c0 + 16 * j + lr] = relu_bf16(f2bf(acc[i][j][v]));
                     }
                 }
         };
-        store(h1buf, 0);
+        store(h1buf);
         if (!IO) load_feat(tile + gridDim.x, fnext);   // training batches give each workgroup about one tile
         __syncthreads();
         if (IO && io.h_out[0]) copy_tile<FT>(h1buf, io.h_out[0], r0, n, tid);
@@ -524,7 +551,7 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
 #pragma unroll
             for (int i = 0; i < RB; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int j = 0; j < 2; ++j) acc[i][j] = bias_init(layer, j);
 #pragma unroll
             for (int sl = 0; sl < 8; ++sl) {
 #pragma unroll
@@ -535,30 +562,28 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                         acc[i][j] = mfma(a, wf[layer - 1][j][sl], acc[i][j]);
                 }
             }
-            store(hout, layer);
+            store(hout);
             __syncthreads();
             if (IO && io.h_out[layer]) copy_tile<FT>(hout, io.h_out[layer], r0, n, tid);
         }
-        // Layer 4 on wavefronts 0 .. RB - 1 (row block = wavefront), outputs 0 and 1.
+        // Layer 4 on wavefronts 0 .. RB - 1 (row block = wavefront), outputs 0
+        // and 1 in columns 0 and 1 of the 16-column block.  Output column c
+        // depends only on the B operand of lanes with lane % 16 = c, so the
+        // other lanes may hold any weights (a copy of row lane % 2) and their
+        // columns are never stored.
         if (wave < RB) {
-            f32x4 o = f32x4{0.f, 0.f, 0.f, 0.f};
+            f32x4 o = f32x4{bias3, bias3, bias3, bias3};
 #pragma unroll
             for (int sl = 0; sl < 8; ++sl) {
                 const bf16x8 a = load_bf16x8(&hA[16 * wave + lr][32 * sl + lk]);
-                bf16x8 b;
-                if (lr < 2) {
-                    b = load_bf16x8(w3 + (int64_t)lr * 256 + 32 * sl + lk);
-                } else {
-                    uint16_t z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-                    b = *reinterpret_cast<const bf16x8*>(z);
-                }
+                const bf16x8 b = load_bf16x8(w3 + (int64_t)(lr & 1) * 256 + 32 * sl + lk);
                 o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, o, 0, 0, 0);
             }
             if (lr < 2) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int64_t row = r0 + 16 * wave + 4 * lq + v;
-                    if (row < n) out[row * 2 + lr] = o[v] + bias3;
+                    if (row < n) out[row * 2 + lr] = o[v];
                 }
             }
             if (IO && io.gout) {
@@ -569,7 +594,7 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                 float lsum = 0.0f;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const float mine = o[v] + bias3;
+                    const float mine = o[v];
                     const float other = swap_adjacent(mine);
                     const int64_t row = r0 + 16 * wave + 4 * lq + v;
                     if (lr == 0 && row < n) {
@@ -596,7 +621,11 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                 if (lane == 0) atomicAdd(io.loss, lsum / (float)n);
             }
         }
-        __syncthreads();   // hA is rewritten by the next tile's layer 1
+        // Inference: the next tile's layer 1 writes hC, which every wavefront
+        // finished reading (layer 2) before the barrier after layer 2, and
+        // its layer 3 rewrites hA only after two more barriers, so layer 4's
+        // reads of hA need no barrier of their own.  Training reads g4s next.
+        if (IO) __syncthreads();
         if (IO && io.gout && io.g3_out) {
             // g3 = (g4 W4) * (h3 > 0) for this wavefront's 32 columns, as
             // the product with K = 2 (padded to one 32-deep slice) and the
@@ -951,6 +980,7 @@ bool net_ok(const pn_mlp* net, bool training) {
 void launch_fused(hipStream_t s, const pn_mlp* net, const float* feat, int64_t n, float* out, const FusedIO& io,
                   int ncu) {
     const bool with_io = io.idx || io.x_out || io.h_out[0] || io.h_out[1] || io.h_out[2];
+    if (n <= 0) return;
     const int ft = with_io ? kTrainFT : kInferFT;
     const int64_t ntiles = (n + ft - 1) / ft;
     const unsigned grid = (unsigned)(ntiles < ncu ? ntiles : ncu);
