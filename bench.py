@@ -529,7 +529,7 @@ def surrogate_bench(args, dev):
     if kname == "k_wrap_scan":
         line["roofline"]["resources"] = pn.balanced_kernel_resources()
     line["inference_roofline"] = dict(bound="mfma", achieved=inf_achieved, peak=2500.0, unit="TFLOP/s",
-                                      frac=inf_achieved / 2500.0, traffic=None, kernel="k_mlp_fused",
+                                      frac=inf_achieved / 2500.0, traffic=None, kernel="k_mlp_infer",
                                       kernel_ms=inf["fused_ms"], layered_ms=inf["layered_ms"],
                                       flops_per_point=inf_flops / grid.n)
     plain_tf = ALG_FLOPS_PER_ORBIT_STEP * plain_steps / (plain_ms * 1e-3) / 1e12

@@ -566,8 +566,9 @@ pn_status pn_mlp_infer(const pn_mlp* net, const float* feat, int64_t n, float* o
                        void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* The same outputs as pn_mlp_infer, bit for bit, from one persistent kernel
- * that runs all four layers on 64-row tiles with the activations in LDS and
- * the layer-2/3 weights in registers (a12: fused inference).  No workspace;
+ * that runs all four layers on 32-row tiles with the activations in LDS and
+ * the hidden-layer weights in registers, layers 1-2 and layers 3-4 on two
+ * halves of each workgroup as a two-stage pipeline.  No workspace;
  * feat [n][8] (16-byte aligned, else PN_EINVAL), out [n][2] device arrays
  * owned by the caller. */
 pn_status pn_mlp_infer_fused(const pn_mlp* net, const float* feat, int64_t n, float* out,
@@ -644,7 +645,7 @@ typedef struct {
  * range or refine_batch <= 0). */
 size_t pn_surrogate_scan_workspace_size(int64_t n, int32_t refine_batch);
 
-/* The surrogate-assisted scan (a12) of n points, end to end on the stream:
+/* The surrogate-assisted scan of n points, end to end on the stream:
  *  1. features of every point (pn_mlp_features with mean/stdv);
  *  2. the audit sample (SplitMix64(seed + i) / 2^64 < audit_frac), sorted by
  *     point index, integrated: with t_end NULL (every point ends at

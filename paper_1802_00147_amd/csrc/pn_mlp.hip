@@ -1,16 +1,19 @@
 // pn_mlp.hip -- learned surrogate of the FLI scan: a 7-256-256-256-2 ReLU
 // multilayer perceptron trained and evaluated on gfx950 matrix cores.
 //
-// Training products run in one hand-written kernel, k_gemm_bf16: bfloat16
+// General products run in one hand-written kernel, k_gemm_bf16: bfloat16
 // operands, FP32 accumulation on v_mfma_f32_16x16x32_bf16, 64x64 output tiles
 // per 256-thread workgroup (each wavefront a 32x32 quarter as 2x2 MFMA
 // tiles), operands staged through LDS with K contiguous so that a lane reads
-// its eight K values with one 16-byte LDS load, and fused epilogues (bias,
-// ReLU, ReLU-mask of the backward pass, FP32 and/or bfloat16 stores).
-// Arbitrary strides let the same kernel form X W^T, G W and G^T H.
-// Inference over scan grids runs all four layers in one persistent kernel,
-// k_mlp_fused, with the same arithmetic.  The surrogate-assisted scan
-// (pn_surrogate_scan) strings these together with the FP64 batch scan.
+// its eight K values with one 16-byte LDS load, and fused epilogues (bias as
+// the accumulators' start, ReLU, ReLU-mask of the backward pass, FP32 and/or
+// bfloat16 stores).  Arbitrary strides let the same kernel form X W^T, G W
+// and G^T H; k_gemm_group runs a training step's four weight gradients in one
+// launch.  A training step's forward pass, loss and layer gradients run in
+// one kernel, k_mlp_train, and inference over scan grids in one persistent
+// kernel, k_mlp_infer, both with the same arithmetic as k_gemm_bf16.  The
+// surrogate-assisted scan (pn_surrogate_scan) strings these together with
+// the FP64 scans.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -333,46 +336,22 @@ __global__ __launch_bounds__(256) void k_gather_rows(const float* feat, const in
     X[e] = c < 7 ? f2bf(feat[r * kFeatLd + c]) : (uint16_t)0;
 }
 
-// Fused inference: all four layers of 64-row tiles in one persistent kernel.
-// A 512-thread workgroup (8 wavefronts, two per SIMD) keeps the bfloat16
-// fragments of W2 and W3 in registers for its whole life -- wavefront w owns
-// output columns 32w .. 32w+31 of both layers, 2 column blocks x 8 K-slices
-// of 16x16x32 MFMA B operands -- and walks row tiles; activations stay in LDS
-// (two 64 x 256 buffers, rows padded by 16 bytes), never in HBM.  Per tile:
-// layer 1 (K = 7 padded to one 32-deep slice, A straight from the features),
-// layers 2-3 from LDS, layer 4 (2 outputs padded to a 16-column block) on
-// wavefronts 0-3, one row block each.  The products, their order of
-// accumulation over K-slices, the bias/ReLU epilogues and the bfloat16
-// rounding between layers are those of k_gemm_bf16, so the result equals the
-// layer-by-layer path bit for bit.
 constexpr int FLD = 256 + 8;        // LDS row stride of an activation buffer (elements)
-// Rows per tile: 64 for inference (a persistent grid walks many tiles per
-// workgroup); a training batch of a few thousand rows is a few dozen such
-// tiles, so the training pass takes tiles of kTrainFT rows and spreads one
-// step over more workgroups.  A row's products do not depend on the tile
-// height, so the outputs are the same bits either way.
-#ifndef PN_TRAIN_FT
-#define PN_TRAIN_FT 16
-#endif
-constexpr int kInferFT = 64, kTrainFT = PN_TRAIN_FT;
 
 __device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t* p) {
     return *reinterpret_cast<const bf16x8*>(p);
 }
 
-// Optional extras of the fused pass, used by training: rows idx[r] of the
-// features instead of row r, the bfloat16 inputs and hidden activations
-// written out ([n][8] and [n][256], 16-byte aligned) for the backward pass,
-// (gout non-null) the loss of the batch added to *loss and its gradient
-// with respect to the two outputs written to gout [n][2] (bfloat16), and
-// (g3_out non-null, with gout) the gradient of the last hidden layer's
-// pre-activation, (gout W4) * (h3 > 0), written to g3_out [n][256]
-// (bfloat16), and (g2_out, g1_out non-null, with g3_out) the two earlier
-// layer gradients g2 = (g3 W3) * (h2 > 0) and g1 = (g2 W2) * (h1 > 0),
-// written to g2_out and g1_out [n][256] (bfloat16).  The backward products
-// take their B operands from wT[1] = W3^T and wT[0] = W2^T ([in][out]
-// bfloat16 copies, so that a fragment's K values are contiguous).
-struct FusedIO {
+// What the training pass reads and leaves behind: rows idx[r] of the
+// features; the gathered bfloat16 inputs x_out [n][8] and hidden activations
+// h_out[l] [n][256] (16-byte aligned) for the weight gradients; the batch's
+// mean loss added to *loss and its gradient with respect to the two outputs
+// in gout [n][2]; the layer gradients g3 = (g4 W4) * (h3 > 0),
+// g2 = (g3 W3) * (h2 > 0) and g1 = (g2 W2) * (h1 > 0) in g3_out, g2_out,
+// g1_out [n][256] (all bfloat16).  The backward products take their B
+// operands from wT[1] = W3^T and wT[0] = W2^T ([in][out] bfloat16 copies, so
+// that a fragment's K values are contiguous).
+struct TrainIO {
     const int32_t* idx;
     uint16_t* x_out;
     uint16_t* h_out[3];
@@ -403,46 +382,39 @@ __device__ __forceinline__ void copy_tile(const uint16_t (*h)[FLD], uint16_t* ds
     }
 }
 
-template <bool IO, int FT>
-__global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ w0, const uint16_t* __restrict__ w1,
+// Training pass of one step over the batch rows, in tiles of FT rows (a
+// batch of a few thousand rows spreads over a hundred or more workgroups):
+// the forward pass through all four layers with the activations in LDS
+// (h1 in hC, h2 in hB, h3 in hA) and copied out, the loss and its output
+// gradient g4 in the last layer's epilogue, then the three layer gradients,
+// each a row-local product: g3 and g2 overwrite h3 (hA) and h2 (hB) in place,
+// element by element, each by the lane that reads that element's ReLU mask.
+// Wavefront w owns output columns 32w .. 32w+31 (2 column blocks of 16);
+// results are in the MFMA's own layout (element v of lane l is row
+// 4 (l / 16) + v, column l % 16).  Products, K-slice order, bias-started
+// accumulators and epilogues are those of k_gemm_bf16.
+#ifndef PN_TRAIN_FT
+#define PN_TRAIN_FT 16
+#endif
+constexpr int kTrainFT = PN_TRAIN_FT;
+
+template <int FT>
+__global__ __launch_bounds__(512) void k_mlp_train(const uint16_t* __restrict__ w0, const uint16_t* __restrict__ w1,
                                                    const uint16_t* __restrict__ w2, const uint16_t* __restrict__ w3,
                                                    const float* __restrict__ b0, const float* __restrict__ b1,
                                                    const float* __restrict__ b2, const float* __restrict__ b3,
                                                    const float* __restrict__ feat, int64_t n, float* __restrict__ out,
-                                                   FusedIO io) {
+                                                   TrainIO io) {
     __shared__ __attribute__((aligned(16))) uint16_t hA[FT][FLD];
     __shared__ __attribute__((aligned(16))) uint16_t hB[FT][FLD];
-    // h1 in hC, h2 in hB, h3 in hA: with three buffers a tile's layer 1 may
-    // start while wavefronts of the previous tile still read h3 in layer 4
-    // (inference), and training keeps h1 for the backward pass's ReLU mask --
-    // g3 and g2 later overwrite hA (h3) and hB (h2) in place, element by
-    // element, each by the lane that reads that element's mask.
     __shared__ __attribute__((aligned(16))) uint16_t hC[FT][FLD];
-    __shared__ uint16_t g4s[IO ? FT : 1][2];          // the tile's output gradient (training)
-    uint16_t (*const h1buf)[FLD] = hC;
+    __shared__ uint16_t g4s[FT][2];                   // the tile's output gradient
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lq = lane >> 4, lk = lq * 8;
     const int c0 = 32 * wave;                         // first output column of this wavefront
     constexpr int RB = FT / 16;                       // 16-row blocks per tile
     static_assert(FT % 16 == 0 && RB >= 1 && RB <= 8, "tile height");
 
-    // Register-resident B fragments of layers 2 and 3: column c0 + 16 j + lr,
-    // K values 32 s + lk .. + 8 (weights are [out][in], K contiguous).
-    // Training reloads them for every tile (a training batch gives each
-    // workgroup about one tile), which frees their registers for the
-    // backward products' fragments.
-    bf16x8 wf[2][2][8];
-    auto load_wf = [&]() {
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int sl = 0; sl < 8; ++sl) {
-                const int col = c0 + 16 * j + lr;
-                wf[0][j][sl] = load_bf16x8(w1 + (int64_t)col * 256 + 32 * sl + lk);
-                wf[1][j][sl] = load_bf16x8(w2 + (int64_t)col * 256 + 32 * sl + lk);
-            }
-    };
-    if (!IO) load_wf();
     // Layer 1 fragments (K = 7; only the lanes of K-group 0 carry values).
     bf16x8 wf0[2];
 #pragma unroll
@@ -453,100 +425,72 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
         for (int t = 0; t < 8; ++t) v[t] = (lq == 0 && t < 7) ? w0[col * 7 + t] : (uint16_t)0;
         wf0[j] = *reinterpret_cast<const bf16x8*>(v);
     }
-    // Inference (TR) runs the products of layers 1-3 with the weights as the
-    // first MFMA operand, which yields the transposed 16 x 16 block: element
-    // v of lane l is row l % 16, column 4 (l / 16) + v, so a lane holds four
-    // consecutive outputs of one row and stores them with one 8-byte LDS
-    // write.  The training pass (IO), which has no registers to spare for the
-    // extra biases, keeps the MFMA's own layout (element v of lane l is row
-    // 4 (l / 16) + v, column l % 16) and 2-byte writes.  Each output is the
-    // same dot product either way.
-    constexpr bool TR = !IO;
-    float bias[3][2][4];
+    // Biases of this lane's column c0 + 16 j + lr, the accumulators' start.
+    float bias[3][2];
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int v = 0; v < (TR ? 4 : 1); ++v) {
-            const int col = TR ? c0 + 16 * j + 4 * lq + v : c0 + 16 * j + lr;
-            bias[0][j][v] = b0[col];
-            bias[1][j][v] = b1[col];
-            bias[2][j][v] = b2[col];
-        }
-    auto mfma = [](const bf16x8& a, const bf16x8& w, const f32x4& c) {
-        return TR ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, a, c, 0, 0, 0)
-                  : __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w, c, 0, 0, 0);
-    };
-    // The bias is the accumulators' starting value, as in k_gemm_bf16.
-    auto bias_init = [&](int layer, int j) {
-        return TR ? f32x4{bias[layer][j][0], bias[layer][j][1], bias[layer][j][2], bias[layer][j][3]}
-                  : f32x4{bias[layer][j][0], bias[layer][j][0], bias[layer][j][0], bias[layer][j][0]};
-    };
+    for (int j = 0; j < 2; ++j) {
+        const int col = c0 + 16 * j + lr;
+        bias[0][j] = b0[col];
+        bias[1][j] = b1[col];
+        bias[2][j] = b2[col];
+    }
     const float bias3 = lr < 2 ? b3[lr] : 0.0f;
+    auto bias_init = [&](int layer, int j) {
+        return f32x4{bias[layer][j], bias[layer][j], bias[layer][j], bias[layer][j]};
+    };
 
     const int64_t ntiles = (n + FT - 1) / FT;
-    // Feature rows of a tile (16-byte loads; the next tile's rows are
-    // requested before this tile's layers 2-4 run, so their latency hides
-    // behind the matrix work).  Every lane loads its row: the lanes of
-    // K-groups 1-3 meet zero weights in layer 1, so their copies add exact
-    // zeros (the features are finite); rows past n repeat row n - 1 and
-    // their results are never stored.
-    float4 fcur[RB][2], fnext[RB][2];
-    auto load_feat = [&](int64_t t, float4 (&dst)[RB][2]) {
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-            int64_t row = t * FT + 16 * i + lr;
-            row = row < n ? row : n - 1;
-            const int64_t src = (IO && io.idx) ? (int64_t)io.idx[row] : row;
-            dst[i][0] = *reinterpret_cast<const float4*>(feat + src * kFeatLd);
-            dst[i][1] = *reinterpret_cast<const float4*>(feat + src * kFeatLd + 4);
-        }
-    };
-    load_feat(blockIdx.x, fcur);
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t r0 = tile * FT;
-        if (IO) load_wf();
+        // B fragments of layers 2 and 3 (column c0 + 16 j + lr, K values
+        // 32 s + lk .. + 8), loaded per tile: a batch gives each workgroup
+        // about one tile, and the registers serve the backward fragments later.
+        bf16x8 wf[2][2][8];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int sl = 0; sl < 8; ++sl) {
+                const int col = c0 + 16 * j + lr;
+                wf[0][j][sl] = load_bf16x8(w1 + (int64_t)col * 256 + 32 * sl + lk);
+                wf[1][j][sl] = load_bf16x8(w2 + (int64_t)col * 256 + 32 * sl + lk);
+            }
         f32x4 acc[RB][2];
-        // Layer 1: A fragment of row block i from the features (7 values, the
-        // eighth is the zero padding of the feature row).
+        // Layer 1: A fragment of row block i from the gathered features (7
+        // values and a zero).  Rows past n repeat row n - 1 (never stored);
+        // the lanes of K-groups 1-3 meet zero weights.
 #pragma unroll
         for (int i = 0; i < RB; ++i) {
+            int64_t row = r0 + 16 * i + lr;
+            row = row < n ? row : n - 1;
+            const float* fr = feat + (int64_t)io.idx[row] * kFeatLd;
+            const float4 f0 = *reinterpret_cast<const float4*>(fr);
+            const float4 f1 = *reinterpret_cast<const float4*>(fr + 4);
             uint16_t v[8];
-            v[0] = f2bf(fcur[i][0].x); v[1] = f2bf(fcur[i][0].y); v[2] = f2bf(fcur[i][0].z);
-            v[3] = f2bf(fcur[i][0].w); v[4] = f2bf(fcur[i][1].x); v[5] = f2bf(fcur[i][1].y);
-            v[6] = f2bf(fcur[i][1].z); v[7] = 0;
+            v[0] = f2bf(f0.x); v[1] = f2bf(f0.y); v[2] = f2bf(f0.z); v[3] = f2bf(f0.w);
+            v[4] = f2bf(f1.x); v[5] = f2bf(f1.y); v[6] = f2bf(f1.z); v[7] = 0;
             const bf16x8 a = *reinterpret_cast<const bf16x8*>(v);
-            if (IO && io.x_out && lq == 0 && r0 + 16 * i + lr < n)
-                *reinterpret_cast<bf16x8*>(io.x_out + (r0 + 16 * i + lr) * kFeatLd) = a;
+            if (lq == 0 && r0 + 16 * i + lr < n) *reinterpret_cast<bf16x8*>(io.x_out + (r0 + 16 * i + lr) * kFeatLd) = a;
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                acc[i][j] = mfma(a, wf0[j], bias_init(0, j));
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wf0[j], bias_init(0, j), 0, 0, 0);
         }
         // Epilogue: bfloat16, ReLU, into an LDS buffer.
         auto store = [&](uint16_t (*h)[FLD]) {
 #pragma unroll
             for (int i = 0; i < RB; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    if (TR) {
-                        uint2 u;
-                        u.x = relu_bf16x2(pack_bf16x2(acc[i][j][0], acc[i][j][1]));
-                        u.y = relu_bf16x2(pack_bf16x2(acc[i][j][2], acc[i][j][3]));
-                        *reinterpret_cast<uint2*>(&h[16 * i + lr][c0 + 16 * j + 4 * lq]) = u;
-                    } else {
+                for (int j = 0; j < 2; ++j)
 #pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            h[16 * i + 4 * lq + v][c0 + 16 * j + lr] = relu_bf16(f2bf(acc[i][j][v]));
-                    }
-                }
+                    for (int v = 0; v < 4; ++v)
+                        h[16 * i + 4 * lq + v][c0 + 16 * j + lr] = relu_bf16(f2bf(acc[i][j][v]));
         };
-        store(h1buf);
-        if (!IO) load_feat(tile + gridDim.x, fnext);   // training batches give each workgroup about one tile
+        store(hC);
         __syncthreads();
-        if (IO && io.h_out[0]) copy_tile<FT>(h1buf, io.h_out[0], r0, n, tid);
+        copy_tile<FT>(hC, io.h_out[0], r0, n, tid);
         // Layers 2 and 3: A fragments from LDS, B fragments from registers.
 #pragma unroll
         for (int layer = 1; layer < 3; ++layer) {
-            uint16_t (*hin)[FLD] = layer == 1 ? h1buf : hB;
+            uint16_t (*hin)[FLD] = layer == 1 ? hC : hB;
             uint16_t (*hout)[FLD] = layer == 1 ? hB : hA;
 #pragma unroll
             for (int i = 0; i < RB; ++i)
@@ -559,17 +503,17 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                     const bf16x8 a = load_bf16x8(&hin[16 * i + lr][32 * sl + lk]);
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
-                        acc[i][j] = mfma(a, wf[layer - 1][j][sl], acc[i][j]);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wf[layer - 1][j][sl], acc[i][j], 0, 0, 0);
                 }
             }
             store(hout);
             __syncthreads();
-            if (IO && io.h_out[layer]) copy_tile<FT>(hout, io.h_out[layer], r0, n, tid);
+            copy_tile<FT>(hout, io.h_out[layer], r0, n, tid);
         }
         // Layer 4 on wavefronts 0 .. RB - 1 (row block = wavefront), outputs 0
         // and 1 in columns 0 and 1 of the 16-column block.  Output column c
         // depends only on the B operand of lanes with lane % 16 = c, so the
-        // other lanes may hold any weights (a copy of row lane % 2) and their
+        // other lanes may hold any weights (a copy of row lane % 2); their
         // columns are never stored.
         if (wave < RB) {
             f32x4 o = f32x4{bias3, bias3, bias3, bias3};
@@ -579,57 +523,45 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                 const bf16x8 b = load_bf16x8(w3 + (int64_t)(lr & 1) * 256 + 32 * sl + lk);
                 o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, o, 0, 0, 0);
             }
-            if (lr < 2) {
+            // Loss of the batch: binary cross-entropy of the logit plus Huber
+            // (delta 1) of the FLI output, averaged over the n rows, and its
+            // gradient.  Lanes lr = 0 and 1 hold the two outputs of rows
+            // 4 lq + v and exchange them.
+            float lsum = 0.0f;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int64_t row = r0 + 16 * wave + 4 * lq + v;
-                    if (row < n) out[row * 2 + lr] = o[v];
+            for (int v = 0; v < 4; ++v) {
+                const float mine = o[v];
+                const float other = swap_adjacent(mine);
+                const int64_t row = r0 + 16 * wave + 4 * lq + v;
+                if (lr < 2 && row < n) out[row * 2 + lr] = mine;
+                if (lr == 0 && row < n) {
+                    const int32_t r = io.idx[row];
+                    const float z = mine, f = other, y = io.label[r], t = io.target[r];
+                    float l = fmaxf(z, 0.0f) - y * z + log1pf(expf(-fabsf(z)));
+                    const float d = f - t;
+                    l += fabsf(d) <= 1.0f ? 0.5f * d * d : fabsf(d) - 0.5f;
+                    const float sig = 1.0f / (1.0f + expf(-z));
+                    const uint16_t g0 = f2bf((sig - y) / (float)n);
+                    const uint16_t g1 = f2bf(fminf(fmaxf(d, -1.0f), 1.0f) / (float)n);
+                    io.gout[2 * row] = g0;
+                    io.gout[2 * row + 1] = g1;
+                    g4s[16 * wave + 4 * lq + v][0] = g0;
+                    g4s[16 * wave + 4 * lq + v][1] = g1;
+                    lsum += l;
+                } else if (lr == 0) {
+                    g4s[16 * wave + 4 * lq + v][0] = 0;
+                    g4s[16 * wave + 4 * lq + v][1] = 0;
                 }
             }
-            if (IO && io.gout) {
-                // Loss of the batch: binary cross-entropy of the logit plus
-                // Huber (delta 1) of the FLI output, averaged over the n rows,
-                // and its gradient.  Lanes lr = 0 and 1 hold the two outputs of
-                // rows 4 lq + v and exchange them.
-                float lsum = 0.0f;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const float mine = o[v];
-                    const float other = swap_adjacent(mine);
-                    const int64_t row = r0 + 16 * wave + 4 * lq + v;
-                    if (lr == 0 && row < n) {
-                        const int32_t r = io.idx[row];
-                        const float z = mine, f = other, y = io.label[r], t = io.target[r];
-                        float l = fmaxf(z, 0.0f) - y * z + log1pf(expf(-fabsf(z)));
-                        const float d = f - t;
-                        l += fabsf(d) <= 1.0f ? 0.5f * d * d : fabsf(d) - 0.5f;
-                        const float sig = 1.0f / (1.0f + expf(-z));
-                        const uint16_t g0 = f2bf((sig - y) / (float)n);
-                        const uint16_t g1 = f2bf(fminf(fmaxf(d, -1.0f), 1.0f) / (float)n);
-                        io.gout[2 * row] = g0;
-                        io.gout[2 * row + 1] = g1;
-                        g4s[16 * wave + 4 * lq + v][0] = g0;
-                        g4s[16 * wave + 4 * lq + v][1] = g1;
-                        lsum += l;
-                    } else if (lr == 0) {
-                        g4s[16 * wave + 4 * lq + v][0] = 0;
-                        g4s[16 * wave + 4 * lq + v][1] = 0;
-                    }
-                }
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
-                if (lane == 0) atomicAdd(io.loss, lsum / (float)n);
-            }
+            for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
+            if (lane == 0) atomicAdd(io.loss, lsum / (float)n);
         }
-        // Inference: the next tile's layer 1 writes hC, which every wavefront
-        // finished reading (layer 2) before the barrier after layer 2, and
-        // its layer 3 rewrites hA only after two more barriers, so layer 4's
-        // reads of hA need no barrier of their own.  Training reads g4s next.
-        if (IO) __syncthreads();
-        if (IO && io.gout && io.g3_out) {
-            // g3 = (g4 W4) * (h3 > 0) for this wavefront's 32 columns, as
-            // the product with K = 2 (padded to one 32-deep slice) and the
-            // ReLU mask of h3 (still in hA) that k_gemm_bf16 would form.
+        __syncthreads();
+        // g3 = (g4 W4) * (h3 > 0) for this wavefront's 32 columns, as the
+        // product with K = 2 (padded to one 32-deep slice) and the ReLU mask
+        // of h3 (still in hA) that k_gemm_bf16 would form; g3 replaces h3.
+        {
             bf16x8 b[2];
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
@@ -652,68 +584,221 @@ __global__ __launch_bounds__(512) void k_mlp_fused(const uint16_t* __restrict__ 
                         const int rl = 16 * i + 4 * lq + v2, col = c0 + 16 * j + lr;
                         const float x = bf2f(hA[rl][col]) > 0.0f ? g[v2] : 0.0f;
                         const uint16_t y = f2bf(x);
-                        if (io.g2_out) hA[rl][col] = y;          // g3 replaces h3 for the next product
+                        hA[rl][col] = y;
                         if (r0 + rl < n) io.g3_out[(r0 + rl) * 256 + col] = y;
                     }
                 }
             }
-            __syncthreads();
-            if (io.g2_out) {
-                // g2 = (g3 W3) * (h2 > 0) from g3 (hA) and the mask h2 (hB),
-                // then g1 = (g2 W2) * (h1 > 0) from g2 (now in hB) and h1
-                // (hC): the products k_gemm_bf16 forms, with the K slices in
-                // the same order, so the same bits.
+        }
+        __syncthreads();
+        // g2 = (g3 W3) * (h2 > 0) from g3 (hA) and the mask h2 (hB), then
+        // g1 = (g2 W2) * (h1 > 0) from g2 (now in hB) and h1 (hC): the
+        // products k_gemm_bf16 forms, with the K slices in the same order.
 #pragma unroll
-                for (int phase = 0; phase < 2; ++phase) {
-                    uint16_t (*ain)[FLD] = phase == 0 ? hA : hB;
-                    uint16_t (*mask)[FLD] = phase == 0 ? hB : h1buf;
-                    const uint16_t* wt = io.wT[1 - phase];
-                    bf16x8 wbk[2][8];
+        for (int phase = 0; phase < 2; ++phase) {
+            uint16_t (*ain)[FLD] = phase == 0 ? hA : hB;
+            uint16_t (*mask)[FLD] = phase == 0 ? hB : hC;
+            const uint16_t* wt = io.wT[1 - phase];
+            bf16x8 wbk[2][8];
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int sl = 0; sl < 8; ++sl)
+                    wbk[j][sl] = load_bf16x8(wt + (int64_t)(c0 + 16 * j + lr) * 256 + 32 * sl + lk);
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int sl = 0; sl < 8; ++sl) {
+#pragma unroll
+                for (int i = 0; i < RB; ++i) {
+                    const bf16x8 a = load_bf16x8(&ain[16 * i + lr][32 * sl + lk]);
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wbk[j][sl], acc[i][j], 0, 0, 0);
+                }
+            }
+            uint16_t* gdst = phase == 0 ? io.g2_out : io.g1_out;
 #pragma unroll
-                        for (int sl = 0; sl < 8; ++sl)
-                            wbk[j][sl] = load_bf16x8(wt + (int64_t)(c0 + 16 * j + lr) * 256 + 32 * sl + lk);
+            for (int i = 0; i < RB; ++i)
 #pragma unroll
-                    for (int i = 0; i < RB; ++i)
+                for (int j = 0; j < 2; ++j)
 #pragma unroll
-                        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int sl = 0; sl < 8; ++sl) {
-#pragma unroll
-                        for (int i = 0; i < RB; ++i) {
-                            const bf16x8 a = load_bf16x8(&ain[16 * i + lr][32 * sl + lk]);
-#pragma unroll
-                            for (int j = 0; j < 2; ++j)
-                                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wbk[j][sl], acc[i][j], 0, 0, 0);
-                        }
+                    for (int v2 = 0; v2 < 4; ++v2) {
+                        const int rl = 16 * i + 4 * lq + v2, col = c0 + 16 * j + lr;
+                        const float x = bf2f(mask[rl][col]) > 0.0f ? acc[i][j][v2] : 0.0f;
+                        const uint16_t y = f2bf(x);
+                        if (phase == 0) hB[rl][col] = y;
+                        if (r0 + rl < n) gdst[(r0 + rl) * 256 + col] = y;
                     }
-                    uint16_t* gdst = phase == 0 ? io.g2_out : io.g1_out;
+            __syncthreads();
+        }
+    }
+}
+
+// Inference as a two-stage pipeline over 32-row tiles, one barrier per
+// tile.  In step k wavefronts 0-3 (the front stage) run layer 2 of tile k
+// and then layer 1 of tile k + 1, while wavefronts 4-7 (the back stage) run
+// layer 3 of tile k - 1 and then layer 4 of tile k - 2.  Every activation
+// buffer is doubled (tile parity), so within a step no wavefront writes a
+// buffer another one reads, and a buffer written in step k is read in step
+// k + 1, after the barrier.  Each wavefront keeps the B fragments of ONE
+// hidden layer for 64 output columns (4 column blocks x 8 K-slices; the same
+// registers hold W2 in the front stage and W3 in the back), so every A
+// fragment read from LDS feeds four MFMAs, and both wavefronts of a SIMD
+// issue a hidden layer's MFMAs in the same step.  Biases and the two output
+// rows sit in LDS.  Products, K-slice order, bias-started accumulators and
+// the bfloat16 ReLU epilogue are those of k_gemm_bf16: the outputs equal the
+// layer-by-layer path bit for bit.
+constexpr int kInferFT = 32;
+
+__global__ __launch_bounds__(512) void k_mlp_infer(const uint16_t* __restrict__ w0, const uint16_t* __restrict__ w1,
+                                                  const uint16_t* __restrict__ w2, const uint16_t* __restrict__ w3,
+                                                  const float* __restrict__ b0, const float* __restrict__ b1,
+                                                  const float* __restrict__ b2, const float* __restrict__ b3,
+                                                  const float* __restrict__ feat, int64_t n, float* __restrict__ out) {
+    constexpr int FT = kInferFT, RB = FT / 16;
+    __shared__ __attribute__((aligned(16))) uint16_t h1[2][FT][FLD];
+    __shared__ __attribute__((aligned(16))) uint16_t h2[2][FT][FLD];
+    __shared__ __attribute__((aligned(16))) uint16_t h3[2][FT][FLD];
+    __shared__ __attribute__((aligned(16))) float bs[3][256];
+    __shared__ __attribute__((aligned(16))) uint16_t w4s[2][256];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lq = lane >> 4, lk = lq * 8;
+    const bool front = wave < 4;                      // uniform per wavefront
+    const int c0 = 64 * (wave & 3);                   // first output column of this wavefront's layer
+    if (tid < 256) {
+        bs[0][tid] = b0[tid];
+        bs[1][tid] = b1[tid];
+        bs[2][tid] = b2[tid];
+    }
+    w4s[tid >> 8][tid & 255] = w3[tid];               // 512 threads, 2 x 256 weights
+    // B fragments: column c0 + 16 j + lr, K values 32 s + lk .. + 8.
+    const uint16_t* wl = front ? w1 : w2;
+    bf16x8 wf[4][8];
 #pragma unroll
-                    for (int i = 0; i < RB; ++i)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
-                        for (int j = 0; j < 2; ++j)
+        for (int sl = 0; sl < 8; ++sl) wf[j][sl] = load_bf16x8(wl + (int64_t)(c0 + 16 * j + lr) * 256 + 32 * sl + lk);
+    // Layer 1 fragments (front; K = 7, only the lanes of K-group 0 carry values).
+    bf16x8 wf0[4];
 #pragma unroll
-                            for (int v2 = 0; v2 < 4; ++v2) {
-                                const int rl = 16 * i + 4 * lq + v2, col = c0 + 16 * j + lr;
-                                const float x = bf2f(mask[rl][col]) > 0.0f ? acc[i][j][v2] : 0.0f;
-                                const uint16_t y = f2bf(x);
-                                if (phase == 0) hB[rl][col] = y;
-                                if (r0 + rl < n) gdst[(r0 + rl) * 256 + col] = y;
-                            }
-                    __syncthreads();
+    for (int j = 0; j < 4; ++j) {
+        uint16_t v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            v[t] = (front && lq == 0 && t < 7) ? w0[(c0 + 16 * j + lr) * 7 + t] : (uint16_t)0;
+        wf0[j] = *reinterpret_cast<const bf16x8*>(v);
+    }
+    const float bias3 = lr < 2 ? b3[lr] : 0.0f;
+
+    const int64_t ntiles = (n + FT - 1) / FT;
+    const int64_t mine = blockIdx.x < ntiles ? (ntiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
+    auto tile_of = [&](int64_t k) { return (int64_t)blockIdx.x + k * gridDim.x; };
+    // Feature rows (front stage): rows past n repeat row n - 1 (never stored);
+    // the lanes of K-groups 1-3 meet zero weights.
+    float4 fnext[RB][2];
+    auto load_feat = [&](int64_t t) {
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            int64_t row = t * FT + 16 * i + lr;
+            row = row < n ? row : n - 1;
+            fnext[i][0] = *reinterpret_cast<const float4*>(feat + row * kFeatLd);
+            fnext[i][1] = *reinterpret_cast<const float4*>(feat + row * kFeatLd + 4);
+        }
+    };
+    // Epilogue of this wavefront's 64 columns (weights as the first MFMA
+    // operand: element v of lane l is tile row l % 16, column 4 (l / 16) + v
+    // of the 16-column block).
+    auto store = [&](uint16_t (*h)[FLD], f32x4 (&acc)[RB][4]) {
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                uint2 u;
+                u.x = relu_bf16x2(pack_bf16x2(acc[i][j][0], acc[i][j][1]));
+                u.y = relu_bf16x2(pack_bf16x2(acc[i][j][2], acc[i][j][3]));
+                *reinterpret_cast<uint2*>(&h[16 * i + lr][c0 + 16 * j + 4 * lq]) = u;
+            }
+    };
+    // Layer 1 of the tile whose features are in fnext, into h.
+    auto layer1 = [&](uint16_t (*h)[FLD]) {
+        f32x4 acc[RB][4];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            uint16_t v[8];
+            v[0] = f2bf(fnext[i][0].x); v[1] = f2bf(fnext[i][0].y); v[2] = f2bf(fnext[i][0].z);
+            v[3] = f2bf(fnext[i][0].w); v[4] = f2bf(fnext[i][1].x); v[5] = f2bf(fnext[i][1].y);
+            v[6] = f2bf(fnext[i][1].z); v[7] = 0;
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(v);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    wf0[j], a, *reinterpret_cast<const f32x4*>(&bs[0][c0 + 16 * j + 4 * lq]), 0, 0, 0);
+        }
+        store(h, acc);
+    };
+    // A hidden layer (1: W2, front; 2: W3, back), accumulators started at the bias.
+    auto hidden = [&](uint16_t (*hin)[FLD], uint16_t (*hout)[FLD], int layer) {
+        f32x4 acc[RB][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const f32x4 b = *reinterpret_cast<const f32x4*>(&bs[layer][c0 + 16 * j + 4 * lq]);
+#pragma unroll
+            for (int i = 0; i < RB; ++i) acc[i][j] = b;
+        }
+#pragma unroll
+        for (int sl = 0; sl < 8; ++sl)
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                const bf16x8 a = load_bf16x8(&hin[16 * i + lr][32 * sl + lk]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[j][sl], a, acc[i][j], 0, 0, 0);
+            }
+        store(hout, acc);
+    };
+    __syncthreads();                                  // biases and output rows in LDS
+    if (front && mine > 0) {
+        load_feat(tile_of(0));
+        layer1(h1[0]);
+        if (mine > 1) load_feat(tile_of(1));
+    }
+    __syncthreads();
+    for (int64_t k = 0; k <= mine + 1; ++k) {
+        const int p = (int)(k & 1);
+        if (front) {
+            if (k < mine) hidden(h1[p], h2[p], 1);
+            if (k + 1 < mine) {
+                layer1(h1[p ^ 1]);
+                if (k + 2 < mine) load_feat(tile_of(k + 2));
+            }
+        } else {
+            if (k >= 1 && k <= mine) hidden(h2[p ^ 1], h3[p ^ 1], 2);
+            // Layer 4, row block wave - 4 of tile k - 2 (parity p): outputs 0
+            // and 1 in columns 0 and 1; the other lanes' B operands (copies of
+            // row lane % 2) feed columns that are never stored.
+            if (k >= 2 && wave - 4 < RB) {
+                const int i = wave - 4;
+                const int64_t r0 = tile_of(k - 2) * FT;
+                f32x4 o = f32x4{bias3, bias3, bias3, bias3};
+#pragma unroll
+                for (int sl = 0; sl < 8; ++sl) {
+                    const bf16x8 a = load_bf16x8(&h3[p][16 * i + lr][32 * sl + lk]);
+                    const bf16x8 b = load_bf16x8(&w4s[lr & 1][32 * sl + lk]);
+                    o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, o, 0, 0, 0);
+                }
+                if (lr < 2) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int64_t row = r0 + 16 * i + 4 * lq + v;
+                        if (row < n) out[row * 2 + lr] = o[v];
+                    }
                 }
             }
         }
-        if (IO) {
-            load_feat(tile + gridDim.x, fcur);
-        } else {
-#pragma unroll
-            for (int i = 0; i < RB; ++i) {
-                fcur[i][0] = fnext[i][0];
-                fcur[i][1] = fnext[i][1];
-            }
-        }
+        __syncthreads();
     }
 }
 
@@ -976,20 +1061,23 @@ bool net_ok(const pn_mlp* net, bool training) {
     return true;
 }
 
-// One fused pass over n rows on a persistent grid of at most one workgroup per CU.
-void launch_fused(hipStream_t s, const pn_mlp* net, const float* feat, int64_t n, float* out, const FusedIO& io,
-                  int ncu) {
-    const bool with_io = io.idx || io.x_out || io.h_out[0] || io.h_out[1] || io.h_out[2];
+// Inference over n rows (persistent grid of at most one workgroup per CU).
+void launch_infer(hipStream_t s, const pn_mlp* net, const float* feat, int64_t n, float* out, int ncu) {
     if (n <= 0) return;
-    const int ft = with_io ? kTrainFT : kInferFT;
-    const int64_t ntiles = (n + ft - 1) / ft;
+    const int64_t ntiles = (n + kInferFT - 1) / kInferFT;
     const unsigned grid = (unsigned)(ntiles < ncu ? ntiles : ncu);
-    if (with_io)
-        hipLaunchKernelGGL((k_mlp_fused<true, kTrainFT>), dim3(grid), dim3(512), 0, s, net->wb[0], net->wb[1],
-                           net->wb[2], net->wb[3], net->b[0], net->b[1], net->b[2], net->b[3], feat, n, out, io);
-    else
-        hipLaunchKernelGGL((k_mlp_fused<false, kInferFT>), dim3(grid), dim3(512), 0, s, net->wb[0], net->wb[1],
-                           net->wb[2], net->wb[3], net->b[0], net->b[1], net->b[2], net->b[3], feat, n, out, io);
+    hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(512), 0, s, net->wb[0], net->wb[1], net->wb[2], net->wb[3],
+                       net->b[0], net->b[1], net->b[2], net->b[3], feat, n, out);
+}
+
+// The training pass over a batch of n rows.
+void launch_train(hipStream_t s, const pn_mlp* net, const float* feat, int64_t n, float* out, const TrainIO& io,
+                  int ncu) {
+    if (n <= 0) return;
+    const int64_t ntiles = (n + kTrainFT - 1) / kTrainFT;
+    const unsigned grid = (unsigned)(ntiles < ncu ? ntiles : ncu);
+    hipLaunchKernelGGL((k_mlp_train<kTrainFT>), dim3(grid), dim3(512), 0, s, net->wb[0], net->wb[1], net->wb[2],
+                       net->wb[3], net->b[0], net->b[1], net->b[2], net->b[3], feat, n, out, io);
 }
 
 int device_cu_count() {
@@ -1103,8 +1191,8 @@ pn_status train_step(pn_mlp* net, const float* feat, const float* label, const f
     // activations, with the loss, its output gradient g4 and the layer
     // gradients g3 = (g4 W4) * (h3 > 0), g2 = (g3 W3) * (h2 > 0) and
     // g1 = (g2 W2) * (h1 > 0), all in one fused pass.
-    FusedIO io{idx, X, {h[0], h[1], h[2]}, label, target, g4, loss, g3, g2, g1, {wT[0], wT[1]}};
-    launch_fused(s, net, feat, B, out, io, ncu);
+    TrainIO io{idx, X, {h[0], h[1], h[2]}, label, target, g4, loss, g3, g2, g1, {wT[0], wT[1]}};
+    launch_train(s, net, feat, B, out, io, ncu);
     // Backward.  Weight gradients dW_l = g_l^T h_(l-1) go to per-layer
     // split-K partials that the Adam launch sums.
     // The four weight gradients and all bias gradients in one launch.
@@ -1215,9 +1303,7 @@ pn_status pn_mlp_infer_fused(const pn_mlp* net, const float* feat, int64_t n, fl
         pn_detail::set_last_error("pn_mlp_infer_fused", "no device");
         return PN_EDEVICE;
     }
-    launch_fused(stream, net, feat, n, out,
-                 FusedIO{nullptr, nullptr, {nullptr, nullptr, nullptr}, nullptr, nullptr, nullptr, nullptr, nullptr},
-                 ncu);
+    launch_infer(stream, net, feat, n, out, ncu);
     return launched("pn_mlp_infer_fused");
 }
 
@@ -1428,7 +1514,7 @@ pn_status pn_surrogate_scan(pn_mlp* net, int32_t* adam_step, const pn_model* mod
     // into slab[0..m), completed steps summed into counts[2 + phase]: points
     // that all end at t_end_all through the balanced scan (which keeps the
     // plain fused scan where that is predicted faster), others with the
-    // persistent batch kernel (a10).
+    // persistent batch kernel.
     auto integrate = [&](const int32_t* list, int64_t m, int phase) -> pn_status {
         PN_TRY(pn_init_state_gather(model, params, m, list, r0, p0, th1, ph1, th2, ph2, y0, m, stream));
         const unsigned g = blocks_for(m, 256);
