@@ -108,12 +108,14 @@ def test_forward_matches_oracle(pn):
     assert err.max() <= 5e-3 * scale     # rare one-ulp bfloat16 flips of hidden activations
 
 
-@pytest.mark.parametrize("n", [1, 63, 64, 3000, 70001])
+@pytest.mark.parametrize("n", [1, 31, 32, 63, 64, 3000, 8193, 70001])
 def test_fused_inference_equals_layer_by_layer(pn, n):
     """The fused kernel runs the same products in the same order with the same
     epilogues as the per-layer path: bitwise equal outputs, ragged tails
-    included (70,001 rows also spread tiles over every workgroup several
-    times), and the oracle bound of the forward test."""
+    included, and the oracle bound of the forward test.  The sizes cover one
+    and two 32-row tiles (the pipeline's fill and drain with nothing between),
+    one workgroup with two tiles while the others have one (8,193 rows on 256
+    workgroups), and tiles spread over every workgroup several times."""
     rng = np.random.default_rng(80 + n)
     net, params = _network(pn)
     X = rng.normal(size=(n, 7))
