@@ -408,12 +408,16 @@ __global__ __launch_bounds__(512) void k_mlp_train(const uint16_t* __restrict__ 
     __shared__ __attribute__((aligned(16))) uint16_t hA[FT][FLD];
     __shared__ __attribute__((aligned(16))) uint16_t hB[FT][FLD];
     __shared__ __attribute__((aligned(16))) uint16_t hC[FT][FLD];
+    __shared__ __attribute__((aligned(16))) uint16_t w4s[2][256];   // the output layer's weights
     __shared__ uint16_t g4s[FT][2];                   // the tile's output gradient
+    __shared__ float labs[FT], tgts[FT];              // the tile's labels and targets
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lq = lane >> 4, lk = lq * 8;
     const int c0 = 32 * wave;                         // first output column of this wavefront
     constexpr int RB = FT / 16;                       // 16-row blocks per tile
     static_assert(FT % 16 == 0 && RB >= 1 && RB <= 8, "tile height");
+    static_assert(FT <= 512, "one thread per row loads the labels");
+    w4s[tid >> 8][tid & 255] = w3[tid];               // 512 threads, 2 x 256 weights; read after barriers
 
     // Layer 1 fragments (K = 7; only the lanes of K-group 0 carry values).
     bf16x8 wf0[2];
@@ -454,6 +458,14 @@ __global__ __launch_bounds__(512) void k_mlp_train(const uint16_t* __restrict__ 
                 wf[0][j][sl] = load_bf16x8(w1 + (int64_t)col * 256 + 32 * sl + lk);
                 wf[1][j][sl] = load_bf16x8(w2 + (int64_t)col * 256 + 32 * sl + lk);
             }
+        // The tile's labels and targets, requested with the features; they
+        // reach LDS before the barrier after layer 1.
+        float lab_t = 0.0f, tgt_t = 0.0f;
+        if (tid < FT && r0 + tid < n) {
+            const int32_t r = io.idx[r0 + tid];
+            lab_t = io.label[r];
+            tgt_t = io.target[r];
+        }
         f32x4 acc[RB][2];
         // Layer 1: A fragment of row block i from the gathered features (7
         // values and a zero).  Rows past n repeat row n - 1 (never stored);
@@ -485,6 +497,10 @@ __global__ __launch_bounds__(512) void k_mlp_train(const uint16_t* __restrict__ 
                         h[16 * i + 4 * lq + v][c0 + 16 * j + lr] = relu_bf16(f2bf(acc[i][j][v]));
         };
         store(hC);
+        if (tid < FT) {
+            labs[tid] = lab_t;
+            tgts[tid] = tgt_t;
+        }
         __syncthreads();
         copy_tile<FT>(hC, io.h_out[0], r0, n, tid);
         // Layers 2 and 3: A fragments from LDS, B fragments from registers.
@@ -520,7 +536,7 @@ __global__ __launch_bounds__(512) void k_mlp_train(const uint16_t* __restrict__ 
 #pragma unroll
             for (int sl = 0; sl < 8; ++sl) {
                 const bf16x8 a = load_bf16x8(&hA[16 * wave + lr][32 * sl + lk]);
-                const bf16x8 b = load_bf16x8(w3 + (int64_t)(lr & 1) * 256 + 32 * sl + lk);
+                const bf16x8 b = load_bf16x8(&w4s[lr & 1][32 * sl + lk]);
                 o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, o, 0, 0, 0);
             }
             // Loss of the batch: binary cross-entropy of the logit plus Huber
@@ -535,8 +551,8 @@ __global__ __launch_bounds__(512) void k_mlp_train(const uint16_t* __restrict__ 
                 const int64_t row = r0 + 16 * wave + 4 * lq + v;
                 if (lr < 2 && row < n) out[row * 2 + lr] = mine;
                 if (lr == 0 && row < n) {
-                    const int32_t r = io.idx[row];
-                    const float z = mine, f = other, y = io.label[r], t = io.target[r];
+                    const int rl = 16 * wave + 4 * lq + v;
+                    const float z = mine, f = other, y = labs[rl], t = tgts[rl];
                     float l = fmaxf(z, 0.0f) - y * z + log1pf(expf(-fabsf(z)));
                     const float d = f - t;
                     l += fabsf(d) <= 1.0f ? 0.5f * d * d : fabsf(d) - 0.5f;
@@ -567,7 +583,7 @@ __global__ __launch_bounds__(512) void k_mlp_train(const uint16_t* __restrict__ 
             for (int j = 0; j < 2; ++j) {
                 const int col = c0 + 16 * j + lr;
                 uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-                if (lq == 0) { v[0] = w3[col]; v[1] = w3[256 + col]; }
+                if (lq == 0) { v[0] = w4s[0][col]; v[1] = w4s[1][col]; }
                 b[j] = *reinterpret_cast<const bf16x8*>(v);
             }
 #pragma unroll
