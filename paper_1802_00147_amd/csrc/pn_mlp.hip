@@ -1158,7 +1158,7 @@ pn_status pn_mlp_sync_bf16(pn_mlp* net, hipStream_t stream) {
 namespace {
 
 // One training step (pn_mlp_train_step).  The workspace also holds bfloat16
-// copies of W2^T and W3^T for the backward products of the fused pass; each
+// copies of W2^T and W3^T for the backward products of the training pass; each
 // Adam update rewrites them with the bfloat16 weights, so a run of steps on
 // one workspace forms them once (fresh_transposes) before its first step.
 pn_status train_step(pn_mlp* net, const float* feat, const float* label, const float* target, const int32_t* idx,
@@ -1206,7 +1206,7 @@ pn_status train_step(pn_mlp* net, const float* feat, const float* label, const f
     // Forward over the batch rows idx[], keeping the inputs and hidden
     // activations, with the loss, its output gradient g4 and the layer
     // gradients g3 = (g4 W4) * (h3 > 0), g2 = (g3 W3) * (h2 > 0) and
-    // g1 = (g2 W2) * (h1 > 0), all in one fused pass.
+    // g1 = (g2 W2) * (h1 > 0), all in one launch of k_mlp_train.
     TrainIO io{idx, X, {h[0], h[1], h[2]}, label, target, g4, loss, g3, g2, g1, {wT[0], wT[1]}};
     launch_train(s, net, feat, B, out, io, ncu);
     // Backward.  Weight gradients dW_l = g_l^T h_(l-1) go to per-layer
