@@ -663,9 +663,10 @@ __global__ __launch_bounds__(512) void k_mlp_train(const uint16_t* __restrict__ 
 // hidden layer for 64 output columns (4 column blocks x 8 K-slices; the same
 // registers hold W2 in the front stage and W3 in the back), so every A
 // fragment read from LDS feeds four MFMAs, and both wavefronts of a SIMD
-// issue a hidden layer's MFMAs in the same step.  Biases and the two output
-// rows sit in LDS.  Products, K-slice order, bias-started accumulators and
-// the bfloat16 ReLU epilogue are those of k_gemm_bf16: the outputs equal the
+// issue a hidden layer's MFMAs in the same step.  The hidden layer's biases
+// sit in registers, layer 1's biases and the two output rows in LDS.
+// Products, K-slice order, bias-started accumulators and the bfloat16 ReLU
+// epilogue are those of k_gemm_bf16: the outputs equal the
 // layer-by-layer path bit for bit.
 constexpr int kInferFT = 32;
 
@@ -678,17 +679,13 @@ __global__ __launch_bounds__(512) void k_mlp_infer(const uint16_t* __restrict__ 
     __shared__ __attribute__((aligned(16))) uint16_t h1[2][FT][FLD];
     __shared__ __attribute__((aligned(16))) uint16_t h2[2][FT][FLD];
     __shared__ __attribute__((aligned(16))) uint16_t h3[2][FT][FLD];
-    __shared__ __attribute__((aligned(16))) float bs[3][256];
+    __shared__ __attribute__((aligned(16))) float bs[1][256];      // layer 1's biases
     __shared__ __attribute__((aligned(16))) uint16_t w4s[2][256];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lq = lane >> 4, lk = lq * 8;
     const bool front = wave < 4;                      // uniform per wavefront
     const int c0 = 64 * (wave & 3);                   // first output column of this wavefront's layer
-    if (tid < 256) {
-        bs[0][tid] = b0[tid];
-        bs[1][tid] = b1[tid];
-        bs[2][tid] = b2[tid];
-    }
+    if (tid < 256) bs[0][tid] = b0[tid];
     w4s[tid >> 8][tid & 255] = w3[tid];               // 512 threads, 2 x 256 weights
     // B fragments: column c0 + 16 j + lr, K values 32 s + lk .. + 8.
     const uint16_t* wl = front ? w1 : w2;
@@ -708,6 +705,15 @@ __global__ __launch_bounds__(512) void k_mlp_infer(const uint16_t* __restrict__ 
         wf0[j] = *reinterpret_cast<const bf16x8*>(v);
     }
     const float bias3 = lr < 2 ? b3[lr] : 0.0f;
+    // The hidden layer's biases for this lane's outputs (columns
+    // c0 + 16 j + 4 lq .. + 3), the accumulators' starting values.
+    f32x4 bh[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float* bl = front ? b1 : b2;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bh[j][v] = bl[c0 + 16 * j + 4 * lq + v];
+    }
 
     const int64_t ntiles = (n + FT - 1) / FT;
     const int64_t mine = blockIdx.x < ntiles ? (ntiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
@@ -741,6 +747,9 @@ __global__ __launch_bounds__(512) void k_mlp_infer(const uint16_t* __restrict__ 
     // Layer 1 of the tile whose features are in fnext, into h.
     auto layer1 = [&](uint16_t (*h)[FLD]) {
         f32x4 acc[RB][4];
+        f32x4 b0v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b0v[j] = *reinterpret_cast<const f32x4*>(&bs[0][c0 + 16 * j + 4 * lq]);
 #pragma unroll
         for (int i = 0; i < RB; ++i) {
             uint16_t v[8];
@@ -750,20 +759,17 @@ __global__ __launch_bounds__(512) void k_mlp_infer(const uint16_t* __restrict__ 
             const bf16x8 a = *reinterpret_cast<const bf16x8*>(v);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    wf0[j], a, *reinterpret_cast<const f32x4*>(&bs[0][c0 + 16 * j + 4 * lq]), 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf0[j], a, b0v[j], 0, 0, 0);
         }
         store(h, acc);
     };
     // A hidden layer (1: W2, front; 2: W3, back), accumulators started at the bias.
-    auto hidden = [&](uint16_t (*hin)[FLD], uint16_t (*hout)[FLD], int layer) {
+    auto hidden = [&](uint16_t (*hin)[FLD], uint16_t (*hout)[FLD]) {
         f32x4 acc[RB][4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const f32x4 b = *reinterpret_cast<const f32x4*>(&bs[layer][c0 + 16 * j + 4 * lq]);
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int i = 0; i < RB; ++i) acc[i][j] = b;
-        }
+            for (int i = 0; i < RB; ++i) acc[i][j] = bh[j];
 #pragma unroll
         for (int sl = 0; sl < 8; ++sl)
 #pragma unroll
@@ -775,7 +781,7 @@ __global__ __launch_bounds__(512) void k_mlp_infer(const uint16_t* __restrict__ 
             }
         store(hout, acc);
     };
-    __syncthreads();                                  // biases and output rows in LDS
+    __syncthreads();                                  // layer 1's biases and output rows in LDS
     if (front && mine > 0) {
         load_feat(tile_of(0));
         layer1(h1[0]);
@@ -785,13 +791,13 @@ __global__ __launch_bounds__(512) void k_mlp_infer(const uint16_t* __restrict__ 
     for (int64_t k = 0; k <= mine + 1; ++k) {
         const int p = (int)(k & 1);
         if (front) {
-            if (k < mine) hidden(h1[p], h2[p], 1);
+            if (k < mine) hidden(h1[p], h2[p]);
             if (k + 1 < mine) {
                 layer1(h1[p ^ 1]);
                 if (k + 2 < mine) load_feat(tile_of(k + 2));
             }
         } else {
-            if (k >= 1 && k <= mine) hidden(h2[p ^ 1], h3[p ^ 1], 2);
+            if (k >= 1 && k <= mine) hidden(h2[p ^ 1], h3[p ^ 1]);
             // Layer 4, row block wave - 4 of tile k - 2 (parity p): outputs 0
             // and 1 in columns 0 and 1; the other lanes' B operands (copies of
             // row lane % 2) feed columns that are never stored.
