@@ -565,9 +565,9 @@ size_t pn_mlp_infer_workspace_size(int64_t chunk);
 pn_status pn_mlp_infer(const pn_mlp* net, const float* feat, int64_t n, float* out, int64_t chunk,
                        void* ws, size_t ws_bytes, hipStream_t stream);
 
-/* The same outputs as pn_mlp_infer, bit for bit for finite features (a
- * non-finite feature makes the row's outputs non-finite on both paths, not
- * necessarily the same bits), from one persistent kernel
+/* The same outputs as pn_mlp_infer, bit for bit for finite features (a row
+ * with a non-finite feature may differ between the two paths), from one
+ * persistent kernel
  * that runs all four layers on 32-row tiles with the activations in LDS and
  * the hidden-layer weights in registers, layers 1-2 and layers 3-4 on two
  * halves of each workgroup as a two-stage pipeline.  No workspace;
