@@ -437,13 +437,17 @@ def surrogate_bench(args, dev):
 
     # The network's own kernel: fused inference over every grid point against
     # its matrix-core roofline (2 x 133,376 multiply-adds per point), and the
-    # layer-by-layer path it replaces.
+    # layer-by-layer path it replaces.  Five untimed launches first: after the
+    # host-side gap the chip's clock ramps from about 1.9 to 2.3 GHz over the
+    # first few launches, and the roofline is taken at the settled clock, as
+    # the FP64 kernels' (which run for seconds) are.
     feat = S.workload_features(grid, ts.stats, dev)
     stream = torch.cuda.current_stream(dev)
     inf = {}
     for name, fn in (("fused", lambda: pn.mlp_infer_fused(net, feat)),
                      ("layered", lambda: pn.mlp_infer(net, feat, chunk=1 << 20))):
-        fn()
+        for _ in range(5):
+            fn()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
         for a, b in evs:
             a.record(stream)
