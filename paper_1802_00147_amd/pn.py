@@ -754,7 +754,7 @@ def mlp_infer(net, feat, chunk=1 << 20, out=None, ws=None):
 
 
 def mlp_infer_fused(net, feat, out=None):
-    """pn_mlp_infer_fused: all four layers in one kernel; same bits as mlp_infer."""
+    """pn_mlp_infer_fused: all four layers in one kernel; same bits as mlp_infer for finite features."""
     n = feat.shape[0]
     if out is None:
         out = torch.empty((n, 2), dtype=torch.float32, device=feat.device)
