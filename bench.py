@@ -141,8 +141,8 @@ def cpu_baseline(wl, sample, flop_sample_steps=2000):
     import oracle as O
     from paper_1802_00147_amd import workloads as W
     idx = W.strided_sample(wl.n, sample, seed=11)
-    # Threads that can work: the host's cores (at most 16, a GPU machine's CPU
-    # share), and no more than the sample has orbits.
+    # Threads that can work: the host's cores (at most 16, the CPU share of
+    # one GPU on a shared host), and no more than the sample has orbits.
     cores = max(1, min(os.cpu_count() or 1, 16, len(idx)))
     sub = wl.subset(idx)
     y0 = O.init_state(sub.r0, sub.p0, sub.th1, sub.ph1, sub.th2, sub.ph2, sub.beta, sub.chi1, sub.chi2,
