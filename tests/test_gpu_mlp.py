@@ -180,7 +180,7 @@ def _ulp_bf16(x):
     return 2.0 ** (e - 7)
 
 
-@pytest.mark.parametrize("B", [100, 1024, 4096])
+@pytest.mark.parametrize("B", [1, 17, 100, 1024, 4096])   # one row; one full and one ragged 16-row tile
 def test_train_step_elementwise(pn, B):
     """One training step checked element by element, layer by layer, against
     FP64 products of the step's own bfloat16 operands (the tensors it leaves
