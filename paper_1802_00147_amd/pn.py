@@ -193,6 +193,27 @@ def _check(fn, st):
         raise PnError(fn, st, (L.pn_status_string(st) or b"").decode() + " " + (L.pn_last_error() or b"").decode())
 
 
+def _dev(t, dtype, name, shape=None, min_numel=None):
+    """A contiguous device tensor of the given dtype (and shape, or at least
+    min_numel elements), else ValueError: the kernels read and write these
+    arrays through bare pointers, so a wrong size would run past them."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous {dtype} device tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{name}: expected at least {min_numel} elements, got {t.numel()}")
+    return t
+
+
+def _feat_rows(feat):
+    """Rows of a feature array [rows][8] (float32, contiguous, on the device)."""
+    if not isinstance(feat, torch.Tensor) or feat.dim() != 2:
+        raise ValueError("feat: expected a [rows][8] float32 device tensor")
+    _dev(feat, torch.float32, "feat", shape=(feat.shape[0], 8))
+    return feat.shape[0]
+
+
 def _dev_f64(t, n=None):
     assert t.dtype == torch.float64 and t.is_cuda, "expected a float64 device tensor"
     if n is not None:
@@ -691,10 +712,21 @@ def mlp_features(n, r0, th1, th2, t_end, beta, chi1, chi2, mean, std, idx=None, 
     return out
 
 
+def _train_args(feat, label, target, order, loss):
+    rows = _feat_rows(feat)
+    _dev(label, torch.float32, "label", shape=(rows,))
+    _dev(target, torch.float32, "target", shape=(rows,))
+    _dev(order, torch.int32, "idx/order")       # its values must lie in [0, rows)
+    _dev(loss, torch.float32, "loss", min_numel=1)
+
+
 def mlp_train_step(net, feat, label, target, idx, lr, loss, ws=None):
+    _train_args(feat, label, target, idx, loss)
     batch = idx.numel()
+    need = int(lib().pn_mlp_train_workspace_size(batch))
     if ws is None:
-        ws = torch.empty(int(lib().pn_mlp_train_workspace_size(batch)), dtype=torch.uint8, device=feat.device)
+        ws = torch.empty(need, dtype=torch.uint8, device=feat.device)
+    _dev(ws, torch.uint8, "ws", min_numel=need)
     net.step += 1
     st = lib().pn_mlp_train_step(ctypes.byref(net.struct), _ptr(feat), _ptr(label), _ptr(target), _ptr(idx),
                                  ctypes.c_int32(batch), ctypes.c_int32(net.step), ctypes.c_float(lr), _ptr(loss),
@@ -728,9 +760,12 @@ def mlp_train_step_tensors(ws, batch):
 def mlp_train(net, feat, label, target, order, batch, lr, loss, ws=None):
     """pn_mlp_train: len(order) // batch steps over the rows in `order` (device
     int32), advancing net.step; returns the workspace."""
+    _train_args(feat, label, target, order, loss)
     nbatch = order.numel() // batch
+    need = int(lib().pn_mlp_train_workspace_size(batch))
     if ws is None:
-        ws = torch.empty(int(lib().pn_mlp_train_workspace_size(batch)), dtype=torch.uint8, device=feat.device)
+        ws = torch.empty(need, dtype=torch.uint8, device=feat.device)
+    _dev(ws, torch.uint8, "ws", min_numel=need)
     step = ctypes.c_int32(net.step)
     st = lib().pn_mlp_train(ctypes.byref(net.struct), ctypes.byref(step), _ptr(feat), _ptr(label), _ptr(target),
                             _ptr(order), ctypes.c_int64(nbatch), ctypes.c_int32(batch), ctypes.c_float(lr), _ptr(loss),
@@ -741,12 +776,15 @@ def mlp_train(net, feat, label, target, order, batch, lr, loss, ws=None):
 
 
 def mlp_infer(net, feat, chunk=1 << 20, out=None, ws=None):
-    n = feat.shape[0]
+    n = _feat_rows(feat)
     if out is None:
         out = torch.empty((n, 2), dtype=torch.float32, device=feat.device)
+    _dev(out, torch.float32, "out", shape=(n, 2))
     chunk = max(1, min(chunk, n))
+    need = int(lib().pn_mlp_infer_workspace_size(chunk))
     if ws is None:
-        ws = torch.empty(int(lib().pn_mlp_infer_workspace_size(chunk)), dtype=torch.uint8, device=feat.device)
+        ws = torch.empty(need, dtype=torch.uint8, device=feat.device)
+    _dev(ws, torch.uint8, "ws", min_numel=need)
     st = lib().pn_mlp_infer(ctypes.byref(net.struct), _ptr(feat), ctypes.c_int64(n), _ptr(out), ctypes.c_int64(chunk),
                             _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(feat.device))
     _check("pn_mlp_infer", st)
@@ -755,9 +793,10 @@ def mlp_infer(net, feat, chunk=1 << 20, out=None, ws=None):
 
 def mlp_infer_fused(net, feat, out=None):
     """pn_mlp_infer_fused: all four layers in one kernel; same bits as mlp_infer for finite features."""
-    n = feat.shape[0]
+    n = _feat_rows(feat)
     if out is None:
         out = torch.empty((n, 2), dtype=torch.float32, device=feat.device)
+    _dev(out, torch.float32, "out", shape=(n, 2))
     st = lib().pn_mlp_infer_fused(ctypes.byref(net.struct), _ptr(feat), ctypes.c_int64(n), _ptr(out),
                                   _stream(feat.device))
     _check("pn_mlp_infer_fused", st)

@@ -391,3 +391,25 @@ def test_noalloc_batch_scan_rejects_more_orbits_than_its_static_workspace(pn):
                                        ctypes.c_int64(n), ctypes.c_void_p(8), ctypes.byref(so), None, None)
     assert st == pn.PN_EINVAL
     assert b"2^20" in pn.lib().pn_last_error()
+
+
+def test_mlp_wrappers_reject_malformed_tensors(pn):
+    """The binding checks the arrays the network's kernels address through
+    bare pointers: host tensors, other dtypes and other shapes raise
+    ValueError before any device call."""
+    import torch
+    host = torch.zeros(4, 8)
+    with pytest.raises(ValueError):
+        pn.mlp_infer_fused(None, host)
+    with pytest.raises(ValueError):
+        pn.mlp_infer(None, host)
+    with pytest.raises(ValueError):
+        pn.mlp_infer_fused(None, torch.zeros(4, 7))
+    with pytest.raises(ValueError):
+        pn.mlp_infer_fused(None, torch.zeros(32, dtype=torch.float32))
+    with pytest.raises(ValueError):
+        pn.mlp_train_step(None, host, torch.zeros(4), torch.zeros(4), torch.zeros(2, dtype=torch.int32), 1e-3,
+                          torch.zeros(1))
+    with pytest.raises(ValueError):
+        pn.mlp_train(None, host, torch.zeros(4), torch.zeros(4), torch.zeros(2, dtype=torch.int32), 2, 1e-3,
+                     torch.zeros(1))
