@@ -193,6 +193,12 @@ def _check(fn, st):
         raise PnError(fn, st, (L.pn_status_string(st) or b"").decode() + " " + (L.pn_last_error() or b"").decode())
 
 
+def _require(cond, msg):
+    """Argument check that stays on under python -O."""
+    if not cond:
+        raise ValueError(msg)
+
+
 def _dev(t, dtype, name, shape=None, min_numel=None):
     """A contiguous device tensor of the given dtype (and shape, or at least
     min_numel elements), else ValueError: the kernels read and write these
@@ -215,9 +221,9 @@ def _feat_rows(feat):
 
 
 def _dev_f64(t, n=None):
-    assert t.dtype == torch.float64 and t.is_cuda, "expected a float64 device tensor"
+    _require(t.dtype == torch.float64 and t.is_cuda, "expected a float64 device tensor")
     if n is not None:
-        assert t.numel() >= n
+        _require(t.numel() >= n, f"expected at least {n} elements, got {t.numel()}")
     return t.contiguous()
 
 
@@ -231,8 +237,9 @@ def params_struct(beta, chi1, chi2):
 
 
 def _state(y):
-    assert y.dim() == 2 and y.shape[0] == 12 and y.dtype == torch.float64 and y.is_cuda
-    assert y.is_contiguous()
+    _require(y.dim() == 2 and y.shape[0] == 12 and y.dtype == torch.float64 and y.is_cuda,
+             "y: expected a float64 [12][ld] device tensor")
+    _require(y.is_contiguous(), "y: expected a contiguous tensor")
     return y.shape[1]
 
 
@@ -276,7 +283,8 @@ def manifold_correct(y, ref, beta, chi1, chi2, model=None, correction=None, n=No
     """Correct y (12, ld) in place against ref (4, ld); returns iteration counts."""
     ld = _state(y)
     n = ld if n is None else n
-    assert ref.shape == (4, ld) and ref.dtype == torch.float64 and ref.is_contiguous()
+    _require(ref.shape == (4, ld) and ref.dtype == torch.float64 and ref.is_contiguous(),
+             "ref: expected a contiguous float64 [4][ld] tensor")
     it = torch.empty(ld, dtype=torch.int32, device=y.device)
     p, keep = params_struct(beta, chi1, chi2)
     st = lib().pn_manifold_correct(ctypes.byref(model_struct(model)), p,
@@ -292,7 +300,8 @@ def step(y, beta, chi1, chi2, nsteps, model=None, integrator=None, correction=No
     ld = _state(y)
     n = ld if n is None else n
     if ref is not None:
-        assert ref.shape == (4, ld) and ref.dtype == torch.float64 and ref.is_contiguous()
+        _require(ref.shape == (4, ld) and ref.dtype == torch.float64 and ref.is_contiguous(),
+                 "ref: expected a contiguous float64 [4][ld] tensor")
     p, keep = params_struct(beta, chi1, chi2)
     cc = ctypes.byref(correction_struct(correction)) if correction is not None else None
     st = lib().pn_step(ctypes.byref(model_struct(model)), p, ctypes.byref(integrator_struct(integrator)), cc,
@@ -329,7 +338,8 @@ def trajectory(y, beta, chi1, chi2, nsteps, every, model=None, integrator=None, 
     rows = nsteps // every
     traj = torch.empty((rows, 12, ld), dtype=torch.float64, device=y.device)
     if ref is not None:
-        assert ref.shape == (4, ld) and ref.dtype == torch.float64 and ref.is_contiguous()
+        _require(ref.shape == (4, ld) and ref.dtype == torch.float64 and ref.is_contiguous(),
+                 "ref: expected a contiguous float64 [4][ld] tensor")
     p, keep = params_struct(beta, chi1, chi2)
     cc = ctypes.byref(correction_struct(correction)) if correction is not None else None
     st = lib().pn_trajectory(ctypes.byref(model_struct(model)), p, ctypes.byref(integrator_struct(integrator)), cc,
@@ -344,7 +354,8 @@ def gw_polarizations(traj, beta, chi1, chi2, nhat, phat, dist=1.0, model=None, n
     or (12, ld)."""
     if traj.dim() == 2:
         traj = traj.unsqueeze(0)
-    assert traj.dim() == 3 and traj.shape[1] == 12 and traj.dtype == torch.float64 and traj.is_contiguous()
+    _require(traj.dim() == 3 and traj.shape[1] == 12 and traj.dtype == torch.float64 and traj.is_contiguous(),
+             "traj: expected a contiguous float64 [rows][12][ld] tensor")
     ns, _, ld = traj.shape
     n = ld if n is None else n
     hp = torch.empty((ns, ld), dtype=torch.float64, device=traj.device)
@@ -407,7 +418,7 @@ def _batch_common(y0, t_end, beta, chi1, chi2, model, integrator, correction, fl
     ld = _state(y0)
     n = ld if n is None else n
     integ = integrator_struct(integrator)
-    assert isinstance(t_end, torch.Tensor), "batch scans take per-orbit end times"
+    _require(isinstance(t_end, torch.Tensor), "batch scans take per-orbit end times")
     t_end = _dev_f64(t_end, n)
     if out is None:
         tmax = float(t_end[:n].max()) if n > 0 else 0.0
@@ -445,7 +456,7 @@ def batch_scan_noalloc(y0, t_end, beta, chi1, chi2, model=None, integrator=None,
     ld = _state(y0)
     n = ld if n is None else n
     integ = integrator_struct(integrator)
-    assert isinstance(t_end, torch.Tensor), "batch scans take per-orbit end times"
+    _require(isinstance(t_end, torch.Tensor), "batch scans take per-orbit end times")
     t_end = _dev_f64(t_end, n)
     if out is None:
         out = scan_outputs(n, ld, y0.device, full=full)
@@ -477,7 +488,7 @@ def batch_scan_resumable(y0, t_end, beta, chi1, chi2, ws, resume, max_chunks, mo
     ld = _state(y0)
     n = ld if n is None else n
     integ = integrator_struct(integrator)
-    assert isinstance(t_end, torch.Tensor), "batch scans take per-orbit end times"
+    _require(isinstance(t_end, torch.Tensor), "batch scans take per-orbit end times")
     t_end = _dev_f64(t_end, n)
     if out is None:
         out = scan_outputs(n, ld, y0.device, full=full)
@@ -679,7 +690,7 @@ class Network:
         self.w = [torch.as_tensor(W, **f32).contiguous() for W in weights]
         self.b = [torch.as_tensor(b, **f32).contiguous() for b in biases]
         for l in range(4):
-            assert tuple(self.w[l].shape) == (LAYER_OUT[l], LAYER_IN[l])
+            _require(tuple(self.w[l].shape) == (LAYER_OUT[l], LAYER_IN[l]), f"layer {l} weights: wrong shape")
         self.wb = [torch.empty(W.shape, dtype=torch.int16, device=device) for W in self.w]
         z = (lambda t: torch.zeros_like(t)) if training else (lambda t: None)
         self.mw, self.vw = [z(W) for W in self.w], [z(W) for W in self.w]
